@@ -1,0 +1,267 @@
+/*
+ * piso.h - C-ABI of a multi-block PISO time step for incompressible flow on
+ * AMD Instinct MI355X (gfx950), with its hand-written adjoint.
+ *
+ * The method is the PISO algorithm with a collocated finite-volume discretisation on
+ * multi-block structured grids with precomputed cell-centre transformations, as given
+ * in arXiv 2505.16992 (PICT), Sec. 2.1-2.3 and App. A.2-A.5.  One step:
+ *
+ *   predictor   C(u^n) u* = b,  b = b_u - grad p^n            (App. A.2, eq. advectionMat)
+ *   corrector   h = A^-1 (b_u - H u);  P p = div h;  u = h - A^-1 grad p
+ *               applied twice (u = u*, then u**)                (eqs. pressureRHS, pressure,
+ *                                                                  correction)
+ *   output      u^{n+1} = u***,  p^{n+1} = p**
+ *
+ * with A = diag(C), H = C - A, P the pressure matrix of eq. pMatDiscrete, b_u the
+ * predictor right-hand side of eq. velRHSdiscrete (plus deferred non-orthogonal terms,
+ * App. A.3.5).  Rows of C are per unit volume (temporal term 1/dt).
+ *
+ * Data layout (all calls):
+ *   - cells of block b are numbered off_b + i + nx*(j + ny*k) (x fastest), blocks
+ *     concatenated in block order; N = total cells, d = 2 or 3;
+ *   - fields are structure-of-arrays: a vector field is [d][N], a scalar [N];
+ *   - face arrays are [d][N]: entry [j][P] belongs to the face between P and its
+ *     +j neighbour (zero where that face is a boundary);
+ *   - the matrix C is stored as its diagonal A [N] and the face array C [2][d][N]:
+ *     C[0][j][P] = C(P, P+j) and C[1][j][P] = C(P+j, P);
+ *   - Dirichlet boundary values u_b are [d][NB]: Dirichlet segments in the order they
+ *     were given to piso_create, faces of a segment in tangential order (first
+ *     tangential axis fastest).
+ *   - element type of every field, intermediate and gradient: double for PISO_F64,
+ *     float for PISO_F32 and PISO_MIXED.
+ *
+ * Pointers: "device" pointers must point to memory of the device that was current at
+ * piso_create; "host" pointers are read during the call only.  The caller owns every
+ * field, intermediate, tape and gradient buffer; the context owns its topology tables,
+ * metric copies and solver workspaces (allocated in piso_create, freed in
+ * piso_destroy).  A context is not thread-safe; calls on one context must not overlap.
+ *
+ * Streams: work is enqueued on the given stream (hipStream_t, may be 0).  The Krylov
+ * solves read their convergence state back to the host every check_every iterations,
+ * which synchronises that stream; everything else is asynchronous.
+ *
+ * Errors: a negative return is a hard error (outputs unspecified, message from
+ * piso_last_error); a positive return is a soft status (outputs written; see the
+ * piso_solve_info).  No call allocates device memory after piso_create.
+ */
+#ifndef PISO_H
+#define PISO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct piso_ctx piso_ctx;
+
+typedef enum {
+  PISO_F64 = 0,    /* all storage and arithmetic in double */
+  PISO_F32 = 1,    /* float storage and stencil arithmetic; Krylov dot products in double */
+  PISO_MIXED = 2   /* as F32, plus a double residual and iterative refinement of the
+                      pressure solve (double pressure accumulator, float inner PCG) */
+} piso_precision;
+
+typedef enum {
+  PISO_OK = 0,
+  PISO_NOT_CONVERGED = 1,   /* solve stopped at max_iter above its tolerance */
+  PISO_BREAKDOWN = 2,       /* BiCGStab breakdown (rho or omega vanished) */
+  PISO_E_ARG = -1,          /* invalid argument (null pointer, bad size, bad option) */
+  PISO_E_TOPOLOGY = -2,     /* invalid block layout (see piso_create) */
+  PISO_E_HIP = -3,          /* a HIP runtime call failed */
+  PISO_E_NAN = -4,          /* a residual became NaN or infinite */
+  PISO_E_OOM = -5           /* device allocation failed in piso_create */
+} piso_status;
+
+typedef enum {
+  PISO_SIDE_CONNECT = 0,    /* conformal connection to the opposite side of another (or the
+                               same, for periodicity) block with the same axis orientation */
+  PISO_SIDE_DIRICHLET = 1   /* prescribed velocity u_b; implies zero-Neumann pressure (App. A.4) */
+} piso_side_kind;
+
+/* One segment of one block side (Sec. 2.2: each side carries a connection or a prescribed
+ * value; a side may be tiled by several segments).  side: 0 -x, 1 +x, 2 -y, 3 +y, 4 -z,
+ * 5 +z.  Tangential axes of a side are the two other axes in increasing order.  */
+typedef struct {
+  int32_t block, side, kind;
+  int32_t begin[2], end[2];        /* tangential cell range [begin, end); 2D: begin[1]=0, end[1]=1 */
+  int32_t other_block;             /* CONNECT: block entered through this segment */
+  int32_t other_begin[2];          /* CONNECT: tangential position of begin on the other side */
+} piso_side_desc;
+
+typedef struct {
+  int32_t dim;                     /* 2 or 3 */
+  int32_t n_blocks;                /* 1 .. 16 */
+  int32_t n_sides;
+  const int32_t* block_cells;      /* host [n_blocks][3] (nx, ny, nz); nz = 1 in 2D */
+  const piso_side_desc* sides;     /* host [n_sides]; must tile every block side exactly once */
+  const double* T;                 /* host [d][d][N]: T[(j*d + i)*N + P] = d xi^j / d x_i at centres */
+  const double* J;                 /* host [N]: det(d x / d xi) > 0 (cell volume) */
+} piso_domain_desc;
+
+typedef struct {
+  double rtol;                     /* stop when ||b - M x||_2 <= rtol ||b||_2 (per component) */
+  int32_t max_iter;                /* Krylov iterations (MIXED pressure: inner iterations per sweep) */
+  int32_t check_every;             /* iterations between convergence read-backs */
+  double inner_rtol;               /* MIXED pressure only: inner float PCG tolerance */
+  int32_t max_refine;              /* MIXED pressure only: refinement sweeps */
+  int32_t reserved;
+} piso_solve_opts;
+
+typedef struct {
+  int32_t status;                  /* PISO_OK, PISO_NOT_CONVERGED, PISO_BREAKDOWN or < 0 */
+  int32_t iters;                   /* Krylov iterations (summed over components / sweeps) */
+  int32_t refinements;             /* MIXED: refinement sweeps */
+  int32_t reserved;
+  double rel_residual;             /* final relative residual (max over components) */
+} piso_solve_info;
+
+typedef struct {
+  piso_solve_opts vel, pres;
+  int32_t n_correctors;            /* pressure correctors per step; 2 in PISO (App. A.2) */
+  int32_t grad_p_in_predictor;     /* 1: b = b_u - grad p^n (eq. implEuler1); 0: b = b_u */
+  int32_t grad_path_flags;         /* backward only: 1 = skip the adjoint velocity solve,
+                                      2 = skip the adjoint pressure solves (Sec. 2.4) */
+  int32_t reserved;
+} piso_step_opts;
+
+typedef struct {
+  piso_solve_info vel;
+  piso_solve_info pres[2];
+} piso_step_info;
+
+/* Intermediates of the fine-grained calls; every pointer is a caller-owned device
+ * buffer of the context's element type. */
+typedef struct {
+  void* A;      /* [N]      diagonal of C */
+  void* C;      /* [2][d][N] off-diagonal face coefficients of C */
+  void* b_u;    /* [d][N]   predictor right-hand side without the pressure gradient */
+  void* b;      /* [d][N]   predictor right-hand side b = b_u - grad p^n */
+  void* Pf;     /* [d][N]   pressure face coefficients lerp(alpha_jj / A) */
+  void* Dinv;   /* [N]      inverse of the pressure matrix diagonal (Jacobi) */
+  void* h;      /* [d][N]   A^-1 (b_u - H u) of the latest piso_solve_pressure */
+  void* rhs;    /* [N]      divergence of h (+ boundary flux, + lag term), before mean removal */
+} piso_system;
+
+/* Gradients of the intermediates, accumulated (+=) by the backward calls. */
+typedef struct {
+  void* dA;     /* [N] */
+  void* dC;     /* [2][d][N] */
+  void* db_u;   /* [d][N] */
+  void* db;     /* [d][N] */
+} piso_system_grad;
+
+/* Build a context for a block layout (Sec. 2.2, App. A.4).  Validates that every block
+ * side is tiled exactly once, connections are conformal and reciprocal (matching
+ * resolution, opposite sides, same orientation), J > 0; returns PISO_E_TOPOLOGY
+ * otherwise.  Derives alpha_jk = J T_j . T_k (App. A.3.3) on the device and detects
+ * non-orthogonal grids (max |alpha_jk| / alpha_jj > 1e-12).  Uses the current HIP device.
+ * On failure *out is NULL and piso_create_error() returns the message. */
+int piso_create(const piso_domain_desc* desc, int32_t precision, piso_ctx** out);
+void piso_destroy(piso_ctx* ctx);
+const char* piso_last_error(const piso_ctx* ctx);
+const char* piso_create_error(void);
+
+/* Sizes: cells, Dirichlet faces, bytes of one step tape (see piso_step), element bytes,
+ * non-orthogonal flag. Any output pointer may be NULL. */
+int piso_sizes(const piso_ctx* ctx, int64_t* n_cells, int64_t* n_bfaces, int64_t* tape_bytes,
+               int64_t* elem_bytes, int32_t* non_orthogonal);
+
+/* Default options for a precision: vel rtol 1e-10 (F64) / 1e-7, pres rtol 1e-10 (F64),
+ * 1e-6 (F32), 1e-8 (MIXED, inner 1e-3), 2 correctors, grad_p_in_predictor = 1. */
+void piso_default_step_opts(int32_t precision, piso_step_opts* opts);
+
+/* Predictor assembly (App. A.3.3-A.3.5, eqs. advMatDiscrete, difMatDiscrete,
+ * velRHSdiscrete, velRHSnonOrtho) and pressure coefficients (eq. pMatDiscrete):
+ * writes sys->A, C, b_u, b, Pf, Dinv.  nu: device [N] if nu_is_field else [1].
+ * u_n [d][N], p_n [N], S [d][N], u_b [d][NB] (may be NULL if NB = 0).
+ * grad_p_in_predictor: 1 subtracts the central gradient of p_n from b. */
+int piso_assemble(piso_ctx* ctx, void* stream, const void* u_n, const void* p_n, const void* nu,
+                  int32_t nu_is_field, const void* S, const void* u_b, double dt,
+                  int32_t grad_p_in_predictor, const piso_system* sys);
+
+/* Velocity predictor solve C u* = b (App. A.6: BiCGStab) for the d components at once,
+ * Jacobi-preconditioned on the right, from x0 = u_star (in) to rtol; u_star [d][N]. */
+int piso_solve_velocity(piso_ctx* ctx, void* stream, const piso_system* sys, void* u_star,
+                        const piso_solve_opts* opts, piso_solve_info* info);
+
+/* Pressure corrector: h = A^-1 (b_u - H u_in) (eq. pressureRHS), rhs = div h + Dirichlet
+ * face flux + deferred non-orthogonal term of p_lag (eqs. pressureRHSdivDiscrete,
+ * pressureRHSnonOrtho), then the zero-mean solution of P p = rhs - mean(rhs) by Jacobi
+ * PCG on -P (App. A.6: CG) from x0 = p (in).  Writes sys->h, sys->rhs and p. */
+int piso_solve_pressure(piso_ctx* ctx, void* stream, const piso_system* sys, const void* u_in,
+                        const void* u_b, const void* p_lag, void* p, const piso_solve_opts* opts,
+                        piso_solve_info* info);
+
+/* Velocity correction u_out = h - A^-1 grad p (eq. velCorrDiscrete) with central
+ * differences and boundary value p_b = p_P.  If F_out [d][N] is not NULL it receives the
+ * corrected face flux lerp(J T_j . h) - P_f (p_F - p_P) - cross(p_lag) of every +j face;
+ * its divergence equals the pressure residual. */
+int piso_correct(piso_ctx* ctx, void* stream, const piso_system* sys, const void* p,
+                 const void* p_lag, const void* u_b, void* u_out, void* F_out);
+
+/* One full PISO step (App. A.2): assemble, velocity solve from u_n, correctors with
+ * pressure initial guesses p_n then p*.  Outputs u_np1 [d][N], p_np1 [N].  If tape is
+ * not NULL (tape_bytes from piso_sizes), everything piso_step_backward needs is stored
+ * there.  info may be NULL. */
+int piso_step(piso_ctx* ctx, void* stream, const void* u_n, const void* p_n, const void* nu,
+              int32_t nu_is_field, const void* S, const void* u_b, double dt, void* u_np1,
+              void* p_np1, void* tape, const piso_step_opts* opts, piso_step_info* info);
+
+/* ---- adjoint (App. A.5; each linear solve A x = b is differentiated by solving
+ * A^T db = dx and dA = -db (x) x on A's sparsity, Sec. 2.3).  All gradient outputs
+ * are accumulated (+=); NULL means "not requested" where stated. */
+
+/* Adjoint of piso_correct: dh += du_out; dp += -G^T (du_out / A); dA += (grad p) . du_out / A^2. */
+int piso_correct_backward(piso_ctx* ctx, void* stream, const piso_system* sys, const void* p,
+                          const void* du_out, void* dh, void* dp, void* dA);
+
+/* Adjoint of piso_solve_pressure given the gradients dh (of sys->h) and dp (of p):
+ * solves P lambda = dp - mean(dp) (same PCG), then accumulates du_in, dp_lag (may be
+ * NULL on orthogonal grids), du_b (may be NULL), and g->db_u, g->dA, g->dC.  p is the
+ * forward solution, u_in the forward input, sys->h the forward h.  skip_solve = 1
+ * takes lambda = 0 (gradient path without the pressure solve, Sec. 2.4). */
+int piso_solve_pressure_backward(piso_ctx* ctx, void* stream, const piso_system* sys,
+                                 const void* u_in, const void* p_lag, const void* p,
+                                 const void* dh, const void* dp, void* du_in, void* dp_lag,
+                                 void* du_b, const piso_system_grad* g, int32_t skip_solve,
+                                 const piso_solve_opts* opts, piso_solve_info* info);
+
+/* Adjoint of piso_solve_velocity: solves C^T mu = du_star (transposed BiCGStab), then
+ * g->db += mu, g->dA += -mu . u*, g->dC += -mu (x) u* on the stencil.  skip_solve = 1
+ * takes mu = 0 (Sec. 2.4). */
+int piso_solve_velocity_backward(piso_ctx* ctx, void* stream, const piso_system* sys,
+                                 const void* u_star, const void* du_star,
+                                 const piso_system_grad* g, int32_t skip_solve,
+                                 const piso_solve_opts* opts, piso_solve_info* info);
+
+/* Adjoint of piso_assemble for the gradients in g (dA, dC, db_u, db; dPf is folded into
+ * dA by piso_solve_pressure_backward): accumulates du_n, dp_n, dS, dnu ([N] if
+ * nu_is_field else [1]) and du_b; any output may be NULL. */
+int piso_assemble_backward(piso_ctx* ctx, void* stream, const void* u_n, const void* nu,
+                           int32_t nu_is_field, const void* u_b, double dt,
+                           int32_t grad_p_in_predictor, const piso_system_grad* g, void* du_n,
+                           void* dp_n, void* dS, void* dnu, void* du_b);
+
+/* Adjoint of piso_step from its tape: given du_np1 [d][N] and dp_np1 [N] (either may be
+ * NULL = zero), accumulates du_n, dp_n, dS, dnu, du_b (any may be NULL).  u_n, p_n, nu,
+ * u_b, dt must be the forward inputs.  opts->grad_path_flags selects Sec. 2.4 paths. */
+int piso_step_backward(piso_ctx* ctx, void* stream, const void* tape, const void* u_n,
+                       const void* p_n, const void* nu, int32_t nu_is_field, const void* u_b,
+                       double dt, const void* du_np1, const void* dp_np1, void* du_n, void* dp_n,
+                       void* dS, void* dnu, void* du_b, const piso_step_opts* opts,
+                       piso_step_info* info);
+
+/* Diagnostics used by tests and benchmarks. */
+/* Last solve's kernel launch counts and the average duration of the pressure PCG
+ * kernels measured with HIP events on the call's stream when timing is enabled. */
+int piso_set_timing(piso_ctx* ctx, int32_t enable);
+int piso_get_timing(piso_ctx* ctx, double* cg_spmv_ms, double* cg_update_ms, int64_t* cg_spmv_calls,
+                    int64_t* cg_update_calls);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PISO_H */

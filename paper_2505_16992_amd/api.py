@@ -1,0 +1,357 @@
+"""Python API over the PISO C-ABI: contexts, one step, its adjoint, an autograd
+Function and a checkpointed rollout.
+
+PyTorch supplies device memory and the stream; every computation is done by the HIP
+kernels behind libpiso.so.  Tensors are SoA: a vector field is [d, N], a scalar [N],
+Dirichlet values [d, NB], viscosity [1] (global) or [N] (per cell).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_KIND = {"connect": L.PISO_SIDE_CONNECT, "dirichlet": L.PISO_SIDE_DIRICHLET}
+_PREC = {"f64": L.PISO_F64, "f32": L.PISO_F32, "mixed": L.PISO_MIXED}
+
+
+class PisoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("piso error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _tangential(block, side, dim):
+    axis = side // 2
+    others = [block[a] for a in range(dim) if a != axis]
+    while len(others) < 2:
+        others.append(1)
+    return others
+
+
+class Context:
+    """A block layout, its metrics and the solver workspaces on the current device.
+
+    domain: any object with .dim, .blocks [(nx, ny, nz)], .sides (objects with block,
+    side, kind in {'connect', 'dirichlet'}, begin, end (None = whole side), other_block,
+    other_begin), .T [d, d, N] and .J [N] (numpy float64).
+    """
+
+    def __init__(self, domain, precision: str = "f32"):
+        self.lib = L.lib()
+        self.precision = precision
+        self.prec = _PREC[precision]
+        self.dim = int(domain.dim)
+        self.dtype = torch.float64 if self.prec == L.PISO_F64 else torch.float32
+        cells = np.array([list(b) for b in domain.blocks], dtype=np.int32).reshape(-1)
+        sides = (L.SideDesc * len(domain.sides))()
+        for q, s in enumerate(domain.sides):
+            t0n, t1n = _tangential(domain.blocks[s.block], s.side, self.dim)
+            end = s.end if s.end is not None else (t0n, t1n)
+            sides[q].block, sides[q].side, sides[q].kind = s.block, s.side, _KIND[s.kind]
+            sides[q].begin[0], sides[q].begin[1] = s.begin
+            sides[q].end[0], sides[q].end[1] = end
+            sides[q].other_block = s.other_block
+            sides[q].other_begin[0], sides[q].other_begin[1] = s.other_begin
+        T = np.ascontiguousarray(domain.T, dtype=np.float64)
+        J = np.ascontiguousarray(domain.J, dtype=np.float64)
+        self._keep = (cells, sides, T, J)
+        desc = L.DomainDesc(self.dim, len(domain.blocks), len(domain.sides),
+                            cells.ctypes.data_as(C.POINTER(C.c_int32)), sides,
+                            T.ctypes.data_as(C.POINTER(C.c_double)), J.ctypes.data_as(C.POINTER(C.c_double)))
+        h = C.c_void_p()
+        rc = self.lib.piso_create(C.byref(desc), self.prec, C.byref(h))
+        if rc != 0:
+            raise PisoError(rc, self.lib.piso_create_error().decode())
+        self.h = h
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        n, nb, tb, eb = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        no = C.c_int32()
+        self.lib.piso_sizes(h, C.byref(n), C.byref(nb), C.byref(tb), C.byref(eb), C.byref(no))
+        self.N, self.NB, self.tape_bytes, self.elem_bytes = n.value, nb.value, tb.value, eb.value
+        self.non_orthogonal = bool(no.value)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.piso_destroy(h)
+            self.h = C.c_void_p()
+
+    # ---------------------------------------------------------------- helpers
+    def _check(self, rc, what):
+        if rc < 0:
+            raise PisoError(rc, "%s: %s" % (what, self.lib.piso_last_error(self.h).decode()))
+        return rc
+
+    def _t(self, x, shape, name, allow_none=False):
+        if x is None:
+            if allow_none:
+                return None
+            raise ValueError("%s is required" % name)
+        if x.device != self.device or x.dtype != self.dtype:
+            raise ValueError("%s must be a %s tensor on %s" % (name, self.dtype, self.device))
+        if tuple(x.shape) != tuple(shape):
+            raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(x.shape)))
+        if not x.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        return x
+
+    def _nu(self, nu):
+        if nu.numel() == 1:
+            return self._t(nu.reshape(1), (1,), "nu"), 0
+        return self._t(nu, (self.N,), "nu"), 1
+
+    def _ub(self, u_b):
+        if self.NB == 0:
+            return None
+        return self._t(u_b, (self.dim, self.NB), "u_b")
+
+    def zeros(self, *shape):
+        return torch.zeros(*shape, dtype=self.dtype, device=self.device)
+
+    def default_opts(self) -> L.StepOpts:
+        o = L.StepOpts()
+        self.lib.piso_default_step_opts(self.prec, C.byref(o))
+        return o
+
+    def new_tape(self):
+        return torch.empty(self.tape_bytes // self.elem_bytes, dtype=self.dtype, device=self.device)
+
+    def new_system(self):
+        d, N = self.dim, self.N
+        z = self.zeros
+        return {"A": z(N), "C": z(2, d, N), "b_u": z(d, N), "b": z(d, N), "Pf": z(d, N),
+                "Dinv": z(N), "h": z(d, N), "rhs": z(N)}
+
+    @staticmethod
+    def _sys(t):
+        return L.System(*[t[k].data_ptr() for k in ("A", "C", "b_u", "b", "Pf", "Dinv", "h", "rhs")])
+
+    def new_system_grad(self):
+        d, N = self.dim, self.N
+        z = self.zeros
+        return {"dA": z(N), "dC": z(2, d, N), "db_u": z(d, N), "db": z(d, N)}
+
+    @staticmethod
+    def _gsys(g):
+        return L.SystemGrad(*[g[k].data_ptr() for k in ("dA", "dC", "db_u", "db")])
+
+    # ---------------------------------------------------------------- whole step
+    def step(self, u, p, nu, S, u_b, dt, opts=None, tape=None, info=False):
+        d, N = self.dim, self.N
+        self._t(u, (d, N), "u")
+        self._t(p, (N,), "p")
+        self._t(S, (d, N), "S")
+        nu_t, nf = self._nu(nu)
+        ub = self._ub(u_b)
+        if tape is not None:
+            self._t(tape, (self.tape_bytes // self.elem_bytes,), "tape")
+        o = opts if opts is not None else self.default_opts()
+        u1 = torch.empty_like(u)
+        p1 = torch.empty_like(p)
+        inf = L.StepInfo()
+        rc = self.lib.piso_step(self.h, _stream(), _ptr(u), _ptr(p), _ptr(nu_t), nf, _ptr(S), _ptr(ub),
+                                float(dt), _ptr(u1), _ptr(p1), _ptr(tape), C.byref(o), C.byref(inf))
+        self._check(rc, "piso_step")
+        return (u1, p1, inf.as_dict()) if info else (u1, p1)
+
+    def step_backward(self, tape, u, p, nu, u_b, dt, du1, dp1, opts=None, want=("u", "p", "S", "nu", "u_b"),
+                      info=False):
+        d, N = self.dim, self.N
+        nu_t, nf = self._nu(nu)
+        ub = self._ub(u_b)
+        o = opts if opts is not None else self.default_opts()
+        du = self.zeros(d, N) if "u" in want else None
+        dp = self.zeros(N) if "p" in want else None
+        dS = self.zeros(d, N) if "S" in want else None
+        dnu = self.zeros(nu_t.shape[0]) if "nu" in want else None
+        dub = self.zeros(d, self.NB) if ("u_b" in want and self.NB) else None
+        du1 = None if du1 is None else self._t(du1.contiguous(), (d, N), "du1")
+        dp1 = None if dp1 is None else self._t(dp1.contiguous(), (N,), "dp1")
+        inf = L.StepInfo()
+        rc = self.lib.piso_step_backward(self.h, _stream(), _ptr(tape), _ptr(u), _ptr(p), _ptr(nu_t), nf,
+                                         _ptr(ub), float(dt), _ptr(du1), _ptr(dp1), _ptr(du), _ptr(dp),
+                                         _ptr(dS), _ptr(dnu), _ptr(dub), C.byref(o), C.byref(inf))
+        self._check(rc, "piso_step_backward")
+        out = {"u": du, "p": dp, "S": dS, "nu": dnu, "u_b": dub}
+        return (out, inf.as_dict()) if info else out
+
+    # ---------------------------------------------------------------- fine-grained calls
+    def assemble(self, sys, u, p, nu, S, u_b, dt, grad_p_in_predictor=1):
+        nu_t, nf = self._nu(nu)
+        rc = self.lib.piso_assemble(self.h, _stream(), _ptr(u), _ptr(p), _ptr(nu_t), nf, _ptr(S),
+                                    _ptr(self._ub(u_b)), float(dt), int(grad_p_in_predictor),
+                                    C.byref(self._sys(sys)))
+        return self._check(rc, "piso_assemble")
+
+    def solve_velocity(self, sys, u_star, opts: L.SolveOpts):
+        inf = L.SolveInfo()
+        rc = self.lib.piso_solve_velocity(self.h, _stream(), C.byref(self._sys(sys)), _ptr(u_star),
+                                          C.byref(opts), C.byref(inf))
+        self._check(rc, "piso_solve_velocity")
+        return inf.as_dict()
+
+    def solve_pressure(self, sys, u_in, u_b, p_lag, p, opts: L.SolveOpts):
+        inf = L.SolveInfo()
+        rc = self.lib.piso_solve_pressure(self.h, _stream(), C.byref(self._sys(sys)), _ptr(u_in),
+                                          _ptr(self._ub(u_b)), _ptr(p_lag), _ptr(p), C.byref(opts),
+                                          C.byref(inf))
+        self._check(rc, "piso_solve_pressure")
+        return inf.as_dict()
+
+    def correct(self, sys, p, p_lag, u_b, u_out, F_out=None):
+        rc = self.lib.piso_correct(self.h, _stream(), C.byref(self._sys(sys)), _ptr(p), _ptr(p_lag),
+                                   _ptr(self._ub(u_b)), _ptr(u_out), _ptr(F_out))
+        return self._check(rc, "piso_correct")
+
+    def correct_backward(self, sys, p, du_out, dh, dp, dA):
+        rc = self.lib.piso_correct_backward(self.h, _stream(), C.byref(self._sys(sys)), _ptr(p),
+                                            _ptr(du_out), _ptr(dh), _ptr(dp), _ptr(dA))
+        return self._check(rc, "piso_correct_backward")
+
+    def solve_pressure_backward(self, sys, u_in, p_lag, p, dh, dp, du_in, dp_lag, du_b, g, opts,
+                                skip_solve=False):
+        inf = L.SolveInfo()
+        rc = self.lib.piso_solve_pressure_backward(
+            self.h, _stream(), C.byref(self._sys(sys)), _ptr(u_in), _ptr(p_lag), _ptr(p), _ptr(dh), _ptr(dp),
+            _ptr(du_in), _ptr(dp_lag), _ptr(du_b), C.byref(self._gsys(g)), int(skip_solve), C.byref(opts),
+            C.byref(inf))
+        self._check(rc, "piso_solve_pressure_backward")
+        return inf.as_dict()
+
+    def solve_velocity_backward(self, sys, u_star, du_star, g, opts, skip_solve=False):
+        inf = L.SolveInfo()
+        rc = self.lib.piso_solve_velocity_backward(self.h, _stream(), C.byref(self._sys(sys)), _ptr(u_star),
+                                                   _ptr(du_star), C.byref(self._gsys(g)), int(skip_solve),
+                                                   C.byref(opts), C.byref(inf))
+        self._check(rc, "piso_solve_velocity_backward")
+        return inf.as_dict()
+
+    def assemble_backward(self, u_n, nu, u_b, dt, g, du_n, dp_n, dS, dnu, du_b, grad_p_in_predictor=1):
+        nu_t, nf = self._nu(nu)
+        rc = self.lib.piso_assemble_backward(self.h, _stream(), _ptr(u_n), _ptr(nu_t), nf, _ptr(self._ub(u_b)),
+                                             float(dt), int(grad_p_in_predictor), C.byref(self._gsys(g)),
+                                             _ptr(du_n), _ptr(dp_n), _ptr(dS), _ptr(dnu), _ptr(du_b))
+        return self._check(rc, "piso_assemble_backward")
+
+    # ---------------------------------------------------------------- diagnostics
+    def set_timing(self, enable: bool):
+        self.lib.piso_set_timing(self.h, int(enable))
+
+    def get_timing(self):
+        a, b = C.c_double(), C.c_double()
+        n1, n2 = C.c_int64(), C.c_int64()
+        self.lib.piso_get_timing(self.h, C.byref(a), C.byref(b), C.byref(n1), C.byref(n2))
+        return {"spmv_ms": a.value, "update_ms": b.value, "spmv_calls": n1.value, "update_calls": n2.value}
+
+
+# ===================================================================== autograd
+
+class PisoStep(torch.autograd.Function):
+    """One differentiable PISO step: (u, p, S, nu, u_b) -> (u^{n+1}, p^{n+1}).
+
+    The forward keeps a tape of the intermediates; the backward runs the hand-written
+    adjoint (transposed solves and per-operation adjoints)."""
+
+    @staticmethod
+    def forward(fctx, pctx: Context, opts, dt, u, p, S, nu, u_b):
+        tape = pctx.new_tape()
+        u1, p1 = pctx.step(u, p, nu, S, u_b, dt, opts, tape=tape)
+        fctx.pctx, fctx.opts, fctx.dt = pctx, opts, dt
+        fctx.save_for_backward(tape, u, p, nu, u_b if u_b is not None else torch.empty(0))
+        fctx.has_ub = u_b is not None
+        return u1, p1
+
+    @staticmethod
+    def backward(fctx, du1, dp1):
+        tape, u, p, nu, u_b = fctx.saved_tensors
+        pctx = fctx.pctx
+        g = pctx.step_backward(tape, u, p, nu, u_b if fctx.has_ub else None, fctx.dt, du1, dp1, fctx.opts)
+        return (None, None, None, g["u"], g["p"], g["S"], g["nu"].reshape(nu.shape),
+                g["u_b"] if fctx.has_ub else None)
+
+
+class _Segment(torch.autograd.Function):
+    """k steps whose tapes are dropped in the forward and recomputed in the backward
+    (step checkpointing): memory O(1 state + k tapes) per segment."""
+
+    @staticmethod
+    def forward(fctx, pctx: Context, opts, dt, k, u, p, S, nu, u_b):
+        uu, pp = u, p
+        for _ in range(k):
+            uu, pp = pctx.step(uu, pp, nu, S, u_b, dt, opts)
+        fctx.pctx, fctx.opts, fctx.dt, fctx.k = pctx, opts, dt, k
+        fctx.has_ub = u_b is not None
+        fctx.save_for_backward(u, p, S, nu, u_b if u_b is not None else torch.empty(0))
+        return uu, pp
+
+    @staticmethod
+    def backward(fctx, du, dp):
+        u, p, S, nu, u_b = fctx.saved_tensors
+        pctx, opts, dt, k = fctx.pctx, fctx.opts, fctx.dt, fctx.k
+        ub = u_b if fctx.has_ub else None
+        states, tapes = [(u, p)], []
+        uu, pp = u, p
+        for _ in range(k):
+            t = pctx.new_tape()
+            uu, pp = pctx.step(uu, pp, nu, S, ub, dt, opts, tape=t)
+            states.append((uu, pp))
+            tapes.append(t)
+        dS = torch.zeros_like(S)
+        dnu = torch.zeros_like(nu.reshape(-1))
+        dub = torch.zeros_like(ub) if ub is not None else None
+        gu, gp = du, dp
+        for q in range(k - 1, -1, -1):
+            un, pn = states[q]
+            g = pctx.step_backward(tapes[q], un, pn, nu, ub, dt, gu, gp, opts)
+            gu, gp = g["u"], g["p"]
+            dS += g["S"]
+            dnu += g["nu"]
+            if dub is not None:
+                dub += g["u_b"]
+            tapes[q] = None
+        return None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), dub
+
+
+def step(pctx: Context, u, p, S, nu, u_b, dt, opts=None):
+    """Differentiable single step (keeps its tape until backward)."""
+    return PisoStep.apply(pctx, opts if opts is not None else pctx.default_opts(), dt, u, p, S, nu, u_b)
+
+
+def rollout(pctx: Context, u0, p0, S, nu, u_b, dt, n_steps: int, checkpoint_every: int = 0, opts=None,
+            warmup: int = 0, return_all: bool = False):
+    """n_steps differentiable steps.  checkpoint_every = 0 keeps every tape; k > 0
+    stores only the state at the start of each k-step segment and recomputes the
+    segment's tapes in the backward.  warmup steps run first without a tape."""
+    o = opts if opts is not None else pctx.default_opts()
+    u, p = u0, p0
+    if warmup:
+        with torch.no_grad():
+            for _ in range(warmup):
+                u, p = pctx.step(u.detach(), p.detach(), nu.detach(), S.detach(),
+                                 None if u_b is None else u_b.detach(), dt, o)
+    traj = []
+    done = 0
+    while done < n_steps:
+        if checkpoint_every > 0:
+            k = min(checkpoint_every, n_steps - done)
+            u, p = _Segment.apply(pctx, o, dt, k, u, p, S, nu, u_b)
+            done += k
+        else:
+            u, p = PisoStep.apply(pctx, o, dt, u, p, S, nu, u_b)
+            done += 1
+        if return_all:
+            traj.append((u, p))
+    return traj if return_all else (u, p)

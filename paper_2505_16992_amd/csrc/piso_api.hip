@@ -1,0 +1,848 @@
+// C-ABI of the PISO library (include/piso.h): context creation with topology
+// validation (Sec. 2.2, App. A.4 of arXiv 2505.16992), the fine-grained forward and
+// backward calls, and the orchestration of one step (App. A.2) and of its adjoint
+// (Sec. 2.3, App. A.5).
+#include <algorithm>
+#include <array>
+#include <climits>
+#include <type_traits>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "piso_impl.h"
+
+using namespace piso;
+
+static std::string g_create_error;
+
+namespace {
+
+void tangential_extent(const int n[3], int side, int dim, int& t0n, int& t1n) {
+  const int axis = side / 2;
+  int e[2] = {1, 1}, q = 0;
+  for (int a = 0; a < dim; ++a)
+    if (a != axis) e[q++] = n[a];
+  t0n = e[0];
+  t1n = e[1];
+}
+
+void magic(uint32_t d, uint32_t& lo, uint32_t& hi, int& shift) {
+  int l = 0;
+  while ((1ull << l) < d) ++l;
+  const uint64_t num = 1ull << (31 + l);
+  const uint64_t m = (num + d - 1) / d;
+  lo = (uint32_t)(m & 0xffffffffu);
+  hi = (uint32_t)(m >> 32);
+  shift = 31 + l;
+}
+
+template <typename R>
+std::vector<R> convert(const std::vector<double>& v) {
+  return std::vector<R>(v.begin(), v.end());
+}
+
+int dev_alloc(piso_ctx* c, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return fail(c, PISO_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  c->allocs.push_back(*p);
+  return PISO_OK;
+}
+
+template <typename T>
+int upload(piso_ctx* c, void** dst, const std::vector<T>& v) {
+  if (int rc = dev_alloc(c, dst, v.size() * sizeof(T))) return rc;
+  PISO_HIP(c, hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return PISO_OK;
+}
+
+// Build the block table and the per-side face map; validates coverage, ranges,
+// conformity and reciprocity.
+int build_topology(piso_ctx* c, const piso_domain_desc* d) {
+  const int D = d->dim, B = d->n_blocks;
+  std::vector<int> off(B + 1, 0);
+  std::vector<std::array<int, 3>> n(B);
+  for (int b = 0; b < B; ++b) {
+    for (int a = 0; a < 3; ++a) n[b][a] = d->block_cells[3 * b + a];
+    if (n[b][0] < 1 || n[b][1] < 1 || n[b][2] < 1 || (D == 2 && n[b][2] != 1))
+      return fail(c, PISO_E_TOPOLOGY, "block " + std::to_string(b) + ": bad cell counts");
+    const long long cells = (long long)n[b][0] * n[b][1] * n[b][2];
+    if ((long long)off[b] + cells >= INT_MAX / 2) return fail(c, PISO_E_ARG, "too many cells");
+    off[b + 1] = off[b] + (int)cells;
+  }
+  c->N = off[B];
+  c->h_tab.assign((size_t)B * kTabStride, 0);
+  int fm = 0;
+  for (int b = 0; b < B; ++b) {
+    int* t = &c->h_tab[(size_t)b * kTabStride];
+    t[0] = off[b];
+    t[1] = n[b][0];
+    t[2] = n[b][1];
+    t[3] = n[b][2];
+    for (int s = 0; s < 2 * D; ++s) {
+      int t0n, t1n;
+      tangential_extent(n[b].data(), s, D, t0n, t1n);
+      t[4 + s] = fm;
+      fm += t0n * t1n;
+    }
+    uint32_t lo, hi;
+    int sh;
+    magic((uint32_t)n[b][0], lo, hi, sh);
+    t[10] = (int)lo; t[11] = (int)hi; t[12] = sh;
+    magic((uint32_t)(n[b][0] * n[b][1]), lo, hi, sh);
+    t[13] = (int)lo; t[14] = (int)hi; t[15] = sh;
+  }
+  c->h_fmap.assign((size_t)fm, INT_MIN);
+  auto cell = [&](int b, int i, int j, int k) { return off[b] + i + n[b][0] * (j + n[b][1] * k); };
+  auto from_t = [&](int axis, int along, int t0, int t1, int& i, int& j, int& k) {
+    if (axis == 0) { i = along; j = t0; k = t1; }
+    else if (axis == 1) { i = t0; j = along; k = t1; }
+    else { i = t0; j = t1; k = along; }
+  };
+  int nbf = 0;
+  for (int si = 0; si < d->n_sides; ++si) {
+    const piso_side_desc& sd = d->sides[si];
+    if (sd.block < 0 || sd.block >= B || sd.side < 0 || sd.side >= 2 * D)
+      return fail(c, PISO_E_TOPOLOGY, "segment " + std::to_string(si) + ": bad block or side");
+    const int b = sd.block, a = sd.side / 2, s = sd.side % 2;
+    int t0n, t1n;
+    tangential_extent(n[b].data(), sd.side, D, t0n, t1n);
+    if (!(0 <= sd.begin[0] && sd.begin[0] < sd.end[0] && sd.end[0] <= t0n && 0 <= sd.begin[1] &&
+          sd.begin[1] < sd.end[1] && sd.end[1] <= t1n))
+      return fail(c, PISO_E_TOPOLOGY, "segment " + std::to_string(si) + ": range outside the side");
+    const int along = s == 0 ? 0 : n[b][a] - 1;
+    for (int t1 = sd.begin[1]; t1 < sd.end[1]; ++t1) {
+      for (int t0 = sd.begin[0]; t0 < sd.end[0]; ++t0) {
+        int i, j, k;
+        from_t(a, along, t0, t1, i, j, k);
+        const int slot = c->h_tab[(size_t)b * kTabStride + 4 + sd.side] + t0 + t0n * t1;
+        if (c->h_fmap[slot] != INT_MIN)
+          return fail(c, PISO_E_TOPOLOGY, "segment " + std::to_string(si) + ": face covered twice");
+        if (sd.kind == PISO_SIDE_DIRICHLET) {
+          c->h_fmap[slot] = -1 - nbf++;
+        } else if (sd.kind == PISO_SIDE_CONNECT) {
+          const int ob = sd.other_block;
+          if (ob < 0 || ob >= B) return fail(c, PISO_E_TOPOLOGY, "segment " + std::to_string(si) + ": bad other block");
+          int ot0n, ot1n;
+          tangential_extent(n[ob].data(), 2 * a + (1 - s), D, ot0n, ot1n);
+          const int o0 = t0 - sd.begin[0] + sd.other_begin[0], o1 = t1 - sd.begin[1] + sd.other_begin[1];
+          if (o0 < 0 || o0 >= ot0n || o1 < 0 || o1 >= ot1n)
+            return fail(c, PISO_E_TOPOLOGY, "segment " + std::to_string(si) + ": connection leaves the other block");
+          const int oalong = s == 1 ? 0 : n[ob][a] - 1;
+          int oi, oj, ok;
+          from_t(a, oalong, o0, o1, oi, oj, ok);
+          c->h_fmap[slot] = cell(ob, oi, oj, ok);
+        } else {
+          return fail(c, PISO_E_TOPOLOGY, "segment " + std::to_string(si) + ": unknown kind");
+        }
+      }
+    }
+  }
+  c->NB = nbf;
+  // coverage and reciprocity
+  for (int b = 0; b < B; ++b) {
+    for (int side = 0; side < 2 * D; ++side) {
+      const int a = side / 2, s = side % 2;
+      int t0n, t1n;
+      tangential_extent(n[b].data(), side, D, t0n, t1n);
+      const int along = s == 0 ? 0 : n[b][a] - 1;
+      for (int t1 = 0; t1 < t1n; ++t1)
+        for (int t0 = 0; t0 < t0n; ++t0) {
+          const int slot = c->h_tab[(size_t)b * kTabStride + 4 + side] + t0 + t0n * t1;
+          const int v = c->h_fmap[slot];
+          if (v == INT_MIN)
+            return fail(c, PISO_E_TOPOLOGY, "block " + std::to_string(b) + " side " + std::to_string(side) +
+                                                ": face not covered");
+          if (v >= 0) {
+            // the other cell's opposite face must lead back here
+            int ob = 0;
+            while (ob + 1 < B && v >= off[ob + 1]) ++ob;
+            const int L = v - off[ob];
+            const int oi = L % n[ob][0], oj = (L / n[ob][0]) % n[ob][1], ok = L / (n[ob][0] * n[ob][1]);
+            const int opos[3] = {oi, oj, ok};
+            const int oside = 2 * a + (1 - s);
+            const int oalong = (1 - s) == 0 ? 0 : n[ob][a] - 1;
+            if (opos[a] != oalong) return fail(c, PISO_E_TOPOLOGY, "connection does not land on a side");
+            int ot0n, ot1n;
+            tangential_extent(n[ob].data(), oside, D, ot0n, ot1n);
+            int ot0 = 0, ot1 = 0, q = 0;
+            for (int aa = 0; aa < 3; ++aa)
+              if (aa != a) (q++ == 0 ? ot0 : ot1) = opos[aa];
+            const int oslot = c->h_tab[(size_t)ob * kTabStride + 4 + oside] + ot0 + ot0n * ot1;
+            int i, j, k;
+            from_t(a, along, t0, t1, i, j, k);
+            if (c->h_fmap[oslot] != cell(b, i, j, k))
+              return fail(c, PISO_E_TOPOLOGY, "non-reciprocal (non-conformal) connection at block " +
+                                                  std::to_string(b) + " side " + std::to_string(side));
+          }
+        }
+    }
+  }
+  return PISO_OK;
+}
+
+template <typename R>
+int upload_metrics(piso_ctx* c, const piso_domain_desc* d) {
+  const int D = c->dim, N = c->N;
+  const double* T = d->T;
+  const double* J = d->J;
+  bool diag = true;
+  for (int j = 0; j < D && diag; ++j)
+    for (int i = 0; i < D && diag; ++i)
+      if (i != j)
+        for (int P = 0; P < N; ++P)
+          if (T[(size_t)(j * D + i) * N + P] != 0.0) { diag = false; break; }
+  c->diagT = diag;
+  std::vector<double> jt((size_t)(diag ? D : D * D) * N), invJ(N), al((size_t)D * N);
+  std::vector<double> alx((size_t)(D == 3 ? 3 : 1) * N, 0.0);
+  double nonorth = 0.0;
+  for (int P = 0; P < N; ++P) {
+    if (!(J[P] > 0.0) || !std::isfinite(J[P]))
+      return fail(c, PISO_E_TOPOLOGY, "non-positive or non-finite Jacobian at cell " + std::to_string(P));
+    invJ[P] = 1.0 / J[P];
+    for (int j = 0; j < D; ++j) {
+      for (int i = 0; i < D; ++i) {
+        const double v = J[P] * T[(size_t)(j * D + i) * N + P];
+        if (diag) { if (i == j) jt[(size_t)j * N + P] = v; }
+        else jt[(size_t)(j * D + i) * N + P] = v;
+      }
+    }
+    double a[3][3];
+    for (int j = 0; j < D; ++j)
+      for (int k = 0; k < D; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < D; ++i) s += T[(size_t)(j * D + i) * N + P] * T[(size_t)(k * D + i) * N + P];
+        a[j][k] = J[P] * s;
+      }
+    double mind = a[0][0];
+    for (int j = 0; j < D; ++j) {
+      al[(size_t)j * N + P] = a[j][j];
+      mind = std::min(mind, std::fabs(a[j][j]));
+    }
+    for (int j = 0; j < D; ++j)
+      for (int k = j + 1; k < D; ++k) {
+        alx[(size_t)(j + k - 1) * N + P] = a[j][k];
+        nonorth = std::max(nonorth, std::fabs(a[j][k]) / mind);
+      }
+  }
+  c->nonorth = nonorth > 1e-12;
+  if (int rc = upload(c, &c->JT, convert<R>(jt))) return rc;
+  if (int rc = upload(c, &c->invJ, convert<R>(invJ))) return rc;
+  if (int rc = upload(c, &c->alpha, convert<R>(al))) return rc;
+  if (c->nonorth) {
+    if (int rc = upload(c, &c->alphax, convert<R>(alx))) return rc;
+  } else {
+    if (int rc = dev_alloc(c, &c->alphax, sizeof(R))) return rc;
+  }
+  return PISO_OK;
+}
+
+int alloc_workspaces(piso_ctx* c) {
+  const size_t N = c->N, D = c->dim, e = c->esz;
+  struct { void** p; size_t bytes; } L[] = {
+      {&c->w_A, N * e}, {&c->w_C, 2 * D * N * e}, {&c->w_bu, D * N * e}, {&c->w_b, D * N * e},
+      {&c->w_Pf, D * N * e}, {&c->w_Dinv, N * e}, {&c->w_h, D * N * e}, {&c->w_W, D * N * e},
+      {&c->w_rhs, N * 8}, {&c->w_us, D * N * e}, {&c->w_u1, D * N * e}, {&c->w_p1, N * e},
+      {&c->w_h1, D * N * e}, {&c->w_tg, D * D * N * e}, {&c->w_tgp, D * N * e},
+      {(void**)&c->w_rhs64, N * 8}, {(void**)&c->w_p64, N * 8}, {&c->m_r32, N * 4}, {&c->m_e32, N * 4},
+      {&c->k_r, N * e}, {&c->k_q, N * e}, {&c->k_d0, N * e}, {&c->k_d1, N * e},
+      {&c->b_r, D * N * e}, {&c->b_rh, D * N * e}, {&c->b_p0, D * N * e}, {&c->b_p1, D * N * e},
+      {&c->b_v0, D * N * e}, {&c->b_v1, D * N * e}, {&c->b_s, D * N * e}, {&c->b_t, D * N * e},
+      {&c->a_g, D * N * e}, {&c->a_uin, D * N * e}, {&c->a_lam, N * e}, {&c->a_pbar, N * e},
+      {&c->a_mu, D * N * e}, {&c->a_dh, D * N * e}, {&c->a_dA, N * e}, {&c->a_dC, 2 * D * N * e},
+      {&c->a_dbu, D * N * e}, {&c->a_db, D * N * e}, {&c->a_dp1, N * e}, {&c->a_dnu, N * e},
+      {&c->a_ybar, D * N * e}, {&c->a_cbar, D * D * N * e},
+      {(void**)&c->partials, 8 * kRedGrid * sizeof(double)}, {(void**)&c->mean, 8 * sizeof(double)},
+      {(void**)&c->cg, sizeof(CgState)}, {(void**)&c->bi, sizeof(BiState)}, {(void**)&c->counter, 64},
+  };
+  for (auto& l : L)
+    if (int rc = dev_alloc(c, l.p, l.bytes)) return rc;
+  PISO_HIP(c, hipMemset(c->cg, 0, sizeof(CgState)));
+  PISO_HIP(c, hipMemset(c->bi, 0, sizeof(BiState)));
+  PISO_HIP(c, hipMemset(c->counter, 0, 64));
+  PISO_HIP(c, hipHostMalloc((void**)&c->h_cg, sizeof(CgState), hipHostMallocDefault));
+  PISO_HIP(c, hipHostMalloc((void**)&c->h_bi, sizeof(BiState), hipHostMallocDefault));
+  PISO_HIP(c, hipHostMalloc((void**)&c->h_scal, 8 * sizeof(double), hipHostMallocDefault));
+  return PISO_OK;
+}
+
+size_t tape_elems(const piso_ctx* c) { return (size_t)(4 + 7 * c->dim) * c->N; }
+
+template <typename R>
+struct Tape {
+  R *A, *C, *Pf, *Dinv, *us, *h1, *p1, *u1, *h2, *p2;
+  Tape(void* base, int N, int D) {
+    R* t = (R*)base;
+    const size_t n = N;
+    A = t;
+    C = A + n;
+    Pf = C + 2 * D * n;
+    Dinv = Pf + D * n;
+    us = Dinv + n;
+    h1 = us + D * n;
+    p1 = h1 + D * n;
+    u1 = p1 + n;
+    h2 = u1 + D * n;
+    p2 = h2 + D * n;
+  }
+};
+
+int check_ctx(piso_ctx* c) {
+  if (!c) return PISO_E_ARG;
+  return PISO_OK;
+}
+
+#define REQUIRE(cond, msg) \
+  do { if (!(cond)) return fail(c, PISO_E_ARG, msg); } while (0)
+
+// ---------------------------------------------------------------- forward pieces
+
+template <typename R>
+int do_assemble(piso_ctx* c, hipStream_t s, const R* u, const R* p, const R* nu, int nu_field, const R* S,
+                const R* ub, double dt, int gradp, R* A, R* C, R* bu, R* b, R* Pf, R* Dinv) {
+  if (int rc = launch_assemble<R>(c, s, u, p, nu, nu_field, S, ub, dt, gradp, A, C, bu, b)) return rc;
+  return launch_pcoef<R>(c, s, A, Pf, Dinv);
+}
+
+// h, rhs and the pressure solve of one corrector.  p holds x0 on entry.
+template <typename R>
+int do_pressure(piso_ctx* c, hipStream_t s, const R* A, const R* C, const R* bu, const R* Pf, const R* Dinv,
+                const R* u_in, const R* ub, const R* p_lag, R* h, R* rhs_out, R* p, const piso_solve_opts* o,
+                piso_solve_info* info) {
+  R* W = (R*)c->w_W;
+  if (int rc = launch_h<R>(c, s, A, C, bu, u_in, h, W)) return rc;
+  if (c->prec == PISO_MIXED) {
+    if constexpr (std::is_same<R, float>::value) {
+      if (int rc = launch_div<float, double>(c, s, W, ub, A, p_lag, c->w_rhs64, c->mean)) return rc;
+      if (rhs_out)
+        if (int rc = launch_copy<double, float>(c, s, c->w_rhs64, rhs_out, c->N)) return rc;
+      if (int rc = launch_copy<float, double>(c, s, p, c->w_p64, c->N)) return rc;
+      if (int rc = pressure_solve_mixed(c, s, Pf, Dinv, c->w_rhs64, c->mean, c->w_p64, o, info)) return rc;
+      return launch_copy<double, float>(c, s, c->w_p64, p, c->N);
+    }
+    return fail(c, PISO_E_ARG, "MIXED requires float storage");
+  }
+  R* rhs = rhs_out ? rhs_out : (R*)c->w_rhs;
+  if (int rc = launch_div<R, R>(c, s, W, ub, A, p_lag, rhs, c->mean)) return rc;
+  return pressure_solve<R, R>(c, s, Pf, Dinv, rhs, c->mean, p, o, info);
+}
+
+// Zero-mean lambda of P lambda = g - mean(g) (pressure adjoint), x0 = 0.
+template <typename R>
+int do_pressure_adjoint(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* g, R* lam,
+                        const piso_solve_opts* o, piso_solve_info* info) {
+  const int N = c->N;
+  if (c->prec == PISO_MIXED) {
+    if constexpr (std::is_same<R, float>::value) {
+      if (int rc = launch_copy<float, double>(c, s, g, c->w_rhs64, N)) return rc;
+      if (int rc = launch_sum<double, double>(c, s, c->w_rhs64, N, 1.0 / N, c->mean)) return rc;
+      PISO_HIP(c, hipMemsetAsync(c->w_p64, 0, sizeof(double) * N, s));
+      if (int rc = pressure_solve_mixed(c, s, Pf, Dinv, c->w_rhs64, c->mean, c->w_p64, o, info)) return rc;
+      return launch_copy<double, float>(c, s, c->w_p64, lam, N);
+    }
+    return fail(c, PISO_E_ARG, "MIXED requires float storage");
+  }
+  if (int rc = launch_sum<R, double>(c, s, g, N, 1.0 / N, c->mean)) return rc;
+  PISO_HIP(c, hipMemsetAsync(lam, 0, sizeof(R) * N, s));
+  return pressure_solve<R, R>(c, s, Pf, Dinv, g, c->mean, lam, o, info);
+}
+
+template <typename R>
+int do_step(piso_ctx* c, hipStream_t s, const R* u_n, const R* p_n, const R* nu, int nu_field, const R* S,
+            const R* ub, double dt, R* u_np1, R* p_np1, void* tape, const piso_step_opts* o, piso_step_info* info) {
+  const int N = c->N, D = c->dim;
+  R *A, *C, *Pf, *Dinv, *us, *h1, *p1, *u1, *h2, *p2;
+  if (tape) {
+    Tape<R> t(tape, N, D);
+    A = t.A; C = t.C; Pf = t.Pf; Dinv = t.Dinv; us = t.us; h1 = t.h1; p1 = t.p1; u1 = t.u1; h2 = t.h2; p2 = t.p2;
+  } else {
+    A = (R*)c->w_A; C = (R*)c->w_C; Pf = (R*)c->w_Pf; Dinv = (R*)c->w_Dinv; us = (R*)c->w_us;
+    h1 = (R*)c->w_h1; p1 = (R*)c->w_p1; u1 = (R*)c->w_u1; h2 = (R*)c->w_h; p2 = p_np1;
+  }
+  R* bu = (R*)c->w_bu;
+  R* b = (R*)c->w_b;
+  if (int rc = do_assemble<R>(c, s, u_n, p_n, nu, nu_field, S, ub, dt, o->grad_p_in_predictor, A, C, bu, b, Pf, Dinv))
+    return rc;
+  PISO_HIP(c, hipMemcpyAsync(us, u_n, sizeof(R) * D * N, hipMemcpyDeviceToDevice, s));
+  piso_solve_info vi{}, pi[2]{};
+  int rc = velocity_solve<R>(c, s, false, A, C, b, us, &o->vel, &vi);
+  if (rc < 0) return rc;
+  const int ncorr = o->n_correctors;
+  const R* u_in = us;
+  const R* p_lag = p_n;
+  for (int k = 0; k < ncorr; ++k) {
+    // the last corrector writes the outputs; earlier ones use the u**, h*, p* slots
+    const bool last = (k == ncorr - 1);
+    R* h = last ? h2 : h1;
+    R* pk = last ? p2 : p1;
+    R* uk = last ? u_np1 : u1;
+    if (pk != p_lag) PISO_HIP(c, hipMemcpyAsync(pk, p_lag, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
+    rc = do_pressure<R>(c, s, A, C, bu, Pf, Dinv, u_in, ub, p_lag, h, nullptr, pk, &o->pres, &pi[std::min(k, 1)]);
+    if (rc < 0) return rc;
+    rc = launch_correct<R>(c, s, A, h, pk, Pf, p_lag, uk, nullptr);
+    if (rc) return rc;
+    u_in = uk;
+    p_lag = pk;
+  }
+  if (p2 != p_np1) PISO_HIP(c, hipMemcpyAsync(p_np1, p2, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
+  if (info) {
+    info->vel = vi;
+    info->pres[0] = pi[0];
+    info->pres[1] = pi[1];
+  }
+  int st = vi.status;
+  for (int k = 0; k < 2; ++k) st = (pi[k].status < 0 || st < 0) ? std::min(st, pi[k].status) : std::max(st, pi[k].status);
+  return st;
+}
+
+// ---------------------------------------------------------------- adjoint pieces
+
+// Adjoint of one corrector (correct after h/rhs/solve).  du_c: gradient of the
+// corrector output u; pbar: gradient of its p (modified in place: receives -G^T du/A).
+// Accumulates dA, dC, dbu, dub; writes du_in_out (+= -H^T g) and p_lag_bar (+=).
+template <typename R>
+int do_corrector_bwd(piso_ctx* c, hipStream_t s, const R* A, const R* C, const R* Pf, const R* Dinv,
+                     const R* h, const R* u_in, const R* p_lag, const R* p, const R* du_c, R* pbar,
+                     R* du_in_out, R* p_lag_bar, R* dA, R* dC, R* dbu, R* dub, bool skip_solve,
+                     const piso_solve_opts* o, piso_solve_info* info) {
+  if (int rc = launch_correct_bwd<R>(c, s, A, p, du_c, pbar, dA)) return rc;
+  R* lam = nullptr;
+  if (!skip_solve) {
+    lam = (R*)c->a_lam;
+    int rc = do_pressure_adjoint<R>(c, s, Pf, Dinv, pbar, lam, o, info);
+    if (rc < 0) return rc;
+    if ((rc = launch_pface_bwd<R>(c, s, A, lam, p, dA))) return rc;
+  } else if (info) {
+    *info = piso_solve_info{};
+  }
+  R* gv = (R*)c->a_g;
+  if (int rc = launch_h_bwd<R>(c, s, A, h, du_c, lam, gv, dbu, dA, dub)) return rc;
+  if (c->nonorth && lam && p_lag_bar) {
+    if (int rc = launch_tgrad<R>(c, s, p_lag, 1, (R*)c->w_tgp)) return rc;
+    if (int rc = launch_cross_bwd<R>(c, s, A, 1, 1, lam, 1, (const R*)c->w_tgp, R(-1), p_lag_bar, dA)) return rc;
+  }
+  return launch_outer_bwd<R>(c, s, C, gv, u_in, du_in_out, dC, nullptr);
+}
+
+// Adjoint of the predictor right-hand side and assembly, given dA, dC, dbu (which
+// already holds db = mu and the h contributions) and the p^n gradient of -grad p^n.
+template <typename R>
+int do_assemble_bwd(piso_ctx* c, hipStream_t s, const R* u_n, const R* nu, int nu_field, const R* ub, double dt,
+                    const R* dA, const R* dC, const R* dbu, R* du_n, R* dS, R* dnu, R* dub) {
+  const int N = c->N, D = c->dim;
+  R* dnu_cell = dnu ? (R*)c->a_dnu : nullptr;
+  if (dnu_cell) PISO_HIP(c, hipMemsetAsync(dnu_cell, 0, sizeof(R) * N, s));
+  if (int rc = launch_assemble_bwd<R>(c, s, u_n, nu, nu_field, ub, dt, dA, dC, dbu, du_n, dS, dnu_cell, dub)) return rc;
+  if (c->nonorth) {
+    R* ybar = (R*)c->a_ybar;
+    if (int rc = launch_scale_invJ<R>(c, s, dbu, D, ybar)) return rc;
+    if (int rc = launch_tgrad<R>(c, s, u_n, D, (R*)c->w_tg)) return rc;
+    if (int rc = launch_cross_bwd<R>(c, s, nu, nu_field, 0, ybar, D, (const R*)c->w_tg, R(1), du_n, dnu_cell)) return rc;
+    if (c->NB && (dnu_cell || dub))
+      if (int rc = launch_bcross_bwd<R>(c, s, nu, nu_field, ub, dbu, dnu_cell, dub)) return rc;
+  }
+  if (dnu) {
+    if (nu_field) return launch_axpy<R>(c, s, N, R(1), dnu_cell, dnu);
+    if (int rc = launch_sum<R, double>(c, s, dnu_cell, N, 1.0, c->mean + 3)) return rc;
+    return launch_add_scalar<R>(c, s, c->mean + 3, dnu);
+  }
+  return PISO_OK;
+}
+
+template <typename R>
+int do_step_backward(piso_ctx* c, hipStream_t s, const void* tape, const R* u_n, const R* p_n, const R* nu,
+                     int nu_field, const R* ub, double dt, const R* du_np1, const R* dp_np1, R* du_n, R* dp_n,
+                     R* dS, R* dnu, R* dub, const piso_step_opts* o, piso_step_info* info) {
+  const int N = c->N, D = c->dim;
+  if (o->n_correctors != 2) return fail(c, PISO_E_ARG, "backward supports n_correctors = 2");
+  Tape<R> t(const_cast<void*>(tape), N, D);
+  R* dA = (R*)c->a_dA;
+  R* dC = (R*)c->a_dC;
+  R* dbu = (R*)c->a_dbu;
+  R* pbar = (R*)c->a_pbar;
+  R* dp1 = (R*)c->a_dp1;
+  R* uin = (R*)c->a_uin;
+  R* duc = (R*)c->a_dh;
+  PISO_HIP(c, hipMemsetAsync(dA, 0, sizeof(R) * N, s));
+  PISO_HIP(c, hipMemsetAsync(dC, 0, sizeof(R) * 2 * D * N, s));
+  PISO_HIP(c, hipMemsetAsync(dbu, 0, sizeof(R) * D * N, s));
+  PISO_HIP(c, hipMemsetAsync(dp1, 0, sizeof(R) * N, s));
+  if (du_np1) PISO_HIP(c, hipMemcpyAsync(duc, du_np1, sizeof(R) * D * N, hipMemcpyDeviceToDevice, s));
+  else PISO_HIP(c, hipMemsetAsync(duc, 0, sizeof(R) * D * N, s));
+  if (dp_np1) PISO_HIP(c, hipMemcpyAsync(pbar, dp_np1, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
+  else PISO_HIP(c, hipMemsetAsync(pbar, 0, sizeof(R) * N, s));
+  const bool skipP = (o->grad_path_flags & 2) != 0, skipV = (o->grad_path_flags & 1) != 0;
+  piso_solve_info pi[2]{}, vi{};
+  // corrector 2: output u***, p**; inputs u**, lag p*
+  PISO_HIP(c, hipMemsetAsync(uin, 0, sizeof(R) * D * N, s));
+  int rc = do_corrector_bwd<R>(c, s, t.A, t.C, t.Pf, t.Dinv, t.h2, t.u1, t.p1, t.p2, duc, pbar, uin, dp1, dA, dC, dbu,
+                               dub, skipP, &o->pres, &pi[1]);
+  if (rc < 0) return rc;
+  // corrector 1: output u**, p*; inputs u*, lag p^n
+  PISO_HIP(c, hipMemcpyAsync(duc, uin, sizeof(R) * D * N, hipMemcpyDeviceToDevice, s));
+  PISO_HIP(c, hipMemcpyAsync(pbar, dp1, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
+  PISO_HIP(c, hipMemsetAsync(uin, 0, sizeof(R) * D * N, s));
+  rc = do_corrector_bwd<R>(c, s, t.A, t.C, t.Pf, t.Dinv, t.h1, t.us, p_n, t.p1, duc, pbar, uin, dp_n, dA, dC, dbu, dub,
+                           skipP, &o->pres, &pi[0]);
+  if (rc < 0) return rc;
+  // velocity solve: mu = C^-T du*, db = mu, dC -= mu (x) u*
+  if (!skipV) {
+    R* mu = (R*)c->a_mu;
+    PISO_HIP(c, hipMemsetAsync(mu, 0, sizeof(R) * D * N, s));
+    rc = velocity_solve<R>(c, s, true, t.A, t.C, uin, mu, &o->vel, &vi);
+    if (rc < 0) return rc;
+    if ((rc = launch_outer_bwd<R>(c, s, t.C, mu, t.us, nullptr, dC, dA))) return rc;
+    if ((rc = launch_axpy<R>(c, s, D * N, R(1), mu, dbu))) return rc;
+    if (dp_n && o->grad_p_in_predictor)
+      if ((rc = launch_gradT<R>(c, s, mu, nullptr, R(-1), dp_n))) return rc;
+  }
+  rc = do_assemble_bwd<R>(c, s, u_n, nu, nu_field, ub, dt, dA, dC, dbu, du_n, dS, dnu, dub);
+  if (rc) return rc;
+  if (info) {
+    info->vel = vi;
+    info->pres[0] = pi[0];
+    info->pres[1] = pi[1];
+  }
+  int st = vi.status;
+  for (int k = 0; k < 2; ++k) st = (pi[k].status < 0 || st < 0) ? std::min(st, pi[k].status) : std::max(st, pi[k].status);
+  return st;
+}
+
+struct DevGuard {
+  int prev = -1;
+  explicit DevGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DevGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+// ====================================================================== C-ABI
+
+extern "C" {
+
+const char* piso_create_error(void) { return g_create_error.c_str(); }
+
+int piso_create(const piso_domain_desc* desc, int32_t precision, piso_ctx** out) {
+  if (!out) return PISO_E_ARG;
+  *out = nullptr;
+  g_create_error.clear();
+  if (!desc || !desc->block_cells || !desc->sides || !desc->T || !desc->J) {
+    g_create_error = "null descriptor field";
+    return PISO_E_ARG;
+  }
+  if (desc->dim != 2 && desc->dim != 3) {
+    g_create_error = "dim must be 2 or 3";
+    return PISO_E_ARG;
+  }
+  if (desc->n_blocks < 1 || desc->n_blocks > kMaxBlocks) {
+    g_create_error = "n_blocks must be 1..16";
+    return PISO_E_ARG;
+  }
+  if (precision < PISO_F64 || precision > PISO_MIXED) {
+    g_create_error = "bad precision";
+    return PISO_E_ARG;
+  }
+  piso_ctx* c = new piso_ctx();
+  c->dim = desc->dim;
+  c->nblocks = desc->n_blocks;
+  c->prec = precision;
+  c->esz = precision == PISO_F64 ? 8 : 4;
+  int rc = hipGetDevice(&c->device) == hipSuccess ? PISO_OK : fail(c, PISO_E_HIP, "hipGetDevice failed");
+  if (!rc) rc = build_topology(c, desc);
+  if (!rc) rc = upload(c, (void**)&c->d_tab, c->h_tab);
+  if (!rc) rc = upload(c, (void**)&c->d_fmap, c->h_fmap);
+  if (!rc) rc = precision == PISO_F64 ? upload_metrics<double>(c, desc) : upload_metrics<float>(c, desc);
+  if (!rc) rc = alloc_workspaces(c);
+  if (rc) {
+    g_create_error = c->err;
+    piso_destroy(c);
+    return rc;
+  }
+  c->grid.dim = c->dim;
+  c->grid.nblocks = c->nblocks;
+  c->grid.N = c->N;
+  c->grid.NB = c->NB;
+  c->grid.tab = c->d_tab;
+  c->grid.fmap = c->d_fmap;
+  *out = c;
+  return PISO_OK;
+}
+
+void piso_destroy(piso_ctx* c) {
+  if (!c) return;
+  DevGuard g(c->device);
+  (void)hipDeviceSynchronize();
+  for (void* p : c->allocs) (void)hipFree(p);
+  if (c->h_cg) (void)hipHostFree(c->h_cg);
+  if (c->h_bi) (void)hipHostFree(c->h_bi);
+  if (c->h_scal) (void)hipHostFree(c->h_scal);
+  for (hipEvent_t e : c->timing.ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* piso_last_error(const piso_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int piso_sizes(const piso_ctx* c, int64_t* n_cells, int64_t* n_bfaces, int64_t* tape_bytes, int64_t* elem_bytes,
+               int32_t* non_orthogonal) {
+  if (!c) return PISO_E_ARG;
+  if (n_cells) *n_cells = c->N;
+  if (n_bfaces) *n_bfaces = c->NB;
+  if (tape_bytes) *tape_bytes = (int64_t)(tape_elems(c) * c->esz);
+  if (elem_bytes) *elem_bytes = (int64_t)c->esz;
+  if (non_orthogonal) *non_orthogonal = c->nonorth ? 1 : 0;
+  return PISO_OK;
+}
+
+void piso_default_step_opts(int32_t precision, piso_step_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->vel.rtol = precision == PISO_F64 ? 1e-10 : 1e-7;
+  o->vel.max_iter = 500;
+  o->vel.check_every = 4;
+  o->pres.rtol = precision == PISO_F64 ? 1e-10 : (precision == PISO_MIXED ? 1e-8 : 1e-6);
+  o->pres.max_iter = 20000;
+  o->pres.check_every = 16;
+  o->pres.inner_rtol = 1e-3;
+  o->pres.max_refine = 20;
+  o->vel.inner_rtol = 1e-3;
+  o->vel.max_refine = 0;
+  o->n_correctors = 2;
+  o->grad_p_in_predictor = 1;
+  o->grad_path_flags = 0;
+}
+
+#define CTX_ENTER()                                  \
+  if (!c) return PISO_E_ARG;                         \
+  DevGuard dg_(c->device);                           \
+  hipStream_t s = (hipStream_t)stream
+
+#define DISPATCH_R(CALL_F64, CALL_F32) (c->prec == PISO_F64 ? (CALL_F64) : (CALL_F32))
+
+int piso_assemble(piso_ctx* c, void* stream, const void* u_n, const void* p_n, const void* nu, int32_t nu_is_field,
+                  const void* S, const void* u_b, double dt, int32_t gradp, const piso_system* sys) {
+  CTX_ENTER();
+  REQUIRE(u_n && p_n && nu && S && sys && sys->A && sys->C && sys->b_u && sys->b && sys->Pf && sys->Dinv,
+          "piso_assemble: null pointer");
+  REQUIRE(c->NB == 0 || u_b, "piso_assemble: u_b required");
+  REQUIRE(dt > 0 && std::isfinite(dt), "piso_assemble: dt must be positive");
+#define ARGS(R)                                                                                                    \
+  c, s, (const R*)u_n, (const R*)p_n, (const R*)nu, nu_is_field, (const R*)S, (const R*)u_b, dt, gradp, (R*)sys->A, \
+      (R*)sys->C, (R*)sys->b_u, (R*)sys->b, (R*)sys->Pf, (R*)sys->Dinv
+  return DISPATCH_R(do_assemble<double>(ARGS(double)), do_assemble<float>(ARGS(float)));
+#undef ARGS
+}
+
+int piso_solve_velocity(piso_ctx* c, void* stream, const piso_system* sys, void* u_star, const piso_solve_opts* o,
+                        piso_solve_info* info) {
+  CTX_ENTER();
+  REQUIRE(sys && sys->A && sys->C && sys->b && u_star && o, "piso_solve_velocity: null pointer");
+  REQUIRE(o->rtol > 0 && o->max_iter > 0, "piso_solve_velocity: bad options");
+  piso_solve_info tmp{};
+  int rc = DISPATCH_R(velocity_solve<double>(c, s, false, (const double*)sys->A, (const double*)sys->C,
+                                             (const double*)sys->b, (double*)u_star, o, &tmp),
+                      velocity_solve<float>(c, s, false, (const float*)sys->A, (const float*)sys->C,
+                                            (const float*)sys->b, (float*)u_star, o, &tmp));
+  if (info) *info = tmp;
+  return rc < 0 ? rc : tmp.status;
+}
+
+int piso_solve_pressure(piso_ctx* c, void* stream, const piso_system* sys, const void* u_in, const void* u_b,
+                        const void* p_lag, void* p, const piso_solve_opts* o, piso_solve_info* info) {
+  CTX_ENTER();
+  REQUIRE(sys && sys->A && sys->C && sys->b_u && sys->Pf && sys->Dinv && sys->h && u_in && p_lag && p && o,
+          "piso_solve_pressure: null pointer");
+  REQUIRE(c->NB == 0 || u_b, "piso_solve_pressure: u_b required");
+  REQUIRE(o->rtol > 0 && o->max_iter > 0, "piso_solve_pressure: bad options");
+  piso_solve_info tmp{};
+#define ARGS(R)                                                                                                 \
+  c, s, (const R*)sys->A, (const R*)sys->C, (const R*)sys->b_u, (const R*)sys->Pf, (const R*)sys->Dinv,          \
+      (const R*)u_in, (const R*)u_b, (const R*)p_lag, (R*)sys->h, (R*)sys->rhs, (R*)p, o, &tmp
+  int rc = DISPATCH_R(do_pressure<double>(ARGS(double)), do_pressure<float>(ARGS(float)));
+#undef ARGS
+  if (info) *info = tmp;
+  return rc < 0 ? rc : tmp.status;
+}
+
+int piso_correct(piso_ctx* c, void* stream, const piso_system* sys, const void* p, const void* p_lag,
+                 const void* u_b, void* u_out, void* F_out) {
+  CTX_ENTER();
+  REQUIRE(sys && sys->A && sys->h && p && u_out, "piso_correct: null pointer");
+  REQUIRE(!F_out || (sys->Pf && p_lag), "piso_correct: F_out needs sys->Pf and p_lag");
+  (void)u_b;
+  return DISPATCH_R(launch_correct<double>(c, s, (const double*)sys->A, (const double*)sys->h, (const double*)p,
+                                           (const double*)sys->Pf, (const double*)p_lag, (double*)u_out,
+                                           (double*)F_out),
+                    launch_correct<float>(c, s, (const float*)sys->A, (const float*)sys->h, (const float*)p,
+                                          (const float*)sys->Pf, (const float*)p_lag, (float*)u_out,
+                                          (float*)F_out));
+}
+
+int piso_step(piso_ctx* c, void* stream, const void* u_n, const void* p_n, const void* nu, int32_t nu_is_field,
+              const void* S, const void* u_b, double dt, void* u_np1, void* p_np1, void* tape,
+              const piso_step_opts* o, piso_step_info* info) {
+  CTX_ENTER();
+  REQUIRE(u_n && p_n && nu && S && u_np1 && p_np1 && o, "piso_step: null pointer");
+  REQUIRE(c->NB == 0 || u_b, "piso_step: u_b required");
+  REQUIRE(dt > 0 && std::isfinite(dt), "piso_step: dt must be positive");
+  REQUIRE(o->n_correctors >= 1 && o->n_correctors <= 8, "piso_step: n_correctors must be 1..8");
+  REQUIRE(!tape || o->n_correctors == 2, "piso_step: a tape requires n_correctors = 2");
+  REQUIRE(u_np1 != u_n && p_np1 != p_n, "piso_step: outputs must not alias inputs");
+#define ARGS(R)                                                                                              \
+  c, s, (const R*)u_n, (const R*)p_n, (const R*)nu, nu_is_field, (const R*)S, (const R*)u_b, dt, (R*)u_np1, \
+      (R*)p_np1, tape, o, info
+  return DISPATCH_R(do_step<double>(ARGS(double)), do_step<float>(ARGS(float)));
+#undef ARGS
+}
+
+int piso_correct_backward(piso_ctx* c, void* stream, const piso_system* sys, const void* p, const void* du_out,
+                          void* dh, void* dp, void* dA) {
+  CTX_ENTER();
+  REQUIRE(sys && sys->A && p && du_out, "piso_correct_backward: null pointer");
+  const int n = c->dim * c->N;
+  if (c->prec == PISO_F64) {
+    if (dh)
+      if (int rc = launch_axpy<double>(c, s, n, 1.0, (const double*)du_out, (double*)dh)) return rc;
+    return launch_correct_bwd<double>(c, s, (const double*)sys->A, (const double*)p, (const double*)du_out,
+                                      (double*)dp, (double*)dA);
+  }
+  if (dh)
+    if (int rc = launch_axpy<float>(c, s, n, 1.0f, (const float*)du_out, (float*)dh)) return rc;
+  return launch_correct_bwd<float>(c, s, (const float*)sys->A, (const float*)p, (const float*)du_out, (float*)dp,
+                                   (float*)dA);
+}
+
+int piso_solve_pressure_backward(piso_ctx* c, void* stream, const piso_system* sys, const void* u_in,
+                                 const void* p_lag, const void* p, const void* dh, const void* dp, void* du_in,
+                                 void* dp_lag, void* du_b, const piso_system_grad* g, int32_t skip_solve,
+                                 const piso_solve_opts* o, piso_solve_info* info) {
+  CTX_ENTER();
+  REQUIRE(sys && sys->A && sys->C && sys->Pf && sys->Dinv && sys->h && u_in && p_lag && p && o,
+          "piso_solve_pressure_backward: null pointer");
+  REQUIRE(g && g->dA && g->dC && g->db_u && du_in, "piso_solve_pressure_backward: null gradient pointer");
+  const int N = c->N;
+  piso_solve_info tmp{};
+  // pbar = dp (copied so the call does not modify the caller's buffer); the correct
+  // adjoint has already been applied by piso_correct_backward.
+#define BODY(R)                                                                                                    \
+  do {                                                                                                             \
+    R* pbar = (R*)c->a_pbar;                                                                                        \
+    if (dp) PISO_HIP(c, hipMemcpyAsync(pbar, dp, sizeof(R) * N, hipMemcpyDeviceToDevice, s));                      \
+    else PISO_HIP(c, hipMemsetAsync(pbar, 0, sizeof(R) * N, s));                                                    \
+    R* lam = nullptr;                                                                                               \
+    if (!skip_solve) {                                                                                              \
+      lam = (R*)c->a_lam;                                                                                           \
+      int rc = do_pressure_adjoint<R>(c, s, (const R*)sys->Pf, (const R*)sys->Dinv, pbar, lam, o, &tmp);           \
+      if (rc < 0) return rc;                                                                                        \
+      if ((rc = launch_pface_bwd<R>(c, s, (const R*)sys->A, lam, (const R*)p, (R*)g->dA))) return rc;              \
+    }                                                                                                               \
+    R* gv = (R*)c->a_g;                                                                                             \
+    if (int rc = launch_h_bwd<R>(c, s, (const R*)sys->A, (const R*)sys->h, (const R*)dh, lam, gv, (R*)g->db_u,     \
+                                 (R*)g->dA, (R*)du_b))                                                              \
+      return rc;                                                                                                    \
+    if (c->nonorth && lam && dp_lag) {                                                                              \
+      if (int rc = launch_tgrad<R>(c, s, (const R*)p_lag, 1, (R*)c->w_tgp)) return rc;                             \
+      if (int rc = launch_cross_bwd<R>(c, s, (const R*)sys->A, 1, 1, lam, 1, (const R*)c->w_tgp, R(-1), (R*)dp_lag, \
+                                       (R*)g->dA))                                                                  \
+        return rc;                                                                                                  \
+    }                                                                                                               \
+    if (int rc = launch_outer_bwd<R>(c, s, (const R*)sys->C, gv, (const R*)u_in, (R*)du_in, (R*)g->dC, nullptr))   \
+      return rc;                                                                                                    \
+  } while (0)
+  if (c->prec == PISO_F64) BODY(double);
+  else BODY(float);
+#undef BODY
+  if (info) *info = tmp;
+  return tmp.status;
+}
+
+int piso_solve_velocity_backward(piso_ctx* c, void* stream, const piso_system* sys, const void* u_star,
+                                 const void* du_star, const piso_system_grad* g, int32_t skip_solve,
+                                 const piso_solve_opts* o, piso_solve_info* info) {
+  CTX_ENTER();
+  REQUIRE(sys && sys->A && sys->C && u_star && du_star && o, "piso_solve_velocity_backward: null pointer");
+  REQUIRE(g && g->dA && g->dC && g->db, "piso_solve_velocity_backward: null gradient pointer");
+  piso_solve_info tmp{};
+  if (skip_solve) {
+    if (info) *info = tmp;
+    return PISO_OK;
+  }
+  const int N = c->N, D = c->dim;
+#define BODY(R)                                                                                                   \
+  do {                                                                                                            \
+    R* mu = (R*)c->a_mu;                                                                                           \
+    PISO_HIP(c, hipMemsetAsync(mu, 0, sizeof(R) * D * N, s));                                                      \
+    int rc = velocity_solve<R>(c, s, true, (const R*)sys->A, (const R*)sys->C, (const R*)du_star, mu, o, &tmp);   \
+    if (rc < 0) return rc;                                                                                         \
+    if ((rc = launch_outer_bwd<R>(c, s, (const R*)sys->C, mu, (const R*)u_star, nullptr, (R*)g->dC, (R*)g->dA)))   \
+      return rc;                                                                                                   \
+    if ((rc = launch_axpy<R>(c, s, D * N, R(1), mu, (R*)g->db))) return rc;                                        \
+  } while (0)
+  if (c->prec == PISO_F64) BODY(double);
+  else BODY(float);
+#undef BODY
+  if (info) *info = tmp;
+  return tmp.status;
+}
+
+int piso_assemble_backward(piso_ctx* c, void* stream, const void* u_n, const void* nu, int32_t nu_is_field,
+                           const void* u_b, double dt, int32_t gradp, const piso_system_grad* g, void* du_n,
+                           void* dp_n, void* dS, void* dnu, void* du_b) {
+  CTX_ENTER();
+  REQUIRE(u_n && nu && g && g->dA && g->dC && g->db_u && g->db, "piso_assemble_backward: null pointer");
+  REQUIRE(c->NB == 0 || u_b, "piso_assemble_backward: u_b required");
+  const int N = c->N, D = c->dim;
+#define BODY(R)                                                                                                   \
+  do {                                                                                                            \
+    R* dbu = (R*)c->a_dbu;                                                                                         \
+    PISO_HIP(c, hipMemcpyAsync(dbu, g->db_u, sizeof(R) * D * N, hipMemcpyDeviceToDevice, s));                      \
+    if (int rc = launch_axpy<R>(c, s, D * N, R(1), (const R*)g->db, dbu)) return rc;                               \
+    if (dp_n && gradp)                                                                                             \
+      if (int rc = launch_gradT<R>(c, s, (const R*)g->db, nullptr, R(-1), (R*)dp_n)) return rc;                   \
+    return do_assemble_bwd<R>(c, s, (const R*)u_n, (const R*)nu, nu_is_field, (const R*)u_b, dt, (const R*)g->dA,  \
+                              (const R*)g->dC, dbu, (R*)du_n, (R*)dS, (R*)dnu, (R*)du_b);                         \
+  } while (0)
+  if (c->prec == PISO_F64) BODY(double);
+  else BODY(float);
+#undef BODY
+}
+
+int piso_step_backward(piso_ctx* c, void* stream, const void* tape, const void* u_n, const void* p_n, const void* nu,
+                       int32_t nu_is_field, const void* u_b, double dt, const void* du_np1, const void* dp_np1,
+                       void* du_n, void* dp_n, void* dS, void* dnu, void* du_b, const piso_step_opts* o,
+                       piso_step_info* info) {
+  CTX_ENTER();
+  REQUIRE(tape && u_n && p_n && nu && o, "piso_step_backward: null pointer");
+  REQUIRE(c->NB == 0 || u_b, "piso_step_backward: u_b required");
+#define ARGS(R)                                                                                                     \
+  c, s, tape, (const R*)u_n, (const R*)p_n, (const R*)nu, nu_is_field, (const R*)u_b, dt, (const R*)du_np1,          \
+      (const R*)dp_np1, (R*)du_n, (R*)dp_n, (R*)dS, (R*)dnu, (R*)du_b, o, info
+  return DISPATCH_R(do_step_backward<double>(ARGS(double)), do_step_backward<float>(ARGS(float)));
+#undef ARGS
+}
+
+int piso_set_timing(piso_ctx* c, int32_t enable) {
+  if (!c) return PISO_E_ARG;
+  c->timing.enabled = enable != 0;
+  c->timing.spmv_ms = c->timing.update_ms = 0.0;
+  c->timing.spmv_calls = c->timing.update_calls = 0;
+  c->timing.used = 0;
+  return PISO_OK;
+}
+
+int piso_get_timing(piso_ctx* c, double* spmv_ms, double* update_ms, int64_t* spmv_calls, int64_t* update_calls) {
+  if (!c) return PISO_E_ARG;
+  if (spmv_ms) *spmv_ms = c->timing.spmv_ms;
+  if (update_ms) *update_ms = c->timing.update_ms;
+  if (spmv_calls) *spmv_calls = c->timing.spmv_calls;
+  if (update_calls) *update_calls = c->timing.update_calls;
+  return PISO_OK;
+}
+
+}  // extern "C"

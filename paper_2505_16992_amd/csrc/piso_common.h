@@ -1,0 +1,181 @@
+// Shared device-side definitions of the PISO library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace piso {
+
+constexpr int kMaxBlocks = 16;
+constexpr int kWG = 256;                 // work-group size: 4 wave64s
+constexpr int kWaves = kWG / 64;
+constexpr int kRedGrid = 2048;           // work-groups of the reduction kernels (upper bound)
+constexpr int kTabStride = 16;           // ints per block in the device block table
+
+// Device block table, kTabStride ints per block:
+//   [0] offset  [1] nx  [2] ny  [3] nz  [4..9] offset of each side in the face map
+//   [10,11] magic for /nx (lo, hi)  [12] shift  [13,14] magic for /(nx*ny)  [15] shift
+struct Grid {
+  int dim;
+  int nblocks;
+  int N;
+  int NB;
+  const int* __restrict__ tab;   // [nblocks][kTabStride]
+  const int* __restrict__ fmap;  // per side face: neighbour cell (>= 0) or -1 - boundary face
+};
+
+// Exact n / d for 0 <= n < 2^31 with m = ceil(2^(31+l) / d), l = ceil(log2 d).
+__host__ __device__ inline uint32_t fast_div(uint32_t n, uint64_t m, int s) {
+  return (uint32_t)(((uint64_t)n * m) >> s);
+}
+
+struct Cell {
+  int b, i, j, k;
+};
+
+__device__ __forceinline__ int tab(const Grid& g, int b, int f) { return g.tab[b * kTabStride + f]; }
+
+__device__ __forceinline__ Cell locate(const Grid& g, int P) {
+  Cell c;
+  int b = 0;
+  for (int q = 1; q < g.nblocks; ++q) b += (P >= tab(g, q, 0)) ? 1 : 0;
+  const int* t = g.tab + b * kTabStride;
+  uint32_t L = (uint32_t)(P - t[0]);
+  uint64_t mx = (uint64_t)(uint32_t)t[10] | ((uint64_t)(uint32_t)t[11] << 32);
+  uint32_t jk = fast_div(L, mx, t[12]);
+  c.b = b;
+  c.i = (int)(L - jk * (uint32_t)t[1]);
+  if (g.dim == 3) {
+    uint64_t mxy = (uint64_t)(uint32_t)t[13] | ((uint64_t)(uint32_t)t[14] << 32);
+    uint32_t k = fast_div(L, mxy, t[15]);
+    c.k = (int)k;
+    c.j = (int)(jk - k * (uint32_t)t[2]);
+  } else {
+    c.k = 0;
+    c.j = (int)jk;
+  }
+  return c;
+}
+
+// Neighbour of cell P (at position c) across face (axis, side): a cell index >= 0, or
+// -1 - f for Dirichlet face f.
+__device__ __forceinline__ int neighbour(const Grid& g, const Cell& c, int P, int axis, int side) {
+  const int* t = g.tab + c.b * kTabStride;
+  int pos = axis == 0 ? c.i : (axis == 1 ? c.j : c.k);
+  int n = t[1 + axis];
+  if (side) {
+    if (pos < n - 1) return P + (axis == 0 ? 1 : (axis == 1 ? t[1] : t[1] * t[2]));
+  } else {
+    if (pos > 0) return P - (axis == 0 ? 1 : (axis == 1 ? t[1] : t[1] * t[2]));
+  }
+  int tg;
+  if (axis == 0) tg = c.j + t[2] * c.k;
+  else if (axis == 1) tg = c.i + t[1] * c.k;
+  else tg = c.i + t[1] * c.j;
+  return g.fmap[t[4 + 2 * axis + side] + tg];
+}
+
+__device__ __forceinline__ int neighbour_of(const Grid& g, int Q, int axis, int side) {
+  Cell c = locate(g, Q);
+  return neighbour(g, c, Q, axis, side);
+}
+
+// ---------------------------------------------------------------- reductions (FP64)
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Work-group sum of NV doubles; result valid in thread 0.  Fixed order: deterministic.
+template <int NV>
+__device__ __forceinline__ void wg_sum(double (&v)[NV], double* lds /* [NV][kWaves] */) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = wave_sum(v[q]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) lds[q * kWaves + wave] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < kWaves; ++w) s += lds[q * kWaves + w];
+      v[q] = s;
+    }
+  }
+}
+
+// Two-stage grid reduction: every work-group writes its NV partial sums, the last
+// work-group to finish sums all partials in work-group order (deterministic) and
+// returns true in all of its threads with the totals in tot (valid in thread 0).
+template <int NV>
+__device__ __forceinline__ bool grid_sum(double (&v)[NV], double* partials /* [NV][gridDim] */,
+                                         unsigned* counter, double (&tot)[NV]) {
+  __shared__ double lds[NV * kWaves];
+  __shared__ bool last;
+  wg_sum<NV>(v, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) partials[q * gridDim.x + blockIdx.x] = v[q];
+    __threadfence();
+    unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  double s[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) s[q] = 0.0;
+  // each thread sums a fixed strided subset, then a fixed-order tree: deterministic
+  for (int w = threadIdx.x; w < (int)gridDim.x; w += kWG) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      volatile double* pp = partials + q * gridDim.x + w;
+      s[q] += *pp;
+    }
+  }
+  __syncthreads();
+  wg_sum<NV>(s, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) tot[q] = s[q];
+    *counter = 0u;
+  }
+  return true;
+}
+
+// Contiguous cell range of work-group `wg` when `nwg` groups share N cells, with the
+// group index remapped so that each of the 8 XCDs (which receive work-groups round
+// robin) covers one contiguous eighth of the cells (keeps stencil neighbours in the
+// XCD's own L2).
+__device__ __forceinline__ int xcd_logical_group() {
+  const int G = gridDim.x, b = blockIdx.x;
+  if (G < 8) return b;
+  const int x = b & 7, q = b >> 3, per = G >> 3, rem = G & 7;
+  return x * per + (x < rem ? x : rem) + q;
+}
+
+__device__ __forceinline__ void chunk_range(int N, int& begin, int& end) {
+  const int G = gridDim.x;
+  int per = (N + G - 1) / G;
+  per = (per + 63) & ~63;
+  const int lg = xcd_logical_group();
+  begin = lg * per;
+  end = begin + per;
+  if (end > N) end = N;
+}
+
+// Cell index of this thread in a one-cell-per-thread launch (XCD-aware), or -1.
+__device__ __forceinline__ int cell_of_thread(int N) {
+  const int P = xcd_logical_group() * kWG + threadIdx.x;
+  return P < N ? P : -1;
+}
+
+}  // namespace piso

@@ -1,0 +1,206 @@
+"""Parity of the HIP library (through the C-ABI) with the FP64 oracle.
+
+Small grids spanning several work-groups with ragged tails, single and multi-block,
+orthogonal and non-orthogonal, 2D and 3D.  FP64 path: relative L2 <= 1e-9 per field
+(solves at 1e-12); FP32 path: <= 1e-5 on velocity (mean-removed pressure: stated per
+test).  Gradients: FP64 <= 1e-8.
+"""
+import numpy as np
+import pytest
+import torch
+
+import cases
+from oracle.adjoint import step_vjp
+from oracle.piso import Geometry, face_flux_divergence, step as oracle_step
+from tests.gpu_common import dev, host, rel, rel_p, say, small_cases, tight_opts, random_state
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["tgv16", "cavity12", "channel", "two_block", "sheared", "cylinder"]
+
+
+@pytest.fixture(scope="module")
+def api():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2505_16992_amd import api as A
+    return A
+
+
+def _setup(api, name, prec="f64", seed=1):
+    case = small_cases()[name]
+    ctx = api.Context(case.domain, prec)
+    u, p, S, ub, nu = random_state(case, seed)
+    dt = ctx.dtype
+    return case, ctx, (u, p, S, ub, nu), (dev(u, dt), dev(p, dt), dev(S, dt), dev(ub, dt), dev(nu, dt))
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_step_f64(api, name):
+    say("test_step_f64", name)
+    case, ctx, (u, p, S, ub, nu), (ud, pd, Sd, ubd, nud) = _setup(api, name)
+    o = tight_opts(ctx)
+    u1, p1, info = ctx.step(ud, pd, nud, Sd, ubd, case.dt, o, info=True)
+    torch.cuda.synchronize()
+    geo = Geometry(case.domain)
+    ref = oracle_step(geo, u, p, nu, S, case.dt, ub)
+    assert info["vel"]["status"] == 0 and info["pres"][1]["status"] == 0, info
+    assert rel(host(u1), ref.u2) < 1e-9
+    assert rel_p(host(p1), ref.p2) < 1e-9
+    assert abs(float(host(p1).mean())) < 1e-10 * max(1.0, float(np.abs(ref.p2).max()))
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_fine_grained_f64(api, name):
+    say("test_fine_grained_f64", name)
+    case, ctx, (u, p, S, ub, nu), (ud, pd, Sd, ubd, nud) = _setup(api, name, seed=2)
+    geo = Geometry(case.domain)
+    ref = oracle_step(geo, u, p, nu, S, case.dt, ub)
+    sys = ctx.new_system()
+    ctx.assemble(sys, ud, pd, nud, Sd, ubd, case.dt)
+    torch.cuda.synchronize()
+    d = geo.d
+    assert rel(host(sys["A"]), ref.A) < 1e-13
+    Cref = np.zeros((2, d, geo.N))
+    for j in range(d):
+        P, F = geo.faces[j]
+        Cref[0, j, P] = np.asarray(ref.H[P, F]).ravel()
+        Cref[1, j, P] = np.asarray(ref.H[F, P]).ravel()
+    assert rel(host(sys["C"]), Cref) < 1e-13
+    assert rel(host(sys["b_u"]), ref.b_u) < 1e-13
+    assert rel(host(sys["b"]), ref.b) < 1e-13
+    Pd = ref.Pm.toarray() if geo.N < 3000 else None
+    if Pd is not None:
+        assert rel(1.0 / host(sys["Dinv"]), -np.diag(Pd)) < 1e-13
+    o = tight_opts(ctx)
+    us = ud.clone()
+    vi = ctx.solve_velocity(sys, us, o.vel)
+    assert vi["status"] == 0
+    assert rel(host(us), ref.u_star) < 1e-10
+    us_ref = torch.as_tensor(ref.u_star, dtype=ctx.dtype, device="cuda").contiguous()
+    p1 = pd.clone()
+    pi = ctx.solve_pressure(sys, us_ref, ubd, pd, p1, o.pres)
+    assert pi["status"] == 0
+    assert rel(host(sys["h"]), ref.h1) < 1e-12
+    assert rel(host(sys["rhs"]), ref.rhs1) < 1e-12
+    assert rel_p(host(p1), ref.p1) < 1e-9
+    p1_ref = torch.as_tensor(ref.p1, dtype=ctx.dtype, device="cuda").contiguous()
+    u_out = torch.empty_like(ud)
+    F_out = torch.empty_like(ud)
+    ctx.correct(sys, p1_ref, pd, ubd, u_out, F_out)
+    torch.cuda.synchronize()
+    assert rel(host(u_out), ref.u1) < 1e-12
+    # divergence of the corrected face flux equals the oracle's face-by-face value
+    Fh = host(F_out)
+    div = np.zeros(geo.N)
+    for j in range(d):
+        P, F = geo.faces[j]
+        np.add.at(div, P, Fh[j, P])
+        np.add.at(div, F, -Fh[j, P])
+    if geo.nb:
+        div += sum(geo.Bflux[i] @ ub[i] for i in range(d))
+    ref_div = face_flux_divergence(geo, ref.h1, ref.A, ref.p1, p, ub)
+    assert np.max(np.abs(div - ref_div)) < 1e-10 * max(1.0, np.abs(Fh).max())
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_step_backward_f64(api, name):
+    say("test_step_backward_f64", name)
+    case, ctx, (u, p, S, ub, nu), (ud, pd, Sd, ubd, nud) = _setup(api, name, seed=3)
+    o = tight_opts(ctx)
+    tape = ctx.new_tape()
+    u1, p1 = ctx.step(ud, pd, nud, Sd, ubd, case.dt, o, tape=tape)
+    rng = np.random.default_rng(4)
+    wu = rng.standard_normal(u.shape)
+    wp = rng.standard_normal(p.shape)
+    g = ctx.step_backward(tape, ud, pd, nud, ubd, case.dt, dev(wu, ctx.dtype), dev(wp, ctx.dtype), o)
+    torch.cuda.synchronize()
+    geo = Geometry(case.domain)
+    ref = oracle_step(geo, u, p, nu, S, case.dt, ub)
+    gr = step_vjp(geo, ref, wu, wp)
+    for k in ("u", "p", "S", "nu"):
+        key = {"u": "u_n", "p": "p_n"}.get(k, k)
+        assert rel(host(g[k]), gr[key]) < 1e-8, k
+    if geo.nb:
+        assert rel(host(g["u_b"]), gr["u_b"]) < 1e-8
+
+
+def test_tgv_config_20_steps(api):
+    """The first workload: 32x32 periodic TGV, nu = 0.01, dt = 0.01, 20 steps, FP64."""
+    say("test_tgv_config_20_steps")
+    case = cases.taylor_green(32)
+    ctx = api.Context(case.domain, "f64")
+    geo = Geometry(case.domain)
+    o = tight_opts(ctx)
+    u, p = case.u0, case.p0
+    ud, pd = dev(u, torch.float64), dev(p, torch.float64)
+    nud = dev(np.array([case.nu]), torch.float64)
+    Sd = dev(case.S, torch.float64)
+    worst = 0.0
+    for n in range(case.n_steps):
+        rec = oracle_step(geo, u, p, case.nu, case.S, case.dt, case.u_b)
+        u, p = rec.u2, rec.p2
+        ud, pd = ctx.step(ud, pd, nud, Sd, None, case.dt, o)
+        worst = max(worst, rel(host(ud), u), rel_p(host(pd), p))
+    assert worst < 1e-9
+    t = case.n_steps * case.dt
+    a = float(np.sum(host(ud) * case.u0) / np.sum(case.u0 * case.u0))
+    assert abs(a - np.exp(-2 * case.nu * t)) < 1e-3
+
+
+@pytest.mark.parametrize("prec", ["f32", "mixed"])
+@pytest.mark.parametrize("name", ["channel", "cavity12", "cylinder"])
+def test_step_single_precision(api, prec, name):
+    say("test_step_single_precision", prec, name)
+    case = small_cases()[name]
+    geo = Geometry(case.domain)
+    # inputs rounded to FP32 once; the oracle upcasts the same values
+    u, p, S, ub, nu = [np.asarray(x, dtype=np.float32).astype(np.float64) for x in random_state(case, 5)]
+    ctx = api.Context(case.domain, prec)
+    o = ctx.default_opts()
+    if prec == "f32":
+        o.pres.rtol = 1e-6
+    d32 = torch.float32
+    u1, p1, info = ctx.step(dev(u, d32), dev(p, d32), dev(nu, d32), dev(S, d32), dev(ub, d32), case.dt, o,
+                            info=True)
+    torch.cuda.synchronize()
+    ref = oracle_step(geo, u, p, nu, S, case.dt, ub)
+    eu = rel(host(u1), ref.u2)
+    ep = rel_p(host(p1), ref.p2)
+    say("  rel err u %.3e p %.3e info %s" % (eu, ep, info))
+    assert eu < 1e-5
+    assert ep < (1e-5 if prec == "mixed" else 1e-4)
+    if prec == "mixed":
+        assert info["pres"][1]["rel_residual"] <= 1e-8
+
+
+def test_errors(api):
+    say("test_errors")
+    case = cases.channel(6, 8, 5)
+    ctx = api.Context(case.domain, "f64")
+    d64 = torch.float64
+    u, p, S, nu = dev(case.u0, d64), dev(case.p0, d64), dev(case.S, d64), dev(np.array([case.nu]), d64)
+    ub = dev(case.u_b, d64)
+    o = ctx.default_opts()
+    o.pres.max_iter = 1
+    o.pres.check_every = 1
+    _, _, info = ctx.step(u, p, nu, S, ub, case.dt, o, info=True)
+    assert info["pres"][0]["status"] == 1          # PISO_NOT_CONVERGED
+    bad = u.clone()
+    bad[0, 3] = float("nan")
+    with pytest.raises(api.PisoError) as e:
+        ctx.step(bad, p, nu, S, ub, case.dt)
+    assert e.value.code == -4                       # PISO_E_NAN
+    with pytest.raises(api.PisoError) as e:
+        ctx.step(u, p, nu, S, ub, -1.0)
+    assert e.value.code == -1                       # PISO_E_ARG
+    # non-conformal connection is rejected at creation
+    T0, J0, c0 = cases.tensor_metrics([np.linspace(0, 1, 4), np.linspace(0, 1, 5)])
+    T1, J1, c1 = cases.tensor_metrics([np.linspace(1, 2, 4), np.linspace(0, 1, 6)])
+    T, J, cc = cases.concat_blocks([(T0, J0, c0), (T1, J1, c1)])
+    S_ = cases.Side
+    sides = [S_(0, 1, cases.CONNECT, other_block=1), S_(1, 0, cases.CONNECT, other_block=0),
+             S_(0, 0, cases.DIRICHLET), S_(1, 1, cases.DIRICHLET)] + \
+        [S_(b, s, cases.DIRICHLET) for b in (0, 1) for s in (2, 3)]
+    with pytest.raises(api.PisoError) as e:
+        api.Context(cases.Domain(2, [(3, 4, 1), (3, 5, 1)], sides, T, J, cc), "f64")
+    assert e.value.code == -2                       # PISO_E_TOPOLOGY
