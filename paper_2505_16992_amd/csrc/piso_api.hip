@@ -7,6 +7,7 @@
 #include <climits>
 #include <type_traits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -254,14 +255,14 @@ int alloc_workspaces(piso_ctx* c) {
       {&c->a_mu, D * N * e}, {&c->a_dh, D * N * e}, {&c->a_dA, N * e}, {&c->a_dC, 2 * D * N * e},
       {&c->a_dbu, D * N * e}, {&c->a_db, D * N * e}, {&c->a_dp1, N * e}, {&c->a_dnu, N * e},
       {&c->a_ybar, D * N * e}, {&c->a_cbar, D * D * N * e},
-      {(void**)&c->partials, 8 * kRedGrid * sizeof(double)}, {(void**)&c->mean, 8 * sizeof(double)},
-      {(void**)&c->cg, sizeof(CgState)}, {(void**)&c->bi, sizeof(BiState)}, {(void**)&c->counter, 64},
+      {(void**)&c->partials, (size_t)kPartRegions * kRedGrid * sizeof(double)},
+      {(void**)&c->mean, 8 * sizeof(double)}, {(void**)&c->cg, sizeof(CgState)}, {(void**)&c->bi, sizeof(BiState)},
   };
   for (auto& l : L)
     if (int rc = dev_alloc(c, l.p, l.bytes)) return rc;
   PISO_HIP(c, hipMemset(c->cg, 0, sizeof(CgState)));
   PISO_HIP(c, hipMemset(c->bi, 0, sizeof(BiState)));
-  PISO_HIP(c, hipMemset(c->counter, 0, 64));
+  PISO_HIP(c, hipMemset(c->partials, 0, (size_t)kPartRegions * kRedGrid * sizeof(double)));
   PISO_HIP(c, hipHostMalloc((void**)&c->h_cg, sizeof(CgState), hipHostMallocDefault));
   PISO_HIP(c, hipHostMalloc((void**)&c->h_bi, sizeof(BiState), hipHostMallocDefault));
   PISO_HIP(c, hipHostMalloc((void**)&c->h_scal, 8 * sizeof(double), hipHostMallocDefault));
@@ -571,6 +572,10 @@ int piso_create(const piso_domain_desc* desc, int32_t precision, piso_ctx** out)
   c->grid.NB = c->NB;
   c->grid.tab = c->d_tab;
   c->grid.fmap = c->d_fmap;
+  c->quad = true;
+  for (int b = 0; b < c->nblocks; ++b)
+    if (desc->block_cells[3 * b] % 4 != 0) c->quad = false;
+  if (const char* e = std::getenv("PISO_NO_QUAD")) c->quad = (e[0] == '0');
   *out = c;
   return PISO_OK;
 }

@@ -111,44 +111,46 @@ __device__ __forceinline__ void wg_sum(double (&v)[NV], double* lds /* [NV][kWav
   }
 }
 
-// Two-stage grid reduction: every work-group writes its NV partial sums, the last
-// work-group to finish sums all partials in work-group order (deterministic) and
-// returns true in all of its threads with the totals in tot (valid in thread 0).
+// Work-group sum of NV doubles broadcast to every thread (fixed order: deterministic).
 template <int NV>
-__device__ __forceinline__ bool grid_sum(double (&v)[NV], double* partials /* [NV][gridDim] */,
-                                         unsigned* counter, double (&tot)[NV]) {
+__device__ __forceinline__ void wg_sum_all(double (&v)[NV]) {
   __shared__ double lds[NV * kWaves];
-  __shared__ bool last;
+  __shared__ double res[NV];
+  wg_sum<NV>(v, lds);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) res[q] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = res[q];
+  __syncthreads();
+}
+
+// Grid reductions avoid device-scope fences and atomics (each costs a write-back of
+// the XCD's L2 on this chip): every work-group writes its NV partial sums to
+// partials[q * G + blockIdx.x], and a later kernel (after the launch boundary has made
+// them visible) re-reduces them in work-group order with reduce_partials.
+template <int NV>
+__device__ __forceinline__ void write_partials(double (&v)[NV], double* partials) {
+  __shared__ double lds[NV * kWaves];
   wg_sum<NV>(v, lds);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) partials[q * gridDim.x + blockIdx.x] = v[q];
-    __threadfence();
-    unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1);
   }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  double s[NV];
+}
+
+// Sum of the G partials of NV values, identical in every thread of every work-group.
+template <int NV>
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ partials, int G, double (&out)[NV]) {
 #pragma unroll
-  for (int q = 0; q < NV; ++q) s[q] = 0.0;
-  // each thread sums a fixed strided subset, then a fixed-order tree: deterministic
-  for (int w = threadIdx.x; w < (int)gridDim.x; w += kWG) {
+  for (int q = 0; q < NV; ++q) out[q] = 0.0;
+  for (int w = threadIdx.x; w < G; w += kWG) {
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      volatile double* pp = partials + q * gridDim.x + w;
-      s[q] += *pp;
-    }
+    for (int q = 0; q < NV; ++q) out[q] += partials[q * G + w];
   }
-  __syncthreads();
-  wg_sum<NV>(s, lds);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) tot[q] = s[q];
-    *counter = 0u;
-  }
-  return true;
+  wg_sum_all<NV>(out);
 }
 
 // Contiguous cell range of work-group `wg` when `nwg` groups share N cells, with the

@@ -245,7 +245,7 @@ template <typename R, typename OT, int D, bool DIAG>
 __global__ void __launch_bounds__(kWG)
 k_div(Grid g, const R* __restrict__ JT, const R* __restrict__ W, const R* __restrict__ ub,
       const R* __restrict__ A, const R* __restrict__ alphax, const R* __restrict__ tgp, int nonorth,
-      OT* __restrict__ rhs, double* __restrict__ partials, unsigned* counter, double* mean_out) {
+      OT* __restrict__ rhs, double* __restrict__ partials) {
   const int N = g.N, NB = g.NB;
   int beg, end;
   chunk_range(N, beg, end);
@@ -285,8 +285,25 @@ k_div(Grid g, const R* __restrict__ JT, const R* __restrict__ W, const R* __rest
     rhs[P] = r;
     acc[0] += (double)r;
   }
-  double tot[1];
-  if (grid_sum<1>(acc, partials, counter, tot) && threadIdx.x == 0) mean_out[0] = tot[0] / (double)N;
+  write_partials<1>(acc, partials);
+}
+
+// One work-group: out[q] = scale * sum of the G partials of value q (q < nv <= 2).
+__global__ void __launch_bounds__(kWG)
+k_finalize(const double* __restrict__ partials, int G, int nv, double scale, double* __restrict__ out) {
+  double t[2];
+  if (nv == 1) {
+    double t1[1];
+    reduce_partials<1>(partials, G, t1);
+    t[0] = t1[0];
+    t[1] = 0.0;
+  } else {
+    reduce_partials<2>(partials, G, t);
+  }
+  if (threadIdx.x == 0) {
+    out[0] = t[0] * scale;
+    if (nv > 1) out[1] = t[1] * scale;
+  }
 }
 
 // u = h - A^-1 grad p with (grad p)_i = sum_j T_ji (p_+ - p_-)/2, p_b = p_P (eq.
@@ -355,14 +372,12 @@ __global__ void k_add_scalar(const double* __restrict__ v, R* __restrict__ y) {
 
 template <typename TI>
 __global__ void __launch_bounds__(kWG)
-k_sum(const TI* __restrict__ x, int n, double scale, double* __restrict__ partials, unsigned* counter,
-      double* out) {
+k_sum(const TI* __restrict__ x, int n, double* __restrict__ partials) {
   int beg, end;
   chunk_range(n, beg, end);
   double acc[1] = {0.0};
   for (int P = beg + (int)threadIdx.x; P < end; P += kWG) acc[0] += (double)x[P];
-  double tot[1];
-  if (grid_sum<1>(acc, partials, counter, tot) && threadIdx.x == 0) out[0] = tot[0] * scale;
+  write_partials<1>(acc, partials);
 }
 
 template <typename TI, typename TO>
@@ -448,11 +463,14 @@ int launch_div(piso_ctx* c, hipStream_t s, const R* W, const R* ub, const R* A, 
     if (rc) return rc;
     tgp = (const R*)c->w_tgp;
   }
-  const int G = grid_red(c->N);
+  const int G = grid_red(c->N, c->red_grid);
+  double* pt = part(c, kPartS);
   PISO_DISPATCH_D_DIAG(c, (k_div<R, OT, D, DG><<<G, kWG, 0, s>>>(
                               c->grid, (const R*)c->JT, W, ub, A, (const R*)c->alphax, tgp,
-                              c->nonorth ? 1 : 0, rhs, c->partials, c->counter, mean_out)));
-  return check_launch(c, "k_div");
+                              c->nonorth ? 1 : 0, rhs, pt)));
+  if (int rc = check_launch(c, "k_div")) return rc;
+  k_finalize<<<1, kWG, 0, s>>>(pt, G, 1, 1.0 / c->N, mean_out);
+  return check_launch(c, "k_finalize");
 }
 
 template <typename R>
@@ -485,8 +503,12 @@ int launch_add_scalar(piso_ctx* c, hipStream_t s, const double* v, R* y) {
 
 template <typename TI, typename TO>
 int launch_sum(piso_ctx* c, hipStream_t s, const TI* x, int n, double scale, double* out) {
-  k_sum<TI><<<grid_red(n), kWG, 0, s>>>(x, n, scale, c->partials, c->counter, out);
-  return check_launch(c, "k_sum");
+  const int G = grid_red(n, c->red_grid);
+  double* pt = part(c, kPartS);
+  k_sum<TI><<<G, kWG, 0, s>>>(x, n, pt);
+  if (int rc = check_launch(c, "k_sum")) return rc;
+  k_finalize<<<1, kWG, 0, s>>>(pt, G, 1, scale, out);
+  return check_launch(c, "k_finalize");
 }
 
 template <typename TI, typename TO>

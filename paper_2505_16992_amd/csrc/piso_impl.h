@@ -13,19 +13,29 @@
 
 namespace piso {
 
+// Solver scalars live on the device.  Values produced at iteration k go to slot k & 1
+// so that a kernel never overwrites a slot that other work-groups of the same launch
+// still read.
 struct CgState {
-  double rz, alpha, beta, rr, bb, tol2, dq, pad0;
+  double rz[2];
+  double rr, bb, tol2, pad0;
   int done, iters, status, zero_rhs;
-  unsigned counter;
-  int pad1[3];
 };
 
 struct BiState {
-  double rho[3], rho_prev[3], alpha[3], omega[3], rr[3], bb[3], tol2;
+  double rho[2][3], alpha[2][3], omega[2][3];
+  double rr[3], bb[3], tol2, pad0;
   int done[3], iters[3], status[3], all_done;
-  unsigned counter;
-  int pad;
 };
+
+// Partial-sum regions inside piso_ctx::partials, each [NV][kRedGrid] doubles.
+constexpr int kPartA = 0;        // CG: d.q                        (1)
+constexpr int kPartB = 1;        // CG: r.z, r.r (+ b.b at init)  (3)
+constexpr int kPart1 = 4;        // BiCGStab: rh.v                 (3)
+constexpr int kPart2 = 7;        // BiCGStab: t.s, t.t             (6)
+constexpr int kPart3 = 13;       // BiCGStab: rh.r, r.r (+ b.b)    (9)
+constexpr int kPartS = 22;       // one-shot sums                  (2)
+constexpr int kPartRegions = 24;
 
 struct Timing {
   bool enabled = false;
@@ -41,6 +51,7 @@ struct piso_ctx {
   int dim = 0, nblocks = 0, N = 0, NB = 0, prec = 0, device = 0;
   size_t esz = 8;                 // element bytes of the working precision
   bool diagT = false, nonorth = false;
+  bool quad = false;              // every block has nx % 4 == 0: vectorised CG kernels
   piso::Grid grid{};
   int* d_tab = nullptr;
   int* d_fmap = nullptr;
@@ -67,14 +78,14 @@ struct piso_ctx {
        *a_dh = nullptr, *a_dA = nullptr, *a_dC = nullptr, *a_dbu = nullptr, *a_db = nullptr,
        *a_dp1 = nullptr, *a_dnu = nullptr, *a_ybar = nullptr, *a_cbar = nullptr;
   // reductions and solver state
-  double* partials = nullptr;      // [8 * kRedGrid]
+  double* partials = nullptr;      // [kPartRegions * kRedGrid]
   double* mean = nullptr;          // [4] device scalars
   piso::CgState* cg = nullptr;
   piso::BiState* bi = nullptr;
   piso::CgState* h_cg = nullptr;   // pinned mirrors
   piso::BiState* h_bi = nullptr;
   double* h_scal = nullptr;        // pinned [8]
-  unsigned* counter = nullptr;     // reduction counter for one-shot sums
+  int red_grid = 512;              // work-groups of the reduction kernels
   std::vector<void*> allocs;
   piso::Timing timing;
   std::string err;
@@ -95,10 +106,12 @@ inline int fail(piso_ctx* c, int code, const std::string& msg) {
   } while (0)
 
 inline int grid_cells(int N) { return (N + kWG - 1) / kWG; }
-inline int grid_red(int N) {
+inline int grid_red(int N, int cap = 512) {
   int g = (N + kWG - 1) / kWG;
-  return g < kRedGrid ? (g < 1 ? 1 : g) : kRedGrid;
+  if (cap > kRedGrid) cap = kRedGrid;
+  return g < cap ? (g < 1 ? 1 : g) : cap;
 }
+inline double* part(piso_ctx* c, int region) { return c->partials + (size_t)region * kRedGrid; }
 
 // ---- forward launch wrappers (piso_fwd.hip) ----
 template <typename R>

@@ -1,9 +1,12 @@
 // Krylov solvers of the PISO step (arXiv 2505.16992, App. A.6: CG for the pressure,
 // BiCGStab for advection-diffusion; the adjoint reuses them with the transposed
-// operator, Sec. 2.3).  Matrix-free stencil operators over the multi-block grid; all
-// dot products accumulate in double with deterministic two-stage reductions; the
-// scalars alpha, beta, omega stay on the device and the host only reads the
-// convergence state every check_every iterations.
+// operator, Sec. 2.3).  Matrix-free stencil operators over the multi-block grid.
+//
+// Reductions: each kernel writes per-work-group partial sums; the next kernel of the
+// iteration re-reduces them (same order in every work-group: deterministic and
+// identical everywhere) and derives its scalar (alpha, beta, omega) on the device.  No
+// device-scope fences or atomics are used.  The host reads the convergence state only
+// every check_every iterations, through a one-work-group check kernel.
 #include <algorithm>
 #include <cmath>
 
@@ -11,11 +14,7 @@
 
 namespace piso {
 
-// ------------------------------------------------------------------------ PCG
-// Solves M x = b with M = -P (symmetric positive semi-definite: (M x)_P =
-// sum_f P_f (x_P - x_F)), Jacobi preconditioner Dinv.  b = sign * (bsrc - mean).
-
-template <typename R, int D>
+template <int D>
 __device__ __forceinline__ void faces_of(const Grid& g, int P, int (&Fp)[D], int (&Fm)[D]) {
   const Cell c = locate(g, P);
 #pragma unroll
@@ -25,11 +24,21 @@ __device__ __forceinline__ void faces_of(const Grid& g, int P, int (&Fp)[D], int
   }
 }
 
+__device__ __forceinline__ bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// ------------------------------------------------------------------------ PCG
+// Solves M x = b with M = -P (symmetric positive semi-definite, (M x)_P =
+// sum_f P_f (x_P - x_F)) and the Jacobi preconditioner Dinv; b = sign (bsrc - mean).
+// Iteration k: spmv_k reduces the r.z, r.r partials of update_{k-1} (or of init),
+// tests convergence, forms beta_k = rz_k / rz_{k-1}, d_k = z + beta_k d_{k-1},
+// q = M d_k and the d.q partials; update_k forms alpha_k = rz_k / (d.q), updates x, r
+// and writes the new r.z, r.r partials.
+
 template <typename R, typename BT, int D>
 __global__ void __launch_bounds__(kWG)
 k_cg_init(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const BT* __restrict__ bsrc,
           const double* __restrict__ mean, double sign, const R* __restrict__ x, R* __restrict__ r,
-          R* __restrict__ dold, CgState* st, double* partials, double tol2) {
+          R* __restrict__ dold, double* __restrict__ partB) {
   const int N = g.N;
   int beg, end;
   chunk_range(N, beg, end);
@@ -37,7 +46,7 @@ k_cg_init(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const BT
   double acc[3] = {0.0, 0.0, 0.0};
   for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
     int Fp[D], Fm[D];
-    faces_of<R, D>(g, P, Fp, Fm);
+    faces_of<D>(g, P, Fp, Fm);
     const R b = (R)(sign * ((double)bsrc[P] - mu));
     const R xP = x[P];
     R Mx = R(0);
@@ -53,42 +62,65 @@ k_cg_init(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const BT
     acc[1] += (double)rv * (double)rv;
     acc[2] += (double)b * (double)b;
   }
+  write_partials<3>(acc, partB);
+}
+
+// One work-group: publishes the state after init (first) or after a chunk of k_total
+// iterations (convergence of the latest residual).
+__global__ void __launch_bounds__(kWG)
+k_cg_check(const double* __restrict__ partB, int G, int first, int k_total, double tol2, CgState* st) {
   double t[3];
-  if (grid_sum<3>(acc, partials, &st->counter, t) && threadIdx.x == 0) {
-    st->rz = t[0];
-    st->rr = t[1];
+  reduce_partials<3>(partB, G, t);
+  if (threadIdx.x != 0) return;
+  if (first) {
     st->bb = t[2];
-    st->beta = 0.0;
-    st->alpha = 0.0;
     st->tol2 = tol2;
+    st->status = 0;
+    st->done = 0;
     st->iters = 0;
-    st->zero_rhs = (t[2] == 0.0) ? 1 : 0;
-    if (!std::isfinite(t[0]) || !std::isfinite(t[1]) || !std::isfinite(t[2])) {
-      st->status = PISO_E_NAN;
-      st->done = 1;
-    } else {
-      st->status = 0;
-      st->done = (t[2] == 0.0 || t[1] <= tol2 * t[2]) ? 1 : 0;
-    }
+    st->zero_rhs = t[2] == 0.0 ? 1 : 0;
+  }
+  if (st->done) return;
+  st->rr = t[1];
+  st->iters = k_total;
+  if (!std::isfinite(t[0]) || !std::isfinite(t[1]) || !std::isfinite(st->bb)) {
+    st->status = PISO_E_NAN;
+    st->done = 1;
+  } else if (st->bb == 0.0 || t[1] <= st->tol2 * st->bb) {
+    st->done = 1;
   }
 }
 
-// d_new = Dinv r + beta d_old (evaluated at the cell and its neighbours), q = M d_new,
-// partial d_new . q; the last work-group sets alpha = (r.z) / (d.q).
 template <typename R, int D>
 __global__ void __launch_bounds__(kWG)
 k_cg_spmv(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
           const R* __restrict__ dold, R* __restrict__ dnew, R* __restrict__ q, CgState* st,
-          double* partials) {
+          const double* __restrict__ partB, double* __restrict__ partA, int Gp, int k) {
   if (st->done) return;
+  double t[2];
+  reduce_partials<2>(partB, Gp, t);
+  const double rz = t[0], rr = t[1];
+  if (!std::isfinite(rz) || !std::isfinite(rr) || rr <= st->tol2 * st->bb) {
+    if (lead()) {
+      st->rr = rr;
+      st->iters = k;
+      if (!std::isfinite(rz) || !std::isfinite(rr)) st->status = PISO_E_NAN;
+      st->done = 1;
+    }
+    return;
+  }
+  const R beta = k == 0 ? R(0) : (R)(rz / st->rz[(k + 1) & 1]);
+  if (lead()) {
+    st->rz[k & 1] = rz;
+    st->rr = rr;
+  }
   const int N = g.N;
-  const R beta = (R)st->beta;
   int beg, end;
   chunk_range(N, beg, end);
   double acc[1] = {0.0};
   for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
     int Fp[D], Fm[D];
-    faces_of<R, D>(g, P, Fp, Fm);
+    faces_of<D>(g, P, Fp, Fm);
     const R dP = Dinv[P] * r[P] + beta * dold[P];
     R Md = R(0);
 #pragma unroll
@@ -106,27 +138,27 @@ k_cg_spmv(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R*
     q[P] = Md;
     acc[0] += (double)dP * (double)Md;
   }
-  double t[1];
-  if (grid_sum<1>(acc, partials, &st->counter, t) && threadIdx.x == 0) {
-    st->dq = t[0];
-    if (t[0] > 0.0 && std::isfinite(t[0])) {
-      st->alpha = st->rz / t[0];
-    } else {
-      st->alpha = 0.0;
-      st->status = std::isfinite(t[0]) ? PISO_BREAKDOWN : PISO_E_NAN;
-      st->done = 1;
-    }
-  }
+  write_partials<1>(acc, partA);
 }
 
-// x += alpha d; r -= alpha q; partial r.z and r.r; the last work-group sets beta and
-// the convergence flag.
 template <typename R>
 __global__ void __launch_bounds__(kWG)
 k_cg_update(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restrict__ r,
-            const R* __restrict__ dnew, const R* __restrict__ q, CgState* st, double* partials) {
+            const R* __restrict__ dnew, const R* __restrict__ q, CgState* st, const double* __restrict__ partA,
+            double* __restrict__ partB, int Gp, int k) {
   if (st->done) return;
-  const R alpha = (R)st->alpha;
+  double t[1];
+  reduce_partials<1>(partA, Gp, t);
+  const double dq = t[0];
+  if (!(dq > 0.0) || !std::isfinite(dq)) {
+    if (lead()) {
+      st->status = std::isfinite(dq) ? PISO_BREAKDOWN : PISO_E_NAN;
+      st->iters = k;
+      st->done = 1;
+    }
+    return;
+  }
+  const R alpha = (R)(st->rz[k & 1] / dq);
   int beg, end;
   chunk_range(N, beg, end);
   double acc[2] = {0.0, 0.0};
@@ -137,28 +169,204 @@ k_cg_update(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restrict_
     acc[0] += (double)rn * (double)(Dinv[P] * rn);
     acc[1] += (double)rn * (double)rn;
   }
-  double t[2];
-  if (grid_sum<2>(acc, partials, &st->counter, t) && threadIdx.x == 0) {
-    st->beta = t[0] / st->rz;
-    st->rz = t[0];
-    st->rr = t[1];
-    st->iters += 1;
-    if (!std::isfinite(t[1])) {
-      st->status = PISO_E_NAN;
-      st->done = 1;
-    } else if (t[1] <= st->tol2 * st->bb) {
-      st->done = 1;
-    }
+  write_partials<2>(acc, partB);
+}
+
+
+// ------------------------------------------------------------ quad fast path
+// Four consecutive x-cells of one row per thread (every block has nx % 4 == 0): the
+// operand, coefficient and output streams move as 16-byte (float) or 32-byte (double)
+// vectors; neighbours across a block side come from the face map cell by cell.
+
+template <typename R>
+struct Q4 {
+  R v[4];
+};
+
+template <typename R>
+__device__ __forceinline__ Q4<R> ldq(const R* __restrict__ p, int P) {
+  Q4<R> q;
+  if constexpr (sizeof(R) == 4) {
+    const float4 t = *reinterpret_cast<const float4*>(p + P);
+    q.v[0] = t.x; q.v[1] = t.y; q.v[2] = t.z; q.v[3] = t.w;
+  } else {
+    const double2 a = *reinterpret_cast<const double2*>(p + P);
+    const double2 b = *reinterpret_cast<const double2*>(p + P + 2);
+    q.v[0] = a.x; q.v[1] = a.y; q.v[2] = b.x; q.v[3] = b.y;
+  }
+  return q;
+}
+
+template <typename R>
+__device__ __forceinline__ void stq(R* __restrict__ p, int P, const Q4<R>& q) {
+  if constexpr (sizeof(R) == 4) {
+    *reinterpret_cast<float4*>(p + P) = make_float4(q.v[0], q.v[1], q.v[2], q.v[3]);
+  } else {
+    *reinterpret_cast<double2*>(p + P) = make_double2(q.v[0], q.v[1]);
+    *reinterpret_cast<double2*>(p + P + 2) = make_double2(q.v[2], q.v[3]);
   }
 }
 
+// M d over the quad starting at P0 for an operand given by dq(P) (4 cells) / d1(P)
+// (one cell); dP is the operand at the quad.  Pf face arrays as in the scalar kernels.
+template <typename R, int D, typename FQ, typename F1>
+__device__ __forceinline__ Q4<R> quad_stencil(const Grid& g, const Cell& c, int P0, const R* __restrict__ Pf,
+                                              const Q4<R>& dP, FQ dq, F1 d1) {
+  const int N = g.N;
+  const int* t = g.tab + c.b * kTabStride;
+  const int nx = t[1], ny = t[2], nz = t[3];
+  Q4<R> M;
+  // x faces
+  const Q4<R> px = ldq(Pf, P0);
+  int Lx = c.i > 0 ? P0 - 1 : g.fmap[t[4] + c.j + ny * c.k];
+  int Rx = c.i + 4 < nx ? P0 + 4 : g.fmap[t[5] + c.j + ny * c.k];
+  const R dl = Lx >= 0 ? d1(Lx) : R(0);
+  const R pl = Lx >= 0 ? Pf[Lx] : R(0);
+  const R dr = Rx >= 0 ? d1(Rx) : R(0);
+  M.v[0] = px.v[0] * (dP.v[0] - dP.v[1]) + pl * (dP.v[0] - dl);
+  M.v[1] = px.v[1] * (dP.v[1] - dP.v[2]) + px.v[0] * (dP.v[1] - dP.v[0]);
+  M.v[2] = px.v[2] * (dP.v[2] - dP.v[3]) + px.v[1] * (dP.v[2] - dP.v[1]);
+  M.v[3] = (Rx >= 0 ? px.v[3] * (dP.v[3] - dr) : R(0)) + px.v[2] * (dP.v[3] - dP.v[2]);
+  // y and z faces
+#pragma unroll
+  for (int a = 1; a < D; ++a) {
+    const int pos = a == 1 ? c.j : c.k;
+    const int n = a == 1 ? ny : nz;
+    const int stride = a == 1 ? nx : nx * ny;
+    const R* Pa = Pf + (size_t)a * N;
+    // +a side: own face coefficients
+    const Q4<R> pp = ldq(Pa, P0);
+    if (pos < n - 1) {
+      const Q4<R> nb = dq(P0 + stride);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) M.v[e] += pp.v[e] * (dP.v[e] - nb.v[e]);
+    } else {
+      const int base = t[4 + 2 * a + 1] + (a == 1 ? c.i + nx * c.k : c.i + nx * c.j);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int F = g.fmap[base + e];
+        if (F >= 0) M.v[e] += pp.v[e] * (dP.v[e] - d1(F));
+      }
+    }
+    // -a side: coefficients stored at the neighbour
+    if (pos > 0) {
+      const Q4<R> nb = dq(P0 - stride);
+      const Q4<R> pm = ldq(Pa, P0 - stride);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) M.v[e] += pm.v[e] * (dP.v[e] - nb.v[e]);
+    } else {
+      const int base = t[4 + 2 * a] + (a == 1 ? c.i + nx * c.k : c.i + nx * c.j);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int F = g.fmap[base + e];
+        if (F >= 0) M.v[e] += Pa[F] * (dP.v[e] - d1(F));
+      }
+    }
+  }
+  return M;
+}
+
+__device__ __forceinline__ void quad_range(int NQ, int& beg, int& end) {
+  const int G = gridDim.x;
+  int per = (NQ + G - 1) / G;
+  per = (per + 63) & ~63;
+  beg = xcd_logical_group() * per;
+  end = beg + per;
+  if (end > NQ) end = NQ;
+}
+
+template <typename R, int D>
+__global__ void __launch_bounds__(kWG)
+k_cg_spmv_q(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
+            const R* __restrict__ dold, R* __restrict__ dnew, R* __restrict__ q, CgState* st,
+            const double* __restrict__ partB, double* __restrict__ partA, int Gp, int k) {
+  if (st->done) return;
+  double t[2];
+  reduce_partials<2>(partB, Gp, t);
+  const double rz = t[0], rr = t[1];
+  if (!std::isfinite(rz) || !std::isfinite(rr) || rr <= st->tol2 * st->bb) {
+    if (lead()) {
+      st->rr = rr;
+      st->iters = k;
+      if (!std::isfinite(rz) || !std::isfinite(rr)) st->status = PISO_E_NAN;
+      st->done = 1;
+    }
+    return;
+  }
+  const R beta = k == 0 ? R(0) : (R)(rz / st->rz[(k + 1) & 1]);
+  if (lead()) {
+    st->rz[k & 1] = rz;
+    st->rr = rr;
+  }
+  auto dq = [&](int P) {
+    const Q4<R> a = ldq(Dinv, P), b = ldq(r, P), c = ldq(dold, P);
+    Q4<R> o;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o.v[e] = a.v[e] * b.v[e] + beta * c.v[e];
+    return o;
+  };
+  auto d1 = [&](int P) { return Dinv[P] * r[P] + beta * dold[P]; };
+  int beg, end;
+  quad_range(g.N >> 2, beg, end);
+  double acc[1] = {0.0};
+  for (int qd = beg + (int)threadIdx.x; qd < end; qd += kWG) {
+    const int P0 = qd << 2;
+    const Cell c = locate(g, P0);
+    const Q4<R> dP = dq(P0);
+    const Q4<R> M = quad_stencil<R, D>(g, c, P0, Pf, dP, dq, d1);
+    stq(dnew, P0, dP);
+    stq(q, P0, M);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[0] += (double)dP.v[e] * (double)M.v[e];
+  }
+  write_partials<1>(acc, partA);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kWG)
+k_cg_update_q(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restrict__ r,
+              const R* __restrict__ dnew, const R* __restrict__ q, CgState* st, const double* __restrict__ partA,
+              double* __restrict__ partB, int Gp, int k) {
+  if (st->done) return;
+  double t[1];
+  reduce_partials<1>(partA, Gp, t);
+  const double dq = t[0];
+  if (!(dq > 0.0) || !std::isfinite(dq)) {
+    if (lead()) {
+      st->status = std::isfinite(dq) ? PISO_BREAKDOWN : PISO_E_NAN;
+      st->iters = k;
+      st->done = 1;
+    }
+    return;
+  }
+  const R alpha = (R)(st->rz[k & 1] / dq);
+  int beg, end;
+  quad_range(N >> 2, beg, end);
+  double acc[2] = {0.0, 0.0};
+  for (int qd = beg + (int)threadIdx.x; qd < end; qd += kWG) {
+    const int P = qd << 2;
+    Q4<R> xv = ldq(x, P), rv = ldq(r, P);
+    const Q4<R> dv = ldq(dnew, P), qv = ldq(q, P), Dv = ldq(Dinv, P);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      xv.v[e] += alpha * dv.v[e];
+      rv.v[e] -= alpha * qv.v[e];
+      acc[0] += (double)rv.v[e] * (double)(Dv.v[e] * rv.v[e]);
+      acc[1] += (double)rv.v[e] * (double)rv.v[e];
+    }
+    stq(x, P, xv);
+    stq(r, P, rv);
+  }
+  write_partials<2>(acc, partB);
+}
+
 // MIXED form: r64 = b64 - M x64 in double with b64 = -(rhs64 - mean) and the float face
-// coefficients, r32 = (float) r64; partial r.r and b.b.
+// coefficients, r32 = (float) r64; partials of r.r and b.b.
 template <int D>
 __global__ void __launch_bounds__(kWG)
 k_mix_resid(Grid g, const float* __restrict__ Pf, const double* __restrict__ rhs64,
             const double* __restrict__ mean, const double* __restrict__ x64, float* __restrict__ r32,
-            double* partials, unsigned* counter, double* out /* [2]: rr, bb */) {
+            double* __restrict__ partials) {
   const int N = g.N;
   int beg, end;
   chunk_range(N, beg, end);
@@ -166,7 +374,7 @@ k_mix_resid(Grid g, const float* __restrict__ Pf, const double* __restrict__ rhs
   double acc[2] = {0.0, 0.0};
   for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
     int Fp[D], Fm[D];
-    faces_of<float, D>(g, P, Fp, Fm);
+    faces_of<D>(g, P, Fp, Fm);
     const double b = -(rhs64[P] - mu);
     const double xP = x64[P];
     double Mx = 0.0;
@@ -180,8 +388,14 @@ k_mix_resid(Grid g, const float* __restrict__ Pf, const double* __restrict__ rhs
     acc[0] += rv * rv;
     acc[1] += b * b;
   }
+  write_partials<2>(acc, partials);
+}
+
+__global__ void __launch_bounds__(kWG)
+k_finalize2(const double* __restrict__ partials, int G, double* __restrict__ out) {
   double t[2];
-  if (grid_sum<2>(acc, partials, counter, t) && threadIdx.x == 0) {
+  reduce_partials<2>(partials, G, t);
+  if (threadIdx.x == 0) {
     out[0] = t[0];
     out[1] = t[1];
   }
@@ -195,12 +409,14 @@ __global__ void __launch_bounds__(kWG) k_mix_add(int N, double* __restrict__ x64
 
 // ------------------------------------------------------------------- BiCGStab
 // d right-hand sides sharing every coefficient read; right Jacobi preconditioning
-// K = diag(A).  TRANS applies C^T instead of C (adjoint solve).
+// K = diag(A); TRANS applies C^T instead of C (adjoint solve).  Iteration k:
+//   bi1_k: rho_k = rh.r, convergence, beta_k, p = r + beta (p - omega v), v = C K^-1 p
+//   bi2_k: alpha_k = rho_k / rh.v, s = r - alpha v, t = C K^-1 s
+//   bi3_k: omega_k = t.s / t.t, x += K^-1 (alpha p + omega s), r = s - omega t
 
 template <typename R, int D, bool TRANS>
-__device__ __forceinline__ R coef_p(const R* __restrict__ C, int j, int P, int Fp, int N) {
+__device__ __forceinline__ R coef_p(const R* __restrict__ C, int j, int P, int N) {
   return TRANS ? C[(size_t)(D + j) * N + P] : C[(size_t)j * N + P];
-  (void)Fp;
 }
 template <typename R, int D, bool TRANS>
 __device__ __forceinline__ R coef_m(const R* __restrict__ C, int j, int Fm, int N) {
@@ -211,20 +427,20 @@ template <typename R, int D, bool TRANS>
 __global__ void __launch_bounds__(kWG)
 k_bi_init(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __restrict__ b,
           const R* __restrict__ x, R* __restrict__ r, R* __restrict__ rh, R* __restrict__ p0,
-          R* __restrict__ v0, BiState* st, double* partials, double tol2) {
+          R* __restrict__ v0, double* __restrict__ part3) {
   const int N = g.N;
   int beg, end;
   chunk_range(N, beg, end);
-  double acc[2 * D];
+  double acc[3 * D];
 #pragma unroll
-  for (int q = 0; q < 2 * D; ++q) acc[q] = 0.0;
+  for (int q = 0; q < 3 * D; ++q) acc[q] = 0.0;
   for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
     int Fp[D], Fm[D];
-    faces_of<R, D>(g, P, Fp, Fm);
+    faces_of<D>(g, P, Fp, Fm);
     R cp[D], cm[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      cp[j] = Fp[j] >= 0 ? coef_p<R, D, TRANS>(C, j, P, Fp[j], N) : R(0);
+      cp[j] = Fp[j] >= 0 ? coef_p<R, D, TRANS>(C, j, P, N) : R(0);
       cm[j] = Fm[j] >= 0 ? coef_m<R, D, TRANS>(C, j, Fm[j], N) : R(0);
     }
     const R AP = A[P];
@@ -244,51 +460,101 @@ k_bi_init(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __r
       p0[(size_t)c * N + P] = R(0);
       v0[(size_t)c * N + P] = R(0);
       acc[c] += (double)rv * (double)rv;
-      acc[D + c] += (double)bv * (double)bv;
+      acc[D + c] += (double)rv * (double)rv;
+      acc[2 * D + c] += (double)bv * (double)bv;
     }
   }
-  double t[2 * D];
-  if (grid_sum<2 * D>(acc, partials, &st->counter, t) && threadIdx.x == 0) {
-    int all = 1;
-    st->tol2 = tol2;
-    for (int c = 0; c < D; ++c) {
-      st->rho[c] = t[c];
-      st->rr[c] = t[c];
-      st->bb[c] = t[D + c];
-      st->rho_prev[c] = 1.0;
-      st->alpha[c] = 1.0;
-      st->omega[c] = 1.0;
-      st->iters[c] = 0;
-      if (!std::isfinite(t[c]) || !std::isfinite(t[D + c])) {
-        st->status[c] = PISO_E_NAN;
-        st->done[c] = 1;
-      } else {
-        st->status[c] = 0;
-        st->done[c] = (t[D + c] == 0.0 || t[c] <= tol2 * t[D + c]) ? 1 : 0;
-      }
-      all &= st->done[c];
-    }
-    for (int c = D; c < 3; ++c) st->done[c] = 1;
-    st->all_done = all;
-  }
+  write_partials<3 * D>(acc, part3);
 }
 
-// p = r + beta (p_old - omega v_old); v = C K^-1 p; partial rh . v; alpha = rho / (rh . v).
+template <int D>
+__global__ void __launch_bounds__(kWG)
+k_bi_check(const double* __restrict__ part3, int G, int first, int k_total, double tol2, BiState* st) {
+  double t[3 * D];
+  if (first) {
+    reduce_partials<3 * D>(part3, G, t);
+  } else {
+    double t2[2 * D];
+    reduce_partials<2 * D>(part3, G, t2);
+#pragma unroll
+    for (int q = 0; q < 2 * D; ++q) t[q] = t2[q];
+#pragma unroll
+    for (int q = 2 * D; q < 3 * D; ++q) t[q] = 0.0;
+  }
+  if (threadIdx.x != 0) return;
+  if (first) {
+    st->tol2 = tol2;
+    for (int c = 0; c < 3; ++c) {
+      st->rho[1][c] = st->alpha[1][c] = st->omega[1][c] = 1.0;
+      st->iters[c] = 0;
+      st->status[c] = 0;
+      st->done[c] = c < D ? 0 : 1;
+    }
+    for (int c = 0; c < D; ++c) st->bb[c] = t[2 * D + c];
+  }
+  int all = 1;
+  for (int c = 0; c < D; ++c) {
+    if (!st->done[c]) {
+      st->rr[c] = t[D + c];
+      st->iters[c] = k_total;
+      if (!std::isfinite(t[c]) || !std::isfinite(t[D + c]) || !std::isfinite(st->bb[c])) {
+        st->status[c] = PISO_E_NAN;
+        st->done[c] = 1;
+      } else if (st->bb[c] == 0.0 || t[D + c] <= tol2 * st->bb[c]) {
+        st->done[c] = 1;
+      }
+    }
+    all &= st->done[c];
+  }
+  st->all_done = all;
+}
+
 template <typename R, int D, bool TRANS>
 __global__ void __launch_bounds__(kWG)
 k_bi_1(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __restrict__ r,
        const R* __restrict__ rh, const R* __restrict__ p_old, const R* __restrict__ v_old,
-       R* __restrict__ p_new, R* __restrict__ v_new, BiState* st, double* partials) {
+       R* __restrict__ p_new, R* __restrict__ v_new, BiState* st, const double* __restrict__ part3,
+       double* __restrict__ part1, int Gp, int k) {
   if (st->all_done) return;
-  const int N = g.N;
+  double t[2 * D];
+  reduce_partials<2 * D>(part3, Gp, t);
+  const int ko = k & 1, kp = (k + 1) & 1;
   R beta[D], omega[D];
   bool act[D];
+  int nact = 0;
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     act[c] = !st->done[c];
-    beta[c] = (R)((st->rho[c] / st->rho_prev[c]) * (st->alpha[c] / st->omega[c]));
-    omega[c] = (R)st->omega[c];
+    beta[c] = R(0);
+    omega[c] = R(0);
+    if (!act[c]) continue;
+    const double rho = t[c], rr = t[D + c];
+    const bool conv = rr <= st->tol2 * st->bb[c];
+    const bool bad = !std::isfinite(rho) || !std::isfinite(rr);
+    const bool brk = !conv && !bad && (rho == 0.0 || st->omega[kp][c] == 0.0);
+    if (conv || bad || brk) {
+      if (lead()) {
+        st->rr[c] = rr;
+        st->iters[c] = k;
+        st->status[c] = bad ? PISO_E_NAN : (brk ? PISO_BREAKDOWN : 0);
+        st->done[c] = 1;
+      }
+      act[c] = false;
+      continue;
+    }
+    beta[c] = (R)((rho / st->rho[kp][c]) * (st->alpha[kp][c] / st->omega[kp][c]));
+    omega[c] = (R)st->omega[kp][c];
+    ++nact;
+    if (lead()) {
+      st->rho[ko][c] = rho;
+      st->rr[c] = rr;
+    }
   }
+  if (nact == 0) {
+    if (lead()) st->all_done = 1;
+    return;
+  }
+  const int N = g.N;
   int beg, end;
   chunk_range(N, beg, end);
   double acc[D];
@@ -296,11 +562,11 @@ k_bi_1(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __rest
   for (int c = 0; c < D; ++c) acc[c] = 0.0;
   for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
     int Fp[D], Fm[D];
-    faces_of<R, D>(g, P, Fp, Fm);
+    faces_of<D>(g, P, Fp, Fm);
     R cp[D], cm[D], iAp[D], iAm[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      cp[j] = Fp[j] >= 0 ? coef_p<R, D, TRANS>(C, j, P, Fp[j], N) : R(0);
+      cp[j] = Fp[j] >= 0 ? coef_p<R, D, TRANS>(C, j, P, N) : R(0);
       cm[j] = Fm[j] >= 0 ? coef_m<R, D, TRANS>(C, j, Fm[j], N) : R(0);
       iAp[j] = Fp[j] >= 0 ? R(1) / A[Fp[j]] : R(0);
       iAm[j] = Fm[j] >= 0 ? R(1) / A[Fm[j]] : R(0);
@@ -311,7 +577,7 @@ k_bi_1(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __rest
       const size_t o = (size_t)c * N;
       auto pn = [&](int X) { return r[o + X] + beta[c] * (p_old[o + X] - omega[c] * v_old[o + X]); };
       const R pP = pn(P);
-      R v = pP;   // A_P * (p_P / A_P)
+      R v = pP;   // A_P (p_P / A_P)
 #pragma unroll
       for (int j = 0; j < D; ++j) {
         if (Fp[j] >= 0) v += cp[j] * pn(Fp[j]) * iAp[j];
@@ -322,38 +588,42 @@ k_bi_1(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __rest
       acc[c] += (double)rh[o + P] * (double)v;
     }
   }
-  double t[D];
-  if (grid_sum<D>(acc, partials, &st->counter, t) && threadIdx.x == 0) {
-    for (int c = 0; c < D; ++c) {
-      if (st->done[c]) continue;
-      if (t[c] != 0.0 && std::isfinite(t[c])) {
-        st->alpha[c] = st->rho[c] / t[c];
-      } else {
-        st->alpha[c] = 0.0;
-        st->status[c] = std::isfinite(t[c]) ? PISO_BREAKDOWN : PISO_E_NAN;
-        st->done[c] = 1;
-      }
-    }
-    int all = 1;
-    for (int c = 0; c < D; ++c) all &= st->done[c];
-    st->all_done = all;
-  }
+  write_partials<D>(acc, part1);
 }
 
-// s = r - alpha v; t = C K^-1 s; partial t.s and t.t; omega = (t.s)/(t.t).
 template <typename R, int D, bool TRANS>
 __global__ void __launch_bounds__(kWG)
 k_bi_2(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __restrict__ r,
-       const R* __restrict__ v, R* __restrict__ s, R* __restrict__ t, BiState* st, double* partials) {
+       const R* __restrict__ v, R* __restrict__ s, R* __restrict__ t, BiState* st,
+       const double* __restrict__ part1, double* __restrict__ part2, int Gp, int k) {
   if (st->all_done) return;
-  const int N = g.N;
+  double rv[D];
+  reduce_partials<D>(part1, Gp, rv);
+  const int ko = k & 1;
   R alpha[D];
   bool act[D];
+  int nact = 0;
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     act[c] = !st->done[c];
-    alpha[c] = (R)st->alpha[c];
+    alpha[c] = R(0);
+    if (!act[c]) continue;
+    if (rv[c] == 0.0 || !std::isfinite(rv[c])) {
+      if (lead()) {
+        st->status[c] = std::isfinite(rv[c]) ? PISO_BREAKDOWN : PISO_E_NAN;
+        st->iters[c] = k;
+        st->done[c] = 1;
+      }
+      act[c] = false;
+      continue;
+    }
+    const double a = st->rho[ko][c] / rv[c];
+    alpha[c] = (R)a;
+    ++nact;
+    if (lead()) st->alpha[ko][c] = a;
   }
+  if (nact == 0) return;
+  const int N = g.N;
   int beg, end;
   chunk_range(N, beg, end);
   double acc[2 * D];
@@ -361,11 +631,11 @@ k_bi_2(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __rest
   for (int q = 0; q < 2 * D; ++q) acc[q] = 0.0;
   for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
     int Fp[D], Fm[D];
-    faces_of<R, D>(g, P, Fp, Fm);
+    faces_of<D>(g, P, Fp, Fm);
     R cp[D], cm[D], iAp[D], iAm[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      cp[j] = Fp[j] >= 0 ? coef_p<R, D, TRANS>(C, j, P, Fp[j], N) : R(0);
+      cp[j] = Fp[j] >= 0 ? coef_p<R, D, TRANS>(C, j, P, N) : R(0);
       cm[j] = Fm[j] >= 0 ? coef_m<R, D, TRANS>(C, j, Fm[j], N) : R(0);
       iAp[j] = Fp[j] >= 0 ? R(1) / A[Fp[j]] : R(0);
       iAm[j] = Fm[j] >= 0 ? R(1) / A[Fm[j]] : R(0);
@@ -388,29 +658,27 @@ k_bi_2(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __rest
       acc[D + c] += (double)tv * (double)tv;
     }
   }
-  double tt[2 * D];
-  if (grid_sum<2 * D>(acc, partials, &st->counter, tt) && threadIdx.x == 0) {
-    for (int c = 0; c < D; ++c) {
-      if (st->done[c]) continue;
-      st->omega[c] = tt[D + c] > 0.0 ? tt[c] / tt[D + c] : 0.0;
-    }
-  }
+  write_partials<2 * D>(acc, part2);
 }
 
-// x += K^-1 (alpha p + omega s); r = s - omega t; partial rh.r and r.r; convergence.
 template <typename R, int D>
 __global__ void __launch_bounds__(kWG)
 k_bi_3(int N, const R* __restrict__ A, R* __restrict__ x, R* __restrict__ r, const R* __restrict__ rh,
        const R* __restrict__ p, const R* __restrict__ s, const R* __restrict__ t, BiState* st,
-       double* partials) {
+       const double* __restrict__ part2, double* __restrict__ part3, int Gp, int k) {
   if (st->all_done) return;
+  double ts[2 * D];
+  reduce_partials<2 * D>(part2, Gp, ts);
+  const int ko = k & 1;
   R alpha[D], omega[D];
   bool act[D];
 #pragma unroll
   for (int c = 0; c < D; ++c) {
     act[c] = !st->done[c];
-    alpha[c] = (R)st->alpha[c];
-    omega[c] = (R)st->omega[c];
+    const double w = ts[D + c] > 0.0 ? ts[c] / ts[D + c] : 0.0;
+    omega[c] = (R)w;
+    alpha[c] = (R)st->alpha[ko][c];
+    if (act[c] && lead()) st->omega[ko][c] = w;
   }
   int beg, end;
   chunk_range(N, beg, end);
@@ -431,29 +699,7 @@ k_bi_3(int N, const R* __restrict__ A, R* __restrict__ x, R* __restrict__ r, con
       acc[D + c] += (double)rn * (double)rn;
     }
   }
-  double tt[2 * D];
-  if (grid_sum<2 * D>(acc, partials, &st->counter, tt) && threadIdx.x == 0) {
-    int all = 1;
-    for (int c = 0; c < D; ++c) {
-      if (!st->done[c]) {
-        st->rho_prev[c] = st->rho[c];
-        st->rho[c] = tt[c];
-        st->rr[c] = tt[D + c];
-        st->iters[c] += 1;
-        if (!std::isfinite(tt[D + c])) {
-          st->status[c] = PISO_E_NAN;
-          st->done[c] = 1;
-        } else if (tt[D + c] <= st->tol2 * st->bb[c]) {
-          st->done[c] = 1;
-        } else if (tt[c] == 0.0 || st->omega[c] == 0.0) {
-          st->status[c] = PISO_BREAKDOWN;
-          st->done[c] = 1;
-        }
-      }
-      all &= st->done[c];
-    }
-    st->all_done = all;
-  }
+  write_partials<2 * D>(acc, part3);
 }
 
 // ------------------------------------------------------------------ host drivers
@@ -490,8 +736,8 @@ static void timing_end(piso_ctx* c, hipStream_t s, const EvPair& p) {
   if (p.b) (void)hipEventRecord(p.b, s);
 }
 
-// After a stream sync: fold the elapsed times of the recorded pairs (spmv, update
-// alternate in the pool) into the totals.
+// After a stream sync: fold the elapsed times of the recorded pairs into the totals
+// (kinds: 0 = spmv, 1 = update).
 static void timing_collect(piso_ctx* c, const std::vector<int>& kinds) {
   Timing& t = c->timing;
   if (!t.enabled) return;
@@ -514,25 +760,28 @@ template <typename R, typename BT>
 static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const BT* b,
                    const double* mean, double sign, R* x, double rtol, int max_iter, int check_every,
                    int* iters_out, double* rel_out, int* status_out) {
-  const int N = c->N, G = grid_red(N);
+  const int N = c->N, G = grid_red(N, c->red_grid);
   R* r = (R*)c->k_r;
   R* q = (R*)c->k_q;
   R* d[2] = {(R*)c->k_d0, (R*)c->k_d1};
   CgState* st = c->cg;
+  double* pA = part(c, kPartA);
+  double* pB = part(c, kPartB);
   const double tol2 = rtol * rtol;
   if (c->dim == 2)
-    k_cg_init<R, BT, 2><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, b, mean, sign, x, r, d[0], st, c->partials, tol2);
+    k_cg_init<R, BT, 2><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, b, mean, sign, x, r, d[0], pB);
   else
-    k_cg_init<R, BT, 3><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, b, mean, sign, x, r, d[0], st, c->partials, tol2);
+    k_cg_init<R, BT, 3><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, b, mean, sign, x, r, d[0], pB);
+  k_cg_check<<<1, kWG, 0, s>>>(pB, G, 1, 0, tol2, st);
   if (int rc = check(c, "k_cg_init")) return rc;
   PISO_HIP(c, hipMemcpyAsync(c->h_cg, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
   PISO_HIP(c, hipStreamSynchronize(s));
-  if (c->h_cg->zero_rhs) {
-    PISO_HIP(c, hipMemsetAsync(x, 0, sizeof(R) * (size_t)N, s));
-  }
+  if (c->h_cg->zero_rhs) PISO_HIP(c, hipMemsetAsync(x, 0, sizeof(R) * (size_t)N, s));
   int it = 0;
   if (check_every < 1) check_every = 8;
   std::vector<int> kinds;
+  // the vectorised kernels need 16-byte aligned operands (caller buffers may be views)
+  const bool quad = c->quad && ((((uintptr_t)Pf) | ((uintptr_t)Dinv) | ((uintptr_t)x)) & 15u) == 0;
   while (!c->h_cg->done && it < max_iter) {
     const int n = std::min(check_every, max_iter - it);
     kinds.clear();
@@ -540,17 +789,26 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
       R* dold = d[it & 1];
       R* dnew = d[(it + 1) & 1];
       EvPair e1 = timing_begin(c, s);
-      if (c->dim == 2)
-        k_cg_spmv<R, 2><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, r, dold, dnew, q, st, c->partials);
-      else
-        k_cg_spmv<R, 3><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, r, dold, dnew, q, st, c->partials);
+      if (quad) {
+        if (c->dim == 2)
+          k_cg_spmv_q<R, 2><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, r, dold, dnew, q, st, pB, pA, G, it);
+        else
+          k_cg_spmv_q<R, 3><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, r, dold, dnew, q, st, pB, pA, G, it);
+      } else {
+        if (c->dim == 2)
+          k_cg_spmv<R, 2><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, r, dold, dnew, q, st, pB, pA, G, it);
+        else
+          k_cg_spmv<R, 3><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, r, dold, dnew, q, st, pB, pA, G, it);
+      }
       timing_end(c, s, e1);
       if (e1.a) kinds.push_back(0);
       EvPair e2 = timing_begin(c, s);
-      k_cg_update<R><<<G, kWG, 0, s>>>(N, Dinv, x, r, dnew, q, st, c->partials);
+      if (quad) k_cg_update_q<R><<<G, kWG, 0, s>>>(N, Dinv, x, r, dnew, q, st, pA, pB, G, it);
+      else k_cg_update<R><<<G, kWG, 0, s>>>(N, Dinv, x, r, dnew, q, st, pA, pB, G, it);
       timing_end(c, s, e2);
       if (e2.a) kinds.push_back(1);
     }
+    k_cg_check<<<1, kWG, 0, s>>>(pB, G, 0, it, tol2, st);
     if (int rc = check(c, "k_cg iteration")) return rc;
     PISO_HIP(c, hipMemcpyAsync(c->h_cg, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
     PISO_HIP(c, hipStreamSynchronize(s));
@@ -590,16 +848,18 @@ int pressure_solve(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
 int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const float* Pf, const float* Dinv,
                          const double* rhs64, const double* mean, double* x64, const piso_solve_opts* o,
                          piso_solve_info* info) {
-  const int N = c->N, G = grid_red(N);
+  const int N = c->N, G = grid_red(N, c->red_grid);
   float* r32 = (float*)c->m_r32;
   float* e32 = (float*)c->m_e32;
+  double* pS = part(c, kPartS);
   int iters = 0, status = 0, sweeps = 0;
   double rel = 0.0;
   for (;;) {
     if (c->dim == 2)
-      k_mix_resid<2><<<G, kWG, 0, s>>>(c->grid, Pf, rhs64, mean, x64, r32, c->partials, c->counter, c->mean + 2);
+      k_mix_resid<2><<<G, kWG, 0, s>>>(c->grid, Pf, rhs64, mean, x64, r32, pS);
     else
-      k_mix_resid<3><<<G, kWG, 0, s>>>(c->grid, Pf, rhs64, mean, x64, r32, c->partials, c->counter, c->mean + 2);
+      k_mix_resid<3><<<G, kWG, 0, s>>>(c->grid, Pf, rhs64, mean, x64, r32, pS);
+    k_finalize2<<<1, kWG, 0, s>>>(pS, G, c->mean + 2);
     if (int rc = check(c, "k_mix_resid")) return rc;
     PISO_HIP(c, hipMemcpyAsync(c->h_scal, c->mean + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     PISO_HIP(c, hipStreamSynchronize(s));
@@ -649,7 +909,7 @@ int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const float* Pf, const floa
 template <typename R>
 int velocity_solve(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* C, const R* b, R* x,
                    const piso_solve_opts* o, piso_solve_info* info) {
-  const int N = c->N, G = grid_red(N), D = c->dim;
+  const int N = c->N, G = grid_red(N, c->red_grid), D = c->dim;
   R* r = (R*)c->b_r;
   R* rh = (R*)c->b_rh;
   R* pb[2] = {(R*)c->b_p0, (R*)c->b_p1};
@@ -657,6 +917,9 @@ int velocity_solve(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* 
   R* sb = (R*)c->b_s;
   R* tb = (R*)c->b_t;
   BiState* st = c->bi;
+  double* p1 = part(c, kPart1);
+  double* p2 = part(c, kPart2);
+  double* p3 = part(c, kPart3);
   const double tol2 = o->rtol * o->rtol;
 #define BI_LAUNCH(KERNEL, ...)                                                    \
   do {                                                                            \
@@ -668,7 +931,13 @@ int velocity_solve(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* 
       else KERNEL<R, 3, false><<<G, kWG, 0, s>>>(__VA_ARGS__);                    \
     }                                                                             \
   } while (0)
-  BI_LAUNCH(k_bi_init, c->grid, A, C, b, x, r, rh, pb[0], vb[0], st, c->partials, tol2);
+#define BI_CHECK(FIRST, KT)                                                       \
+  do {                                                                            \
+    if (D == 2) k_bi_check<2><<<1, kWG, 0, s>>>(p3, G, FIRST, KT, tol2, st);      \
+    else k_bi_check<3><<<1, kWG, 0, s>>>(p3, G, FIRST, KT, tol2, st);             \
+  } while (0)
+  BI_LAUNCH(k_bi_init, c->grid, A, C, b, x, r, rh, pb[0], vb[0], p3);
+  BI_CHECK(1, 0);
   if (int rc = check(c, "k_bi_init")) return rc;
   PISO_HIP(c, hipMemcpyAsync(c->h_bi, st, sizeof(BiState), hipMemcpyDeviceToHost, s));
   PISO_HIP(c, hipStreamSynchronize(s));
@@ -683,16 +952,18 @@ int velocity_solve(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* 
       R* pn = pb[(it + 1) & 1];
       R* vo = vb[it & 1];
       R* vn = vb[(it + 1) & 1];
-      BI_LAUNCH(k_bi_1, c->grid, A, C, r, rh, po, vo, pn, vn, st, c->partials);
-      BI_LAUNCH(k_bi_2, c->grid, A, C, r, vn, sb, tb, st, c->partials);
-      if (D == 2) k_bi_3<R, 2><<<G, kWG, 0, s>>>(N, A, x, r, rh, pn, sb, tb, st, c->partials);
-      else k_bi_3<R, 3><<<G, kWG, 0, s>>>(N, A, x, r, rh, pn, sb, tb, st, c->partials);
+      BI_LAUNCH(k_bi_1, c->grid, A, C, r, rh, po, vo, pn, vn, st, p3, p1, G, it);
+      BI_LAUNCH(k_bi_2, c->grid, A, C, r, vn, sb, tb, st, p1, p2, G, it);
+      if (D == 2) k_bi_3<R, 2><<<G, kWG, 0, s>>>(N, A, x, r, rh, pn, sb, tb, st, p2, p3, G, it);
+      else k_bi_3<R, 3><<<G, kWG, 0, s>>>(N, A, x, r, rh, pn, sb, tb, st, p2, p3, G, it);
     }
+    BI_CHECK(0, it);
     if (int rc = check(c, "k_bi iteration")) return rc;
     PISO_HIP(c, hipMemcpyAsync(c->h_bi, st, sizeof(BiState), hipMemcpyDeviceToHost, s));
     PISO_HIP(c, hipStreamSynchronize(s));
   }
 #undef BI_LAUNCH
+#undef BI_CHECK
   const BiState& h = *c->h_bi;
   int status = 0, iters = 0;
   double rel = 0.0;
