@@ -25,6 +25,37 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+KRYLOV_SRC = os.path.join(ROOT, "paper_2505_16992_amd", "csrc", "piso_krylov.hip")
+COMMON_SRC = os.path.join(ROOT, "paper_2505_16992_amd", "csrc", "piso_common.h")
+COUNTERS = os.path.join(ROOT, "profiles", "k_cg_spmv_q_channel96_f32_counters.md")
+
+
+def kernel_digest():
+    """sha256 of the vectorised CG kernels' source (the quad section of the Krylov file
+    and the shared device header): counter figures are used only while it matches."""
+    import hashlib
+    with open(KRYLOV_SRC) as f:
+        txt = f.read()
+    a = txt.index("// ------------------------------------------------------------ quad fast path")
+    b = txt.index("// MIXED form:")
+    with open(COMMON_SRC) as f:
+        common = f.read()
+    return hashlib.sha256((txt[a:b] + common).encode()).hexdigest()
+
+
+def counter_traffic(workload, precision):
+    """HBM bytes per launch of the stencil kernel from the committed counter summary."""
+    if workload != "channel96" or precision != "f32" or not os.path.exists(COUNTERS):
+        return None
+    vals = {}
+    with open(COUNTERS) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_digest():
+        return None
+    return int(vals["traffic_bytes_per_launch"])
 
 
 def log(*a):
@@ -80,8 +111,16 @@ def main():
     ap.add_argument("--workload", default="channel96")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--kernel-digest", action="store_true", help="print the CG kernel source digest")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of 256 MiB (counter calibration)")
+    ap.add_argument("--pres-rtol", type=float, default=None,
+                    help="pressure tolerance (equal-residual comparisons of the precision forms)")
     args = ap.parse_args()
 
+    if args.kernel_digest:
+        print(kernel_digest())
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the PISO step here runs on a single MI355X "
@@ -94,6 +133,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # one elementwise kernel that reads 256 MiB and writes 256 MiB
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        torch.add(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"read_bytes": x.numel() * 4, "write_bytes": y.numel() * 4}}))
+        return
     case = make_case(args.workload)
     dom = case.domain
     ctx = api.Context(dom, args.precision)
@@ -107,6 +155,8 @@ def main():
     u0, p0, S, ub = dev(case.u0), dev(case.p0), dev(case.S), dev(case.u_b)
     nu = dev(np.array([case.nu]))
     opts = ctx.default_opts()
+    if args.pres_rtol is not None:
+        opts.pres.rtol = args.pres_rtol
     K, W = args.steps, args.warmup
     is_channel = args.workload.startswith("channel") or args.workload == "pcg256"
     if is_channel:
@@ -183,18 +233,20 @@ def main():
         tm = ctx.get_timing()
         ctx.set_timing(False)
         es = ctx.elem_bytes
-        spmv_bytes = N * (2 * d + 4) * es       # Pf (d), r, Dinv, d_old -> d_new, q
+        spmv_bytes = N * (d + 5) * es           # Pf (d), r, Dinv, d_old -> d_new, q
         upd_bytes = N * 7 * es                   # Dinv, x, r, d_new, q -> x, r
         if tm["spmv_calls"]:
             avg = tm["spmv_ms"] / tm["spmv_calls"]
             ach = spmv_bytes / (avg * 1e-3) / 1e9
-            roof = {"bound": "hbm", "kernel": "k_cg_spmv", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None,
+            quad = all(b[0] % 4 == 0 for b in dom.blocks)
+            roof = {"bound": "hbm", "kernel": "k_cg_spmv_q" if quad else "k_cg_spmv", "achieved": round(ach, 1),
+                    "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
+                    "traffic": counter_traffic(args.workload, args.precision),
                     "avg_launch_us": round(avg * 1e3, 3), "bytes_per_launch": spmv_bytes,
                     "launches": tm["spmv_calls"]}
             avg_u = tm["update_ms"] / max(tm["update_calls"], 1)
             it_bytes = spmv_bytes + upd_bytes
-            pcg = {"kernels": ["k_cg_spmv", "k_cg_update"],
+            pcg = {"kernels": ["k_cg_spmv_q", "k_cg_update_q"] if quad else ["k_cg_spmv", "k_cg_update"],
                    "GBps": round(it_bytes / ((avg + avg_u) * 1e-3) / 1e9, 1),
                    "update_avg_us": round(avg_u * 1e3, 3), "iter_bytes": it_bytes}
         log("timing %s" % tm)
@@ -229,7 +281,8 @@ def main():
         "dtype": {"f32": "f32", "mixed": "f32+f64", "f64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": args.workload, "cells": N, "dt": case.dt, "precision": args.precision,
-                   "rollout_steps": K},
+                   "rollout_steps": K, "pres_rtol": opts.pres.rtol, "vel_rtol": opts.vel.rtol},
+        "pres_rel_residual_last": finfos[-1]["pres"][1]["rel_residual"],
         "fwd_steps_per_s": round(K / Tf, 4),
         "cell_updates_per_s_fwd": round(N * K / Tf, 1),
         "cell_updates_per_s_fwd_adj": round(N * K / T, 1),

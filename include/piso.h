@@ -169,7 +169,7 @@ int piso_sizes(const piso_ctx* ctx, int64_t* n_cells, int64_t* n_bfaces, int64_t
                int64_t* elem_bytes, int32_t* non_orthogonal);
 
 /* Default options for a precision: vel rtol 1e-10 (F64) / 1e-7, pres rtol 1e-10 (F64),
- * 1e-6 (F32), 1e-8 (MIXED, inner 1e-3), 2 correctors, grad_p_in_predictor = 1. */
+ * 1e-6 (F32), 1e-8 (MIXED, inner 5e-5), 2 correctors, grad_p_in_predictor = 1. */
 void piso_default_step_opts(int32_t precision, piso_step_opts* opts);
 
 /* Predictor assembly (App. A.3.3-A.3.5, eqs. advMatDiscrete, difMatDiscrete,

@@ -85,9 +85,12 @@ class Context:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
-            self.lib.piso_destroy(h)
-            self.h = C.c_void_p()
+        try:
+            if h is not None and h.value:
+                self.lib.piso_destroy(h)
+                self.h = None
+        except Exception:      # interpreter shutdown: the library may already be gone
+            pass
 
     # ---------------------------------------------------------------- helpers
     def _check(self, rc, what):

@@ -614,7 +614,7 @@ void piso_default_step_opts(int32_t precision, piso_step_opts* o) {
   o->pres.rtol = precision == PISO_F64 ? 1e-10 : (precision == PISO_MIXED ? 1e-8 : 1e-6);
   o->pres.max_iter = 20000;
   o->pres.check_every = 16;
-  o->pres.inner_rtol = 1e-3;
+  o->pres.inner_rtol = 5e-5;
   o->pres.max_refine = 20;
   o->vel.inner_rtol = 1e-3;
   o->vel.max_refine = 0;

@@ -7,6 +7,8 @@
 // identical everywhere) and derives its scalar (alpha, beta, omega) on the device.  No
 // device-scope fences or atomics are used.  The host reads the convergence state only
 // every check_every iterations, through a one-work-group check kernel.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <cmath>
 
@@ -710,12 +712,14 @@ static int check(piso_ctx* c, const char* what) {
   return PISO_OK;
 }
 
-// Timed launch: when timing is enabled, brackets the launch with an event pair.
+// Kernel timing for the benchmark: when enabled, the CG kernels are launched with
+// start/stop events attached to the dispatch itself (hipExtLaunchKernelGGL), so the
+// elapsed time is the kernel's execution, as a kernel trace reports it.
 struct EvPair {
   hipEvent_t a = nullptr, b = nullptr;
 };
 
-static EvPair timing_begin(piso_ctx* c, hipStream_t s) {
+static EvPair timing_pair(piso_ctx* c) {
   EvPair p;
   Timing& t = c->timing;
   if (!t.enabled) return p;
@@ -728,16 +732,11 @@ static EvPair timing_begin(piso_ctx* c, hipStream_t s) {
   }
   p.a = t.ev[t.used++];
   p.b = t.ev[t.used++];
-  (void)hipEventRecord(p.a, s);
   return p;
 }
 
-static void timing_end(piso_ctx* c, hipStream_t s, const EvPair& p) {
-  if (p.b) (void)hipEventRecord(p.b, s);
-}
-
 // After a stream sync: fold the elapsed times of the recorded pairs into the totals
-// (kinds: 0 = spmv, 1 = update).
+// (kinds: 0 = stencil kernel, 1 = update kernel).
 static void timing_collect(piso_ctx* c, const std::vector<int>& kinds) {
   Timing& t = c->timing;
   if (!t.enabled) return;
@@ -754,6 +753,19 @@ static void timing_collect(piso_ctx* c, const std::vector<int>& kinds) {
     }
   }
   t.used = 0;
+}
+
+// Launch with optional dispatch-attached timing events.
+template <typename K, typename... Args>
+static void launch_timed(piso_ctx* c, hipStream_t s, int kind, std::vector<int>& kinds, K kernel, int G,
+                         Args... args) {
+  EvPair e = timing_pair(c);
+  if (e.a) {
+    hipExtLaunchKernelGGL(kernel, dim3(G), dim3(kWG), 0, s, e.a, e.b, 0, args...);
+    kinds.push_back(kind);
+  } else {
+    hipLaunchKernelGGL(kernel, dim3(G), dim3(kWG), 0, s, args...);
+  }
 }
 
 template <typename R, typename BT>
@@ -788,25 +800,25 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
     for (int k = 0; k < n; ++k, ++it) {
       R* dold = d[it & 1];
       R* dnew = d[(it + 1) & 1];
-      EvPair e1 = timing_begin(c, s);
       if (quad) {
         if (c->dim == 2)
-          k_cg_spmv_q<R, 2><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, r, dold, dnew, q, st, pB, pA, G, it);
+          launch_timed(c, s, 0, kinds, k_cg_spmv_q<R, 2>, G, c->grid, Pf, Dinv, (const R*)r, (const R*)dold, dnew, q,
+                       st, (const double*)pB, pA, G, it);
         else
-          k_cg_spmv_q<R, 3><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, r, dold, dnew, q, st, pB, pA, G, it);
+          launch_timed(c, s, 0, kinds, k_cg_spmv_q<R, 3>, G, c->grid, Pf, Dinv, (const R*)r, (const R*)dold, dnew, q,
+                       st, (const double*)pB, pA, G, it);
+        launch_timed(c, s, 1, kinds, k_cg_update_q<R>, G, N, Dinv, x, r, (const R*)dnew, (const R*)q, st,
+                     (const double*)pA, pB, G, it);
       } else {
         if (c->dim == 2)
-          k_cg_spmv<R, 2><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, r, dold, dnew, q, st, pB, pA, G, it);
+          launch_timed(c, s, 0, kinds, k_cg_spmv<R, 2>, G, c->grid, Pf, Dinv, (const R*)r, (const R*)dold, dnew, q,
+                       st, (const double*)pB, pA, G, it);
         else
-          k_cg_spmv<R, 3><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, r, dold, dnew, q, st, pB, pA, G, it);
+          launch_timed(c, s, 0, kinds, k_cg_spmv<R, 3>, G, c->grid, Pf, Dinv, (const R*)r, (const R*)dold, dnew, q,
+                       st, (const double*)pB, pA, G, it);
+        launch_timed(c, s, 1, kinds, k_cg_update<R>, G, N, Dinv, x, r, (const R*)dnew, (const R*)q, st,
+                     (const double*)pA, pB, G, it);
       }
-      timing_end(c, s, e1);
-      if (e1.a) kinds.push_back(0);
-      EvPair e2 = timing_begin(c, s);
-      if (quad) k_cg_update_q<R><<<G, kWG, 0, s>>>(N, Dinv, x, r, dnew, q, st, pA, pB, G, it);
-      else k_cg_update<R><<<G, kWG, 0, s>>>(N, Dinv, x, r, dnew, q, st, pA, pB, G, it);
-      timing_end(c, s, e2);
-      if (e2.a) kinds.push_back(1);
     }
     k_cg_check<<<1, kWG, 0, s>>>(pB, G, 0, it, tol2, st);
     if (int rc = check(c, "k_cg iteration")) return rc;

@@ -67,4 +67,7 @@ def small_cases():
         "two_block": two_block(),
         "sheared": cases.sheared_channel(9, 10, shear=0.6),
         "cylinder": cases.cylinder_oh(16, 6, 5),
+        # every block with nx % 4 == 0: exercises the vectorised CG kernels
+        "channel_q": cases.channel(12, 10, 8),
+        "cylinder_q": cases.cylinder_oh(16, 8, 4),
     }

@@ -16,7 +16,7 @@ from tests.gpu_common import dev, host, rel, rel_p, say, small_cases, tight_opts
 
 pytestmark = pytest.mark.gpu
 
-CASES = ["tgv16", "cavity12", "channel", "two_block", "sheared", "cylinder"]
+CASES = ["tgv16", "cavity12", "channel", "two_block", "sheared", "cylinder", "channel_q", "cylinder_q"]
 
 
 @pytest.fixture(scope="module")

@@ -1,0 +1,163 @@
+"""GPU rollouts: autograd Function, step checkpointing, gradient paths, determinism,
+quad-vs-generic kernels, and finite differences through a multi-block rollout."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import cases
+from oracle.adjoint import step_vjp
+from oracle.piso import Geometry, step as oracle_step
+from tests.gpu_common import dev, host, rel, rel_p, say, small_cases, tight_opts, random_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def api():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2505_16992_amd import api as A
+    return A
+
+
+def _inputs(ctx, case, seed, scale=0.1):
+    u, p, S, ub, nu = random_state(case, seed, scale)
+    t = ctx.dtype
+    return (u, p, S, ub, nu), [dev(x, t) for x in (u, p, S, ub)] + [dev(np.array([case.nu]), t)]
+
+
+@pytest.mark.parametrize("name", ["channel_q", "cylinder_q"])
+def test_quad_matches_generic(api, name):
+    say("test_quad_matches_generic", name)
+    case = small_cases()[name]
+    outs = []
+    for env in ("0", "1"):
+        os.environ["PISO_NO_QUAD"] = env
+        try:
+            ctx = api.Context(case.domain, "f64")
+        finally:
+            os.environ.pop("PISO_NO_QUAD", None)
+        _, (u, p, S, ub, nu) = _inputs(ctx, case, 3)
+        o = tight_opts(ctx)
+        u1, p1 = ctx.step(u, p, nu, S, ub, case.dt, o)
+        outs.append((host(u1), host(p1)))
+    assert rel(outs[0][0], outs[1][0]) < 1e-11
+    assert rel_p(outs[0][1], outs[1][1]) < 1e-10
+
+
+def test_deterministic(api):
+    say("test_deterministic")
+    case = cases.channel(16, 12, 8)
+    ctx = api.Context(case.domain, "f32")
+    _, (u, p, S, ub, nu) = _inputs(ctx, case, 4)
+    a = ctx.step(u, p, nu, S, ub, case.dt)
+    b = ctx.step(u, p, nu, S, ub, case.dt)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("name", ["channel_q", "cylinder_q"])
+def test_rollout_matches_oracle_chain(api, name):
+    """3-step rollout through the autograd Function vs the chained oracle adjoint."""
+    say("test_rollout_matches_oracle_chain", name)
+    case = small_cases()[name]
+    ctx = api.Context(case.domain, "f64")
+    (u0, p0, S0, ub0, _), (u, p, S, ub, nu) = _inputs(ctx, case, 5)
+    o = tight_opts(ctx)
+    rng = np.random.default_rng(6)
+    w = rng.standard_normal(u0.shape)
+    S_ = S.clone().requires_grad_(True)
+    u_ = u.clone().requires_grad_(True)
+    nu_ = nu.clone().requires_grad_(True)
+    uT, pT = api.rollout(ctx, u_, p, S_, nu_, ub, case.dt, 3, checkpoint_every=0, opts=o)
+    L = (uT * dev(w, ctx.dtype)).sum()
+    gS, gu, gnu = torch.autograd.grad(L, [S_, u_, nu_])
+    geo = Geometry(case.domain)
+    recs, uu, pp = [], u0, p0
+    for _ in range(3):
+        r = oracle_step(geo, uu, pp, case.nu, S0, case.dt, ub0)
+        recs.append(r)
+        uu, pp = r.u2, r.p2
+    gu_o, gp_o = w, np.zeros(geo.N)
+    dS, dnu = 0.0, 0.0
+    for r in reversed(recs):
+        g = step_vjp(geo, r, gu_o, gp_o)
+        gu_o, gp_o = g["u_n"], g["p_n"]
+        dS = dS + g["S"]
+        dnu = dnu + g["nu"].sum()
+    assert rel(host(gS), dS) < 1e-8
+    assert rel(host(gu), gu_o) < 1e-8
+    assert abs(float(host(gnu)[0]) - dnu) <= 1e-8 * abs(dnu)
+
+
+def test_checkpointing_is_exact(api):
+    """Recomputing segment tapes reproduces the stored-tape adjoint chain bit for bit
+    (the initial-state gradient); gradients of parameters shared by all steps (S) are
+    sums whose order differs between segmentings, so they agree to rounding."""
+    say("test_checkpointing_is_exact")
+    case = small_cases()["cylinder_q"]
+    ctx = api.Context(case.domain, "f32")
+    _, (u, p, S, ub, nu) = _inputs(ctx, case, 7)
+    w = torch.randn_like(u)
+    grads = []
+    for k in (0, 2, 3):
+        S_ = S.clone().requires_grad_(True)
+        u_ = u.clone().requires_grad_(True)
+        uT, _ = api.rollout(ctx, u_, p, S_, nu, ub, case.dt, 6, checkpoint_every=k)
+        grads.append(torch.autograd.grad((uT * w).sum(), [u_, S_]))
+    for g in grads[1:]:
+        assert torch.equal(grads[0][0], g[0])
+        assert rel(host(g[1]), host(grads[0][1])) < 1e-6
+
+
+def test_fd_through_multiblock_rollout(api):
+    """Central differences of a 6-step rollout loss on the non-orthogonal 5-block grid
+    (FP64, checkpoint every 2) against the adjoint gradient with respect to S."""
+    say("test_fd_through_multiblock_rollout")
+    case = small_cases()["cylinder_q"]
+    ctx = api.Context(case.domain, "f64")
+    _, (u, p, S, ub, nu) = _inputs(ctx, case, 8)
+    o = tight_opts(ctx, 1e-14, 1e-14)
+    w = dev(np.random.default_rng(9).standard_normal((2, ctx.N)), torch.float64)
+    S_ = S.clone().requires_grad_(True)
+    uT, _ = api.rollout(ctx, u, p, S_, nu, ub, case.dt, 6, checkpoint_every=2, opts=o)
+    (gS,) = torch.autograd.grad((uT * w).sum(), [S_])
+
+    def loss(Sx):
+        with torch.no_grad():
+            uu, pp = u, p
+            for _ in range(6):
+                uu, pp = ctx.step(uu, pp, nu, Sx, ub, case.dt, o)
+            return float((uu * w).sum())
+
+    rng = np.random.default_rng(10)
+    for _ in range(6):
+        comp, cell = int(rng.integers(2)), int(rng.integers(ctx.N))
+        eps = 1e-4
+        Sp, Sm = S.clone(), S.clone()
+        Sp[comp, cell] += eps
+        Sm[comp, cell] -= eps
+        fd = (loss(Sp) - loss(Sm)) / (2 * eps)
+        an = float(gS[comp, cell])
+        assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-2), (comp, cell, fd, an)
+
+
+def test_gradient_path_flags(api):
+    """Skipping the adjoint solves (Sec. 2.4) matches the oracle's bypass gradients."""
+    say("test_gradient_path_flags")
+    case = small_cases()["channel_q"]
+    ctx = api.Context(case.domain, "f64")
+    (u0, p0, S0, ub0, nu0), (u, p, S, ub, nu) = _inputs(ctx, case, 11)
+    o = tight_opts(ctx)
+    geo = Geometry(case.domain)
+    rec = oracle_step(geo, u0, p0, case.nu, S0, case.dt, ub0)
+    w = np.random.default_rng(12).standard_normal(u0.shape)
+    for flags, kw in ((1, dict(skip_velocity_solve=True)), (2, dict(skip_pressure_solve=True)),
+                      (3, dict(skip_velocity_solve=True, skip_pressure_solve=True))):
+        o.grad_path_flags = flags
+        tape = ctx.new_tape()
+        ctx.step(u, p, nu, S, ub, case.dt, o, tape=tape)
+        g = ctx.step_backward(tape, u, p, nu, ub, case.dt, dev(w, torch.float64), None, o)
+        gr = step_vjp(geo, rec, w, np.zeros(geo.N), **kw)
+        assert rel(host(g["S"]), gr["S"]) < 1e-8, flags
+        assert rel(host(g["u"]), gr["u_n"]) < 1e-8, flags
