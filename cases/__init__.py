@@ -399,6 +399,41 @@ def cylinder_oh(n_theta: int = 256, n_r: int = 128, n_out: int = 128, r_in: floa
                 n_steps)
 
 
+def segment_mask(dom: Domain, pick) -> np.ndarray:
+    """Boolean mask over the Dirichlet faces [NB]: True on the faces of every Dirichlet
+    segment whose index si in dom.sides satisfies pick(si)."""
+    mask = np.zeros(n_boundary_faces(dom), dtype=bool)
+    for si, off, n in dirichlet_segments(dom):
+        if pick(si):
+            mask[off:off + n] = True
+    return mask
+
+
+def open_channel(nx: int = 32, ny: int = 16, length: float = 4.0, u_in: float = 1.0,
+                 nu: float = 0.01, cfl: float = 0.5, beta: float = 1.2, n_steps: int = 16) -> Case:
+    """2D channel [0, length] x [0, 1]: parabolic inflow u = 4 u_in y (1 - y) on the
+    -x side, an advective outflow on the +x side (extra["outflow"], the face mask, and
+    extra["u_m"], the characteristic velocity), no-slip walls at y = 0, 1 with
+    tanh-clustered rows."""
+    xv = np.linspace(0.0, length, nx + 1)
+    yv = tanh_vertices(ny, beta, 0.0, 1.0)
+    T, J, c = tensor_metrics([xv, yv])
+    sides = [Side(0, 0, DIRICHLET), Side(0, 1, DIRICHLET), Side(0, 2, DIRICHLET), Side(0, 3, DIRICHLET)]
+    dom = Domain(2, [(nx, ny, 1)], sides, T, J, c)
+    yc = 0.5 * (yv[1:] + yv[:-1])
+    prof = 4.0 * u_in * yc * (1.0 - yc)
+    ub = np.zeros((2, n_boundary_faces(dom)))
+    for si, off, n in dirichlet_segments(dom):
+        if si in (0, 1):                 # -x inflow and +x outflow (initial value)
+            ub[0, off:off + n] = prof
+    u0 = np.zeros((2, dom.n_cells))
+    u0[0] = prof.repeat(nx)
+    outflow = segment_mask(dom, lambda si: si == 1)
+    dt = cfl * float(np.min(np.diff(xv))) / u_in
+    return Case("open_channel", dom, u0, np.zeros(dom.n_cells), np.zeros_like(u0), nu, dt, ub,
+                n_steps, extra={"outflow": outflow, "u_m": np.array([u_in, 0.0])})
+
+
 def random_fields(case: Case, seed: int, scale: float = 1.0):
     """Seeded random velocity/pressure/source/boundary perturbations of a case (tests)."""
     rng = np.random.default_rng(seed)
