@@ -25,30 +25,29 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-KRYLOV_SRC = os.path.join(ROOT, "paper_2505_16992_amd", "csrc", "piso_krylov.hip")
-COMMON_SRC = os.path.join(ROOT, "paper_2505_16992_amd", "csrc", "piso_common.h")
-COUNTERS = os.path.join(ROOT, "profiles", "k_cg_spmv_q_channel96_f32_counters.md")
+CSRC = os.path.join(ROOT, "paper_2505_16992_amd", "csrc")
+DIGEST_SOURCES = ["piso_common.h", "piso_quad.h", "piso_krylov.hip", "piso_mg.hip"]
 
 
 def kernel_digest():
-    """sha256 of the vectorised CG kernels' source (the quad section of the Krylov file
-    and the shared device header): counter figures are used only while it matches."""
+    """sha256 of the pressure-solver kernels' sources: counter figures recorded with a
+    digest are used only while it still matches."""
     import hashlib
-    with open(KRYLOV_SRC) as f:
-        txt = f.read()
-    a = txt.index("// ------------------------------------------------------------ quad fast path")
-    b = txt.index("// MIXED form:")
-    with open(COMMON_SRC) as f:
-        common = f.read()
-    return hashlib.sha256((txt[a:b] + common).encode()).hexdigest()
+    h = hashlib.sha256()
+    for name in DIGEST_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
-def counter_traffic(workload, precision):
-    """HBM bytes per launch of the stencil kernel from the committed counter summary."""
-    if workload != "channel96" or precision != "f32" or not os.path.exists(COUNTERS):
+def counter_traffic(kernel, workload, precision):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if one was
+    taken for this workload with the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_%s_counters.md" % (kernel, workload, precision))
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(COUNTERS) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
@@ -233,22 +232,48 @@ def main():
         tm = ctx.get_timing()
         ctx.set_timing(False)
         es = ctx.elem_bytes
-        spmv_bytes = N * (d + 5) * es           # Pf (d), r, Dinv, d_old -> d_new, q
-        upd_bytes = N * 7 * es                   # Dinv, x, r, d_new, q -> x, r
-        if tm["spmv_calls"]:
-            avg = tm["spmv_ms"] / tm["spmv_calls"]
-            ach = spmv_bytes / (avg * 1e-3) / 1e9
-            quad = all(b[0] % 4 == 0 for b in dom.blocks)
-            roof = {"bound": "hbm", "kernel": "k_cg_spmv_q" if quad else "k_cg_spmv", "achieved": round(ach, 1),
-                    "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
-                    "traffic": counter_traffic(args.workload, args.precision),
-                    "avg_launch_us": round(avg * 1e3, 3), "bytes_per_launch": spmv_bytes,
-                    "launches": tm["spmv_calls"]}
-            avg_u = tm["update_ms"] / max(tm["update_calls"], 1)
-            it_bytes = spmv_bytes + upd_bytes
-            pcg = {"kernels": ["k_cg_spmv_q", "k_cg_update_q"] if quad else ["k_cg_spmv", "k_cg_update"],
-                   "GBps": round(it_bytes / ((avg + avg_u) * 1e-3) / 1e9, 1),
-                   "update_avg_us": round(avg_u * 1e3, 3), "iter_bytes": it_bytes}
+        mg = opts.pres.precond == 1 and bool(ctx.mg_levels)
+        quad = all(b[0] % 4 == 0 for b in dom.blocks)
+        nch = 2 ** d
+        # algorithmic bytes per launch of each fine-grid kernel class (each stream once)
+        model = {
+            # Pf (d), operand (z, or r and Dinv), d_old -> d_new, q
+            "cg_stencil": ("k_cg_spmv_q" if quad else "k_cg_spmv", N * ((d + 4) if mg else (d + 5)) * es),
+            # x, r, d_new, q (+ Dinv) -> x, r
+            "cg_update": ("k_cg_update_q" if quad else "k_cg_update", N * (6 if mg else 7) * es),
+            # r, Dinv, Pf (d) -> level-1 residual
+            "mg_down0": ("k_mg_down0", N * (d + 2) * es + (N // nch) * es),
+            # r, Dinv, Pf (d), level-1 correction -> z
+            "mg_up0": ("k_mg_up0_q" if quad else "k_mg_up0", N * (d + 3) * es + (N // nch) * es),
+        }
+        per = {}
+        for k, (ms, n) in tm.items():
+            if n:
+                per[k] = {"avg_us": round(1e3 * ms / n, 3), "launches": n, "total_ms": round(ms, 3)}
+                if k in model:
+                    per[k]["kernel"] = model[k][0]
+                    per[k]["bytes_per_launch"] = model[k][1]
+                    per[k]["GBps"] = round(model[k][1] / (ms / n * 1e-3) / 1e9, 1)
+        fine = [k for k in model if k in per]
+        if fine:
+            dom_k = max(fine, key=lambda k: per[k]["total_ms"])
+            kname, kbytes = model[dom_k]
+            avg = tm[dom_k][0] / tm[dom_k][1]
+            ach = kbytes / (avg * 1e-3) / 1e9
+            roof = {"bound": "hbm", "kernel": kname, "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
+                    "traffic": counter_traffic(kname, args.workload, args.precision),
+                    "avg_launch_us": round(avg * 1e3, 3), "bytes_per_launch": kbytes,
+                    "launches": tm[dom_k][1]}
+            iters = tm["cg_stencil"][1]
+            it_ms = sum(ms for ms, _ in tm.values()) / max(iters, 1)
+            it_bytes = sum(model[k][1] * tm[k][1] for k in fine) / max(iters, 1)
+            pcg = {"preconditioner": "multigrid" if mg else "jacobi",
+                   "mg_levels": [n for n, _ in ctx.mg_levels] if mg else [],
+                   "iteration_us": round(1e3 * it_ms, 3),
+                   "fine_bytes_per_iteration": int(it_bytes),
+                   "GBps": round(it_bytes / (it_ms * 1e-3) / 1e9, 1),
+                   "kernels": per}
         log("timing %s" % tm)
 
     cpu = None

@@ -100,13 +100,24 @@ typedef struct {
   const double* J;                 /* host [N]: det(d x / d xi) > 0 (cell volume) */
 } piso_domain_desc;
 
+/* Preconditioner of a Krylov solve (piso_solve_opts.precond). */
+typedef enum {
+  PISO_PRECOND_JACOBI = 0,  /* diagonal scaling (pressure CG and velocity BiCGStab) */
+  PISO_PRECOND_MG = 1       /* pressure CG only: one V-cycle of aggregation multigrid per
+                               iteration (2^d cells per aggregate inside each block, Galerkin
+                               coarse operators, damped Jacobi smoothing).  The paper names
+                               multigrid for the pressure as the way to a faster solver
+                               (Sec. 6, App. A.6); the converged solution is the same. */
+} piso_precond;
+
 typedef struct {
   double rtol;                     /* stop when ||b - M x||_2 <= rtol ||b||_2 (per component) */
   int32_t max_iter;                /* Krylov iterations (MIXED pressure: inner iterations per sweep) */
   int32_t check_every;             /* iterations between convergence read-backs */
   double inner_rtol;               /* MIXED pressure only: inner float PCG tolerance */
   int32_t max_refine;              /* MIXED pressure only: refinement sweeps */
-  int32_t reserved;
+  int32_t precond;                 /* piso_precond; PISO_PRECOND_MG is accepted for the pressure
+                                      only (PISO_E_ARG for the velocity solve) */
 } piso_solve_opts;
 
 typedef struct {
@@ -168,8 +179,15 @@ const char* piso_create_error(void);
 int piso_sizes(const piso_ctx* ctx, int64_t* n_cells, int64_t* n_bfaces, int64_t* tape_bytes,
                int64_t* elem_bytes, int32_t* non_orthogonal);
 
-/* Default options for a precision: vel rtol 1e-10 (F64) / 1e-7, pres rtol 1e-10 (F64),
- * 1e-6 (F32), 1e-8 (MIXED, inner 5e-5), 2 correctors, grad_p_in_predictor = 1. */
+/* Shape of the multigrid hierarchy of the pressure preconditioner, built in piso_create:
+ * n_levels coarse levels (0 when the grid cannot be coarsened: PISO_PRECOND_MG then
+ * runs as Jacobi), and for level l = 1 .. n_levels the cell count cells[l-1] and graph
+ * slots per cell slots[l-1] (host arrays of at least 16 entries, may be NULL). */
+int piso_mg_info(const piso_ctx* ctx, int32_t* n_levels, int64_t* cells, int32_t* slots);
+
+/* Default options for a precision: vel rtol 1e-10 (F64) / 1e-7, Jacobi; pres rtol 1e-10
+ * (F64), 1e-6 (F32), 1e-8 (MIXED, inner 5e-5), multigrid-preconditioned, read back every
+ * 4 iterations; 2 correctors, grad_p_in_predictor = 1. */
 void piso_default_step_opts(int32_t precision, piso_step_opts* opts);
 
 /* Predictor assembly (App. A.3.3-A.3.5, eqs. advMatDiscrete, difMatDiscrete,
@@ -188,8 +206,9 @@ int piso_solve_velocity(piso_ctx* ctx, void* stream, const piso_system* sys, voi
 
 /* Pressure corrector: h = A^-1 (b_u - H u_in) (eq. pressureRHS), rhs = div h + Dirichlet
  * face flux + deferred non-orthogonal term of p_lag (eqs. pressureRHSdivDiscrete,
- * pressureRHSnonOrtho), then the zero-mean solution of P p = rhs - mean(rhs) by Jacobi
- * PCG on -P (App. A.6: CG) from x0 = p (in).  Writes sys->h, sys->rhs and p. */
+ * pressureRHSnonOrtho), then the zero-mean solution of P p = rhs - mean(rhs) by PCG on
+ * -P (App. A.6: CG; opts->precond: Jacobi or multigrid) from x0 = p (in).  Writes
+ * sys->h, sys->rhs and p. */
 int piso_solve_pressure(piso_ctx* ctx, void* stream, const piso_system* sys, const void* u_in,
                         const void* u_b, const void* p_lag, void* p, const piso_solve_opts* opts,
                         piso_solve_info* info);
@@ -253,12 +272,67 @@ int piso_step_backward(piso_ctx* ctx, void* stream, const void* tape, const void
                        void* dS, void* dnu, void* du_b, const piso_step_opts* opts,
                        piso_step_info* info);
 
-/* Diagnostics used by tests and benchmarks. */
-/* Last solve's kernel launch counts and the average duration of the pressure PCG
- * kernels measured with HIP events on the call's stream when timing is enabled. */
+/* Advective outflow boundary (App. A.4, eq. advOut), applied between steps: on the
+ * Dirichlet faces with outflow[f] != 0 (device int32 [NB]) the value is advanced
+ * implicitly and upwind from the face's boundary cell P,
+ *     u_b* = (u_b + c u_P) / (1 + c),   c = 2 dt |T_j(P) . u_m|   (j: the face's axis),
+ * with u_m the characteristic velocity (host [d]); then every outflow value is scaled
+ * by s = -Q_rest / Q_out so that the net boundary flux sum_f N_f J_P T_j(P) . u_b (the
+ * Dirichlet flux of the pressure right-hand side; N_f = +1 on high sides) vanishes
+ * (s = 1 if Q_out = 0).  Faces without the flag keep their value.  The printed update
+ * factor has the opposite sign inside its fraction, which would be anti-upwind for an
+ * outflow; this is the upwind reading.  u_n [d][N], u_b and u_b_out [d][NB] (may be the
+ * same buffer).  Deterministic. */
+int piso_outflow_update(piso_ctx* ctx, void* stream, const void* u_n, const void* u_b,
+                        const int32_t* outflow, const double* u_m, double dt, void* u_b_out);
+
+/* Adjoint of piso_outflow_update for the gradient du_b_out of u_b_out: writes du_b
+ * [d][NB] and ADDS the gradient with respect to u_n into du_n [d][N] (may be NULL to
+ * skip it).  du_b must not alias du_b_out. */
+int piso_outflow_update_backward(piso_ctx* ctx, void* stream, const void* u_n, const void* u_b,
+                                 const int32_t* outflow, const double* u_m, double dt,
+                                 const void* du_b_out, void* du_n, void* du_b);
+
+/* Online turbulence statistics over homogeneous planes (Sec. 2.5), for single-block
+ * contexts (PISO_E_ARG otherwise).  The planes are normal to `axis` (0 .. d-1); every
+ * accumulated step adds its cells' d velocity components to their plane.  The state is
+ * a caller-owned device array of n_planes records of record_len doubles,
+ * [n, mu_0 .. mu_{d-1}, C_ij for i <= j (row-major)]: sample count, mean and central
+ * comoment sums; all zeros is the empty state.  piso_stats_size gives both sizes. */
+int piso_stats_size(const piso_ctx* ctx, int32_t axis, int64_t* n_planes, int64_t* record_len);
+
+/* Merge one field u [d][N] into the state: per plane, the step's mean and central sums
+ * are taken in two passes and merged with the pairwise update for central comoments
+ * (no raw second moments).  Deterministic. */
+int piso_stats_accumulate(piso_ctx* ctx, void* stream, const void* u, int32_t axis, double* state);
+
+/* mean [n_planes][d] and population covariance C / n [n_planes][d(d+1)/2] (i <= j,
+ * row-major), device doubles. */
+int piso_stats_finalize(piso_ctx* ctx, void* stream, int32_t axis, const double* state, double* mean,
+                        double* cov);
+
+/* For a non-empty final state and the gradients mean_bar, cov_bar of the finalized
+ * statistics, ADDS to du [d][N] the gradient with respect to one accumulated field u:
+ * mean_bar_k / n + sum_{i<=j} cov_bar_ij (delta_ik (u_j - mu_j) + delta_jk (u_i - mu_i)) / n. */
+int piso_stats_backward(piso_ctx* ctx, void* stream, const void* u, int32_t axis, const double* state,
+                        const double* mean_bar, const double* cov_bar, void* du);
+
+/* Diagnostics used by tests and benchmarks.  While timing is enabled, the pressure
+ * solver's kernels are launched with HIP events attached to the dispatch
+ * (hipExtLaunchKernelGGL) and their durations summed per kernel class; enabling resets
+ * the sums.  Timing adds host work per launch: leave it off outside measurements. */
+typedef enum {
+  PISO_TIME_CG_STENCIL = 0,  /* PCG direction update and stencil product q = M d */
+  PISO_TIME_CG_UPDATE = 1,   /* PCG x, r update */
+  PISO_TIME_MG_DOWN0 = 2,    /* multigrid restriction from the fine grid */
+  PISO_TIME_MG_UP0 = 3,      /* multigrid prolongation and smoothing on the fine grid */
+  PISO_TIME_MG_COARSE = 4,   /* multigrid kernels on the coarse levels */
+  PISO_TIME_KINDS = 5
+} piso_time_kind;
+
 int piso_set_timing(piso_ctx* ctx, int32_t enable);
-int piso_get_timing(piso_ctx* ctx, double* cg_spmv_ms, double* cg_update_ms, int64_t* cg_spmv_calls,
-                    int64_t* cg_update_calls);
+/* Total milliseconds and launch count of one kernel class since timing was enabled. */
+int piso_get_timing(piso_ctx* ctx, int32_t kind, double* ms, int64_t* calls);
 
 #ifdef __cplusplus
 }

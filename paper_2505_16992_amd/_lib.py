@@ -17,6 +17,8 @@ PISO_F64, PISO_F32, PISO_MIXED = 0, 1, 2
 PISO_OK, PISO_NOT_CONVERGED, PISO_BREAKDOWN = 0, 1, 2
 PISO_E_ARG, PISO_E_TOPOLOGY, PISO_E_HIP, PISO_E_NAN, PISO_E_OOM = -1, -2, -3, -4, -5
 PISO_SIDE_CONNECT, PISO_SIDE_DIRICHLET = 0, 1
+PISO_PRECOND_JACOBI, PISO_PRECOND_MG = 0, 1
+TIME_KINDS = ("cg_stencil", "cg_update", "mg_down0", "mg_up0", "mg_coarse")
 
 
 class SideDesc(C.Structure):
@@ -33,7 +35,7 @@ class DomainDesc(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int32), ("check_every", C.c_int32),
-                ("inner_rtol", C.c_double), ("max_refine", C.c_int32), ("reserved", C.c_int32)]
+                ("inner_rtol", C.c_double), ("max_refine", C.c_int32), ("precond", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -77,6 +79,7 @@ _SIGS = {
     "piso_create_error": (C.c_char_p, []),
     "piso_sizes": (I32, [VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                          C.POINTER(C.c_int64), C.POINTER(I32)]),
+    "piso_mg_info": (I32, [VP, C.POINTER(I32), C.POINTER(C.c_int64), C.POINTER(I32)]),
     "piso_default_step_opts": (None, [I32, C.POINTER(StepOpts)]),
     "piso_assemble": (I32, [VP, VP, VP, VP, VP, I32, VP, VP, F64, I32, C.POINTER(System)]),
     "piso_solve_velocity": (I32, [VP, VP, C.POINTER(System), VP, C.POINTER(SolveOpts),
@@ -96,9 +99,14 @@ _SIGS = {
                                      VP, VP, VP, VP]),
     "piso_step_backward": (I32, [VP, VP, VP, VP, VP, VP, I32, VP, F64, VP, VP, VP, VP, VP, VP, VP,
                                  C.POINTER(StepOpts), C.POINTER(StepInfo)]),
+    "piso_outflow_update": (I32, [VP, VP, VP, VP, VP, C.POINTER(F64), F64, VP]),
+    "piso_outflow_update_backward": (I32, [VP, VP, VP, VP, VP, C.POINTER(F64), F64, VP, VP, VP]),
+    "piso_stats_size": (I32, [VP, I32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "piso_stats_accumulate": (I32, [VP, VP, VP, I32, VP]),
+    "piso_stats_finalize": (I32, [VP, VP, I32, VP, VP, VP]),
+    "piso_stats_backward": (I32, [VP, VP, VP, I32, VP, VP, VP, VP]),
     "piso_set_timing": (I32, [VP, I32]),
-    "piso_get_timing": (I32, [VP, C.POINTER(F64), C.POINTER(F64), C.POINTER(C.c_int64),
-                              C.POINTER(C.c_int64)]),
+    "piso_get_timing": (I32, [VP, I32, C.POINTER(F64), C.POINTER(C.c_int64)]),
 }
 
 

@@ -82,6 +82,10 @@ class Context:
         self.lib.piso_sizes(h, C.byref(n), C.byref(nb), C.byref(tb), C.byref(eb), C.byref(no))
         self.N, self.NB, self.tape_bytes, self.elem_bytes = n.value, nb.value, tb.value, eb.value
         self.non_orthogonal = bool(no.value)
+        nl = C.c_int32()
+        cells_l, slots_l = (C.c_int64 * 16)(), (C.c_int32 * 16)()
+        self.lib.piso_mg_info(h, C.byref(nl), cells_l, slots_l)
+        self.mg_levels = [(int(cells_l[q]), int(slots_l[q])) for q in range(nl.value)]
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -250,14 +254,89 @@ class Context:
         return self._check(rc, "piso_assemble_backward")
 
     # ---------------------------------------------------------------- diagnostics
+    def outflow_mask(self, mask):
+        """Device int32 [NB] outflow flags from a boolean/integer array."""
+        m = torch.as_tensor(np.asarray(mask).astype(np.int32), device=self.device)
+        if tuple(m.shape) != (self.NB,):
+            raise ValueError("outflow mask must have shape (%d,)" % self.NB)
+        return m.contiguous()
+
+    def _mask(self, mask):
+        if mask.device != self.device or mask.dtype != torch.int32 or tuple(mask.shape) != (self.NB,):
+            raise ValueError("outflow mask must be an int32 tensor of shape (%d,) on %s" % (self.NB, self.device))
+        return mask.contiguous()
+
+    def outflow_update(self, u, u_b, mask, u_m, dt, out=None):
+        """Advective outflow update of the Dirichlet values before a step."""
+        d, N = self.dim, self.N
+        self._t(u, (d, N), "u")
+        ub = self._t(u_b, (d, self.NB), "u_b")
+        m = self._mask(mask)
+        um = (C.c_double * 3)(*[float(x) for x in list(u_m)[:d]])
+        out = torch.empty_like(ub) if out is None else self._t(out, (d, self.NB), "out")
+        self._check(self.lib.piso_outflow_update(self.h, _stream(), _ptr(u), _ptr(ub), _ptr(m), um, float(dt),
+                                                 _ptr(out)), "piso_outflow_update")
+        return out
+
+    def outflow_update_backward(self, u, u_b, mask, u_m, dt, dub_out, du=None):
+        """(du_b, du) for the gradient dub_out of the updated values; du (if given) is
+        accumulated into, else a new tensor is returned."""
+        d, N = self.dim, self.N
+        m = self._mask(mask)
+        um = (C.c_double * 3)(*[float(x) for x in list(u_m)[:d]])
+        g = self._t(dub_out.contiguous(), (d, self.NB), "dub_out")
+        dub = torch.empty_like(g)
+        du = self.zeros(d, N) if du is None else self._t(du, (d, N), "du")
+        self._check(self.lib.piso_outflow_update_backward(self.h, _stream(), _ptr(u), _ptr(u_b), _ptr(m), um,
+                                                          float(dt), _ptr(g), _ptr(du), _ptr(dub)),
+                    "piso_outflow_update_backward")
+        return dub, du
+
+    # ---------------------------------------------------------------- statistics
+    def stats_size(self, axis=1):
+        n, r = C.c_int64(), C.c_int64()
+        self._check(self.lib.piso_stats_size(self.h, int(axis), C.byref(n), C.byref(r)), "piso_stats_size")
+        return n.value, r.value
+
+    def stats_state(self, axis=1):
+        """Empty statistics state (device float64)."""
+        n, r = self.stats_size(axis)
+        return torch.zeros(n, r, dtype=torch.float64, device=self.device)
+
+    def stats_accumulate(self, u, state, axis=1):
+        self._t(u, (self.dim, self.N), "u")
+        self._check(self.lib.piso_stats_accumulate(self.h, _stream(), _ptr(u), int(axis), _ptr(state)),
+                    "piso_stats_accumulate")
+        return state
+
+    def stats_finalize(self, state, axis=1):
+        n, _ = self.stats_size(axis)
+        npair = self.dim * (self.dim + 1) // 2
+        mean = torch.empty(n, self.dim, dtype=torch.float64, device=self.device)
+        cov = torch.empty(n, npair, dtype=torch.float64, device=self.device)
+        self._check(self.lib.piso_stats_finalize(self.h, _stream(), int(axis), _ptr(state), _ptr(mean), _ptr(cov)),
+                    "piso_stats_finalize")
+        return mean, cov
+
+    def stats_backward(self, u, state, mean_bar, cov_bar, axis=1, du=None):
+        du = self.zeros(self.dim, self.N) if du is None else self._t(du, (self.dim, self.N), "du")
+        mb = mean_bar.to(torch.float64).contiguous()
+        cb = cov_bar.to(torch.float64).contiguous()
+        self._check(self.lib.piso_stats_backward(self.h, _stream(), _ptr(u), int(axis), _ptr(state), _ptr(mb),
+                                                 _ptr(cb), _ptr(du)), "piso_stats_backward")
+        return du
+
     def set_timing(self, enable: bool):
         self.lib.piso_set_timing(self.h, int(enable))
 
     def get_timing(self):
-        a, b = C.c_double(), C.c_double()
-        n1, n2 = C.c_int64(), C.c_int64()
-        self.lib.piso_get_timing(self.h, C.byref(a), C.byref(b), C.byref(n1), C.byref(n2))
-        return {"spmv_ms": a.value, "update_ms": b.value, "spmv_calls": n1.value, "update_calls": n2.value}
+        """{kernel class: (total ms, launches)} since timing was enabled."""
+        out = {}
+        for k, name in enumerate(L.TIME_KINDS):
+            ms, n = C.c_double(), C.c_int64()
+            self._check(self.lib.piso_get_timing(self.h, k, C.byref(ms), C.byref(n)), "piso_get_timing")
+            out[name] = (ms.value, n.value)
+        return out
 
 
 # ===================================================================== autograd
@@ -328,33 +407,144 @@ class _Segment(torch.autograd.Function):
         return None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), dub
 
 
+class OutflowUpdate(torch.autograd.Function):
+    """Differentiable advective outflow update (u, u_b) -> u_b' applied before a step."""
+
+    @staticmethod
+    def forward(fctx, pctx: Context, mask, u_m, dt, u, u_b):
+        fctx.pctx, fctx.mask, fctx.u_m, fctx.dt = pctx, mask, u_m, dt
+        fctx.save_for_backward(u, u_b)
+        return pctx.outflow_update(u, u_b, mask, u_m, dt)
+
+    @staticmethod
+    def backward(fctx, dub_out):
+        u, u_b = fctx.saved_tensors
+        dub, du = fctx.pctx.outflow_update_backward(u, u_b, fctx.mask, fctx.u_m, fctx.dt, dub_out)
+        return None, None, None, None, du, dub
+
+
+class _OutflowSegment(torch.autograd.Function):
+    """k checkpointed steps, each preceded by the outflow update of the boundary
+    values: (u, p, S, nu, u_b) -> (u^{n+k}, p^{n+k}, u_b^{n+k})."""
+
+    @staticmethod
+    def forward(fctx, pctx: Context, opts, dt, k, mask, u_m, u, p, S, nu, u_b):
+        uu, pp, bb = u, p, u_b
+        for _ in range(k):
+            bb = pctx.outflow_update(uu, bb, mask, u_m, dt)
+            uu, pp = pctx.step(uu, pp, nu, S, bb, dt, opts)
+        fctx.pctx, fctx.opts, fctx.dt, fctx.k, fctx.mask, fctx.u_m = pctx, opts, dt, k, mask, u_m
+        fctx.save_for_backward(u, p, S, nu, u_b)
+        return uu, pp, bb
+
+    @staticmethod
+    def backward(fctx, du, dp, dbb):
+        u, p, S, nu, u_b = fctx.saved_tensors
+        pctx, opts, dt, k, mask, u_m = fctx.pctx, fctx.opts, fctx.dt, fctx.k, fctx.mask, fctx.u_m
+        states, tapes, used = [(u, p, u_b)], [], []
+        uu, pp, bb = u, p, u_b
+        for _ in range(k):
+            nb = pctx.outflow_update(uu, bb, mask, u_m, dt)
+            t = pctx.new_tape()
+            uu, pp = pctx.step(uu, pp, nu, S, nb, dt, opts, tape=t)
+            used.append(nb)
+            states.append((uu, pp, nb))
+            tapes.append(t)
+            bb = nb
+        dS = torch.zeros_like(S)
+        dnu = torch.zeros_like(nu.reshape(-1))
+        gu, gp = du, dp
+        gb = dbb.contiguous() if dbb is not None else torch.zeros_like(u_b)
+        for q in range(k - 1, -1, -1):
+            un, pn, bprev = states[q]
+            g = pctx.step_backward(tapes[q], un, pn, nu, used[q], dt, gu, gp, opts)
+            dS += g["S"]
+            dnu += g["nu"]
+            gb_used = g["u_b"] + gb
+            gb, gu = pctx.outflow_update_backward(un, bprev, mask, u_m, dt, gb_used, du=g["u"])
+            gp = g["p"]
+            tapes[q] = None
+        return None, None, None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), gb
+
+
+class PlaneStatistics(torch.autograd.Function):
+    """Mean [n_planes, d] and covariance [n_planes, d(d+1)/2] of fields accumulated over
+    homogeneous planes (online merging in the library), differentiable with respect to
+    every field."""
+
+    @staticmethod
+    def forward(fctx, pctx: Context, axis, *us):
+        state = pctx.stats_state(axis)
+        for u in us:
+            pctx.stats_accumulate(u, state, axis)
+        mean, cov = pctx.stats_finalize(state, axis)
+        fctx.pctx, fctx.axis = pctx, axis
+        fctx.save_for_backward(state, *us)
+        return mean, cov
+
+    @staticmethod
+    def backward(fctx, mbar, cbar):
+        state, *us = fctx.saved_tensors
+        pctx = fctx.pctx
+        mbar = torch.zeros_like(state[:, 1:1 + pctx.dim]) if mbar is None else mbar
+        npair = pctx.dim * (pctx.dim + 1) // 2
+        cbar = torch.zeros(state.shape[0], npair, dtype=torch.float64, device=state.device) if cbar is None else cbar
+        grads = [pctx.stats_backward(u, state, mbar, cbar, fctx.axis) for u in us]
+        return (None, None, *grads)
+
+
+def plane_statistics(pctx: Context, us, axis=1):
+    """(mean, cov) over the fields `us` (list of [d, N] tensors)."""
+    return PlaneStatistics.apply(pctx, axis, *us)
+
+
 def step(pctx: Context, u, p, S, nu, u_b, dt, opts=None):
     """Differentiable single step (keeps its tape until backward)."""
     return PisoStep.apply(pctx, opts if opts is not None else pctx.default_opts(), dt, u, p, S, nu, u_b)
 
 
 def rollout(pctx: Context, u0, p0, S, nu, u_b, dt, n_steps: int, checkpoint_every: int = 0, opts=None,
-            warmup: int = 0, return_all: bool = False):
+            warmup: int = 0, return_all: bool = False, outflow=None):
     """n_steps differentiable steps.  checkpoint_every = 0 keeps every tape; k > 0
     stores only the state at the start of each k-step segment and recomputes the
-    segment's tapes in the backward.  warmup steps run first without a tape."""
+    segment's tapes in the backward.  warmup steps run first without a tape.
+
+    outflow = (mask, u_m): before every step the Dirichlet values of the masked faces
+    are advanced by the advective outflow update (the boundary values then become part
+    of the state; the result gains a third entry, the final u_b)."""
     o = opts if opts is not None else pctx.default_opts()
-    u, p = u0, p0
+    u, p, ub = u0, p0, u_b
+    if outflow is not None:
+        mask, u_m = outflow
+        mask = pctx._mask(mask)
     if warmup:
         with torch.no_grad():
+            ub = None if ub is None else ub.detach()
             for _ in range(warmup):
-                u, p = pctx.step(u.detach(), p.detach(), nu.detach(), S.detach(),
-                                 None if u_b is None else u_b.detach(), dt, o)
+                if outflow is not None:
+                    ub = pctx.outflow_update(u.detach(), ub, mask, u_m, dt)
+                u, p = pctx.step(u.detach(), p.detach(), nu.detach(), S.detach(), ub, dt, o)
     traj = []
     done = 0
     while done < n_steps:
-        if checkpoint_every > 0:
+        if outflow is not None:
+            if checkpoint_every > 0:
+                k = min(checkpoint_every, n_steps - done)
+                u, p, ub = _OutflowSegment.apply(pctx, o, dt, k, mask, u_m, u, p, S, nu, ub)
+                done += k
+            else:
+                ub = OutflowUpdate.apply(pctx, mask, u_m, dt, u, ub)
+                u, p = PisoStep.apply(pctx, o, dt, u, p, S, nu, ub)
+                done += 1
+        elif checkpoint_every > 0:
             k = min(checkpoint_every, n_steps - done)
-            u, p = _Segment.apply(pctx, o, dt, k, u, p, S, nu, u_b)
+            u, p = _Segment.apply(pctx, o, dt, k, u, p, S, nu, ub)
             done += k
         else:
-            u, p = PisoStep.apply(pctx, o, dt, u, p, S, nu, u_b)
+            u, p = PisoStep.apply(pctx, o, dt, u, p, S, nu, ub)
             done += 1
         if return_all:
-            traj.append((u, p))
-    return traj if return_all else (u, p)
+            traj.append((u, p) if outflow is None else (u, p, ub))
+    if return_all:
+        return traj
+    return (u, p) if outflow is None else (u, p, ub)

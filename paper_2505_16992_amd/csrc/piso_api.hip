@@ -29,34 +29,9 @@ void tangential_extent(const int n[3], int side, int dim, int& t0n, int& t1n) {
   t1n = e[1];
 }
 
-void magic(uint32_t d, uint32_t& lo, uint32_t& hi, int& shift) {
-  int l = 0;
-  while ((1ull << l) < d) ++l;
-  const uint64_t num = 1ull << (31 + l);
-  const uint64_t m = (num + d - 1) / d;
-  lo = (uint32_t)(m & 0xffffffffu);
-  hi = (uint32_t)(m >> 32);
-  shift = 31 + l;
-}
-
 template <typename R>
 std::vector<R> convert(const std::vector<double>& v) {
   return std::vector<R>(v.begin(), v.end());
-}
-
-int dev_alloc(piso_ctx* c, void** p, size_t bytes) {
-  if (bytes == 0) bytes = 256;
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) return fail(c, PISO_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
-  c->allocs.push_back(*p);
-  return PISO_OK;
-}
-
-template <typename T>
-int upload(piso_ctx* c, void** dst, const std::vector<T>& v) {
-  if (int rc = dev_alloc(c, dst, v.size() * sizeof(T))) return rc;
-  PISO_HIP(c, hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-  return PISO_OK;
 }
 
 // Build the block table and the per-side face map; validates coverage, ranges,
@@ -90,9 +65,9 @@ int build_topology(piso_ctx* c, const piso_domain_desc* d) {
     }
     uint32_t lo, hi;
     int sh;
-    magic((uint32_t)n[b][0], lo, hi, sh);
+    div_magic((uint32_t)n[b][0], lo, hi, sh);
     t[10] = (int)lo; t[11] = (int)hi; t[12] = sh;
-    magic((uint32_t)(n[b][0] * n[b][1]), lo, hi, sh);
+    div_magic((uint32_t)(n[b][0] * n[b][1]), lo, hi, sh);
     t[13] = (int)lo; t[14] = (int)hi; t[15] = sh;
   }
   c->h_fmap.assign((size_t)fm, INT_MIN);
@@ -561,6 +536,8 @@ int piso_create(const piso_domain_desc* desc, int32_t precision, piso_ctx** out)
   if (!rc) rc = upload(c, (void**)&c->d_fmap, c->h_fmap);
   if (!rc) rc = precision == PISO_F64 ? upload_metrics<double>(c, desc) : upload_metrics<float>(c, desc);
   if (!rc) rc = alloc_workspaces(c);
+  if (!rc) rc = mg_build(c);
+  if (!rc) rc = outflow_build(c);
   if (rc) {
     g_create_error = c->err;
     piso_destroy(c);
@@ -605,6 +582,16 @@ int piso_sizes(const piso_ctx* c, int64_t* n_cells, int64_t* n_bfaces, int64_t* 
   return PISO_OK;
 }
 
+int piso_mg_info(const piso_ctx* c, int32_t* n_levels, int64_t* cells, int32_t* slots) {
+  if (!c) return PISO_E_ARG;
+  if (n_levels) *n_levels = (int32_t)c->mg.size();
+  for (size_t l = 0; l < c->mg.size(); ++l) {
+    if (cells) cells[l] = c->mg[l].n;
+    if (slots) slots[l] = c->mg[l].K;
+  }
+  return PISO_OK;
+}
+
 void piso_default_step_opts(int32_t precision, piso_step_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
@@ -613,7 +600,9 @@ void piso_default_step_opts(int32_t precision, piso_step_opts* o) {
   o->vel.check_every = 4;
   o->pres.rtol = precision == PISO_F64 ? 1e-10 : (precision == PISO_MIXED ? 1e-8 : 1e-6);
   o->pres.max_iter = 20000;
-  o->pres.check_every = 16;
+  o->pres.check_every = 4;
+  o->pres.precond = PISO_PRECOND_MG;
+  o->vel.precond = PISO_PRECOND_JACOBI;
   o->pres.inner_rtol = 5e-5;
   o->pres.max_refine = 20;
   o->vel.inner_rtol = 1e-3;
@@ -832,21 +821,88 @@ int piso_step_backward(piso_ctx* c, void* stream, const void* tape, const void* 
 #undef ARGS
 }
 
-int piso_set_timing(piso_ctx* c, int32_t enable) {
+int piso_outflow_update(piso_ctx* c, void* stream, const void* u_n, const void* u_b, const int32_t* outflow,
+                        const double* u_m, double dt, void* u_b_out) {
+  CTX_ENTER();
+  REQUIRE(u_n && outflow && u_m, "piso_outflow_update: null pointer");
+  REQUIRE(c->NB == 0 || (u_b && u_b_out), "piso_outflow_update: u_b and u_b_out required");
+  REQUIRE(dt > 0 && std::isfinite(dt), "piso_outflow_update: dt must be positive");
+  OutflowUm um{};
+  for (int i = 0; i < c->dim; ++i) {
+    REQUIRE(std::isfinite(u_m[i]), "piso_outflow_update: u_m must be finite");
+    um.v[i] = u_m[i];
+  }
+  return DISPATCH_R(outflow_update<double>(c, s, (const double*)u_n, (const double*)u_b, outflow, um, dt,
+                                           (double*)u_b_out),
+                    outflow_update<float>(c, s, (const float*)u_n, (const float*)u_b, outflow, um, dt,
+                                          (float*)u_b_out));
+}
+
+int piso_outflow_update_backward(piso_ctx* c, void* stream, const void* u_n, const void* u_b,
+                                 const int32_t* outflow, const double* u_m, double dt, const void* du_b_out,
+                                 void* du_n, void* du_b) {
+  CTX_ENTER();
+  REQUIRE(u_n && outflow && u_m, "piso_outflow_update_backward: null pointer");
+  REQUIRE(c->NB == 0 || (u_b && du_b_out && du_b), "piso_outflow_update_backward: boundary arrays required");
+  REQUIRE(du_b != du_b_out || c->NB == 0, "piso_outflow_update_backward: du_b must not alias du_b_out");
+  REQUIRE(dt > 0 && std::isfinite(dt), "piso_outflow_update_backward: dt must be positive");
+  OutflowUm um{};
+  for (int i = 0; i < c->dim; ++i) {
+    REQUIRE(std::isfinite(u_m[i]), "piso_outflow_update_backward: u_m must be finite");
+    um.v[i] = u_m[i];
+  }
+  return DISPATCH_R(outflow_update_bwd<double>(c, s, (const double*)u_n, (const double*)u_b, outflow, um, dt,
+                                               (const double*)du_b_out, (double*)du_n, (double*)du_b),
+                    outflow_update_bwd<float>(c, s, (const float*)u_n, (const float*)u_b, outflow, um, dt,
+                                              (const float*)du_b_out, (float*)du_n, (float*)du_b));
+}
+
+int piso_stats_size(const piso_ctx* c, int32_t axis, int64_t* n_planes, int64_t* record_len) {
   if (!c) return PISO_E_ARG;
-  c->timing.enabled = enable != 0;
-  c->timing.spmv_ms = c->timing.update_ms = 0.0;
-  c->timing.spmv_calls = c->timing.update_calls = 0;
-  c->timing.used = 0;
+  int np, m;
+  if (stats_planes(c, axis, &np, &m)) return PISO_E_ARG;
+  if (n_planes) *n_planes = np;
+  if (record_len) *record_len = 1 + c->dim + c->dim * (c->dim + 1) / 2;
   return PISO_OK;
 }
 
-int piso_get_timing(piso_ctx* c, double* spmv_ms, double* update_ms, int64_t* spmv_calls, int64_t* update_calls) {
+int piso_stats_accumulate(piso_ctx* c, void* stream, const void* u, int32_t axis, double* state) {
+  CTX_ENTER();
+  REQUIRE(u && state, "piso_stats_accumulate: null pointer");
+  return DISPATCH_R(stats_accumulate<double>(c, s, (const double*)u, axis, state),
+                    stats_accumulate<float>(c, s, (const float*)u, axis, state));
+}
+
+int piso_stats_finalize(piso_ctx* c, void* stream, int32_t axis, const double* state, double* mean, double* cov) {
+  CTX_ENTER();
+  REQUIRE(state && mean && cov, "piso_stats_finalize: null pointer");
+  return stats_finalize(c, s, axis, state, mean, cov);
+}
+
+int piso_stats_backward(piso_ctx* c, void* stream, const void* u, int32_t axis, const double* state,
+                        const double* mean_bar, const double* cov_bar, void* du) {
+  CTX_ENTER();
+  REQUIRE(u && state && mean_bar && cov_bar && du, "piso_stats_backward: null pointer");
+  return DISPATCH_R(stats_backward<double>(c, s, (const double*)u, axis, state, mean_bar, cov_bar, (double*)du),
+                    stats_backward<float>(c, s, (const float*)u, axis, state, mean_bar, cov_bar, (float*)du));
+}
+
+int piso_set_timing(piso_ctx* c, int32_t enable) {
   if (!c) return PISO_E_ARG;
-  if (spmv_ms) *spmv_ms = c->timing.spmv_ms;
-  if (update_ms) *update_ms = c->timing.update_ms;
-  if (spmv_calls) *spmv_calls = c->timing.spmv_calls;
-  if (update_calls) *update_calls = c->timing.update_calls;
+  c->timing.enabled = enable != 0;
+  for (int k = 0; k < kTimeKinds; ++k) {
+    c->timing.ms[k] = 0.0;
+    c->timing.calls[k] = 0;
+  }
+  c->timing.used = 0;
+  c->timing.kinds.clear();
+  return PISO_OK;
+}
+
+int piso_get_timing(piso_ctx* c, int32_t kind, double* ms, int64_t* calls) {
+  if (!c || kind < 0 || kind >= kTimeKinds) return PISO_E_ARG;
+  if (ms) *ms = c->timing.ms[kind];
+  if (calls) *calls = c->timing.calls[kind];
   return PISO_OK;
 }
 

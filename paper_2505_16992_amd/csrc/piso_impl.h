@@ -3,6 +3,7 @@
 // piso_krylov.hip and piso_bwd.hip.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -37,13 +38,46 @@ constexpr int kPart3 = 13;       // BiCGStab: rh.r, r.r (+ b.b)    (9)
 constexpr int kPartS = 22;       // one-shot sums                  (2)
 constexpr int kPartRegions = 24;
 
+// Kernel classes of the solver timing (piso_get_timing).
+constexpr int kTimeCgStencil = 0;   // PCG stencil kernel (direction update and M d)
+constexpr int kTimeCgUpdate = 1;    // PCG x, r update
+constexpr int kTimeMgDown0 = 2;     // multigrid restriction from the fine grid
+constexpr int kTimeMgUp0 = 3;       // multigrid prolongation and smoothing on the fine grid
+constexpr int kTimeMgCoarse = 4;    // multigrid kernels on the coarse levels
+constexpr int kTimeKinds = 5;
+
 struct Timing {
   bool enabled = false;
-  double spmv_ms = 0.0, update_ms = 0.0;
-  long long spmv_calls = 0, update_calls = 0;
+  double ms[kTimeKinds] = {};
+  long long calls[kTimeKinds] = {};
   std::vector<hipEvent_t> ev;   // pool: pairs around each timed launch
+  std::vector<int> kinds;       // kind of each recorded pair
   size_t used = 0;
 };
+
+// One coarse level of the aggregation multigrid preconditioner of the pressure
+// solve.  Level 0 is the fine grid itself (face coefficients Pf, Jacobi scale Dinv);
+// level l >= 1 aggregates 2^d cells of level l-1 (2 per axis inside each block) and
+// carries its operator as a graph: slot s of cell I joins I to nbr[s][I] with face
+// weight W[s][I] (both directions stored), the Galerkin sum of the finer level's face
+// weights between the two aggregates.
+struct MgLevel {
+  int n = 0, K = 0;
+  int* nbr = nullptr;     // [K][n] neighbour on this level, or -1
+  int* child = nullptr;   // [2^d][n] finer-level cells of each aggregate, or -1
+  int* parent = nullptr;  // [n_finer] aggregate of each finer-level cell
+  int* ptr = nullptr;     // [K*n + 1] contribution range of (slot s, cell I) at s*n + I
+  int* idx = nullptr;     // finer-level face-weight positions summed into each slot
+  void* W = nullptr;      // [K][n] working precision
+  void* Dinv = nullptr;   // [n] inverse of the diagonal sum_s W[s][I] (0 if isolated)
+  void* r = nullptr;      // [n] restricted residual
+  void* e = nullptr;      // [n] correction
+};
+
+constexpr int kMgCoarse = 64;       // stop coarsening at this many cells (one wave solves it)
+constexpr int kMgMaxLevels = 16;
+constexpr int kMgCoarseSweeps = 30; // damped Jacobi sweeps on the coarsest level
+constexpr double kMgOmega = 0.8;    // Jacobi damping of the smoother
 
 }  // namespace piso
 
@@ -71,6 +105,15 @@ struct piso_ctx {
   double* w_p64 = nullptr;        // [N] (MIXED)
   void *m_r32 = nullptr, *m_e32 = nullptr;   // float [N] (MIXED refinement)
   void *k_r = nullptr, *k_q = nullptr, *k_d0 = nullptr, *k_d1 = nullptr;   // PCG [N]
+  void* k_z = nullptr;            // PCG preconditioned residual [N] (multigrid)
+  std::vector<piso::MgLevel> mg;  // coarse levels 1..L of the pressure preconditioner
+  piso::Grid mg_g1{};             // level 1 as a block table (offsets, dims, division magic)
+  // Dirichlet faces: owning cell and side (2 * axis + high), and the boundary cells
+  // with their faces (ascending) for deterministic gathers
+  int *out_bcell = nullptr, *out_bside = nullptr, *out_bc_cell = nullptr, *out_bc_ptr = nullptr,
+      *out_bc_face = nullptr;
+  int out_nbc = 0;
+  void *out_star = nullptr, *out_contrib = nullptr;   // [d][NB] working precision
   void *b_r = nullptr, *b_rh = nullptr, *b_p0 = nullptr, *b_p1 = nullptr, *b_v0 = nullptr,
        *b_v1 = nullptr, *b_s = nullptr, *b_t = nullptr;                    // BiCGStab [d][N]
   // adjoint workspaces
@@ -104,6 +147,82 @@ inline int fail(piso_ctx* c, int code, const std::string& msg) {
     if (e_ != hipSuccess)                                                          \
       return ::piso::fail((ctx), PISO_E_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
   } while (0)
+
+// Device allocation owned by the context (freed by piso_destroy).
+inline int dev_alloc(piso_ctx* c, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return fail(c, PISO_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  c->allocs.push_back(*p);
+  return PISO_OK;
+}
+
+template <typename T>
+int upload(piso_ctx* c, void** dst, const std::vector<T>& v) {
+  if (int rc = dev_alloc(c, dst, v.size() * sizeof(T))) return rc;
+  PISO_HIP(c, hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return PISO_OK;
+}
+
+// Multiplier and shift for fast_div by d (see piso_common.h).
+inline void div_magic(uint32_t d, uint32_t& lo, uint32_t& hi, int& shift) {
+  int l = 0;
+  while ((1ull << l) < d) ++l;
+  const uint64_t num = 1ull << (31 + l);
+  const uint64_t m = (num + d - 1) / d;
+  lo = (uint32_t)(m & 0xffffffffu);
+  hi = (uint32_t)(m >> 32);
+  shift = 31 + l;
+}
+
+// Kernel timing for the benchmark: when enabled, solver kernels are launched with
+// start/stop events attached to the dispatch itself (hipExtLaunchKernelGGL), so the
+// elapsed time is the kernel's execution, as a kernel trace reports it.
+inline bool timing_pair(piso_ctx* c, hipEvent_t& a, hipEvent_t& b) {
+  Timing& t = c->timing;
+  if (!t.enabled) return false;
+  if (t.used + 2 > t.ev.size()) {
+    for (int k = 0; k < 64; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return false;
+      t.ev.push_back(e);
+    }
+  }
+  a = t.ev[t.used++];
+  b = t.ev[t.used++];
+  return true;
+}
+
+// After a stream sync: fold the elapsed times of the recorded pairs into the totals.
+inline void timing_collect(piso_ctx* c) {
+  Timing& t = c->timing;
+  if (!t.enabled) return;
+  for (size_t q = 0, k = 0; q + 1 < t.used && k < t.kinds.size(); q += 2, ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.ev[q], t.ev[q + 1]) != hipSuccess) continue;
+    t.ms[t.kinds[k]] += ms;
+    t.calls[t.kinds[k]] += 1;
+  }
+  t.used = 0;
+  t.kinds.clear();
+}
+
+// Launch with optional dispatch-attached timing events.
+template <typename K, typename... Args>
+void launch_timed_wg(piso_ctx* c, hipStream_t s, int kind, K kernel, int G, int wg, Args... args) {
+  hipEvent_t a, b;
+  if (timing_pair(c, a, b)) {
+    hipExtLaunchKernelGGL(kernel, dim3(G), dim3(wg), 0, s, a, b, 0, args...);
+    c->timing.kinds.push_back(kind);
+  } else {
+    hipLaunchKernelGGL(kernel, dim3(G), dim3(wg), 0, s, args...);
+  }
+}
+
+template <typename K, typename... Args>
+void launch_timed(piso_ctx* c, hipStream_t s, int kind, K kernel, int G, Args... args) {
+  launch_timed_wg(c, s, kind, kernel, G, kWG, args...);
+}
 
 inline int grid_cells(int N) { return (N + kWG - 1) / kWG; }
 inline int grid_red(int N, int cap = 512) {
@@ -139,6 +258,39 @@ template <typename TI, typename TO>
 int launch_sub_mean(piso_ctx* c, hipStream_t s, const TI* x, const double* mean, TO* y, int n);
 template <typename TI, typename TO>
 int launch_copy(piso_ctx* c, hipStream_t s, const TI* x, TO* y, int n);
+
+// ---- multigrid preconditioner (piso_mg.hip) ----
+// Host construction of the aggregation hierarchy from the block table and face map.
+int mg_build(piso_ctx* c);
+// Coarse operators of every level from the fine face coefficients Pf.
+template <typename R>
+int mg_setup(piso_ctx* c, hipStream_t s, const R* Pf);
+// z = B r (one V-cycle, zero initial guess) and the partial sums of r.z and r.r over
+// G work-groups into partB; every kernel returns at once when st->done is set.
+template <typename R>
+int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, R* z, CgState* st,
+             double* partB, int G);
+
+// ---- advective outflow boundary (piso_outflow.hip) ----
+struct OutflowUm {
+  double v[3];
+};
+int outflow_build(piso_ctx* c);
+template <typename R>
+int outflow_update(piso_ctx* c, hipStream_t s, const R* u, const R* ub, const int* outflow, OutflowUm um,
+                   double dt, R* ub_out);
+template <typename R>
+int outflow_update_bwd(piso_ctx* c, hipStream_t s, const R* u, const R* ub, const int* outflow, OutflowUm um,
+                       double dt, const R* gbar, R* du, R* dub);
+
+// ---- online plane statistics (piso_stats.hip) ----
+int stats_planes(const piso_ctx* c, int axis, int* n_planes, int* m);
+template <typename R>
+int stats_accumulate(piso_ctx* c, hipStream_t s, const R* u, int axis, double* state);
+int stats_finalize(piso_ctx* c, hipStream_t s, int axis, const double* state, double* mean, double* cov);
+template <typename R>
+int stats_backward(piso_ctx* c, hipStream_t s, const R* u, int axis, const double* state, const double* mbar,
+                   const double* cbar, R* du);
 
 // ---- Krylov solvers (piso_krylov.hip) ----
 // Zero-mean solution of P x = rhs - mean: rhs of type BT, mean a device scalar or null.

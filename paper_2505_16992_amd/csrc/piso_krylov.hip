@@ -7,12 +7,11 @@
 // identical everywhere) and derives its scalar (alpha, beta, omega) on the device.  No
 // device-scope fences or atomics are used.  The host reads the convergence state only
 // every check_every iterations, through a one-work-group check kernel.
-#include <hip/hip_ext.h>
-
 #include <algorithm>
 #include <cmath>
 
 #include "piso_impl.h"
+#include "piso_quad.h"
 
 namespace piso {
 
@@ -93,7 +92,7 @@ k_cg_check(const double* __restrict__ partB, int G, int first, int k_total, doub
   }
 }
 
-template <typename R, int D>
+template <typename R, int D, bool ZOP = false>
 __global__ void __launch_bounds__(kWG)
 k_cg_spmv(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
           const R* __restrict__ dold, R* __restrict__ dnew, R* __restrict__ q, CgState* st,
@@ -123,18 +122,13 @@ k_cg_spmv(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R*
   for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
     int Fp[D], Fm[D];
     faces_of<D>(g, P, Fp, Fm);
-    const R dP = Dinv[P] * r[P] + beta * dold[P];
+    auto op = [&](int Q) { return (ZOP ? r[Q] : Dinv[Q] * r[Q]) + beta * dold[Q]; };
+    const R dP = op(P);
     R Md = R(0);
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      if (Fp[j] >= 0) {
-        const int F = Fp[j];
-        Md += Pf[(size_t)j * N + P] * (dP - (Dinv[F] * r[F] + beta * dold[F]));
-      }
-      if (Fm[j] >= 0) {
-        const int F = Fm[j];
-        Md += Pf[(size_t)j * N + F] * (dP - (Dinv[F] * r[F] + beta * dold[F]));
-      }
+      if (Fp[j] >= 0) Md += Pf[(size_t)j * N + P] * (dP - op(Fp[j]));
+      if (Fm[j] >= 0) Md += Pf[(size_t)j * N + Fm[j]] * (dP - op(Fm[j]));
     }
     dnew[P] = dP;
     q[P] = Md;
@@ -143,7 +137,7 @@ k_cg_spmv(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R*
   write_partials<1>(acc, partA);
 }
 
-template <typename R>
+template <typename R, bool RED = true>
 __global__ void __launch_bounds__(kWG)
 k_cg_update(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restrict__ r,
             const R* __restrict__ dnew, const R* __restrict__ q, CgState* st, const double* __restrict__ partA,
@@ -168,116 +162,16 @@ k_cg_update(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restrict_
     x[P] += alpha * dnew[P];
     const R rn = r[P] - alpha * q[P];
     r[P] = rn;
-    acc[0] += (double)rn * (double)(Dinv[P] * rn);
-    acc[1] += (double)rn * (double)rn;
-  }
-  write_partials<2>(acc, partB);
-}
-
-
-// ------------------------------------------------------------ quad fast path
-// Four consecutive x-cells of one row per thread (every block has nx % 4 == 0): the
-// operand, coefficient and output streams move as 16-byte (float) or 32-byte (double)
-// vectors; neighbours across a block side come from the face map cell by cell.
-
-template <typename R>
-struct Q4 {
-  R v[4];
-};
-
-template <typename R>
-__device__ __forceinline__ Q4<R> ldq(const R* __restrict__ p, int P) {
-  Q4<R> q;
-  if constexpr (sizeof(R) == 4) {
-    const float4 t = *reinterpret_cast<const float4*>(p + P);
-    q.v[0] = t.x; q.v[1] = t.y; q.v[2] = t.z; q.v[3] = t.w;
-  } else {
-    const double2 a = *reinterpret_cast<const double2*>(p + P);
-    const double2 b = *reinterpret_cast<const double2*>(p + P + 2);
-    q.v[0] = a.x; q.v[1] = a.y; q.v[2] = b.x; q.v[3] = b.y;
-  }
-  return q;
-}
-
-template <typename R>
-__device__ __forceinline__ void stq(R* __restrict__ p, int P, const Q4<R>& q) {
-  if constexpr (sizeof(R) == 4) {
-    *reinterpret_cast<float4*>(p + P) = make_float4(q.v[0], q.v[1], q.v[2], q.v[3]);
-  } else {
-    *reinterpret_cast<double2*>(p + P) = make_double2(q.v[0], q.v[1]);
-    *reinterpret_cast<double2*>(p + P + 2) = make_double2(q.v[2], q.v[3]);
-  }
-}
-
-// M d over the quad starting at P0 for an operand given by dq(P) (4 cells) / d1(P)
-// (one cell); dP is the operand at the quad.  Pf face arrays as in the scalar kernels.
-template <typename R, int D, typename FQ, typename F1>
-__device__ __forceinline__ Q4<R> quad_stencil(const Grid& g, const Cell& c, int P0, const R* __restrict__ Pf,
-                                              const Q4<R>& dP, FQ dq, F1 d1) {
-  const int N = g.N;
-  const int* t = g.tab + c.b * kTabStride;
-  const int nx = t[1], ny = t[2], nz = t[3];
-  Q4<R> M;
-  // x faces
-  const Q4<R> px = ldq(Pf, P0);
-  int Lx = c.i > 0 ? P0 - 1 : g.fmap[t[4] + c.j + ny * c.k];
-  int Rx = c.i + 4 < nx ? P0 + 4 : g.fmap[t[5] + c.j + ny * c.k];
-  const R dl = Lx >= 0 ? d1(Lx) : R(0);
-  const R pl = Lx >= 0 ? Pf[Lx] : R(0);
-  const R dr = Rx >= 0 ? d1(Rx) : R(0);
-  M.v[0] = px.v[0] * (dP.v[0] - dP.v[1]) + pl * (dP.v[0] - dl);
-  M.v[1] = px.v[1] * (dP.v[1] - dP.v[2]) + px.v[0] * (dP.v[1] - dP.v[0]);
-  M.v[2] = px.v[2] * (dP.v[2] - dP.v[3]) + px.v[1] * (dP.v[2] - dP.v[1]);
-  M.v[3] = (Rx >= 0 ? px.v[3] * (dP.v[3] - dr) : R(0)) + px.v[2] * (dP.v[3] - dP.v[2]);
-  // y and z faces
-#pragma unroll
-  for (int a = 1; a < D; ++a) {
-    const int pos = a == 1 ? c.j : c.k;
-    const int n = a == 1 ? ny : nz;
-    const int stride = a == 1 ? nx : nx * ny;
-    const R* Pa = Pf + (size_t)a * N;
-    // +a side: own face coefficients
-    const Q4<R> pp = ldq(Pa, P0);
-    if (pos < n - 1) {
-      const Q4<R> nb = dq(P0 + stride);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) M.v[e] += pp.v[e] * (dP.v[e] - nb.v[e]);
-    } else {
-      const int base = t[4 + 2 * a + 1] + (a == 1 ? c.i + nx * c.k : c.i + nx * c.j);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int F = g.fmap[base + e];
-        if (F >= 0) M.v[e] += pp.v[e] * (dP.v[e] - d1(F));
-      }
-    }
-    // -a side: coefficients stored at the neighbour
-    if (pos > 0) {
-      const Q4<R> nb = dq(P0 - stride);
-      const Q4<R> pm = ldq(Pa, P0 - stride);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) M.v[e] += pm.v[e] * (dP.v[e] - nb.v[e]);
-    } else {
-      const int base = t[4 + 2 * a] + (a == 1 ? c.i + nx * c.k : c.i + nx * c.j);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int F = g.fmap[base + e];
-        if (F >= 0) M.v[e] += Pa[F] * (dP.v[e] - d1(F));
-      }
+    if (RED) {
+      acc[0] += (double)rn * (double)(Dinv[P] * rn);
+      acc[1] += (double)rn * (double)rn;
     }
   }
-  return M;
+  if (RED) write_partials<2>(acc, partB);
 }
 
-__device__ __forceinline__ void quad_range(int NQ, int& beg, int& end) {
-  const int G = gridDim.x;
-  int per = (NQ + G - 1) / G;
-  per = (per + 63) & ~63;
-  beg = xcd_logical_group() * per;
-  end = beg + per;
-  if (end > NQ) end = NQ;
-}
 
-template <typename R, int D>
+template <typename R, int D, bool ZOP = false>
 __global__ void __launch_bounds__(kWG)
 k_cg_spmv_q(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
             const R* __restrict__ dold, R* __restrict__ dnew, R* __restrict__ q, CgState* st,
@@ -301,13 +195,19 @@ k_cg_spmv_q(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const 
     st->rr = rr;
   }
   auto dq = [&](int P) {
-    const Q4<R> a = ldq(Dinv, P), b = ldq(r, P), c = ldq(dold, P);
+    const Q4<R> b = ldq(r, P), c = ldq(dold, P);
     Q4<R> o;
+    if constexpr (ZOP) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) o.v[e] = a.v[e] * b.v[e] + beta * c.v[e];
+      for (int e = 0; e < 4; ++e) o.v[e] = b.v[e] + beta * c.v[e];
+    } else {
+      const Q4<R> a = ldq(Dinv, P);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) o.v[e] = a.v[e] * b.v[e] + beta * c.v[e];
+    }
     return o;
   };
-  auto d1 = [&](int P) { return Dinv[P] * r[P] + beta * dold[P]; };
+  auto d1 = [&](int P) { return (ZOP ? r[P] : Dinv[P] * r[P]) + beta * dold[P]; };
   int beg, end;
   quad_range(g.N >> 2, beg, end);
   double acc[1] = {0.0};
@@ -324,7 +224,7 @@ k_cg_spmv_q(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const 
   write_partials<1>(acc, partA);
 }
 
-template <typename R>
+template <typename R, bool RED = true>
 __global__ void __launch_bounds__(kWG)
 k_cg_update_q(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restrict__ r,
               const R* __restrict__ dnew, const R* __restrict__ q, CgState* st, const double* __restrict__ partA,
@@ -348,18 +248,24 @@ k_cg_update_q(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restric
   for (int qd = beg + (int)threadIdx.x; qd < end; qd += kWG) {
     const int P = qd << 2;
     Q4<R> xv = ldq(x, P), rv = ldq(r, P);
-    const Q4<R> dv = ldq(dnew, P), qv = ldq(q, P), Dv = ldq(Dinv, P);
+    const Q4<R> dv = ldq(dnew, P), qv = ldq(q, P);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       xv.v[e] += alpha * dv.v[e];
       rv.v[e] -= alpha * qv.v[e];
-      acc[0] += (double)rv.v[e] * (double)(Dv.v[e] * rv.v[e]);
-      acc[1] += (double)rv.v[e] * (double)rv.v[e];
+    }
+    if constexpr (RED) {
+      const Q4<R> Dv = ldq(Dinv, P);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        acc[0] += (double)rv.v[e] * (double)(Dv.v[e] * rv.v[e]);
+        acc[1] += (double)rv.v[e] * (double)rv.v[e];
+      }
     }
     stq(x, P, xv);
     stq(r, P, rv);
   }
-  write_partials<2>(acc, partB);
+  if constexpr (RED) write_partials<2>(acc, partB);
 }
 
 // MIXED form: r64 = b64 - M x64 in double with b64 = -(rhs64 - mean) and the float face
@@ -712,66 +618,10 @@ static int check(piso_ctx* c, const char* what) {
   return PISO_OK;
 }
 
-// Kernel timing for the benchmark: when enabled, the CG kernels are launched with
-// start/stop events attached to the dispatch itself (hipExtLaunchKernelGGL), so the
-// elapsed time is the kernel's execution, as a kernel trace reports it.
-struct EvPair {
-  hipEvent_t a = nullptr, b = nullptr;
-};
-
-static EvPair timing_pair(piso_ctx* c) {
-  EvPair p;
-  Timing& t = c->timing;
-  if (!t.enabled) return p;
-  if (t.used + 2 > t.ev.size()) {
-    for (int k = 0; k < 64; ++k) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return p;
-      t.ev.push_back(e);
-    }
-  }
-  p.a = t.ev[t.used++];
-  p.b = t.ev[t.used++];
-  return p;
-}
-
-// After a stream sync: fold the elapsed times of the recorded pairs into the totals
-// (kinds: 0 = stencil kernel, 1 = update kernel).
-static void timing_collect(piso_ctx* c, const std::vector<int>& kinds) {
-  Timing& t = c->timing;
-  if (!t.enabled) return;
-  size_t k = 0;
-  for (size_t q = 0; q + 1 < t.used && k < kinds.size(); q += 2, ++k) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, t.ev[q], t.ev[q + 1]) != hipSuccess) continue;
-    if (kinds[k] == 0) {
-      t.spmv_ms += ms;
-      t.spmv_calls += 1;
-    } else {
-      t.update_ms += ms;
-      t.update_calls += 1;
-    }
-  }
-  t.used = 0;
-}
-
-// Launch with optional dispatch-attached timing events.
-template <typename K, typename... Args>
-static void launch_timed(piso_ctx* c, hipStream_t s, int kind, std::vector<int>& kinds, K kernel, int G,
-                         Args... args) {
-  EvPair e = timing_pair(c);
-  if (e.a) {
-    hipExtLaunchKernelGGL(kernel, dim3(G), dim3(kWG), 0, s, e.a, e.b, 0, args...);
-    kinds.push_back(kind);
-  } else {
-    hipLaunchKernelGGL(kernel, dim3(G), dim3(kWG), 0, s, args...);
-  }
-}
-
 template <typename R, typename BT>
 static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const BT* b,
                    const double* mean, double sign, R* x, double rtol, int max_iter, int check_every,
-                   int* iters_out, double* rel_out, int* status_out) {
+                   int precond, int* iters_out, double* rel_out, int* status_out) {
   const int N = c->N, G = grid_red(N, c->red_grid);
   R* r = (R*)c->k_r;
   R* q = (R*)c->k_q;
@@ -780,51 +630,85 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
   double* pA = part(c, kPartA);
   double* pB = part(c, kPartB);
   const double tol2 = rtol * rtol;
+  // multigrid: z = B r is stored by the V-cycle (which also writes the r.z, r.r
+  // partials); the stencil kernel then forms d from z instead of Dinv r
+  const bool mg = precond == PISO_PRECOND_MG && !c->mg.empty();
+  R* z = (R*)c->k_z;
+  if (mg) {
+    if (int rc = mg_setup<R>(c, s, Pf)) return rc;
+  }
   if (c->dim == 2)
     k_cg_init<R, BT, 2><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, b, mean, sign, x, r, d[0], pB);
   else
     k_cg_init<R, BT, 3><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, b, mean, sign, x, r, d[0], pB);
   k_cg_check<<<1, kWG, 0, s>>>(pB, G, 1, 0, tol2, st);
   if (int rc = check(c, "k_cg_init")) return rc;
+  if (mg) {
+    if (int rc = mg_apply<R>(c, s, Pf, Dinv, (const R*)r, z, st, pB, G)) return rc;
+  }
   PISO_HIP(c, hipMemcpyAsync(c->h_cg, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
   PISO_HIP(c, hipStreamSynchronize(s));
   if (c->h_cg->zero_rhs) PISO_HIP(c, hipMemsetAsync(x, 0, sizeof(R) * (size_t)N, s));
   int it = 0;
   if (check_every < 1) check_every = 8;
-  std::vector<int> kinds;
   // the vectorised kernels need 16-byte aligned operands (caller buffers may be views)
   const bool quad = c->quad && ((((uintptr_t)Pf) | ((uintptr_t)Dinv) | ((uintptr_t)x)) & 15u) == 0;
+  const R* opnd = mg ? (const R*)z : (const R*)r;
   while (!c->h_cg->done && it < max_iter) {
     const int n = std::min(check_every, max_iter - it);
-    kinds.clear();
     for (int k = 0; k < n; ++k, ++it) {
       R* dold = d[it & 1];
       R* dnew = d[(it + 1) & 1];
       if (quad) {
-        if (c->dim == 2)
-          launch_timed(c, s, 0, kinds, k_cg_spmv_q<R, 2>, G, c->grid, Pf, Dinv, (const R*)r, (const R*)dold, dnew, q,
-                       st, (const double*)pB, pA, G, it);
-        else
-          launch_timed(c, s, 0, kinds, k_cg_spmv_q<R, 3>, G, c->grid, Pf, Dinv, (const R*)r, (const R*)dold, dnew, q,
-                       st, (const double*)pB, pA, G, it);
-        launch_timed(c, s, 1, kinds, k_cg_update_q<R>, G, N, Dinv, x, r, (const R*)dnew, (const R*)q, st,
-                     (const double*)pA, pB, G, it);
+        if (mg) {
+          if (c->dim == 2)
+            launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 2, true>, G, c->grid, Pf, Dinv, opnd, (const R*)dold, dnew,
+                         q, st, (const double*)pB, pA, G, it);
+          else
+            launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 3, true>, G, c->grid, Pf, Dinv, opnd, (const R*)dold, dnew,
+                         q, st, (const double*)pB, pA, G, it);
+          launch_timed(c, s, kTimeCgUpdate, k_cg_update_q<R, false>, G, N, Dinv, x, r, (const R*)dnew, (const R*)q, st,
+                       (const double*)pA, pB, G, it);
+        } else {
+          if (c->dim == 2)
+            launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 2>, G, c->grid, Pf, Dinv, opnd, (const R*)dold, dnew, q,
+                         st, (const double*)pB, pA, G, it);
+          else
+            launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 3>, G, c->grid, Pf, Dinv, opnd, (const R*)dold, dnew, q,
+                         st, (const double*)pB, pA, G, it);
+          launch_timed(c, s, kTimeCgUpdate, k_cg_update_q<R>, G, N, Dinv, x, r, (const R*)dnew, (const R*)q, st,
+                       (const double*)pA, pB, G, it);
+        }
       } else {
-        if (c->dim == 2)
-          launch_timed(c, s, 0, kinds, k_cg_spmv<R, 2>, G, c->grid, Pf, Dinv, (const R*)r, (const R*)dold, dnew, q,
-                       st, (const double*)pB, pA, G, it);
-        else
-          launch_timed(c, s, 0, kinds, k_cg_spmv<R, 3>, G, c->grid, Pf, Dinv, (const R*)r, (const R*)dold, dnew, q,
-                       st, (const double*)pB, pA, G, it);
-        launch_timed(c, s, 1, kinds, k_cg_update<R>, G, N, Dinv, x, r, (const R*)dnew, (const R*)q, st,
-                     (const double*)pA, pB, G, it);
+        if (mg) {
+          if (c->dim == 2)
+            launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 2, true>, G, c->grid, Pf, Dinv, opnd, (const R*)dold, dnew,
+                         q, st, (const double*)pB, pA, G, it);
+          else
+            launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 3, true>, G, c->grid, Pf, Dinv, opnd, (const R*)dold, dnew,
+                         q, st, (const double*)pB, pA, G, it);
+          launch_timed(c, s, kTimeCgUpdate, k_cg_update<R, false>, G, N, Dinv, x, r, (const R*)dnew, (const R*)q, st,
+                       (const double*)pA, pB, G, it);
+        } else {
+          if (c->dim == 2)
+            launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 2>, G, c->grid, Pf, Dinv, opnd, (const R*)dold, dnew, q,
+                         st, (const double*)pB, pA, G, it);
+          else
+            launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 3>, G, c->grid, Pf, Dinv, opnd, (const R*)dold, dnew, q,
+                         st, (const double*)pB, pA, G, it);
+          launch_timed(c, s, kTimeCgUpdate, k_cg_update<R>, G, N, Dinv, x, r, (const R*)dnew, (const R*)q, st,
+                       (const double*)pA, pB, G, it);
+        }
+      }
+      if (mg) {
+        if (int rc = mg_apply<R>(c, s, Pf, Dinv, (const R*)r, z, st, pB, G)) return rc;
       }
     }
-    k_cg_check<<<1, kWG, 0, s>>>(pB, G, 0, it, tol2, st);
+  k_cg_check<<<1, kWG, 0, s>>>(pB, G, 0, it, tol2, st);
     if (int rc = check(c, "k_cg iteration")) return rc;
     PISO_HIP(c, hipMemcpyAsync(c->h_cg, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
     PISO_HIP(c, hipStreamSynchronize(s));
-    timing_collect(c, kinds);
+    timing_collect(c);
   }
   const CgState& h = *c->h_cg;
   *iters_out += h.iters;
@@ -838,10 +722,12 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
 template <typename R, typename BT>
 int pressure_solve(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const BT* rhs,
                    const double* mean, R* x, const piso_solve_opts* o, piso_solve_info* info) {
+  if (o->precond != PISO_PRECOND_JACOBI && o->precond != PISO_PRECOND_MG)
+    return fail(c, PISO_E_ARG, "pressure solve: unknown preconditioner");
   int iters = 0, status = 0;
   double rel = 0.0;
   int rc = pcg_run<R, BT>(c, s, Pf, Dinv, rhs, mean, -1.0, x, o->rtol, o->max_iter, o->check_every,
-                          &iters, &rel, &status);
+                          o->precond, &iters, &rel, &status);
   if (rc) return rc;
   // zero-mean gauge
   rc = launch_sum<R, double>(c, s, x, c->N, 1.0 / c->N, c->mean + 1);
@@ -860,6 +746,8 @@ int pressure_solve(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
 int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const float* Pf, const float* Dinv,
                          const double* rhs64, const double* mean, double* x64, const piso_solve_opts* o,
                          piso_solve_info* info) {
+  if (o->precond != PISO_PRECOND_JACOBI && o->precond != PISO_PRECOND_MG)
+    return fail(c, PISO_E_ARG, "pressure solve: unknown preconditioner");
   const int N = c->N, G = grid_red(N, c->red_grid);
   float* r32 = (float*)c->m_r32;
   float* e32 = (float*)c->m_e32;
@@ -895,7 +783,7 @@ int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const float* Pf, const floa
     int st_in = 0;
     double rel_in = 0.0;
     int rc = pcg_run<float, float>(c, s, Pf, Dinv, r32, nullptr, 1.0, e32, o->inner_rtol, o->max_iter,
-                                   o->check_every, &iters, &rel_in, &st_in);
+                                   o->check_every, o->precond, &iters, &rel_in, &st_in);
     if (rc) return rc;
     if (st_in < 0) {
       status = st_in;
@@ -921,6 +809,8 @@ int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const float* Pf, const floa
 template <typename R>
 int velocity_solve(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* C, const R* b, R* x,
                    const piso_solve_opts* o, piso_solve_info* info) {
+  if (o->precond != PISO_PRECOND_JACOBI)
+    return fail(c, PISO_E_ARG, "velocity solve: only the Jacobi preconditioner is available");
   const int N = c->N, G = grid_red(N, c->red_grid), D = c->dim;
   R* r = (R*)c->b_r;
   R* rh = (R*)c->b_rh;

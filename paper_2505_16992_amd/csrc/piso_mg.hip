@@ -1,0 +1,543 @@
+// Aggregation multigrid preconditioner for the pressure PCG.
+//
+// The paper solves the pressure system with CG (App. A.6) and names multigrid for the
+// pressure as the next step for speed (Sec. 6, App. A.6).  This is that step, kept
+// inside the same CG so that the solution is the one the paper's solver converges to:
+// only the preconditioner changes.
+//
+// Operator: M = -P, (M x)_P = sum_f P_f (x_P - x_F) (eq. pMatDiscrete), symmetric
+// positive semi-definite with the constant vectors as null space.
+//
+// Hierarchy (built once per context on the host): level l+1 aggregates the cells of
+// level l in 2x2(x2) boxes inside each block; prolongation is piecewise constant (Q),
+// restriction its transpose, and the coarse operator the Galerkin product Q^T M Q,
+// which for a graph Laplacian is again a graph Laplacian whose face weight between
+// two aggregates is the sum of the finer face weights between them.  The weights are
+// refreshed from Pf before every solve (P depends on A, eq. pMatDiscrete).
+//
+// One application z = B r is a V-cycle from a zero guess: on each level one damped
+// Jacobi sweep before and one after the coarse correction (omega = 0.8), a fixed
+// number of damped Jacobi sweeps on the coarsest level (<= 64 cells, one wave).
+// Every step is a fixed linear map and the pre- and post-smoothers are the same
+// symmetric operator, so B is symmetric positive definite on the range of M and the
+// outer CG keeps its theory.  The pre-smoothing result omega D^-1 r is never stored:
+// the kernels that need it at a neighbour recompute it from r and D^-1.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "piso_impl.h"
+#include "piso_quad.h"
+
+namespace piso {
+
+// ------------------------------------------------------------------ kernels
+
+// W[s][I] = sum of the finer face weights listed for (s, I); Dinv[I] = 1 / sum_s W.
+template <typename R>
+__global__ void __launch_bounds__(kWG)
+k_mg_coef(int n, int K, const int* __restrict__ ptr, const int* __restrict__ idx, const R* __restrict__ Wsrc,
+          R* __restrict__ W, R* __restrict__ Dinv) {
+  const int I = blockIdx.x * kWG + threadIdx.x;
+  if (I >= n) return;
+  R diag = R(0);
+  for (int s = 0; s < K; ++s) {
+    const int q = s * n + I;
+    R w = R(0);
+    for (int t = ptr[q]; t < ptr[q + 1]; ++t) w += Wsrc[idx[t]];
+    W[q] = w;
+    diag += w;
+  }
+  Dinv[I] = diag > R(0) ? R(1) / diag : R(0);
+}
+
+// Restriction from the fine grid: rc[I] = sum over the children P of aggregate I of the
+// residual r_P - (M x)_P of the pre-smoothed x = omega D^-1 r.  Faces between two
+// children of I cancel in the sum and are skipped; the children's positions follow
+// from the aggregate's (g1 is level 1 as a block table).
+template <typename R, int D>
+__global__ void __launch_bounds__(kWG)
+k_mg_down0(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
+           R omega, R* __restrict__ rc, const CgState* st) {
+  if (st->done) return;
+  const int I = blockIdx.x * kWG + threadIdx.x;
+  if (I >= g1.N) return;
+  const int N = g.N;
+  const Cell cc = locate(g1, I);
+  const int* t = g.tab + cc.b * kTabStride;
+  const int n[3] = {t[1], t[2], t[3]};
+  R acc = R(0);
+#pragma unroll
+  for (int q = 0; q < (1 << D); ++q) {
+    const int bit[3] = {q & 1, (q >> 1) & 1, (q >> 2) & 1};
+    Cell c;
+    c.b = cc.b;
+    c.i = 2 * cc.i + bit[0];
+    c.j = 2 * cc.j + bit[1];
+    c.k = 2 * cc.k + bit[2];
+    if (c.i >= n[0] || c.j >= n[1] || c.k >= n[2]) continue;
+    const int pos[3] = {c.i, c.j, c.k};
+    const int P = t[0] + c.i + n[0] * (c.j + n[1] * c.k);
+    const R rP = r[P];
+    const R xP = omega * Dinv[P] * rP;
+    R res = rP;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        const bool internal = sd ? (bit[j] == 0 && pos[j] + 1 < n[j]) : (bit[j] == 1);
+        if (internal) continue;
+        const int F = neighbour(g, c, P, j, sd);
+        if (F >= 0) {
+          const R w = sd ? Pf[(size_t)j * N + P] : Pf[(size_t)j * N + F];
+          res -= w * (xP - omega * Dinv[F] * r[F]);
+        }
+      }
+    }
+    acc += res;
+  }
+  rc[I] = acc;
+}
+
+// Restriction between coarse levels (level lf, graph form) to the next level.
+template <typename R, int NCH>
+__global__ void __launch_bounds__(kWG)
+k_mg_down(int nf, int Kf, const int* __restrict__ nbr, const R* __restrict__ W, const R* __restrict__ Dinv,
+          const R* __restrict__ r, const int* __restrict__ child, int nc, R omega, R* __restrict__ rc,
+          const CgState* st) {
+  if (st->done) return;
+  const int I = blockIdx.x * kWG + threadIdx.x;
+  if (I >= nc) return;
+  R acc = R(0);
+#pragma unroll
+  for (int q = 0; q < NCH; ++q) {
+    const int P = child[q * nc + I];
+    if (P < 0) continue;
+    const R rP = r[P];
+    const R xP = omega * Dinv[P] * rP;
+    R res = rP;
+    for (int s = 0; s < Kf; ++s) {
+      const int Q = nbr[s * nf + P];
+      if (Q >= 0) res -= W[s * nf + P] * (xP - omega * Dinv[Q] * r[Q]);
+    }
+    acc += res;
+  }
+  rc[I] = acc;
+}
+
+// Coarsest level (n <= 64 cells, one wave): e = sweeps damped Jacobi sweeps from zero.
+template <typename R>
+__global__ void __launch_bounds__(64)
+k_mg_coarse(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, const R* __restrict__ Dinv,
+            const R* __restrict__ r, R omega, int sweeps, R* __restrict__ e, const CgState* st) {
+  if (st->done) return;
+  __shared__ R xs[kMgCoarse];
+  const int I = threadIdx.x;
+  const bool on = I < n;
+  const R rI = on ? r[I] : R(0);
+  const R dI = on ? Dinv[I] : R(0);
+  R x = omega * dI * rI;
+  xs[I] = x;
+  __syncthreads();
+  for (int it = 1; it < sweeps; ++it) {
+    R mx = R(0);
+    if (on) {
+      for (int s = 0; s < K; ++s) {
+        const int Q = nbr[s * n + I];
+        if (Q >= 0) mx += W[s * n + I] * (x - xs[Q]);
+      }
+    }
+    x += omega * dI * (rI - mx);
+    __syncthreads();
+    xs[I] = x;
+    __syncthreads();
+  }
+  if (on) e[I] = x;
+}
+
+// Prolongation and post-smoothing on a coarse level: with z = omega D^-1 r + ec[parent],
+// e = z + omega D^-1 (r - M z).
+template <typename R>
+__global__ void __launch_bounds__(kWG)
+k_mg_up(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, const R* __restrict__ Dinv,
+        const R* __restrict__ r, const int* __restrict__ parent, const R* __restrict__ ec, R omega,
+        R* __restrict__ e, const CgState* st) {
+  if (st->done) return;
+  const int P = blockIdx.x * kWG + threadIdx.x;
+  if (P >= n) return;
+  const R rP = r[P], dP = Dinv[P];
+  const R zP = omega * dP * rP + ec[parent[P]];
+  R mz = R(0);
+  for (int s = 0; s < K; ++s) {
+    const int Q = nbr[s * n + P];
+    if (Q >= 0) mz += W[s * n + P] * (zP - (omega * Dinv[Q] * r[Q] + ec[parent[Q]]));
+  }
+  e[P] = zP + omega * dP * (rP - mz);
+}
+
+// Aggregate (level-1 cell) of the fine cell at (b, i, j, k).
+__device__ __forceinline__ int mg_parent(const Grid& g1, int b, int i, int j, int k) {
+  const int* t = g1.tab + b * kTabStride;
+  return t[0] + (i >> 1) + t[1] * ((j >> 1) + t[2] * (k >> 1));
+}
+
+// The same on the fine grid, writing z and the partial sums of r.z and r.r.  Parents of
+// neighbours inside the block follow from the coordinates; across a block side they
+// come from the parent table.
+template <typename R, int D>
+__global__ void __launch_bounds__(kWG)
+k_mg_up0(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
+         const int* __restrict__ parent, const R* __restrict__ ec, R omega, R* __restrict__ z,
+         double* __restrict__ partB, const CgState* st) {
+  if (st->done) return;
+  const int N = g.N;
+  int beg, end;
+  chunk_range(N, beg, end);
+  double acc[2] = {0.0, 0.0};
+  for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
+    const Cell c = locate(g, P);
+    const int* t = g.tab + c.b * kTabStride;
+    const R rP = r[P], dP = Dinv[P];
+    const R zP = omega * dP * rP + ec[mg_parent(g1, c.b, c.i, c.j, c.k)];
+    R mz = R(0);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int pos = j == 0 ? c.i : (j == 1 ? c.j : c.k);
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        const int F = neighbour(g, c, P, j, sd);
+        if (F >= 0) {
+          const bool inside = sd ? pos < t[1 + j] - 1 : pos > 0;
+          const int dd = sd ? 1 : -1;
+          const int pF = inside ? mg_parent(g1, c.b, c.i + (j == 0 ? dd : 0), c.j + (j == 1 ? dd : 0),
+                                            c.k + (j == 2 ? dd : 0))
+                                : parent[F];
+          const R w = sd ? Pf[(size_t)j * N + P] : Pf[(size_t)j * N + F];
+          mz += w * (zP - (omega * Dinv[F] * r[F] + ec[pF]));
+        }
+      }
+    }
+    const R zo = zP + omega * dP * (rP - mz);
+    z[P] = zo;
+    acc[0] += (double)rP * (double)zo;
+    acc[1] += (double)rP * (double)rP;
+  }
+  write_partials<2>(acc, partB);
+}
+
+// Quad form (every block has nx % 4 == 0): cells i0 .. i0+3 of a row share the
+// aggregates i0/2 and i0/2 + 1.
+template <typename R, int D>
+__global__ void __launch_bounds__(kWG)
+k_mg_up0_q(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
+           const int* __restrict__ parent, const R* __restrict__ ec, R omega, R* __restrict__ z,
+           double* __restrict__ partB, const CgState* st) {
+  if (st->done) return;
+  int beg, end;
+  quad_range(g.N >> 2, beg, end);
+  double acc[2] = {0.0, 0.0};
+  for (int qd = beg + (int)threadIdx.x; qd < end; qd += kWG) {
+    const int P0 = qd << 2;
+    const Cell c = locate(g, P0);
+    const int* t = g.tab + c.b * kTabStride;
+    const int nxy = t[1] * t[2];
+    const int* t1 = g1.tab + c.b * kTabStride;
+    // operand z = omega D^-1 r + e[parent] over the quad at P (P0 or a y/z neighbour)
+    auto dq = [&](int P) {
+      int jj = c.j, kk = c.k;
+      const int dl = P - P0;
+      if (dl != 0) {
+        if (D == 3 && (dl == nxy || dl == -nxy)) kk += dl > 0 ? 1 : -1;
+        else jj += dl > 0 ? 1 : -1;
+      }
+      const int base = t1[0] + (c.i >> 1) + t1[1] * ((jj >> 1) + t1[2] * (kk >> 1));
+      const R e0 = ec[base], e1 = ec[base + 1];
+      const Q4<R> a = ldq(Dinv, P), b = ldq(r, P);
+      Q4<R> o;
+      o.v[0] = omega * a.v[0] * b.v[0] + e0;
+      o.v[1] = omega * a.v[1] * b.v[1] + e0;
+      o.v[2] = omega * a.v[2] * b.v[2] + e1;
+      o.v[3] = omega * a.v[3] * b.v[3] + e1;
+      return o;
+    };
+    auto d1 = [&](int P) { return omega * Dinv[P] * r[P] + ec[parent[P]]; };
+    const Q4<R> zq = dq(P0);
+    const Q4<R> M = quad_stencil<R, D>(g, c, P0, Pf, zq, dq, d1);
+    const Q4<R> rq = ldq(r, P0), Dq = ldq(Dinv, P0);
+    Q4<R> o;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      o.v[e] = zq.v[e] + omega * Dq.v[e] * (rq.v[e] - M.v[e]);
+      acc[0] += (double)rq.v[e] * (double)o.v[e];
+      acc[1] += (double)rq.v[e] * (double)rq.v[e];
+    }
+    stq(z, P0, o);
+  }
+  write_partials<2>(acc, partB);
+}
+
+// ------------------------------------------------------------------ host
+
+namespace {
+
+struct HostLevel {
+  int n = 0, K = 0;
+  std::vector<std::array<int, 3>> dims;   // per block
+  std::vector<int> off;                   // per block (+1)
+};
+
+int host_neighbour(const piso_ctx* c, int P, int axis, int side) {
+  int b = 0;
+  while (b + 1 < c->nblocks && P >= c->h_tab[(size_t)(b + 1) * kTabStride]) ++b;
+  const int* t = &c->h_tab[(size_t)b * kTabStride];
+  const int L = P - t[0];
+  const int nx = t[1], ny = t[2];
+  const int pos[3] = {L % nx, (L / nx) % ny, L / (nx * ny)};
+  const int stride[3] = {1, nx, nx * ny};
+  const int n = t[1 + axis];
+  if (side && pos[axis] < n - 1) return P + stride[axis];
+  if (!side && pos[axis] > 0) return P - stride[axis];
+  int tg;
+  if (axis == 0) tg = pos[1] + ny * pos[2];
+  else if (axis == 1) tg = pos[0] + nx * pos[2];
+  else tg = pos[0] + nx * pos[1];
+  return c->h_fmap[(size_t)t[4 + 2 * axis + side] + tg];
+}
+
+}  // namespace
+
+int mg_build(piso_ctx* c) {
+  const int D = c->dim, B = c->nblocks, NCH = 1 << D;
+  HostLevel fine;
+  fine.n = c->N;
+  fine.K = 2 * D;
+  fine.dims.resize(B);
+  fine.off.resize(B + 1);
+  for (int b = 0; b < B; ++b) {
+    const int* t = &c->h_tab[(size_t)b * kTabStride];
+    fine.dims[b] = {t[1], t[2], t[3]};
+    fine.off[b] = t[0];
+  }
+  fine.off[B] = c->N;
+  // finer-level adjacency, slot-major; on the fine grid slot 2*axis + side
+  std::vector<int> nbr_f((size_t)fine.K * fine.n);
+  for (int P = 0; P < fine.n; ++P)
+    for (int a = 0; a < D; ++a)
+      for (int sd = 0; sd < 2; ++sd) {
+        const int F = host_neighbour(c, P, a, sd);
+        nbr_f[(size_t)(2 * a + sd) * fine.n + P] = F >= 0 ? F : -1;
+      }
+  c->mg.clear();
+  HostLevel cur = fine;
+  for (int level = 1; level <= kMgMaxLevels; ++level) {
+    if (level > 1 && cur.n <= kMgCoarse) break;
+    HostLevel nx;
+    nx.dims.resize(B);
+    nx.off.assign(B + 1, 0);
+    for (int b = 0; b < B; ++b) {
+      for (int a = 0; a < 3; ++a) nx.dims[b][a] = a < D ? (cur.dims[b][a] + 1) / 2 : 1;
+      nx.off[b + 1] = nx.off[b] + nx.dims[b][0] * nx.dims[b][1] * nx.dims[b][2];
+    }
+    nx.n = nx.off[B];
+    if (nx.n >= cur.n) break;
+    // parent of each finer cell, children of each aggregate
+    std::vector<int> parent(cur.n), child((size_t)NCH * nx.n, -1);
+    for (int b = 0; b < B; ++b) {
+      const auto& d = cur.dims[b];
+      const auto& e = nx.dims[b];
+      for (int k = 0; k < d[2]; ++k)
+        for (int j = 0; j < d[1]; ++j)
+          for (int i = 0; i < d[0]; ++i) {
+            const int P = cur.off[b] + i + d[0] * (j + d[1] * k);
+            const int I = nx.off[b] + i / 2 + e[0] * (j / 2 + e[1] * (k / 2));
+            const int q = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
+            parent[P] = I;
+            child[(size_t)q * nx.n + I] = P;
+          }
+    }
+    // coarse adjacency and contribution lists (fixed traversal order)
+    std::vector<int> nb_off(nx.n + 1, 0), nb_list;
+    std::vector<int> pr_off(nx.n + 1, 0), pr_slot, pr_face;
+    nb_list.reserve((size_t)nx.n * 2 * D);
+    int K = 0;
+    for (int I = 0; I < nx.n; ++I) {
+      const size_t nb0 = nb_list.size(), pr0 = pr_slot.size();
+      for (int q = 0; q < NCH; ++q) {
+        const int P = child[(size_t)q * nx.n + I];
+        if (P < 0) continue;
+        for (int s = 0; s < cur.K; ++s) {
+          const int Q = nbr_f[(size_t)s * cur.n + P];
+          if (Q < 0) continue;
+          const int J = parent[Q];
+          if (J == I) continue;
+          int slot = -1;
+          for (size_t u = nb0; u < nb_list.size(); ++u)
+            if (nb_list[u] == J) slot = (int)(u - nb0);
+          if (slot < 0) {
+            slot = (int)(nb_list.size() - nb0);
+            nb_list.push_back(J);
+          }
+          long long face;
+          if (level == 1) {
+            const int a = s / 2;
+            face = (long long)a * c->N + ((s & 1) ? P : Q);
+          } else {
+            face = (long long)s * cur.n + P;
+          }
+          if (face > INT32_MAX) return fail(c, PISO_E_ARG, "multigrid: face index overflow");
+          pr_slot.push_back(slot);
+          pr_face.push_back((int)face);
+        }
+      }
+      nb_off[I + 1] = (int)nb_list.size();
+      pr_off[I + 1] = (int)pr_slot.size();
+      K = std::max(K, (int)(nb_list.size() - nb0));
+      (void)pr0;
+    }
+    if (K == 0) K = 1;
+    std::vector<int> nbr((size_t)K * nx.n, -1), ptr((size_t)K * nx.n + 1, 0), idx;
+    idx.reserve(pr_face.size());
+    for (int I = 0; I < nx.n; ++I)
+      for (int u = nb_off[I]; u < nb_off[I + 1]; ++u) nbr[(size_t)(u - nb_off[I]) * nx.n + I] = nb_list[u];
+    size_t q = 0;
+    for (int s = 0; s < K; ++s)
+      for (int I = 0; I < nx.n; ++I) {
+        for (int u = pr_off[I]; u < pr_off[I + 1]; ++u)
+          if (pr_slot[u] == s) idx.push_back(pr_face[u]);
+        ptr[++q] = (int)idx.size();
+      }
+    nx.K = K;
+    MgLevel L;
+    L.n = nx.n;
+    L.K = K;
+    if (int rc = upload(c, (void**)&L.nbr, nbr)) return rc;
+    if (int rc = upload(c, (void**)&L.child, child)) return rc;
+    if (int rc = upload(c, (void**)&L.parent, parent)) return rc;
+    if (int rc = upload(c, (void**)&L.ptr, ptr)) return rc;
+    if (int rc = upload(c, (void**)&L.idx, idx)) return rc;
+    if (int rc = dev_alloc(c, &L.W, (size_t)K * nx.n * c->esz)) return rc;
+    if (int rc = dev_alloc(c, &L.Dinv, (size_t)nx.n * c->esz)) return rc;
+    if (int rc = dev_alloc(c, &L.r, (size_t)nx.n * c->esz)) return rc;
+    if (int rc = dev_alloc(c, &L.e, (size_t)nx.n * c->esz)) return rc;
+    if (level == 1) {
+      // level 1 as a block table for the structured fine-level kernels
+      std::vector<int> tab1((size_t)B * kTabStride, 0);
+      for (int b = 0; b < B; ++b) {
+        int* t = &tab1[(size_t)b * kTabStride];
+        t[0] = nx.off[b];
+        t[1] = nx.dims[b][0];
+        t[2] = nx.dims[b][1];
+        t[3] = nx.dims[b][2];
+        uint32_t lo, hi;
+        int sh;
+        div_magic((uint32_t)t[1], lo, hi, sh);
+        t[10] = (int)lo; t[11] = (int)hi; t[12] = sh;
+        div_magic((uint32_t)(t[1] * t[2]), lo, hi, sh);
+        t[13] = (int)lo; t[14] = (int)hi; t[15] = sh;
+      }
+      int* d_tab1 = nullptr;
+      if (int rc = upload(c, (void**)&d_tab1, tab1)) return rc;
+      c->mg_g1.dim = D;
+      c->mg_g1.nblocks = B;
+      c->mg_g1.N = nx.n;
+      c->mg_g1.NB = 0;
+      c->mg_g1.tab = d_tab1;
+      c->mg_g1.fmap = nullptr;
+    }
+    c->mg.push_back(L);
+    nbr_f.swap(nbr);
+    cur = nx;
+  }
+  if (!c->mg.empty() && c->mg.back().n > kMgCoarse) c->mg.clear();   // cannot happen: blocks <= 16
+  if (!c->mg.empty()) {
+    if (int rc = dev_alloc(c, &c->k_z, (size_t)c->N * c->esz)) return rc;
+  }
+  return PISO_OK;
+}
+
+static int mg_check(piso_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, PISO_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return PISO_OK;
+}
+
+template <typename R>
+int mg_setup(piso_ctx* c, hipStream_t s, const R* Pf) {
+  const R* src = Pf;
+  for (const MgLevel& L : c->mg) {
+    k_mg_coef<R><<<grid_cells(L.n), kWG, 0, s>>>(L.n, L.K, L.ptr, L.idx, src, (R*)L.W, (R*)L.Dinv);
+    src = (const R*)L.W;
+  }
+  return mg_check(c, "k_mg_coef");
+}
+
+template <typename R>
+int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, R* z, CgState* st,
+             double* partB, int G) {
+  const int nl = (int)c->mg.size();
+  const R om = (R)kMgOmega;
+  const Grid& g1 = c->mg_g1;
+  if (c->dim == 2)
+    launch_timed(c, s, kTimeMgDown0, k_mg_down0<R, 2>, grid_cells(g1.N), c->grid, g1, Pf, Dinv, r, om,
+                 (R*)c->mg[0].r, (const CgState*)st);
+  else
+    launch_timed(c, s, kTimeMgDown0, k_mg_down0<R, 3>, grid_cells(g1.N), c->grid, g1, Pf, Dinv, r, om,
+                 (R*)c->mg[0].r, (const CgState*)st);
+  for (int l = 1; l < nl; ++l) {
+    const MgLevel& F = c->mg[l - 1];
+    const MgLevel& C = c->mg[l];
+    if (c->dim == 2)
+      launch_timed(c, s, kTimeMgCoarse, k_mg_down<R, 4>, grid_cells(C.n), F.n, F.K, (const int*)F.nbr,
+                   (const R*)F.W, (const R*)F.Dinv, (const R*)F.r, (const int*)C.child, C.n, om, (R*)C.r,
+                   (const CgState*)st);
+    else
+      launch_timed(c, s, kTimeMgCoarse, k_mg_down<R, 8>, grid_cells(C.n), F.n, F.K, (const int*)F.nbr,
+                   (const R*)F.W, (const R*)F.Dinv, (const R*)F.r, (const int*)C.child, C.n, om, (R*)C.r,
+                   (const CgState*)st);
+  }
+  {
+    const MgLevel& L = c->mg[nl - 1];
+    launch_timed_wg(c, s, kTimeMgCoarse, k_mg_coarse<R>, 1, 64, L.n, L.K, (const int*)L.nbr, (const R*)L.W,
+                    (const R*)L.Dinv, (const R*)L.r, om, (int)kMgCoarseSweeps, (R*)L.e, (const CgState*)st);
+  }
+  for (int l = nl - 2; l >= 0; --l) {
+    const MgLevel& F = c->mg[l];
+    const MgLevel& C = c->mg[l + 1];
+    launch_timed(c, s, kTimeMgCoarse, k_mg_up<R>, grid_cells(F.n), F.n, F.K, (const int*)F.nbr, (const R*)F.W,
+                 (const R*)F.Dinv, (const R*)F.r, (const int*)C.parent, (const R*)C.e, om, (R*)F.e,
+                 (const CgState*)st);
+  }
+  {
+    const MgLevel& L1 = c->mg[0];
+    const bool quad =
+        c->quad && ((((uintptr_t)Pf) | ((uintptr_t)Dinv) | ((uintptr_t)r) | ((uintptr_t)z)) & 15u) == 0;
+    const R* e1 = (const R*)L1.e;
+    if (quad) {
+      if (c->dim == 2)
+        launch_timed(c, s, kTimeMgUp0, k_mg_up0_q<R, 2>, G, c->grid, g1, Pf, Dinv, r, (const int*)L1.parent, e1,
+                     om, z, partB, (const CgState*)st);
+      else
+        launch_timed(c, s, kTimeMgUp0, k_mg_up0_q<R, 3>, G, c->grid, g1, Pf, Dinv, r, (const int*)L1.parent, e1,
+                     om, z, partB, (const CgState*)st);
+    } else {
+      if (c->dim == 2)
+        launch_timed(c, s, kTimeMgUp0, k_mg_up0<R, 2>, G, c->grid, g1, Pf, Dinv, r, (const int*)L1.parent, e1, om,
+                     z, partB, (const CgState*)st);
+      else
+        launch_timed(c, s, kTimeMgUp0, k_mg_up0<R, 3>, G, c->grid, g1, Pf, Dinv, r, (const int*)L1.parent, e1, om,
+                     z, partB, (const CgState*)st);
+    }
+  }
+  return mg_check(c, "multigrid V-cycle");
+}
+
+template int mg_setup<float>(piso_ctx*, hipStream_t, const float*);
+template int mg_setup<double>(piso_ctx*, hipStream_t, const double*);
+template int mg_apply<float>(piso_ctx*, hipStream_t, const float*, const float*, const float*, float*, CgState*,
+                             double*, int);
+template int mg_apply<double>(piso_ctx*, hipStream_t, const double*, const double*, const double*, double*,
+                              CgState*, double*, int);
+
+}  // namespace piso

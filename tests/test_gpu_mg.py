@@ -1,0 +1,159 @@
+"""Multigrid-preconditioned pressure CG against the oracle and against the Jacobi path.
+
+The preconditioner changes only how fast the CG converges, not what it converges to,
+so every check is against the oracle's direct solution of the same system (FP64 to a
+tight tolerance), plus properties of the hierarchy and of the iteration counts.
+"""
+import numpy as np
+import pytest
+import torch
+
+import cases
+from oracle.piso import Geometry, step as oracle_step
+from tests.gpu_common import dev, host, random_state, rel, rel_p, say, small_cases, tight_opts
+
+pytestmark = pytest.mark.gpu
+
+JACOBI, MG = 0, 1
+
+
+def _api():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2505_16992_amd import api
+    return api
+
+
+def expected_levels(domain, coarse=64, max_levels=16):
+    """Cell counts of the aggregation levels: 2 cells per axis and block, until at most
+    `coarse` cells remain (at least one level) or no block can be halved."""
+    dims = [list(b) for b in domain.blocks]
+    d = domain.dim
+    n = sum(a * b * c for a, b, c in dims)
+    out = []
+    for level in range(1, max_levels + 1):
+        if level > 1 and n <= coarse:
+            break
+        nd = [[(x + 1) // 2 if a < d else 1 for a, x in enumerate(b)] for b in dims]
+        nn = sum(a * b * c for a, b, c in nd)
+        if nn >= n:
+            break
+        out.append(nn)
+        dims, n = nd, nn
+    return out
+
+
+@pytest.mark.parametrize("name", list(small_cases()) + ["channel96", "cylinder5"])
+def test_hierarchy_shape(name):
+    api = _api()
+    if name == "channel96":
+        case = cases.channel(96, 96, 96)
+    elif name == "cylinder5":
+        case = cases.cylinder_oh()
+    else:
+        case = small_cases()[name]
+    ctx = api.Context(case.domain, "f32")
+    got = [n for n, _ in ctx.mg_levels]
+    say("%s: levels %s slots %s" % (name, got, [k for _, k in ctx.mg_levels]))
+    assert got == expected_levels(case.domain)
+    assert got[-1] <= 64
+    # conformal aligned blocks halved together: at most 2d graph neighbours per cell
+    assert all(1 <= k <= 2 * case.domain.dim for _, k in ctx.mg_levels)
+    if name == "channel96":
+        assert got == [110592, 13824, 1728, 216, 27]
+
+
+@pytest.mark.parametrize("name", list(small_cases()))
+@pytest.mark.parametrize("precond", [JACOBI, MG])
+def test_step_both_preconditioners_f64(name, precond):
+    """One FP64 step of every small case with each preconditioner: identical to the
+    oracle's direct-solve step to solver tolerance."""
+    api = _api()
+    case = small_cases()[name]
+    u, p, S, ub, nu = random_state(case, seed=11)
+    geo = Geometry(case.domain)
+    ref = oracle_step(geo, u, p, nu, S, case.dt, ub)
+    ctx = api.Context(case.domain, "f64")
+    o = tight_opts(ctx)
+    o.pres.precond = precond
+    t = ctx.dtype
+    u1, p1, info = ctx.step(dev(u, t), dev(p, t), dev(nu, t), dev(S, t), dev(ub, t), case.dt, o, info=True)
+    eu, ep = rel(host(u1), ref.u2), rel_p(host(p1), ref.p2)
+    say("%s precond %d: iters %s, rel err u %.2e p %.2e" % (
+        name, precond, [q["iters"] for q in info["pres"]], eu, ep))
+    assert all(q["status"] == 0 for q in info["pres"])
+    assert eu < 1e-9 and ep < 1e-8
+
+
+@pytest.mark.parametrize("prec", ["f32", "mixed"])
+def test_step_mg_single_precision(prec):
+    api = _api()
+    for name in ("channel_q", "cylinder_q", "two_block"):
+        case = small_cases()[name]
+        u, p, S, ub, nu = random_state(case, seed=12)
+        ref = oracle_step(Geometry(case.domain), u, p, nu, S, case.dt, ub)
+        ctx = api.Context(case.domain, prec)
+        o = ctx.default_opts()
+        assert o.pres.precond == MG
+        t = ctx.dtype
+        u1, p1, info = ctx.step(dev(u, t), dev(p, t), dev(nu, t), dev(S, t), dev(ub, t), case.dt, o, info=True)
+        eu, ep = rel(host(u1), ref.u2), rel_p(host(p1), ref.p2)
+        say("%s %s: iters %s, rel err u %.2e p %.2e" % (name, prec, [q["iters"] for q in info["pres"]], eu, ep))
+        assert eu < 1e-5 and ep < 2e-4
+
+
+def test_mg_iteration_counts():
+    """On the stretched channel the V-cycle cuts the CG iterations several-fold and the
+    count grows slowly with the grid (Jacobi: about doubling per refinement)."""
+    api = _api()
+    counts = {}
+    for n in (24, 48):
+        case = cases.channel(n, n, n)
+        ctx = api.Context(case.domain, "f64")
+        t = ctx.dtype
+        for precond in (JACOBI, MG):
+            o = ctx.default_opts()
+            o.pres.rtol = 1e-8
+            o.pres.precond = precond
+            _, _, info = ctx.step(dev(case.u0, t), dev(case.p0, t), dev([case.nu], t), dev(case.S, t),
+                                  dev(case.u_b, t), case.dt, o, info=True)
+            counts[(n, precond)] = info["pres"][0]["iters"]
+    say("iterations (n, precond): %s" % counts)
+    assert counts[(48, MG)] * 4 < counts[(48, JACOBI)]
+    assert counts[(48, MG)] < 1.6 * counts[(24, MG)]
+
+
+def test_mg_adjoint_matches_jacobi_adjoint():
+    """The adjoint pressure solves use the same preconditioner; the gradient of one
+    step agrees with the Jacobi path to solver tolerance (FP64, multi-block)."""
+    api = _api()
+    case = small_cases()["cylinder"]
+    u, p, S, ub, nu = random_state(case, seed=13)
+    ctx = api.Context(case.domain, "f64")
+    t = ctx.dtype
+    rng = np.random.default_rng(14)
+    du1 = dev(rng.standard_normal(u.shape), t)
+    dp1 = dev(rng.standard_normal(p.shape), t)
+    grads = []
+    for precond in (JACOBI, MG):
+        o = tight_opts(ctx)
+        o.pres.precond = precond
+        tape = ctx.new_tape()
+        args = (dev(u, t), dev(p, t), dev(nu, t), dev(S, t), dev(ub, t))
+        ctx.step(*args, case.dt, o, tape=tape)
+        g = ctx.step_backward(tape, args[0], args[1], args[2], args[4], case.dt, du1, dp1, o)
+        grads.append({k: host(v) for k, v in g.items()})
+    for k in grads[0]:
+        e = rel(grads[1][k], grads[0][k])
+        say("grad %s: MG vs Jacobi rel %.2e" % (k, e))
+        assert e < 1e-9
+
+
+def test_velocity_rejects_mg():
+    api = _api()
+    case = small_cases()["tgv16"]
+    ctx = api.Context(case.domain, "f64")
+    o = ctx.default_opts()
+    o.vel.precond = MG
+    t = ctx.dtype
+    with pytest.raises(api.PisoError):
+        ctx.step(dev(case.u0, t), dev(case.p0, t), dev([case.nu], t), dev(case.S, t), dev(case.u_b, t), case.dt, o)
