@@ -101,6 +101,7 @@ _SIGS = {
                                  C.POINTER(StepOpts), C.POINTER(StepInfo)]),
     "piso_outflow_update": (I32, [VP, VP, VP, VP, VP, C.POINTER(F64), F64, VP]),
     "piso_outflow_update_backward": (I32, [VP, VP, VP, VP, VP, C.POINTER(F64), F64, VP, VP, VP]),
+    "piso_divfree_gradient": (I32, [VP, VP, VP, VP, F64, C.POINTER(SolveOpts), VP, VP, C.POINTER(SolveInfo)]),
     "piso_stats_size": (I32, [VP, I32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "piso_stats_accumulate": (I32, [VP, VP, VP, I32, VP]),
     "piso_stats_finalize": (I32, [VP, VP, I32, VP, VP, VP]),

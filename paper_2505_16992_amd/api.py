@@ -292,6 +292,19 @@ class Context:
                     "piso_outflow_update_backward")
         return dub, du
 
+    def divfree_gradient(self, S, dS, lam, opts=None, info=False):
+        """(dS + lam grad p_S, p_S) with P(A = 1) p_S = div S (eq. SgradPsgrad)."""
+        d, N = self.dim, self.N
+        self._t(S, (d, N), "S")
+        g = self._t(dS.contiguous(), (d, N), "dS")
+        o = opts if opts is not None else self.default_opts().pres
+        out = torch.empty_like(g)
+        p = self.zeros(N)
+        inf = L.SolveInfo()
+        self._check(self.lib.piso_divfree_gradient(self.h, _stream(), _ptr(S), _ptr(g), float(lam), C.byref(o),
+                                                   _ptr(out), _ptr(p), C.byref(inf)), "piso_divfree_gradient")
+        return (out, p, inf.as_dict()) if info else (out, p)
+
     # ---------------------------------------------------------------- statistics
     def stats_size(self, axis=1):
         n, r = C.c_int64(), C.c_int64()
@@ -496,6 +509,28 @@ class PlaneStatistics(torch.autograd.Function):
 def plane_statistics(pctx: Context, us, axis=1):
     """(mean, cov) over the fields `us` (list of [d, N] tensors)."""
     return PlaneStatistics.apply(pctx, axis, *us)
+
+
+class DivFreeGradient(torch.autograd.Function):
+    """Identity on a learned source S whose backward adds lam grad p_S to the incoming
+    gradient (eq. SgradPsgrad)."""
+
+    @staticmethod
+    def forward(fctx, pctx: Context, lam, opts, S):
+        fctx.pctx, fctx.lam, fctx.opts = pctx, lam, opts
+        fctx.save_for_backward(S)
+        return S.clone()
+
+    @staticmethod
+    def backward(fctx, gS):
+        (S,) = fctx.saved_tensors
+        g, _ = fctx.pctx.divfree_gradient(S.detach(), gS, fctx.lam, fctx.opts)
+        return None, None, None, g
+
+
+def divfree_gradient_hook(pctx: Context, S, lam, opts=None):
+    """S unchanged in the forward; its gradient gains lam grad p_S in the backward."""
+    return DivFreeGradient.apply(pctx, lam, opts, S)
 
 
 def step(pctx: Context, u, p, S, nu, u_b, dt, opts=None):

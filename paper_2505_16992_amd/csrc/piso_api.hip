@@ -224,17 +224,19 @@ int alloc_workspaces(piso_ctx* c) {
       {&c->w_h1, D * N * e}, {&c->w_tg, D * D * N * e}, {&c->w_tgp, D * N * e},
       {(void**)&c->w_rhs64, N * 8}, {(void**)&c->w_p64, N * 8}, {&c->m_r32, N * 4}, {&c->m_e32, N * 4},
       {&c->k_r, N * e}, {&c->k_q, N * e}, {&c->k_d0, N * e}, {&c->k_d1, N * e},
+      {&c->g_Pf, D * N * e}, {&c->g_Dinv, N * e}, {&c->g_x, N * e},
       {&c->b_r, D * N * e}, {&c->b_rh, D * N * e}, {&c->b_p0, D * N * e}, {&c->b_p1, D * N * e},
       {&c->b_v0, D * N * e}, {&c->b_v1, D * N * e}, {&c->b_s, D * N * e}, {&c->b_t, D * N * e},
       {&c->a_g, D * N * e}, {&c->a_uin, D * N * e}, {&c->a_lam, N * e}, {&c->a_pbar, N * e},
       {&c->a_mu, D * N * e}, {&c->a_dh, D * N * e}, {&c->a_dA, N * e}, {&c->a_dC, 2 * D * N * e},
       {&c->a_dbu, D * N * e}, {&c->a_db, D * N * e}, {&c->a_dp1, N * e}, {&c->a_dnu, N * e},
-      {&c->a_ybar, D * N * e}, {&c->a_cbar, D * D * N * e},
+      {&c->a_ybar, D * N * e}, {&c->a_cbar, D * D * N * e}, {&c->w_zb, D * (size_t)std::max(c->NB, 1) * e},
       {(void**)&c->partials, (size_t)kPartRegions * kRedGrid * sizeof(double)},
       {(void**)&c->mean, 8 * sizeof(double)}, {(void**)&c->cg, sizeof(CgState)}, {(void**)&c->bi, sizeof(BiState)},
   };
   for (auto& l : L)
     if (int rc = dev_alloc(c, l.p, l.bytes)) return rc;
+  PISO_HIP(c, hipMemset(c->w_zb, 0, D * (size_t)std::max(c->NB, 1) * e));
   PISO_HIP(c, hipMemset(c->cg, 0, sizeof(CgState)));
   PISO_HIP(c, hipMemset(c->bi, 0, sizeof(BiState)));
   PISO_HIP(c, hipMemset(c->partials, 0, (size_t)kPartRegions * kRedGrid * sizeof(double)));
@@ -323,6 +325,44 @@ int do_pressure_adjoint(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, 
   if (int rc = launch_sum<R, double>(c, s, g, N, 1.0 / N, c->mean)) return rc;
   PISO_HIP(c, hipMemsetAsync(lam, 0, sizeof(R) * N, s));
   return pressure_solve<R, R>(c, s, Pf, Dinv, g, c->mean, lam, o, info);
+}
+
+// Divergence-free gradient modification (eq. SgradPsgrad): p_S from P(A = 1) p_S =
+// div lerp(J T . S) (no Dirichlet flux, zero lagged pressure, x0 = 0), then
+// g_out = gS + lambda grad p_S, computed as the correction h - A^-1 grad p with h = gS
+// and A = -1 / lambda.
+template <typename R>
+int do_divfree(piso_ctx* c, hipStream_t s, const R* S, const R* gS, double lam, const piso_solve_opts* o,
+               R* g_out, R* p_out, piso_solve_info* info) {
+  const int N = c->N;
+  R* A = (R*)c->w_A;
+  R* Pf = (R*)c->w_Pf;
+  R* Dinv = (R*)c->w_Dinv;
+  R* W = (R*)c->w_W;
+  R* p = p_out ? p_out : (R*)c->a_lam;
+  R* plag = (R*)c->w_p1;
+  const R* zb = (const R*)c->w_zb;
+  if (int rc = launch_fill<R>(c, s, N, R(1), A)) return rc;
+  if (int rc = launch_pcoef<R>(c, s, A, Pf, Dinv)) return rc;
+  if (int rc = launch_jt_field<R>(c, s, S, W)) return rc;
+  PISO_HIP(c, hipMemsetAsync(plag, 0, sizeof(R) * N, s));
+  if (c->prec == PISO_MIXED) {
+    if constexpr (std::is_same<R, float>::value) {
+      if (int rc = launch_div<float, double>(c, s, W, zb, A, plag, c->w_rhs64, c->mean)) return rc;
+      PISO_HIP(c, hipMemsetAsync(c->w_p64, 0, sizeof(double) * N, s));
+      if (int rc = pressure_solve_mixed(c, s, Pf, Dinv, c->w_rhs64, c->mean, c->w_p64, o, info)) return rc;
+      if (int rc = launch_copy<double, float>(c, s, c->w_p64, p, N)) return rc;
+    } else {
+      return fail(c, PISO_E_ARG, "MIXED requires float storage");
+    }
+  } else {
+    PISO_HIP(c, hipMemsetAsync(p, 0, sizeof(R) * N, s));
+    if (int rc = launch_div<R, R>(c, s, W, zb, A, plag, (R*)c->w_rhs, c->mean)) return rc;
+    if (int rc = pressure_solve<R, R>(c, s, Pf, Dinv, (const R*)c->w_rhs, c->mean, p, o, info)) return rc;
+  }
+  if (lam == 0.0) return launch_copy<R, R>(c, s, gS, g_out, c->dim * N);
+  if (int rc = launch_fill<R>(c, s, N, (R)(-1.0 / lam), A)) return rc;
+  return launch_correct<R>(c, s, A, gS, p, Pf, nullptr, g_out, nullptr);
 }
 
 template <typename R>
@@ -553,6 +593,7 @@ int piso_create(const piso_domain_desc* desc, int32_t precision, piso_ctx** out)
   for (int b = 0; b < c->nblocks; ++b)
     if (desc->block_cells[3 * b] % 4 != 0) c->quad = false;
   if (const char* e = std::getenv("PISO_NO_QUAD")) c->quad = (e[0] == '0');
+  if (const char* e = std::getenv("PISO_NO_GRAPH")) c->use_graphs = (e[0] == '0');
   *out = c;
   return PISO_OK;
 }
@@ -561,6 +602,9 @@ void piso_destroy(piso_ctx* c) {
   if (!c) return;
   DevGuard g(c->device);
   (void)hipDeviceSynchronize();
+  for (hipGraphExec_t& g : c->cg_graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (void* p : c->allocs) (void)hipFree(p);
   if (c->h_cg) (void)hipHostFree(c->h_cg);
   if (c->h_bi) (void)hipHostFree(c->h_bi);
@@ -855,6 +899,22 @@ int piso_outflow_update_backward(piso_ctx* c, void* stream, const void* u_n, con
                                                (const double*)du_b_out, (double*)du_n, (double*)du_b),
                     outflow_update_bwd<float>(c, s, (const float*)u_n, (const float*)u_b, outflow, um, dt,
                                               (const float*)du_b_out, (float*)du_n, (float*)du_b));
+}
+
+int piso_divfree_gradient(piso_ctx* c, void* stream, const void* S, const void* dS, double lambda,
+                          const piso_solve_opts* o, void* dS_out, void* p_S, piso_solve_info* info) {
+  CTX_ENTER();
+  REQUIRE(S && dS && dS_out && o, "piso_divfree_gradient: null pointer");
+  REQUIRE(std::isfinite(lambda), "piso_divfree_gradient: lambda must be finite");
+  REQUIRE(o->rtol > 0 && o->max_iter > 0, "piso_divfree_gradient: bad options");
+  REQUIRE(dS_out != S, "piso_divfree_gradient: dS_out must not alias S");
+  piso_solve_info tmp{};
+  int rc = DISPATCH_R(do_divfree<double>(c, s, (const double*)S, (const double*)dS, lambda, o, (double*)dS_out,
+                                         (double*)p_S, &tmp),
+                      do_divfree<float>(c, s, (const float*)S, (const float*)dS, lambda, o, (float*)dS_out,
+                                        (float*)p_S, &tmp));
+  if (info) *info = tmp;
+  return rc < 0 ? rc : tmp.status;
 }
 
 int piso_stats_size(const piso_ctx* c, int32_t axis, int64_t* n_planes, int64_t* record_len) {

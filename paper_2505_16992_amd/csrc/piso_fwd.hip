@@ -370,6 +370,31 @@ __global__ void k_add_scalar(const double* __restrict__ v, R* __restrict__ y) {
   if (threadIdx.x == 0 && blockIdx.x == 0) y[0] += (R)v[0];
 }
 
+template <typename R>
+__global__ void __launch_bounds__(kWG) k_fill(int n, R v, R* __restrict__ y) {
+  const int i = blockIdx.x * kWG + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+
+// W^j = J T_j . S for a cell vector field S (the contravariant flux of eq. pressureRHS
+// without the A^-1 (b_u - H u) part).
+template <typename R, int D, bool DIAG>
+__global__ void __launch_bounds__(kWG)
+k_jt_field(int N, const R* __restrict__ JT, const R* __restrict__ S, R* __restrict__ W) {
+  const int P = cell_of_thread(N);
+  if (P < 0) return;
+  R v[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) v[i] = S[(size_t)i * N + P];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    R w = R(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i) w += jt<R, D, DIAG>(JT, j, i, P, N) * v[i];
+    W[(size_t)j * N + P] = w;
+  }
+}
+
 template <typename TI>
 __global__ void __launch_bounds__(kWG)
 k_sum(const TI* __restrict__ x, int n, double* __restrict__ partials) {
@@ -501,6 +526,19 @@ int launch_add_scalar(piso_ctx* c, hipStream_t s, const double* v, R* y) {
   return check_launch(c, "k_add_scalar");
 }
 
+template <typename R>
+int launch_fill(piso_ctx* c, hipStream_t s, int n, R v, R* y) {
+  k_fill<R><<<grid_cells(n), kWG, 0, s>>>(n, v, y);
+  return check_launch(c, "k_fill");
+}
+
+template <typename R>
+int launch_jt_field(piso_ctx* c, hipStream_t s, const R* S, R* W) {
+  const int G = grid_cells(c->N);
+  PISO_DISPATCH_D_DIAG(c, (k_jt_field<R, D, DG><<<G, kWG, 0, s>>>(c->N, (const R*)c->JT, S, W)));
+  return check_launch(c, "k_jt_field");
+}
+
 template <typename TI, typename TO>
 int launch_sum(piso_ctx* c, hipStream_t s, const TI* x, int n, double scale, double* out) {
   const int G = grid_red(n, c->red_grid);
@@ -532,7 +570,9 @@ int launch_copy(piso_ctx* c, hipStream_t s, const TI* x, TO* y, int n) {
   template int launch_correct<R>(piso_ctx*, hipStream_t, const R*, const R*, const R*, const R*,     \
                                  const R*, R*, R*);                                                  \
   template int launch_scale_invJ<R>(piso_ctx*, hipStream_t, const R*, int, R*);                      \
-  template int launch_add_scalar<R>(piso_ctx*, hipStream_t, const double*, R*);
+  template int launch_add_scalar<R>(piso_ctx*, hipStream_t, const double*, R*);                       \
+  template int launch_fill<R>(piso_ctx*, hipStream_t, int, R, R*);                                    \
+  template int launch_jt_field<R>(piso_ctx*, hipStream_t, const R*, R*);
 
 PISO_INST_FWD(float)
 PISO_INST_FWD(double)

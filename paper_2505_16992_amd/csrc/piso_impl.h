@@ -17,10 +17,14 @@ namespace piso {
 // Solver scalars live on the device.  Values produced at iteration k go to slot k & 1
 // so that a kernel never overwrites a slot that other work-groups of the same launch
 // still read.
+// The iteration index k lives here too: the update kernel's lead thread advances it,
+// and kernels take only its parity (slot) as an argument, so that a recorded sequence
+// of two iterations can be replayed as a graph.
 struct CgState {
   double rz[2];
   double rr, bb, tol2, pad0;
   int done, iters, status, zero_rhs;
+  int k, max_k, pad1, pad2;
 };
 
 struct BiState {
@@ -76,7 +80,7 @@ struct MgLevel {
 
 constexpr int kMgCoarse = 64;       // stop coarsening at this many cells (one wave solves it)
 constexpr int kMgMaxLevels = 16;
-constexpr int kMgCoarseSweeps = 30; // damped Jacobi sweeps on the coarsest level
+constexpr int kMgCoarseSweeps = 24; // damped Jacobi sweeps on the coarsest level
 constexpr double kMgOmega = 0.8;    // Jacobi damping of the smoother
 
 }  // namespace piso
@@ -101,11 +105,18 @@ struct piso_ctx {
        *w_u1 = nullptr, *w_p1 = nullptr, *w_h1 = nullptr;
   void* w_tg = nullptr;           // [d*d][N] tangential gradients (non-orthogonal)
   void* w_tgp = nullptr;          // [d][N]
+  void* w_zb = nullptr;           // [d][max(NB,1)] zeros (boundary values of a source field)
   double* w_rhs64 = nullptr;      // [N] (MIXED)
   double* w_p64 = nullptr;        // [N] (MIXED)
   void *m_r32 = nullptr, *m_e32 = nullptr;   // float [N] (MIXED refinement)
   void *k_r = nullptr, *k_q = nullptr, *k_d0 = nullptr, *k_d1 = nullptr;   // PCG [N]
   void* k_z = nullptr;            // PCG preconditioned residual [N] (multigrid)
+  void* k_y = nullptr;            // omega D^-1 r, the multigrid pre-smoothing [N]
+  // PCG operands copied into context-owned buffers (graph-stable pointers)
+  void *g_Pf = nullptr, *g_Dinv = nullptr, *g_x = nullptr;
+  hipGraphExec_t cg_graph[2] = {nullptr, nullptr};   // recorded iteration pair: Jacobi, multigrid
+  hipStream_t cap_stream = nullptr;                 // stream used only for recording
+  bool use_graphs = true;
   std::vector<piso::MgLevel> mg;  // coarse levels 1..L of the pressure preconditioner
   piso::Grid mg_g1{};             // level 1 as a block table (offsets, dims, division magic)
   // Dirichlet faces: owning cell and side (2 * axis + high), and the boundary cells
@@ -252,6 +263,10 @@ template <typename R>
 int launch_scale_invJ(piso_ctx* c, hipStream_t s, const R* x, int ncomp, R* y);
 template <typename R>
 int launch_add_scalar(piso_ctx* c, hipStream_t s, const double* v, R* y);
+template <typename R>
+int launch_fill(piso_ctx* c, hipStream_t s, int n, R v, R* y);
+template <typename R>
+int launch_jt_field(piso_ctx* c, hipStream_t s, const R* S, R* W);
 template <typename TI, typename TO>
 int launch_sum(piso_ctx* c, hipStream_t s, const TI* x, int n, double scale, double* out);
 template <typename TI, typename TO>
@@ -267,8 +282,11 @@ template <typename R>
 int mg_setup(piso_ctx* c, hipStream_t s, const R* Pf);
 // z = B r (one V-cycle, zero initial guess) and the partial sums of r.z and r.r over
 // G work-groups into partB; every kernel returns at once when st->done is set.
+// y = omega D^-1 r for a fresh residual (the PCG update writes it in the iterations).
 template <typename R>
-int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, R* z, CgState* st,
+int mg_prescale(piso_ctx* c, hipStream_t s, const R* Dinv, const R* r, R* y);
+template <typename R>
+int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, const R* y, R* z, CgState* st,
              double* partB, int G);
 
 // ---- advective outflow boundary (piso_outflow.hip) ----

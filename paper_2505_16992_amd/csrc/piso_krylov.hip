@@ -66,10 +66,11 @@ k_cg_init(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const BT
   write_partials<3>(acc, partB);
 }
 
-// One work-group: publishes the state after init (first) or after a chunk of k_total
-// iterations (convergence of the latest residual).
+// One work-group: publishes the state after init (first: also resets the iteration
+// index and sets its limit) or after a chunk of iterations (convergence of the latest
+// residual).
 __global__ void __launch_bounds__(kWG)
-k_cg_check(const double* __restrict__ partB, int G, int first, int k_total, double tol2, CgState* st) {
+k_cg_check(const double* __restrict__ partB, int G, int first, int max_k, double tol2, CgState* st) {
   double t[3];
   reduce_partials<3>(partB, G, t);
   if (threadIdx.x != 0) return;
@@ -79,11 +80,13 @@ k_cg_check(const double* __restrict__ partB, int G, int first, int k_total, doub
     st->status = 0;
     st->done = 0;
     st->iters = 0;
+    st->k = 0;
+    st->max_k = max_k;
     st->zero_rhs = t[2] == 0.0 ? 1 : 0;
   }
   if (st->done) return;
   st->rr = t[1];
-  st->iters = k_total;
+  st->iters = st->k;
   if (!std::isfinite(t[0]) || !std::isfinite(t[1]) || !std::isfinite(st->bb)) {
     st->status = PISO_E_NAN;
     st->done = 1;
@@ -96,23 +99,25 @@ template <typename R, int D, bool ZOP = false>
 __global__ void __launch_bounds__(kWG)
 k_cg_spmv(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
           const R* __restrict__ dold, R* __restrict__ dnew, R* __restrict__ q, CgState* st,
-          const double* __restrict__ partB, double* __restrict__ partA, int Gp, int k) {
+          const double* __restrict__ partB, double* __restrict__ partA, int Gp, int par) {
   if (st->done) return;
+  const int kd = st->k;
   double t[2];
   reduce_partials<2>(partB, Gp, t);
   const double rz = t[0], rr = t[1];
-  if (!std::isfinite(rz) || !std::isfinite(rr) || rr <= st->tol2 * st->bb) {
+  if (!std::isfinite(rz) || !std::isfinite(rr) || rr <= st->tol2 * st->bb || kd >= st->max_k) {
     if (lead()) {
       st->rr = rr;
-      st->iters = k;
+      st->iters = kd;
       if (!std::isfinite(rz) || !std::isfinite(rr)) st->status = PISO_E_NAN;
+      else if (!(rr <= st->tol2 * st->bb)) st->status = PISO_NOT_CONVERGED;
       st->done = 1;
     }
     return;
   }
-  const R beta = k == 0 ? R(0) : (R)(rz / st->rz[(k + 1) & 1]);
+  const R beta = kd == 0 ? R(0) : (R)(rz / st->rz[par ^ 1]);
   if (lead()) {
-    st->rz[k & 1] = rz;
+    st->rz[par] = rz;
     st->rr = rr;
   }
   const int N = g.N;
@@ -141,7 +146,7 @@ template <typename R, bool RED = true>
 __global__ void __launch_bounds__(kWG)
 k_cg_update(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restrict__ r,
             const R* __restrict__ dnew, const R* __restrict__ q, CgState* st, const double* __restrict__ partA,
-            double* __restrict__ partB, int Gp, int k) {
+            double* __restrict__ partB, int Gp, int par, R* __restrict__ y, R omega) {
   if (st->done) return;
   double t[1];
   reduce_partials<1>(partA, Gp, t);
@@ -149,12 +154,13 @@ k_cg_update(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restrict_
   if (!(dq > 0.0) || !std::isfinite(dq)) {
     if (lead()) {
       st->status = std::isfinite(dq) ? PISO_BREAKDOWN : PISO_E_NAN;
-      st->iters = k;
+      st->iters = st->k;
       st->done = 1;
     }
     return;
   }
-  const R alpha = (R)(st->rz[k & 1] / dq);
+  const R alpha = (R)(st->rz[par] / dq);
+  if (lead()) st->k = st->k + 1;   // no other work-group reads the index in this kernel
   int beg, end;
   chunk_range(N, beg, end);
   double acc[2] = {0.0, 0.0};
@@ -165,6 +171,8 @@ k_cg_update(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restrict_
     if (RED) {
       acc[0] += (double)rn * (double)(Dinv[P] * rn);
       acc[1] += (double)rn * (double)rn;
+    } else {
+      y[P] = omega * Dinv[P] * rn;   // multigrid pre-smoothing of the new residual
     }
   }
   if (RED) write_partials<2>(acc, partB);
@@ -175,23 +183,25 @@ template <typename R, int D, bool ZOP = false>
 __global__ void __launch_bounds__(kWG)
 k_cg_spmv_q(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
             const R* __restrict__ dold, R* __restrict__ dnew, R* __restrict__ q, CgState* st,
-            const double* __restrict__ partB, double* __restrict__ partA, int Gp, int k) {
+            const double* __restrict__ partB, double* __restrict__ partA, int Gp, int par) {
   if (st->done) return;
+  const int kd = st->k;
   double t[2];
   reduce_partials<2>(partB, Gp, t);
   const double rz = t[0], rr = t[1];
-  if (!std::isfinite(rz) || !std::isfinite(rr) || rr <= st->tol2 * st->bb) {
+  if (!std::isfinite(rz) || !std::isfinite(rr) || rr <= st->tol2 * st->bb || kd >= st->max_k) {
     if (lead()) {
       st->rr = rr;
-      st->iters = k;
+      st->iters = kd;
       if (!std::isfinite(rz) || !std::isfinite(rr)) st->status = PISO_E_NAN;
+      else if (!(rr <= st->tol2 * st->bb)) st->status = PISO_NOT_CONVERGED;
       st->done = 1;
     }
     return;
   }
-  const R beta = k == 0 ? R(0) : (R)(rz / st->rz[(k + 1) & 1]);
+  const R beta = kd == 0 ? R(0) : (R)(rz / st->rz[par ^ 1]);
   if (lead()) {
-    st->rz[k & 1] = rz;
+    st->rz[par] = rz;
     st->rr = rr;
   }
   auto dq = [&](int P) {
@@ -228,7 +238,7 @@ template <typename R, bool RED = true>
 __global__ void __launch_bounds__(kWG)
 k_cg_update_q(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restrict__ r,
               const R* __restrict__ dnew, const R* __restrict__ q, CgState* st, const double* __restrict__ partA,
-              double* __restrict__ partB, int Gp, int k) {
+              double* __restrict__ partB, int Gp, int par, R* __restrict__ y, R omega) {
   if (st->done) return;
   double t[1];
   reduce_partials<1>(partA, Gp, t);
@@ -236,12 +246,13 @@ k_cg_update_q(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restric
   if (!(dq > 0.0) || !std::isfinite(dq)) {
     if (lead()) {
       st->status = std::isfinite(dq) ? PISO_BREAKDOWN : PISO_E_NAN;
-      st->iters = k;
+      st->iters = st->k;
       st->done = 1;
     }
     return;
   }
-  const R alpha = (R)(st->rz[k & 1] / dq);
+  const R alpha = (R)(st->rz[par] / dq);
+  if (lead()) st->k = st->k + 1;   // no other work-group reads the index in this kernel
   int beg, end;
   quad_range(N >> 2, beg, end);
   double acc[2] = {0.0, 0.0};
@@ -254,13 +265,18 @@ k_cg_update_q(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restric
       xv.v[e] += alpha * dv.v[e];
       rv.v[e] -= alpha * qv.v[e];
     }
+    const Q4<R> Dv = ldq(Dinv, P);
     if constexpr (RED) {
-      const Q4<R> Dv = ldq(Dinv, P);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         acc[0] += (double)rv.v[e] * (double)(Dv.v[e] * rv.v[e]);
         acc[1] += (double)rv.v[e] * (double)rv.v[e];
       }
+    } else {
+      Q4<R> yv;   // multigrid pre-smoothing of the new residual
+#pragma unroll
+      for (int e = 0; e < 4; ++e) yv.v[e] = omega * Dv.v[e] * rv.v[e];
+      stq(y, P, yv);
     }
     stq(x, P, xv);
     stq(r, P, rv);
@@ -618,98 +634,171 @@ static int check(piso_ctx* c, const char* what) {
   return PISO_OK;
 }
 
+// Operands of the PCG iterations.  The solver copies the caller's coefficients and
+// iterate into context-owned buffers, so that every pointer an iteration uses belongs
+// to the context and a recorded iteration stays valid for the context's lifetime.
+template <typename R>
+struct PcgOps {
+  const R* Pf;
+  const R* Dinv;
+  R* x;
+  R *r, *q, *d0, *d1, *z, *y;
+  double *pA, *pB;
+  int G;
+  bool mg, quad;
+};
+
+// One PCG iteration with slot parity par (the direction buffers alternate with it).
+template <typename R>
+static int pcg_iteration(piso_ctx* c, hipStream_t s, const PcgOps<R>& o, int par) {
+  const int N = c->N, G = o.G;
+  CgState* st = c->cg;
+  R* dold = par ? o.d1 : o.d0;
+  R* dnew = par ? o.d0 : o.d1;
+  const R* opnd = o.mg ? (const R*)o.z : (const R*)o.r;
+  const R om = (R)kMgOmega;
+  const double* pBc = o.pB;
+  if (o.quad) {
+    if (c->dim == 2) {
+      if (o.mg)
+        launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 2, true>, G, c->grid, o.Pf, o.Dinv, opnd,
+                     (const R*)dold, dnew, o.q, st, pBc, o.pA, G, par);
+      else
+        launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 2>, G, c->grid, o.Pf, o.Dinv, opnd, (const R*)dold,
+                     dnew, o.q, st, pBc, o.pA, G, par);
+    } else {
+      if (o.mg)
+        launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 3, true>, G, c->grid, o.Pf, o.Dinv, opnd,
+                     (const R*)dold, dnew, o.q, st, pBc, o.pA, G, par);
+      else
+        launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 3>, G, c->grid, o.Pf, o.Dinv, opnd, (const R*)dold,
+                     dnew, o.q, st, pBc, o.pA, G, par);
+    }
+    if (o.mg)
+      launch_timed(c, s, kTimeCgUpdate, k_cg_update_q<R, false>, G, N, o.Dinv, o.x, o.r, (const R*)dnew,
+                   (const R*)o.q, st, (const double*)o.pA, o.pB, G, par, o.y, om);
+    else
+      launch_timed(c, s, kTimeCgUpdate, k_cg_update_q<R>, G, N, o.Dinv, o.x, o.r, (const R*)dnew, (const R*)o.q,
+                   st, (const double*)o.pA, o.pB, G, par, o.y, om);
+  } else {
+    if (c->dim == 2) {
+      if (o.mg)
+        launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 2, true>, G, c->grid, o.Pf, o.Dinv, opnd, (const R*)dold,
+                     dnew, o.q, st, pBc, o.pA, G, par);
+      else
+        launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 2>, G, c->grid, o.Pf, o.Dinv, opnd, (const R*)dold, dnew,
+                     o.q, st, pBc, o.pA, G, par);
+    } else {
+      if (o.mg)
+        launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 3, true>, G, c->grid, o.Pf, o.Dinv, opnd, (const R*)dold,
+                     dnew, o.q, st, pBc, o.pA, G, par);
+      else
+        launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 3>, G, c->grid, o.Pf, o.Dinv, opnd, (const R*)dold, dnew,
+                     o.q, st, pBc, o.pA, G, par);
+    }
+    if (o.mg)
+      launch_timed(c, s, kTimeCgUpdate, k_cg_update<R, false>, G, N, o.Dinv, o.x, o.r, (const R*)dnew,
+                   (const R*)o.q, st, (const double*)o.pA, o.pB, G, par, o.y, om);
+    else
+      launch_timed(c, s, kTimeCgUpdate, k_cg_update<R>, G, N, o.Dinv, o.x, o.r, (const R*)dnew, (const R*)o.q, st,
+                   (const double*)o.pA, o.pB, G, par, o.y, om);
+  }
+  if (o.mg) return mg_apply<R>(c, s, o.Pf, o.Dinv, (const R*)o.r, (const R*)o.y, o.z, st, o.pB, G);
+  return check(c, "PCG iteration");
+}
+
+// Two iterations (parity 0 then 1) recorded once per preconditioner and replayed.
+template <typename R>
+static int pcg_graph(piso_ctx* c, const PcgOps<R>& o, hipGraphExec_t* out) {
+  if (!c->cap_stream) PISO_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  hipStream_t cs = c->cap_stream;
+  PISO_HIP(c, hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+  int rc = pcg_iteration<R>(c, cs, o, 0);
+  if (!rc) rc = pcg_iteration<R>(c, cs, o, 1);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(cs, &g);
+  if (rc || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return rc ? rc : fail(c, PISO_E_HIP, std::string("PCG graph capture: ") + hipGetErrorString(e));
+  }
+  const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return fail(c, PISO_E_HIP, std::string("PCG graph instantiate: ") + hipGetErrorString(ei));
+  return PISO_OK;
+}
+
 template <typename R, typename BT>
 static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const BT* b,
                    const double* mean, double sign, R* x, double rtol, int max_iter, int check_every,
                    int precond, int* iters_out, double* rel_out, int* status_out) {
   const int N = c->N, G = grid_red(N, c->red_grid);
-  R* r = (R*)c->k_r;
-  R* q = (R*)c->k_q;
-  R* d[2] = {(R*)c->k_d0, (R*)c->k_d1};
   CgState* st = c->cg;
-  double* pA = part(c, kPartA);
-  double* pB = part(c, kPartB);
-  const double tol2 = rtol * rtol;
+  PcgOps<R> o;
+  o.Pf = (const R*)c->g_Pf;
+  o.Dinv = (const R*)c->g_Dinv;
+  o.x = (R*)c->g_x;
+  o.r = (R*)c->k_r;
+  o.q = (R*)c->k_q;
+  o.d0 = (R*)c->k_d0;
+  o.d1 = (R*)c->k_d1;
+  o.z = (R*)c->k_z;
+  o.y = (R*)c->k_y;
+  o.pA = part(c, kPartA);
+  o.pB = part(c, kPartB);
+  o.G = G;
   // multigrid: z = B r is stored by the V-cycle (which also writes the r.z, r.r
   // partials); the stencil kernel then forms d from z instead of Dinv r
-  const bool mg = precond == PISO_PRECOND_MG && !c->mg.empty();
-  R* z = (R*)c->k_z;
-  if (mg) {
-    if (int rc = mg_setup<R>(c, s, Pf)) return rc;
+  o.mg = precond == PISO_PRECOND_MG && !c->mg.empty();
+  o.quad = c->quad;   // the context's buffers are 256-byte aligned
+  const size_t es = sizeof(R);
+  PISO_HIP(c, hipMemcpyAsync((void*)o.Pf, Pf, es * (size_t)c->dim * N, hipMemcpyDeviceToDevice, s));
+  PISO_HIP(c, hipMemcpyAsync((void*)o.Dinv, Dinv, es * (size_t)N, hipMemcpyDeviceToDevice, s));
+  PISO_HIP(c, hipMemcpyAsync(o.x, x, es * (size_t)N, hipMemcpyDeviceToDevice, s));
+  const double tol2 = rtol * rtol;
+  if (o.mg) {
+    if (int rc = mg_setup<R>(c, s, o.Pf)) return rc;
   }
   if (c->dim == 2)
-    k_cg_init<R, BT, 2><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, b, mean, sign, x, r, d[0], pB);
+    k_cg_init<R, BT, 2><<<G, kWG, 0, s>>>(c->grid, o.Pf, o.Dinv, b, mean, sign, o.x, o.r, o.d0, o.pB);
   else
-    k_cg_init<R, BT, 3><<<G, kWG, 0, s>>>(c->grid, Pf, Dinv, b, mean, sign, x, r, d[0], pB);
-  k_cg_check<<<1, kWG, 0, s>>>(pB, G, 1, 0, tol2, st);
+    k_cg_init<R, BT, 3><<<G, kWG, 0, s>>>(c->grid, o.Pf, o.Dinv, b, mean, sign, o.x, o.r, o.d0, o.pB);
+  k_cg_check<<<1, kWG, 0, s>>>(o.pB, G, 1, max_iter, tol2, st);
   if (int rc = check(c, "k_cg_init")) return rc;
-  if (mg) {
-    if (int rc = mg_apply<R>(c, s, Pf, Dinv, (const R*)r, z, st, pB, G)) return rc;
+  if (o.mg) {
+    if (int rc = mg_prescale<R>(c, s, o.Dinv, (const R*)o.r, o.y)) return rc;
+    if (int rc = mg_apply<R>(c, s, o.Pf, o.Dinv, (const R*)o.r, (const R*)o.y, o.z, st, o.pB, G)) return rc;
   }
   PISO_HIP(c, hipMemcpyAsync(c->h_cg, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
   PISO_HIP(c, hipStreamSynchronize(s));
-  if (c->h_cg->zero_rhs) PISO_HIP(c, hipMemsetAsync(x, 0, sizeof(R) * (size_t)N, s));
-  int it = 0;
-  if (check_every < 1) check_every = 8;
-  // the vectorised kernels need 16-byte aligned operands (caller buffers may be views)
-  const bool quad = c->quad && ((((uintptr_t)Pf) | ((uintptr_t)Dinv) | ((uintptr_t)x)) & 15u) == 0;
-  const R* opnd = mg ? (const R*)z : (const R*)r;
-  while (!c->h_cg->done && it < max_iter) {
-    const int n = std::min(check_every, max_iter - it);
-    for (int k = 0; k < n; ++k, ++it) {
-      R* dold = d[it & 1];
-      R* dnew = d[(it + 1) & 1];
-      if (quad) {
-        if (mg) {
-          if (c->dim == 2)
-            launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 2, true>, G, c->grid, Pf, Dinv, opnd, (const R*)dold, dnew,
-                         q, st, (const double*)pB, pA, G, it);
-          else
-            launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 3, true>, G, c->grid, Pf, Dinv, opnd, (const R*)dold, dnew,
-                         q, st, (const double*)pB, pA, G, it);
-          launch_timed(c, s, kTimeCgUpdate, k_cg_update_q<R, false>, G, N, Dinv, x, r, (const R*)dnew, (const R*)q, st,
-                       (const double*)pA, pB, G, it);
-        } else {
-          if (c->dim == 2)
-            launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 2>, G, c->grid, Pf, Dinv, opnd, (const R*)dold, dnew, q,
-                         st, (const double*)pB, pA, G, it);
-          else
-            launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 3>, G, c->grid, Pf, Dinv, opnd, (const R*)dold, dnew, q,
-                         st, (const double*)pB, pA, G, it);
-          launch_timed(c, s, kTimeCgUpdate, k_cg_update_q<R>, G, N, Dinv, x, r, (const R*)dnew, (const R*)q, st,
-                       (const double*)pA, pB, G, it);
-        }
+  if (c->h_cg->zero_rhs) PISO_HIP(c, hipMemsetAsync(o.x, 0, es * (size_t)N, s));
+  // chunks of an even number of iterations: the recorded pair keeps the slot parity
+  if (check_every < 2) check_every = 2;
+  check_every += check_every & 1;
+  // replay the recorded pair unless the kernels are being timed one by one
+  hipGraphExec_t* gx = &c->cg_graph[o.mg ? 1 : 0];
+  const bool use_graph = !c->timing.enabled && c->use_graphs;
+  if (use_graph && !*gx) {
+    if (int rc = pcg_graph<R>(c, o, gx)) return rc;
+  }
+  int launched = 0;
+  while (!c->h_cg->done && launched < max_iter) {
+    for (int k = 0; k < check_every; k += 2) {
+      if (use_graph) {
+        PISO_HIP(c, hipGraphLaunch(*gx, s));
       } else {
-        if (mg) {
-          if (c->dim == 2)
-            launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 2, true>, G, c->grid, Pf, Dinv, opnd, (const R*)dold, dnew,
-                         q, st, (const double*)pB, pA, G, it);
-          else
-            launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 3, true>, G, c->grid, Pf, Dinv, opnd, (const R*)dold, dnew,
-                         q, st, (const double*)pB, pA, G, it);
-          launch_timed(c, s, kTimeCgUpdate, k_cg_update<R, false>, G, N, Dinv, x, r, (const R*)dnew, (const R*)q, st,
-                       (const double*)pA, pB, G, it);
-        } else {
-          if (c->dim == 2)
-            launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 2>, G, c->grid, Pf, Dinv, opnd, (const R*)dold, dnew, q,
-                         st, (const double*)pB, pA, G, it);
-          else
-            launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 3>, G, c->grid, Pf, Dinv, opnd, (const R*)dold, dnew, q,
-                         st, (const double*)pB, pA, G, it);
-          launch_timed(c, s, kTimeCgUpdate, k_cg_update<R>, G, N, Dinv, x, r, (const R*)dnew, (const R*)q, st,
-                       (const double*)pA, pB, G, it);
-        }
-      }
-      if (mg) {
-        if (int rc = mg_apply<R>(c, s, Pf, Dinv, (const R*)r, z, st, pB, G)) return rc;
+        if (int rc = pcg_iteration<R>(c, s, o, 0)) return rc;
+        if (int rc = pcg_iteration<R>(c, s, o, 1)) return rc;
       }
     }
-  k_cg_check<<<1, kWG, 0, s>>>(pB, G, 0, it, tol2, st);
+    launched += check_every;
+    k_cg_check<<<1, kWG, 0, s>>>(o.pB, G, 0, max_iter, tol2, st);
     if (int rc = check(c, "k_cg iteration")) return rc;
     PISO_HIP(c, hipMemcpyAsync(c->h_cg, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
     PISO_HIP(c, hipStreamSynchronize(s));
     timing_collect(c);
   }
+  PISO_HIP(c, hipMemcpyAsync(x, o.x, es * (size_t)N, hipMemcpyDeviceToDevice, s));
   const CgState& h = *c->h_cg;
   *iters_out += h.iters;
   *rel_out = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;

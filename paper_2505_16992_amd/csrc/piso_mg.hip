@@ -54,80 +54,111 @@ k_mg_coef(int n, int K, const int* __restrict__ ptr, const int* __restrict__ idx
 }
 
 // Restriction from the fine grid: rc[I] = sum over the children P of aggregate I of the
-// residual r_P - (M x)_P of the pre-smoothed x = omega D^-1 r.  Faces between two
-// children of I cancel in the sum and are skipped; the children's positions follow
-// from the aggregate's (g1 is level 1 as a block table).
+// residual r_P - (M y)_P of the pre-smoothed y = omega D^-1 r (stored by the PCG update).
+// Faces between two children of I cancel in the sum and are skipped.  One thread per
+// (aggregate, child) -- the child's position follows from the aggregate's (g1 is level
+// 1 as a block table) -- and a fixed shuffle butterfly sums the 2^d lanes.
 template <typename R, int D>
 __global__ void __launch_bounds__(kWG)
-k_mg_down0(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
-           R omega, R* __restrict__ rc, const CgState* st) {
+k_mg_down0(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ y, const R* __restrict__ r,
+           R* __restrict__ rc, const CgState* st) {
   if (st->done) return;
-  const int I = blockIdx.x * kWG + threadIdx.x;
-  if (I >= g1.N) return;
-  const int N = g.N;
-  const Cell cc = locate(g1, I);
-  const int* t = g.tab + cc.b * kTabStride;
-  const int n[3] = {t[1], t[2], t[3]};
-  R acc = R(0);
-#pragma unroll
-  for (int q = 0; q < (1 << D); ++q) {
+  constexpr int NCH = 1 << D;
+  const int t = blockIdx.x * kWG + threadIdx.x;
+  const int I = t / NCH, q = t % NCH;
+  R v = R(0);
+  if (I < g1.N) {
+    const int N = g.N;
+    const Cell cc = locate(g1, I);
+    const int* tb = g.tab + cc.b * kTabStride;
+    const int n[3] = {tb[1], tb[2], tb[3]};
     const int bit[3] = {q & 1, (q >> 1) & 1, (q >> 2) & 1};
     Cell c;
     c.b = cc.b;
     c.i = 2 * cc.i + bit[0];
     c.j = 2 * cc.j + bit[1];
     c.k = 2 * cc.k + bit[2];
-    if (c.i >= n[0] || c.j >= n[1] || c.k >= n[2]) continue;
-    const int pos[3] = {c.i, c.j, c.k};
-    const int P = t[0] + c.i + n[0] * (c.j + n[1] * c.k);
-    const R rP = r[P];
-    const R xP = omega * Dinv[P] * rP;
-    R res = rP;
+    if (c.i < n[0] && c.j < n[1] && c.k < n[2]) {
+      const int pos[3] = {c.i, c.j, c.k};
+      const int P = tb[0] + c.i + n[0] * (c.j + n[1] * c.k);
+      const R yP = y[P];
+      R res = r[P];
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
+      for (int j = 0; j < D; ++j) {
 #pragma unroll
-      for (int sd = 0; sd < 2; ++sd) {
-        const bool internal = sd ? (bit[j] == 0 && pos[j] + 1 < n[j]) : (bit[j] == 1);
-        if (internal) continue;
-        const int F = neighbour(g, c, P, j, sd);
-        if (F >= 0) {
-          const R w = sd ? Pf[(size_t)j * N + P] : Pf[(size_t)j * N + F];
-          res -= w * (xP - omega * Dinv[F] * r[F]);
+        for (int sd = 0; sd < 2; ++sd) {
+          const bool internal = sd ? (bit[j] == 0 && pos[j] + 1 < n[j]) : (bit[j] == 1);
+          if (internal) continue;
+          const int F = neighbour(g, c, P, j, sd);
+          if (F >= 0) {
+            const R w = sd ? Pf[(size_t)j * N + P] : Pf[(size_t)j * N + F];
+            res -= w * (yP - y[F]);
+          }
         }
       }
+      v = res;
     }
-    acc += res;
   }
-  rc[I] = acc;
+#pragma unroll
+  for (int o = 1; o < NCH; o <<= 1) v += __shfl_xor(v, o, 64);
+  if (I < g1.N && q == 0) rc[I] = v;
 }
 
-// Restriction between coarse levels (level lf, graph form) to the next level.
+// y = omega D^-1 r (pre-smoothing from zero) after the PCG initialisation.
+template <typename R>
+__global__ void __launch_bounds__(kWG)
+k_mg_prescale(int N, const R* __restrict__ Dinv, const R* __restrict__ r, R omega, R* __restrict__ y) {
+  const int P = blockIdx.x * kWG + threadIdx.x;
+  if (P < N) y[P] = omega * Dinv[P] * r[P];
+}
+
+// Restriction between coarse levels (graph form).  One thread per (aggregate, child)
+// so that the loads of different children are in flight together; a graph row is read
+// as independent loads (up to kMgRowMax slots unrolled), and the NCH lanes of an
+// aggregate are summed with a fixed butterfly of shuffles (deterministic).
+constexpr int kMgRowMax = 8;
+
+template <typename R>
+__device__ __forceinline__ R mg_row_residual(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W,
+                                             const R* __restrict__ Dinv, const R* __restrict__ r, int P, R omega) {
+  const R rP = r[P];
+  const R xP = omega * Dinv[P] * rP;
+  int q[kMgRowMax];
+#pragma unroll
+  for (int s = 0; s < kMgRowMax; ++s) q[s] = s < K ? nbr[s * n + P] : -1;
+  R res = rP;
+#pragma unroll
+  for (int s = 0; s < kMgRowMax; ++s)
+    if (q[s] >= 0) res -= W[s * n + P] * (xP - omega * Dinv[q[s]] * r[q[s]]);
+  for (int s = kMgRowMax; s < K; ++s) {
+    const int Q = nbr[s * n + P];
+    if (Q >= 0) res -= W[s * n + P] * (xP - omega * Dinv[Q] * r[Q]);
+  }
+  return res;
+}
+
 template <typename R, int NCH>
 __global__ void __launch_bounds__(kWG)
 k_mg_down(int nf, int Kf, const int* __restrict__ nbr, const R* __restrict__ W, const R* __restrict__ Dinv,
           const R* __restrict__ r, const int* __restrict__ child, int nc, R omega, R* __restrict__ rc,
           const CgState* st) {
   if (st->done) return;
-  const int I = blockIdx.x * kWG + threadIdx.x;
-  if (I >= nc) return;
-  R acc = R(0);
-#pragma unroll
-  for (int q = 0; q < NCH; ++q) {
+  const int t = blockIdx.x * kWG + threadIdx.x;
+  const int I = t / NCH, q = t % NCH;
+  R v = R(0);
+  if (I < nc) {
     const int P = child[q * nc + I];
-    if (P < 0) continue;
-    const R rP = r[P];
-    const R xP = omega * Dinv[P] * rP;
-    R res = rP;
-    for (int s = 0; s < Kf; ++s) {
-      const int Q = nbr[s * nf + P];
-      if (Q >= 0) res -= W[s * nf + P] * (xP - omega * Dinv[Q] * r[Q]);
-    }
-    acc += res;
+    if (P >= 0) v = mg_row_residual<R>(nf, Kf, nbr, W, Dinv, r, P, omega);
   }
-  rc[I] = acc;
+#pragma unroll
+  for (int o = 1; o < NCH; o <<= 1) v += __shfl_xor(v, o, 64);
+  if (I < nc && q == 0) rc[I] = v;
 }
 
 // Coarsest level (n <= 64 cells, one wave): e = sweeps damped Jacobi sweeps from zero.
+// The cell's graph row is held in registers (up to kMgRowMax slots) so that a sweep
+// touches only the shared iterate.
+
 template <typename R>
 __global__ void __launch_bounds__(64)
 k_mg_coarse(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, const R* __restrict__ Dinv,
@@ -138,16 +169,24 @@ k_mg_coarse(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, 
   const bool on = I < n;
   const R rI = on ? r[I] : R(0);
   const R dI = on ? Dinv[I] : R(0);
+  int q[kMgRowMax];
+  R w[kMgRowMax];
+#pragma unroll
+  for (int s = 0; s < kMgRowMax; ++s) {
+    q[s] = (on && s < K) ? nbr[s * n + I] : -1;
+    w[s] = q[s] >= 0 ? W[s * n + I] : R(0);
+    if (q[s] < 0) q[s] = I;   // an absent slot contributes w (x - x) = 0
+  }
   R x = omega * dI * rI;
   xs[I] = x;
   __syncthreads();
   for (int it = 1; it < sweeps; ++it) {
     R mx = R(0);
-    if (on) {
-      for (int s = 0; s < K; ++s) {
-        const int Q = nbr[s * n + I];
-        if (Q >= 0) mx += W[s * n + I] * (x - xs[Q]);
-      }
+#pragma unroll
+    for (int s = 0; s < kMgRowMax; ++s) mx += w[s] * (x - xs[q[s]]);
+    for (int s = kMgRowMax; s < K; ++s) {   // rows longer than the register block
+      const int Q = on ? nbr[s * n + I] : -1;
+      if (Q >= 0) mx += W[s * n + I] * (x - xs[Q]);
     }
     x += omega * dI * (rI - mx);
     __syncthreads();
@@ -158,7 +197,7 @@ k_mg_coarse(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, 
 }
 
 // Prolongation and post-smoothing on a coarse level: with z = omega D^-1 r + ec[parent],
-// e = z + omega D^-1 (r - M z).
+// e = z + omega D^-1 (r - M z).  The row's loads are issued together (unrolled slots).
 template <typename R>
 __global__ void __launch_bounds__(kWG)
 k_mg_up(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, const R* __restrict__ Dinv,
@@ -169,8 +208,14 @@ k_mg_up(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, cons
   if (P >= n) return;
   const R rP = r[P], dP = Dinv[P];
   const R zP = omega * dP * rP + ec[parent[P]];
+  int q[kMgRowMax];
+#pragma unroll
+  for (int s = 0; s < kMgRowMax; ++s) q[s] = s < K ? nbr[s * n + P] : -1;
   R mz = R(0);
-  for (int s = 0; s < K; ++s) {
+#pragma unroll
+  for (int s = 0; s < kMgRowMax; ++s)
+    if (q[s] >= 0) mz += W[s * n + P] * (zP - (omega * Dinv[q[s]] * r[q[s]] + ec[parent[q[s]]]));
+  for (int s = kMgRowMax; s < K; ++s) {
     const int Q = nbr[s * n + P];
     if (Q >= 0) mz += W[s * n + P] * (zP - (omega * Dinv[Q] * r[Q] + ec[parent[Q]]));
   }
@@ -183,13 +228,14 @@ __device__ __forceinline__ int mg_parent(const Grid& g1, int b, int i, int j, in
   return t[0] + (i >> 1) + t[1] * ((j >> 1) + t[2] * (k >> 1));
 }
 
-// The same on the fine grid, writing z and the partial sums of r.z and r.r.  Parents of
+// The same on the fine grid (with y = omega D^-1 r as stored by the PCG update), writing
+// z and the partial sums of r.z and r.r.  Parents of
 // neighbours inside the block follow from the coordinates; across a block side they
 // come from the parent table.
 template <typename R, int D>
 __global__ void __launch_bounds__(kWG)
 k_mg_up0(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
-         const int* __restrict__ parent, const R* __restrict__ ec, R omega, R* __restrict__ z,
+         const R* __restrict__ y, const int* __restrict__ parent, const R* __restrict__ ec, R omega, R* __restrict__ z,
          double* __restrict__ partB, const CgState* st) {
   if (st->done) return;
   const int N = g.N;
@@ -200,7 +246,7 @@ k_mg_up0(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ Dinv, 
     const Cell c = locate(g, P);
     const int* t = g.tab + c.b * kTabStride;
     const R rP = r[P], dP = Dinv[P];
-    const R zP = omega * dP * rP + ec[mg_parent(g1, c.b, c.i, c.j, c.k)];
+    const R zP = y[P] + ec[mg_parent(g1, c.b, c.i, c.j, c.k)];
     R mz = R(0);
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -215,7 +261,7 @@ k_mg_up0(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ Dinv, 
                                             c.k + (j == 2 ? dd : 0))
                                 : parent[F];
           const R w = sd ? Pf[(size_t)j * N + P] : Pf[(size_t)j * N + F];
-          mz += w * (zP - (omega * Dinv[F] * r[F] + ec[pF]));
+          mz += w * (zP - (y[F] + ec[pF]));
         }
       }
     }
@@ -232,7 +278,7 @@ k_mg_up0(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ Dinv, 
 template <typename R, int D>
 __global__ void __launch_bounds__(kWG)
 k_mg_up0_q(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
-           const int* __restrict__ parent, const R* __restrict__ ec, R omega, R* __restrict__ z,
+           const R* __restrict__ y, const int* __restrict__ parent, const R* __restrict__ ec, R omega, R* __restrict__ z,
            double* __restrict__ partB, const CgState* st) {
   if (st->done) return;
   int beg, end;
@@ -244,7 +290,7 @@ k_mg_up0_q(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ Dinv
     const int* t = g.tab + c.b * kTabStride;
     const int nxy = t[1] * t[2];
     const int* t1 = g1.tab + c.b * kTabStride;
-    // operand z = omega D^-1 r + e[parent] over the quad at P (P0 or a y/z neighbour)
+    // operand z = y + e[parent] over the quad at P (P0 or a y/z neighbour)
     auto dq = [&](int P) {
       int jj = c.j, kk = c.k;
       const int dl = P - P0;
@@ -254,15 +300,15 @@ k_mg_up0_q(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ Dinv
       }
       const int base = t1[0] + (c.i >> 1) + t1[1] * ((jj >> 1) + t1[2] * (kk >> 1));
       const R e0 = ec[base], e1 = ec[base + 1];
-      const Q4<R> a = ldq(Dinv, P), b = ldq(r, P);
+      const Q4<R> a = ldq(y, P);
       Q4<R> o;
-      o.v[0] = omega * a.v[0] * b.v[0] + e0;
-      o.v[1] = omega * a.v[1] * b.v[1] + e0;
-      o.v[2] = omega * a.v[2] * b.v[2] + e1;
-      o.v[3] = omega * a.v[3] * b.v[3] + e1;
+      o.v[0] = a.v[0] + e0;
+      o.v[1] = a.v[1] + e0;
+      o.v[2] = a.v[2] + e1;
+      o.v[3] = a.v[3] + e1;
       return o;
     };
-    auto d1 = [&](int P) { return omega * Dinv[P] * r[P] + ec[parent[P]]; };
+    auto d1 = [&](int P) { return y[P] + ec[parent[P]]; };
     const Q4<R> zq = dq(P0);
     const Q4<R> M = quad_stencil<R, D>(g, c, P0, Pf, zq, dq, d1);
     const Q4<R> rq = ldq(r, P0), Dq = ldq(Dinv, P0);
@@ -453,6 +499,7 @@ int mg_build(piso_ctx* c) {
   if (!c->mg.empty() && c->mg.back().n > kMgCoarse) c->mg.clear();   // cannot happen: blocks <= 16
   if (!c->mg.empty()) {
     if (int rc = dev_alloc(c, &c->k_z, (size_t)c->N * c->esz)) return rc;
+    if (int rc = dev_alloc(c, &c->k_y, (size_t)c->N * c->esz)) return rc;
   }
   return PISO_OK;
 }
@@ -474,26 +521,32 @@ int mg_setup(piso_ctx* c, hipStream_t s, const R* Pf) {
 }
 
 template <typename R>
-int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, R* z, CgState* st,
+int mg_prescale(piso_ctx* c, hipStream_t s, const R* Dinv, const R* r, R* y) {
+  k_mg_prescale<R><<<grid_cells(c->N), kWG, 0, s>>>(c->N, Dinv, r, (R)kMgOmega, y);
+  return mg_check(c, "k_mg_prescale");
+}
+
+template <typename R>
+int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, const R* y, R* z, CgState* st,
              double* partB, int G) {
   const int nl = (int)c->mg.size();
   const R om = (R)kMgOmega;
   const Grid& g1 = c->mg_g1;
   if (c->dim == 2)
-    launch_timed(c, s, kTimeMgDown0, k_mg_down0<R, 2>, grid_cells(g1.N), c->grid, g1, Pf, Dinv, r, om,
+    launch_timed(c, s, kTimeMgDown0, k_mg_down0<R, 2>, grid_cells(4 * g1.N), c->grid, g1, Pf, y, r,
                  (R*)c->mg[0].r, (const CgState*)st);
   else
-    launch_timed(c, s, kTimeMgDown0, k_mg_down0<R, 3>, grid_cells(g1.N), c->grid, g1, Pf, Dinv, r, om,
+    launch_timed(c, s, kTimeMgDown0, k_mg_down0<R, 3>, grid_cells(8 * g1.N), c->grid, g1, Pf, y, r,
                  (R*)c->mg[0].r, (const CgState*)st);
   for (int l = 1; l < nl; ++l) {
     const MgLevel& F = c->mg[l - 1];
     const MgLevel& C = c->mg[l];
     if (c->dim == 2)
-      launch_timed(c, s, kTimeMgCoarse, k_mg_down<R, 4>, grid_cells(C.n), F.n, F.K, (const int*)F.nbr,
+      launch_timed(c, s, kTimeMgCoarse, k_mg_down<R, 4>, grid_cells(4 * C.n), F.n, F.K, (const int*)F.nbr,
                    (const R*)F.W, (const R*)F.Dinv, (const R*)F.r, (const int*)C.child, C.n, om, (R*)C.r,
                    (const CgState*)st);
     else
-      launch_timed(c, s, kTimeMgCoarse, k_mg_down<R, 8>, grid_cells(C.n), F.n, F.K, (const int*)F.nbr,
+      launch_timed(c, s, kTimeMgCoarse, k_mg_down<R, 8>, grid_cells(8 * C.n), F.n, F.K, (const int*)F.nbr,
                    (const R*)F.W, (const R*)F.Dinv, (const R*)F.r, (const int*)C.child, C.n, om, (R*)C.r,
                    (const CgState*)st);
   }
@@ -511,22 +564,22 @@ int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r,
   }
   {
     const MgLevel& L1 = c->mg[0];
-    const bool quad =
-        c->quad && ((((uintptr_t)Pf) | ((uintptr_t)Dinv) | ((uintptr_t)r) | ((uintptr_t)z)) & 15u) == 0;
+    const bool quad = c->quad && ((((uintptr_t)Pf) | ((uintptr_t)Dinv) | ((uintptr_t)r) | ((uintptr_t)y) |
+                                   ((uintptr_t)z)) & 15u) == 0;
     const R* e1 = (const R*)L1.e;
     if (quad) {
       if (c->dim == 2)
-        launch_timed(c, s, kTimeMgUp0, k_mg_up0_q<R, 2>, G, c->grid, g1, Pf, Dinv, r, (const int*)L1.parent, e1,
+        launch_timed(c, s, kTimeMgUp0, k_mg_up0_q<R, 2>, G, c->grid, g1, Pf, Dinv, r, y, (const int*)L1.parent, e1,
                      om, z, partB, (const CgState*)st);
       else
-        launch_timed(c, s, kTimeMgUp0, k_mg_up0_q<R, 3>, G, c->grid, g1, Pf, Dinv, r, (const int*)L1.parent, e1,
+        launch_timed(c, s, kTimeMgUp0, k_mg_up0_q<R, 3>, G, c->grid, g1, Pf, Dinv, r, y, (const int*)L1.parent, e1,
                      om, z, partB, (const CgState*)st);
     } else {
       if (c->dim == 2)
-        launch_timed(c, s, kTimeMgUp0, k_mg_up0<R, 2>, G, c->grid, g1, Pf, Dinv, r, (const int*)L1.parent, e1, om,
+        launch_timed(c, s, kTimeMgUp0, k_mg_up0<R, 2>, G, c->grid, g1, Pf, Dinv, r, y, (const int*)L1.parent, e1, om,
                      z, partB, (const CgState*)st);
       else
-        launch_timed(c, s, kTimeMgUp0, k_mg_up0<R, 3>, G, c->grid, g1, Pf, Dinv, r, (const int*)L1.parent, e1, om,
+        launch_timed(c, s, kTimeMgUp0, k_mg_up0<R, 3>, G, c->grid, g1, Pf, Dinv, r, y, (const int*)L1.parent, e1, om,
                      z, partB, (const CgState*)st);
     }
   }
@@ -535,9 +588,11 @@ int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r,
 
 template int mg_setup<float>(piso_ctx*, hipStream_t, const float*);
 template int mg_setup<double>(piso_ctx*, hipStream_t, const double*);
-template int mg_apply<float>(piso_ctx*, hipStream_t, const float*, const float*, const float*, float*, CgState*,
-                             double*, int);
-template int mg_apply<double>(piso_ctx*, hipStream_t, const double*, const double*, const double*, double*,
-                              CgState*, double*, int);
+template int mg_prescale<float>(piso_ctx*, hipStream_t, const float*, const float*, float*);
+template int mg_prescale<double>(piso_ctx*, hipStream_t, const double*, const double*, double*);
+template int mg_apply<float>(piso_ctx*, hipStream_t, const float*, const float*, const float*, const float*, float*,
+                             CgState*, double*, int);
+template int mg_apply<double>(piso_ctx*, hipStream_t, const double*, const double*, const double*, const double*,
+                              double*, CgState*, double*, int);
 
 }  // namespace piso
