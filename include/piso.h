@@ -114,7 +114,9 @@ typedef struct {
   double rtol;                     /* stop when ||b - M x||_2 <= rtol ||b||_2 (per component) */
   int32_t max_iter;                /* Krylov iterations (MIXED pressure: inner iterations per sweep) */
   int32_t check_every;             /* iterations between convergence read-backs */
-  double inner_rtol;               /* MIXED pressure only: inner float PCG tolerance */
+  double inner_rtol;               /* MIXED pressure only: smallest inner float PCG tolerance;
+                                      each sweep asks for the residual reduction still
+                                      needed (with a factor-2 margin), but not below this */
   int32_t max_refine;              /* MIXED pressure only: refinement sweeps */
   int32_t precond;                 /* piso_precond; PISO_PRECOND_MG is accepted for the pressure
                                       only (PISO_E_ARG for the velocity solve) */
@@ -186,7 +188,7 @@ int piso_sizes(const piso_ctx* ctx, int64_t* n_cells, int64_t* n_bfaces, int64_t
 int piso_mg_info(const piso_ctx* ctx, int32_t* n_levels, int64_t* cells, int32_t* slots);
 
 /* Default options for a precision: vel rtol 1e-10 (F64) / 1e-7, Jacobi; pres rtol 1e-10
- * (F64), 1e-6 (F32), 1e-8 (MIXED, inner 5e-5), multigrid-preconditioned, read back every
+ * (F64), 1e-6 (F32), 1e-8 (MIXED, inner floor 1e-5), multigrid-preconditioned, read back every
  * 4 iterations; 2 correctors, grad_p_in_predictor = 1. */
 void piso_default_step_opts(int32_t precision, piso_step_opts* opts);
 
@@ -292,6 +294,17 @@ int piso_outflow_update(piso_ctx* ctx, void* stream, const void* u_n, const void
 int piso_outflow_update_backward(piso_ctx* ctx, void* stream, const void* u_n, const void* u_b,
                                  const int32_t* outflow, const double* u_m, double dt,
                                  const void* du_b_out, void* du_n, void* du_b);
+
+/* Divergence-free gradient modification (Sec. 3.1, eq. SgradPsgrad) for a learned
+ * source (or velocity correction) S [d][N] with incoming gradient dS [d][N]: solves the
+ * extra pressure equation with the step's operators at A = 1,
+ *     P(A = 1) p_S = div lerp(J T . S) - mean   (no Dirichlet flux, zero lagged
+ *     pressure, x0 = 0, opts as for piso_solve_pressure),
+ * and writes dS_out = dS + lambda grad p_S (the correction's central gradient with
+ * p_b = p_P).  S - grad p_S then has zero corrected face-flux divergence.  p_S [N] is
+ * written if not NULL.  Uses the context's step workspaces; dS_out may alias dS, not S. */
+int piso_divfree_gradient(piso_ctx* ctx, void* stream, const void* S, const void* dS, double lambda,
+                          const piso_solve_opts* opts, void* dS_out, void* p_S, piso_solve_info* info);
 
 /* Online turbulence statistics over homogeneous planes (Sec. 2.5), for single-block
  * contexts (PISO_E_ARG otherwise).  The planes are normal to `axis` (0 .. d-1); every

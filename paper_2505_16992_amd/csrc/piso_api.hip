@@ -647,7 +647,7 @@ void piso_default_step_opts(int32_t precision, piso_step_opts* o) {
   o->pres.check_every = 4;
   o->pres.precond = PISO_PRECOND_MG;
   o->vel.precond = PISO_PRECOND_JACOBI;
-  o->pres.inner_rtol = 5e-5;
+  o->pres.inner_rtol = 1e-5;
   o->pres.max_refine = 20;
   o->vel.inner_rtol = 1e-3;
   o->vel.max_refine = 0;

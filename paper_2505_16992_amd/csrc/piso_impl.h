@@ -78,7 +78,7 @@ struct MgLevel {
   void* e = nullptr;      // [n] correction
 };
 
-constexpr int kMgCoarse = 64;       // stop coarsening at this many cells (one wave solves it)
+constexpr int kMgCoarse = 256;      // stop coarsening at this many cells (one work-group solves it)
 constexpr int kMgMaxLevels = 16;
 constexpr int kMgCoarseSweeps = 24; // damped Jacobi sweeps on the coarsest level
 constexpr double kMgOmega = 0.8;    // Jacobi damping of the smoother

@@ -871,7 +871,10 @@ int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const float* Pf, const floa
     PISO_HIP(c, hipMemsetAsync(e32, 0, sizeof(float) * (size_t)N, s));
     int st_in = 0;
     double rel_in = 0.0;
-    int rc = pcg_run<float, float>(c, s, Pf, Dinv, r32, nullptr, 1.0, e32, o->inner_rtol, o->max_iter,
+    // ask the inner solve only for the reduction still missing (with a margin of 2), but
+    // never for more than inner_rtol, the floor the float iteration reliably reaches
+    const double tol_in = std::min(0.5, std::max(o->inner_rtol, 0.5 * o->rtol / rel));
+    int rc = pcg_run<float, float>(c, s, Pf, Dinv, r32, nullptr, 1.0, e32, tol_in, o->max_iter,
                                    o->check_every, o->precond, &iters, &rel_in, &st_in);
     if (rc) return rc;
     if (st_in < 0) {

@@ -17,7 +17,7 @@
 //
 // One application z = B r is a V-cycle from a zero guess: on each level one damped
 // Jacobi sweep before and one after the coarse correction (omega = 0.8), a fixed
-// number of damped Jacobi sweeps on the coarsest level (<= 64 cells, one wave).
+// number of damped Jacobi sweeps on the coarsest level (<= 256 cells, one work-group).
 // Every step is a fixed linear map and the pre- and post-smoothers are the same
 // symmetric operator, so B is symmetric positive definite on the range of M and the
 // outer CG keeps its theory.  The pre-smoothing result omega D^-1 r is never stored:
@@ -155,16 +155,17 @@ k_mg_down(int nf, int Kf, const int* __restrict__ nbr, const R* __restrict__ W, 
   if (I < nc && q == 0) rc[I] = v;
 }
 
-// Coarsest level (n <= 64 cells, one wave): e = sweeps damped Jacobi sweeps from zero.
+// Coarsest level (n <= kMgCoarse cells, one work-group): e = sweeps damped Jacobi sweeps
+// from zero.
 // The cell's graph row is held in registers (up to kMgRowMax slots) so that a sweep
 // touches only the shared iterate.
 
 template <typename R>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(kMgCoarse)
 k_mg_coarse(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, const R* __restrict__ Dinv,
             const R* __restrict__ r, R omega, int sweeps, R* __restrict__ e, const CgState* st) {
   if (st->done) return;
-  __shared__ R xs[kMgCoarse];
+  __shared__ R xs[2][kMgCoarse];   // iterate of the previous sweep / of this sweep
   const int I = threadIdx.x;
   const bool on = I < n;
   const R rI = on ? r[I] : R(0);
@@ -178,19 +179,19 @@ k_mg_coarse(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, 
     if (q[s] < 0) q[s] = I;   // an absent slot contributes w (x - x) = 0
   }
   R x = omega * dI * rI;
-  xs[I] = x;
+  xs[0][I] = x;
   __syncthreads();
   for (int it = 1; it < sweeps; ++it) {
+    const R* xo = xs[(it + 1) & 1];
     R mx = R(0);
 #pragma unroll
-    for (int s = 0; s < kMgRowMax; ++s) mx += w[s] * (x - xs[q[s]]);
+    for (int s = 0; s < kMgRowMax; ++s) mx += w[s] * (x - xo[q[s]]);
     for (int s = kMgRowMax; s < K; ++s) {   // rows longer than the register block
       const int Q = on ? nbr[s * n + I] : -1;
-      if (Q >= 0) mx += W[s * n + I] * (x - xs[Q]);
+      if (Q >= 0) mx += W[s * n + I] * (x - xo[Q]);
     }
     x += omega * dI * (rI - mx);
-    __syncthreads();
-    xs[I] = x;
+    xs[it & 1][I] = x;   // the other buffer: nobody reads it during this sweep
     __syncthreads();
   }
   if (on) e[I] = x;
@@ -552,8 +553,9 @@ int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r,
   }
   {
     const MgLevel& L = c->mg[nl - 1];
-    launch_timed_wg(c, s, kTimeMgCoarse, k_mg_coarse<R>, 1, 64, L.n, L.K, (const int*)L.nbr, (const R*)L.W,
-                    (const R*)L.Dinv, (const R*)L.r, om, (int)kMgCoarseSweeps, (R*)L.e, (const CgState*)st);
+    launch_timed_wg(c, s, kTimeMgCoarse, k_mg_coarse<R>, 1, kMgCoarse, L.n, L.K, (const int*)L.nbr,
+                    (const R*)L.W, (const R*)L.Dinv, (const R*)L.r, om, (int)kMgCoarseSweeps, (R*)L.e,
+                    (const CgState*)st);
   }
   for (int l = nl - 2; l >= 0; --l) {
     const MgLevel& F = c->mg[l];
