@@ -117,6 +117,7 @@ struct piso_ctx {
   hipGraphExec_t cg_graph[2] = {nullptr, nullptr};   // recorded iteration pair: Jacobi, multigrid
   hipStream_t cap_stream = nullptr;                 // stream used only for recording
   bool use_graphs = true;
+  int pcg_hint[2] = {0, 0};                         // iterations of the last solve: Jacobi, multigrid
   std::vector<piso::MgLevel> mg;  // coarse levels 1..L of the pressure preconditioner
   piso::Grid mg_g1{};             // level 1 as a block table (offsets, dims, division magic)
   // Dirichlet faces: owning cell and side (2 * axis + high), and the boundary cells

@@ -781,9 +781,15 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
   if (use_graph && !*gx) {
     if (int rc = pcg_graph<R>(c, o, gx)) return rc;
   }
+  // the first chunk covers three quarters of the previous solve's iterations (solves of
+  // one step and of consecutive steps take similar counts), later chunks check_every
+  int& hint = c->pcg_hint[o.mg ? 1 : 0];
+  int chunk = std::max(check_every, (3 * hint / 4) & ~1);
   int launched = 0;
   while (!c->h_cg->done && launched < max_iter) {
-    for (int k = 0; k < check_every; k += 2) {
+    const int n = std::min(chunk, max_iter - launched + 1);
+    chunk = check_every;
+    for (int k = 0; k < n; k += 2) {
       if (use_graph) {
         PISO_HIP(c, hipGraphLaunch(*gx, s));
       } else {
@@ -791,7 +797,7 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
         if (int rc = pcg_iteration<R>(c, s, o, 1)) return rc;
       }
     }
-    launched += check_every;
+    launched += n + (n & 1);
     k_cg_check<<<1, kWG, 0, s>>>(o.pB, G, 0, max_iter, tol2, st);
     if (int rc = check(c, "k_cg iteration")) return rc;
     PISO_HIP(c, hipMemcpyAsync(c->h_cg, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
@@ -800,6 +806,7 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
   }
   PISO_HIP(c, hipMemcpyAsync(x, o.x, es * (size_t)N, hipMemcpyDeviceToDevice, s));
   const CgState& h = *c->h_cg;
+  if (h.status == 0) hint = h.iters;
   *iters_out += h.iters;
   *rel_out = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
   if (h.status < 0) *status_out = h.status;
