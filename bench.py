@@ -78,27 +78,71 @@ def make_case(name):
     raise SystemExit("unknown workload " + name)
 
 
-def stats_loss_grads(us, y_planes, targets, nx, ny, nz):
-    """Channel statistics loss over a rollout: plane means of u and of the uv
-    covariance, averaged over the steps, against seeded target profiles.  Returns
-    (L, [dL/du_n])."""
+def stats_loss_grads(ctx, us, targets):
+    """Channel statistics loss over a rollout (Sec. 3.2): the mean u(y) and the uv
+    covariance over the homogeneous planes and the rolled-out steps, accumulated online
+    by the library (piso_stats_*), against seeded target profiles.  Returns
+    (L, [dL/du_n]); the gradients come from the library's statistics adjoint."""
     import torch
     u_hat, uv_hat = targets
-    leaves = [u.detach().requires_grad_(True) for u in us]
-    ubar = 0.0
-    uv = 0.0
-    for u in leaves:
-        U = u[0].reshape(nz, ny, nx)
-        V = u[1].reshape(nz, ny, nx)
-        mu = U.mean(dim=(0, 2))
-        mv = V.mean(dim=(0, 2))
-        ubar = ubar + mu
-        uv = uv + (U * V).mean(dim=(0, 2)) - mu * mv
-    ubar = ubar / len(leaves)
-    uv = uv / len(leaves)
-    L = ((ubar - u_hat) ** 2 + (uv - uv_hat) ** 2).mean()
-    grads = torch.autograd.grad(L, leaves)
-    return L.detach(), [g.contiguous() for g in grads]
+    state = ctx.stats_state(1)
+    for u in us:
+        ctx.stats_accumulate(u, state, 1)
+    mean, cov = ctx.stats_finalize(state, 1)
+    # cov columns: (0,0) (0,1) (0,2) (1,1) (1,2) (2,2)
+    ny = mean.shape[0]
+    du = mean[:, 0] - u_hat
+    duv = cov[:, 1] - uv_hat
+    L = ((du ** 2 + duv ** 2).sum() / ny)
+    mbar = torch.zeros_like(mean)
+    cbar = torch.zeros_like(cov)
+    mbar[:, 0] = 2.0 * du / ny
+    cbar[:, 1] = 2.0 * duv / ny
+    grads = [ctx.stats_backward(u, state, mbar, cbar, 1) for u in us]
+    return L, grads
+
+
+def _time_call(fn, reps):
+    """Average ms of fn() over reps calls, HIP events on the current stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def time_extras(ctx, case, precision, u0, S):
+    """Per-call times of the calls beyond the step (the paper's outflow boundary,
+    online statistics and divergence-free gradient modification)."""
+    import torch
+    import cases
+    from paper_2505_16992_amd import api
+    out = {}
+    state = ctx.stats_state(1)
+    out["stats_accumulate_96^3_ms"] = round(_time_call(lambda: ctx.stats_accumulate(u0, state, 1), 20), 4)
+    mean, cov = ctx.stats_finalize(state, 1)
+    mb, cb = torch.ones_like(mean), torch.ones_like(cov)
+    du = torch.zeros_like(u0)
+    out["stats_backward_96^3_ms"] = round(_time_call(lambda: ctx.stats_backward(u0, state, mb, cb, 1, du=du), 20), 4)
+    g = torch.ones_like(S)
+    o = ctx.default_opts().pres
+    out["divfree_gradient_96^3_ms"] = round(_time_call(lambda: ctx.divfree_gradient(S, g, 1.0, o), 3), 3)
+    cyl = cases.cylinder_oh()
+    cctx = api.Context(cyl.domain, precision)
+    mask = cctx.outflow_mask(cases.segment_mask(cyl.domain, lambda si: cyl.domain.sides[si].block == 1))
+    t = cctx.dtype
+    uc = torch.as_tensor(cyl.u0, dtype=t, device="cuda")
+    ub = torch.as_tensor(cyl.u_b, dtype=t, device="cuda")
+    out["outflow_update_cylinder_ms"] = round(_time_call(lambda: cctx.outflow_update(uc, ub, mask, (1.0, 0.0), cyl.dt), 20), 4)
+    gb = torch.ones_like(ub)
+    out["outflow_update_backward_cylinder_ms"] = round(
+        _time_call(lambda: cctx.outflow_update_backward(uc, ub, mask, (1.0, 0.0), cyl.dt, gb), 20), 4)
+    return out
 
 
 def main():
@@ -110,6 +154,8 @@ def main():
     ap.add_argument("--workload", default="channel96")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the per-call timings of the outflow, statistics and gradient-modification calls")
     ap.add_argument("--kernel-digest", action="store_true", help="print the CG kernel source digest")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 256 MiB (counter calibration)")
@@ -161,7 +207,8 @@ def main():
     if is_channel:
         nx, ny, nz = dom.blocks[0]
         u_hat, uv_hat = cases.channel_loss_targets(case)
-        targets = (dev(u_hat), dev(uv_hat))
+        targets = (torch.as_tensor(u_hat, dtype=torch.float64, device="cuda"),
+                   torch.as_tensor(uv_hat, dtype=torch.float64, device="cuda"))
 
     def fwd_adj(n_steps):
         """n-step rollout with tapes, then its adjoint; returns (dS, info)."""
@@ -175,7 +222,7 @@ def main():
             tapes.append(t)
             infos.append(inf)
         if is_channel:
-            _, gus = stats_loss_grads(us[1:], None, targets, nx, ny, nz)
+            _, gus = stats_loss_grads(ctx, us[1:], targets)
         else:
             gus = [torch.zeros_like(u0) for _ in range(n_steps)]
             gus[-1] = torch.ones_like(u0)
@@ -276,6 +323,11 @@ def main():
                    "kernels": per}
         log("timing %s" % tm)
 
+    extras = None
+    if not args.no_extras and args.workload == "channel96":
+        extras = time_extras(ctx, case, args.precision, u0, S)
+        log("extras %s" % extras)
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle.piso import Geometry, step as oracle_step
@@ -316,6 +368,7 @@ def main():
         "pressure_cg": pcg,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "extras": extras,
     }
     print(json.dumps(out), flush=True)
 
