@@ -156,6 +156,26 @@ int build_topology(piso_ctx* c, const piso_domain_desc* d) {
         }
     }
   }
+  // sides that wrap onto the opposite side of the same block cell for cell (periodicity):
+  // the kernels then index them arithmetically instead of through the face map
+  for (int b = 0; b < B; ++b) {
+    int bits = 0;
+    for (int side = 0; side < 2 * D; ++side) {
+      const int a = side / 2, s = side % 2;
+      int t0n, t1n;
+      tangential_extent(n[b].data(), side, D, t0n, t1n);
+      bool wraps = true;
+      for (int t1 = 0; t1 < t1n && wraps; ++t1)
+        for (int t0 = 0; t0 < t0n && wraps; ++t0) {
+          const int slot = c->h_tab[(size_t)b * kTabStride + 4 + side] + t0 + t0n * t1;
+          int i, j, k;
+          from_t(a, s ? 0 : n[b][a] - 1, t0, t1, i, j, k);
+          wraps = c->h_fmap[slot] == cell(b, i, j, k);
+        }
+      if (wraps) bits |= 1 << side;
+    }
+    c->h_tab[(size_t)b * kTabStride + kTabWrap] = bits;
+  }
   return PISO_OK;
 }
 

@@ -12,11 +12,15 @@ constexpr int kMaxBlocks = 16;
 constexpr int kWG = 256;                 // work-group size: 4 wave64s
 constexpr int kWaves = kWG / 64;
 constexpr int kRedGrid = 2048;           // work-groups of the reduction kernels (upper bound)
-constexpr int kTabStride = 16;           // ints per block in the device block table
+constexpr int kTabStride = 20;           // ints per block in the device block table
+constexpr int kTabWrap = 16;             // entry: bit (2 * axis + side) set when that side of the
+                                         // block joins the opposite side of the same block
+                                         // cell for cell (periodicity)
 
 // Device block table, kTabStride ints per block:
 //   [0] offset  [1] nx  [2] ny  [3] nz  [4..9] offset of each side in the face map
 //   [10,11] magic for /nx (lo, hi)  [12] shift  [13,14] magic for /(nx*ny)  [15] shift
+//   [16] periodic-side bits (kTabWrap)  [17..19] unused
 struct Grid {
   int dim;
   int nblocks;
@@ -65,10 +69,13 @@ __device__ __forceinline__ int neighbour(const Grid& g, const Cell& c, int P, in
   const int* t = g.tab + c.b * kTabStride;
   int pos = axis == 0 ? c.i : (axis == 1 ? c.j : c.k);
   int n = t[1 + axis];
+  const int stride = axis == 0 ? 1 : (axis == 1 ? t[1] : t[1] * t[2]);
   if (side) {
-    if (pos < n - 1) return P + (axis == 0 ? 1 : (axis == 1 ? t[1] : t[1] * t[2]));
+    if (pos < n - 1) return P + stride;
+    if ((t[kTabWrap] >> (2 * axis + 1)) & 1) return P - (n - 1) * stride;
   } else {
-    if (pos > 0) return P - (axis == 0 ? 1 : (axis == 1 ? t[1] : t[1] * t[2]));
+    if (pos > 0) return P - stride;
+    if ((t[kTabWrap] >> (2 * axis)) & 1) return P + (n - 1) * stride;
   }
   int tg;
   if (axis == 0) tg = c.j + t[2] * c.k;

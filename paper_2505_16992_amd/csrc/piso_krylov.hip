@@ -204,7 +204,7 @@ k_cg_spmv_q(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const 
     st->rz[par] = rz;
     st->rr = rr;
   }
-  auto dq = [&](int P) {
+  auto dq = [&](int P, int, int) {
     const Q4<R> b = ldq(r, P), c = ldq(dold, P);
     Q4<R> o;
     if constexpr (ZOP) {
@@ -217,14 +217,14 @@ k_cg_spmv_q(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const 
     }
     return o;
   };
-  auto d1 = [&](int P) { return (ZOP ? r[P] : Dinv[P] * r[P]) + beta * dold[P]; };
+  auto d1 = [&](int P, bool, int, int, int) { return (ZOP ? r[P] : Dinv[P] * r[P]) + beta * dold[P]; };
   int beg, end;
   quad_range(g.N >> 2, beg, end);
   double acc[1] = {0.0};
   for (int qd = beg + (int)threadIdx.x; qd < end; qd += kWG) {
     const int P0 = qd << 2;
     const Cell c = locate(g, P0);
-    const Q4<R> dP = dq(P0);
+    const Q4<R> dP = dq(P0, c.j, c.k);
     const Q4<R> M = quad_stencil<R, D>(g, c, P0, Pf, dP, dq, d1);
     stq(dnew, P0, dP);
     stq(q, P0, M);

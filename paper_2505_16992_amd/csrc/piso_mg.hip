@@ -288,17 +288,9 @@ k_mg_up0_q(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ Dinv
   for (int qd = beg + (int)threadIdx.x; qd < end; qd += kWG) {
     const int P0 = qd << 2;
     const Cell c = locate(g, P0);
-    const int* t = g.tab + c.b * kTabStride;
-    const int nxy = t[1] * t[2];
     const int* t1 = g1.tab + c.b * kTabStride;
-    // operand z = y + e[parent] over the quad at P (P0 or a y/z neighbour)
-    auto dq = [&](int P) {
-      int jj = c.j, kk = c.k;
-      const int dl = P - P0;
-      if (dl != 0) {
-        if (D == 3 && (dl == nxy || dl == -nxy)) kk += dl > 0 ? 1 : -1;
-        else jj += dl > 0 ? 1 : -1;
-      }
+    // operand z = y + e[parent] over the quad at P (row jj, plane kk of this block)
+    auto dq = [&](int P, int jj, int kk) {
       const int base = t1[0] + (c.i >> 1) + t1[1] * ((jj >> 1) + t1[2] * (kk >> 1));
       const R e0 = ec[base], e1 = ec[base + 1];
       const Q4<R> a = ldq(y, P);
@@ -309,8 +301,10 @@ k_mg_up0_q(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ Dinv
       o.v[3] = a.v[3] + e1;
       return o;
     };
-    auto d1 = [&](int P) { return y[P] + ec[parent[P]]; };
-    const Q4<R> zq = dq(P0);
+    auto d1 = [&](int P, bool known, int ii, int jj, int kk) {
+      return y[P] + ec[known ? mg_parent(g1, c.b, ii, jj, kk) : parent[P]];
+    };
+    const Q4<R> zq = dq(P0, c.j, c.k);
     const Q4<R> M = quad_stencil<R, D>(g, c, P0, Pf, zq, dq, d1);
     const Q4<R> rq = ldq(r, P0), Dq = ldq(Dinv, P0);
     Q4<R> o;

@@ -39,22 +39,47 @@ __device__ __forceinline__ void stq(R* __restrict__ p, int P, const Q4<R>& q) {
   }
 }
 
-// M d over the quad starting at P0 for an operand given by dq(P) (4 cells) / d1(P)
-// (one cell); dP is the operand at the quad.  Pf face arrays as in the scalar kernels.
+// M d over the quad starting at P0 for an operand given by dq(P, j, k) (the 4 cells of
+// the quad at P, which lies in row j, plane k of the same block) and d1(F, known, i, j, k)
+// (one cell; its position in this block when known, else it lies across a block side);
+// dP is the operand at the quad.  Pf face arrays as in the scalar kernels.  Sides that
+// wrap onto the same block are indexed arithmetically, other block sides through the
+// face map.
 template <typename R, int D, typename FQ, typename F1>
 __device__ __forceinline__ Q4<R> quad_stencil(const Grid& g, const Cell& c, int P0, const R* __restrict__ Pf,
                                               const Q4<R>& dP, FQ dq, F1 d1) {
   const int N = g.N;
   const int* t = g.tab + c.b * kTabStride;
   const int nx = t[1], ny = t[2], nz = t[3];
+  const int wrap = t[kTabWrap];
   Q4<R> M;
   // x faces
   const Q4<R> px = ldq(Pf, P0);
-  int Lx = c.i > 0 ? P0 - 1 : g.fmap[t[4] + c.j + ny * c.k];
-  int Rx = c.i + 4 < nx ? P0 + 4 : g.fmap[t[5] + c.j + ny * c.k];
-  const R dl = Lx >= 0 ? d1(Lx) : R(0);
+  int Lx, Rx, Li = 0, Ri = 0;
+  bool Lk = true, Rk = true;
+  if (c.i > 0) {
+    Lx = P0 - 1;
+    Li = c.i - 1;
+  } else if (wrap & 1) {
+    Lx = P0 + nx - 1;
+    Li = nx - 1;
+  } else {
+    Lx = g.fmap[t[4] + c.j + ny * c.k];
+    Lk = false;
+  }
+  if (c.i + 4 < nx) {
+    Rx = P0 + 4;
+    Ri = c.i + 4;
+  } else if (wrap & 2) {
+    Rx = P0 + 4 - nx;
+    Ri = 0;
+  } else {
+    Rx = g.fmap[t[5] + c.j + ny * c.k];
+    Rk = false;
+  }
+  const R dl = Lx >= 0 ? d1(Lx, Lk, Li, c.j, c.k) : R(0);
   const R pl = Lx >= 0 ? Pf[Lx] : R(0);
-  const R dr = Rx >= 0 ? d1(Rx) : R(0);
+  const R dr = Rx >= 0 ? d1(Rx, Rk, Ri, c.j, c.k) : R(0);
   M.v[0] = px.v[0] * (dP.v[0] - dP.v[1]) + pl * (dP.v[0] - dl);
   M.v[1] = px.v[1] * (dP.v[1] - dP.v[2]) + px.v[0] * (dP.v[1] - dP.v[0]);
   M.v[2] = px.v[2] * (dP.v[2] - dP.v[3]) + px.v[1] * (dP.v[2] - dP.v[1]);
@@ -68,8 +93,11 @@ __device__ __forceinline__ Q4<R> quad_stencil(const Grid& g, const Cell& c, int 
     const R* Pa = Pf + (size_t)a * N;
     // +a side: own face coefficients
     const Q4<R> pp = ldq(Pa, P0);
-    if (pos < n - 1) {
-      const Q4<R> nb = dq(P0 + stride);
+    if (pos < n - 1 || ((wrap >> (2 * a + 1)) & 1)) {
+      const bool in = pos < n - 1;
+      const int Pn = in ? P0 + stride : P0 - (n - 1) * stride;
+      const int q = in ? pos + 1 : 0;
+      const Q4<R> nb = dq(Pn, a == 1 ? q : c.j, a == 2 ? q : c.k);
 #pragma unroll
       for (int e = 0; e < 4; ++e) M.v[e] += pp.v[e] * (dP.v[e] - nb.v[e]);
     } else {
@@ -77,13 +105,16 @@ __device__ __forceinline__ Q4<R> quad_stencil(const Grid& g, const Cell& c, int 
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int F = g.fmap[base + e];
-        if (F >= 0) M.v[e] += pp.v[e] * (dP.v[e] - d1(F));
+        if (F >= 0) M.v[e] += pp.v[e] * (dP.v[e] - d1(F, false, 0, 0, 0));
       }
     }
     // -a side: coefficients stored at the neighbour
-    if (pos > 0) {
-      const Q4<R> nb = dq(P0 - stride);
-      const Q4<R> pm = ldq(Pa, P0 - stride);
+    if (pos > 0 || ((wrap >> (2 * a)) & 1)) {
+      const bool in = pos > 0;
+      const int Pn = in ? P0 - stride : P0 + (n - 1) * stride;
+      const int q = in ? pos - 1 : n - 1;
+      const Q4<R> nb = dq(Pn, a == 1 ? q : c.j, a == 2 ? q : c.k);
+      const Q4<R> pm = ldq(Pa, Pn);
 #pragma unroll
       for (int e = 0; e < 4; ++e) M.v[e] += pm.v[e] * (dP.v[e] - nb.v[e]);
     } else {
@@ -91,7 +122,7 @@ __device__ __forceinline__ Q4<R> quad_stencil(const Grid& g, const Cell& c, int 
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int F = g.fmap[base + e];
-        if (F >= 0) M.v[e] += Pa[F] * (dP.v[e] - d1(F));
+        if (F >= 0) M.v[e] += Pa[F] * (dP.v[e] - d1(F, false, 0, 0, 0));
       }
     }
   }
