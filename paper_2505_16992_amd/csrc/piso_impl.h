@@ -82,6 +82,7 @@ constexpr int kMgCoarse = 256;      // stop coarsening at this many cells (one w
 constexpr int kMgMaxLevels = 16;
 constexpr int kMgCoarseSweeps = 24; // damped Jacobi sweeps on the coarsest level
 constexpr double kMgOmega = 0.8;    // Jacobi damping of the smoother
+constexpr int kMgPinGroups = 64;    // coarse-level launches up to this many work-groups run on one XCD
 
 }  // namespace piso
 

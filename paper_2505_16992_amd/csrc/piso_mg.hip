@@ -35,6 +35,15 @@ namespace piso {
 
 // ------------------------------------------------------------------ kernels
 
+// Work-group index for launches pinned to one XCD: small coarse-level kernels are
+// launched with 8x the work-groups and only every eighth one (all on the XCD that
+// receives work-group 0) works, so that consecutive small kernels share that XCD's L2.
+// Returns -1 for the idle groups.  Unpinned launches use blockIdx.x directly.
+__device__ __forceinline__ int mg_group(int pin) {
+  if (!pin) return blockIdx.x;
+  return (blockIdx.x & 7) ? -1 : (int)(blockIdx.x >> 3);
+}
+
 // W[s][I] = sum of the finer face weights listed for (s, I); Dinv[I] = 1 / sum_s W.
 template <typename R>
 __global__ void __launch_bounds__(kWG)
@@ -141,9 +150,11 @@ template <typename R, int NCH>
 __global__ void __launch_bounds__(kWG)
 k_mg_down(int nf, int Kf, const int* __restrict__ nbr, const R* __restrict__ W, const R* __restrict__ Dinv,
           const R* __restrict__ r, const int* __restrict__ child, int nc, R omega, R* __restrict__ rc,
-          const CgState* st) {
+          const CgState* st, int pin) {
   if (st->done) return;
-  const int t = blockIdx.x * kWG + threadIdx.x;
+  const int wg = mg_group(pin);
+  if (wg < 0) return;
+  const int t = wg * kWG + threadIdx.x;
   const int I = t / NCH, q = t % NCH;
   R v = R(0);
   if (I < nc) {
@@ -203,9 +214,11 @@ template <typename R>
 __global__ void __launch_bounds__(kWG)
 k_mg_up(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, const R* __restrict__ Dinv,
         const R* __restrict__ r, const int* __restrict__ parent, const R* __restrict__ ec, R omega,
-        R* __restrict__ e, const CgState* st) {
+        R* __restrict__ e, const CgState* st, int pin) {
   if (st->done) return;
-  const int P = blockIdx.x * kWG + threadIdx.x;
+  const int wg = mg_group(pin);
+  if (wg < 0) return;
+  const int P = wg * kWG + threadIdx.x;
   if (P >= n) return;
   const R rP = r[P], dP = Dinv[P];
   const R zP = omega * dP * rP + ec[parent[P]];
@@ -533,17 +546,21 @@ int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r,
   else
     launch_timed(c, s, kTimeMgDown0, k_mg_down0<R, 3>, grid_cells(8 * g1.N), c->grid, g1, Pf, y, r,
                  (R*)c->mg[0].r, (const CgState*)st);
+  // launches of at most kMgPinGroups work-groups run on one XCD (see mg_group)
+  auto pinned = [](int groups) { return groups <= kMgPinGroups ? 1 : 0; };
+  auto grid_of = [](int groups, int pin) { return pin ? 8 * groups : groups; };
   for (int l = 1; l < nl; ++l) {
     const MgLevel& F = c->mg[l - 1];
     const MgLevel& C = c->mg[l];
+    const int gw = grid_cells((1 << c->dim) * C.n), pin = pinned(gw);
     if (c->dim == 2)
-      launch_timed(c, s, kTimeMgCoarse, k_mg_down<R, 4>, grid_cells(4 * C.n), F.n, F.K, (const int*)F.nbr,
+      launch_timed(c, s, kTimeMgCoarse, k_mg_down<R, 4>, grid_of(gw, pin), F.n, F.K, (const int*)F.nbr,
                    (const R*)F.W, (const R*)F.Dinv, (const R*)F.r, (const int*)C.child, C.n, om, (R*)C.r,
-                   (const CgState*)st);
+                   (const CgState*)st, pin);
     else
-      launch_timed(c, s, kTimeMgCoarse, k_mg_down<R, 8>, grid_cells(8 * C.n), F.n, F.K, (const int*)F.nbr,
+      launch_timed(c, s, kTimeMgCoarse, k_mg_down<R, 8>, grid_of(gw, pin), F.n, F.K, (const int*)F.nbr,
                    (const R*)F.W, (const R*)F.Dinv, (const R*)F.r, (const int*)C.child, C.n, om, (R*)C.r,
-                   (const CgState*)st);
+                   (const CgState*)st, pin);
   }
   {
     const MgLevel& L = c->mg[nl - 1];
@@ -554,9 +571,10 @@ int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r,
   for (int l = nl - 2; l >= 0; --l) {
     const MgLevel& F = c->mg[l];
     const MgLevel& C = c->mg[l + 1];
-    launch_timed(c, s, kTimeMgCoarse, k_mg_up<R>, grid_cells(F.n), F.n, F.K, (const int*)F.nbr, (const R*)F.W,
+    const int gw = grid_cells(F.n), pin = pinned(gw);
+    launch_timed(c, s, kTimeMgCoarse, k_mg_up<R>, grid_of(gw, pin), F.n, F.K, (const int*)F.nbr, (const R*)F.W,
                  (const R*)F.Dinv, (const R*)F.r, (const int*)C.parent, (const R*)C.e, om, (R*)F.e,
-                 (const CgState*)st);
+                 (const CgState*)st, pin);
   }
   {
     const MgLevel& L1 = c->mg[0];
