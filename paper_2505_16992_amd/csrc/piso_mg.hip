@@ -38,9 +38,9 @@ namespace piso {
 // Work-group index for launches pinned to one XCD: small coarse-level kernels are
 // launched with 8x the work-groups and only every eighth one (all on the XCD that
 // receives work-group 0) works, so that consecutive small kernels share that XCD's L2.
-// Returns -1 for the idle groups.  Unpinned launches use blockIdx.x directly.
+// Returns -1 for the idle groups.  Unpinned launches use the XCD-aware group order.
 __device__ __forceinline__ int mg_group(int pin) {
-  if (!pin) return blockIdx.x;
+  if (!pin) return xcd_logical_group();   // contiguous index ranges per XCD, as on the fine grid
   return (blockIdx.x & 7) ? -1 : (int)(blockIdx.x >> 3);
 }
 
@@ -73,7 +73,9 @@ k_mg_down0(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ y, c
            R* __restrict__ rc, const CgState* st) {
   if (st->done) return;
   constexpr int NCH = 1 << D;
-  const int t = blockIdx.x * kWG + threadIdx.x;
+  // XCD-aware group order: each XCD restricts the aggregates of the planes whose fine
+  // cells its L2 already holds
+  const int t = xcd_logical_group() * kWG + threadIdx.x;
   const int I = t / NCH, q = t % NCH;
   R v = R(0);
   if (I < g1.N) {
