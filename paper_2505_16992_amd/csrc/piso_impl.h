@@ -78,6 +78,14 @@ struct MgLevel {
   void* e = nullptr;      // [n] correction
 };
 
+// Tiles of the fine-grid restriction: per block, the first tile and the number of
+// 64-cell segments per fine row.
+struct MgTiles {
+  int nb;
+  int off[kMaxBlocks + 1];
+  int nseg[kMaxBlocks];
+};
+
 constexpr int kMgCoarse = 256;      // stop coarsening at this many cells (one work-group solves it)
 constexpr int kMgMaxLevels = 16;
 constexpr int kMgCoarseSweeps = 24; // damped Jacobi sweeps on the coarsest level
@@ -121,6 +129,7 @@ struct piso_ctx {
   int pcg_hint[2] = {0, 0};                         // iterations of the last solve: Jacobi, multigrid
   std::vector<piso::MgLevel> mg;  // coarse levels 1..L of the pressure preconditioner
   piso::Grid mg_g1{};             // level 1 as a block table (offsets, dims, division magic)
+  piso::MgTiles mg_tiles{};       // work-group tiles of the fine-grid restriction
   // Dirichlet faces: owning cell and side (2 * axis + high), and the boundary cells
   // with their faces (ascending) for deterministic gathers
   int *out_bcell = nullptr, *out_bside = nullptr, *out_bc_cell = nullptr, *out_bc_ptr = nullptr,

@@ -64,55 +64,71 @@ k_mg_coef(int n, int K, const int* __restrict__ ptr, const int* __restrict__ idx
 
 // Restriction from the fine grid: rc[I] = sum over the children P of aggregate I of the
 // residual r_P - (M y)_P of the pre-smoothed y = omega D^-1 r (stored by the PCG update).
-// Faces between two children of I cancel in the sum and are skipped.  One thread per
-// (aggregate, child) -- the child's position follows from the aggregate's (g1 is level
-// 1 as a block table) -- and a fixed shuffle butterfly sums the 2^d lanes.
+// Faces between two children of I cancel in the sum and are skipped.  A work-group is a
+// tile of 32 aggregates along x of one coarse row: wave (row parity, plane parity) holds
+// 64 consecutive fine cells of one fine row, so every load is coalesced; lane pairs sum
+// the x children with a shuffle and the waves' pair sums are added in LDS in a fixed
+// order.  Tiles run seg-fastest, then coarse rows, then coarse planes (XCD-aware order).
 template <typename R, int D>
-__global__ void __launch_bounds__(kWG)
-k_mg_down0(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ y, const R* __restrict__ r,
-           R* __restrict__ rc, const CgState* st) {
+__global__ void __launch_bounds__(64 << (D - 1))
+k_mg_down0(Grid g, Grid g1, MgTiles tl, const R* __restrict__ Pf, const R* __restrict__ y,
+           const R* __restrict__ r, R* __restrict__ rc, const CgState* st) {
   if (st->done) return;
-  constexpr int NCH = 1 << D;
-  // XCD-aware group order: each XCD restricts the aggregates of the planes whose fine
-  // cells its L2 already holds
-  const int t = xcd_logical_group() * kWG + threadIdx.x;
-  const int I = t / NCH, q = t % NCH;
+  constexpr int NW = 1 << (D - 1);
+  __shared__ R part[NW][32];
+  const int tile = xcd_logical_group();
+  int b = 0;
+  for (int q = 1; q < tl.nb; ++q) b += tile >= tl.off[q] ? 1 : 0;
+  int lt = tile - tl.off[b];
+  const int* tf = g.tab + b * kTabStride;
+  const int* tc = g1.tab + b * kTabStride;
+  const int n[3] = {tf[1], tf[2], tf[3]};
+  const int cx = tc[1], cy = tc[2];
+  const int nseg = tl.nseg[b];
+  const int seg = lt % nseg;
+  lt /= nseg;
+  const int cj = lt % cy, ck = lt / cy;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int bit[3] = {lane & 1, w & 1, (w >> 1) & 1};
+  Cell c;
+  c.b = b;
+  c.i = seg * 64 + lane;
+  c.j = 2 * cj + bit[1];
+  c.k = 2 * ck + bit[2];
   R v = R(0);
-  if (I < g1.N) {
+  if (c.i < n[0] && c.j < n[1] && c.k < n[2]) {
     const int N = g.N;
-    const Cell cc = locate(g1, I);
-    const int* tb = g.tab + cc.b * kTabStride;
-    const int n[3] = {tb[1], tb[2], tb[3]};
-    const int bit[3] = {q & 1, (q >> 1) & 1, (q >> 2) & 1};
-    Cell c;
-    c.b = cc.b;
-    c.i = 2 * cc.i + bit[0];
-    c.j = 2 * cc.j + bit[1];
-    c.k = 2 * cc.k + bit[2];
-    if (c.i < n[0] && c.j < n[1] && c.k < n[2]) {
-      const int pos[3] = {c.i, c.j, c.k};
-      const int P = tb[0] + c.i + n[0] * (c.j + n[1] * c.k);
-      const R yP = y[P];
-      R res = r[P];
+    const int pos[3] = {c.i, c.j, c.k};
+    const int P = tf[0] + c.i + n[0] * (c.j + n[1] * c.k);
+    const R yP = y[P];
+    R res = r[P];
 #pragma unroll
-      for (int j = 0; j < D; ++j) {
+    for (int j = 0; j < D; ++j) {
 #pragma unroll
-        for (int sd = 0; sd < 2; ++sd) {
-          const bool internal = sd ? (bit[j] == 0 && pos[j] + 1 < n[j]) : (bit[j] == 1);
-          if (internal) continue;
-          const int F = neighbour(g, c, P, j, sd);
-          if (F >= 0) {
-            const R w = sd ? Pf[(size_t)j * N + P] : Pf[(size_t)j * N + F];
-            res -= w * (yP - y[F]);
-          }
+      for (int sd = 0; sd < 2; ++sd) {
+        const bool internal = sd ? (bit[j] == 0 && pos[j] + 1 < n[j]) : (bit[j] == 1);
+        if (internal) continue;
+        const int F = neighbour(g, c, P, j, sd);
+        if (F >= 0) {
+          const R wf = sd ? Pf[(size_t)j * N + P] : Pf[(size_t)j * N + F];
+          res -= wf * (yP - y[F]);
         }
       }
-      v = res;
+    }
+    v = res;
+  }
+  v += __shfl_xor(v, 1, 64);
+  if (!(lane & 1)) part[w][lane >> 1] = v;
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    const int ci = seg * 32 + threadIdx.x;
+    if (ci < cx) {
+      R sum = part[0][threadIdx.x];
+#pragma unroll
+      for (int q = 1; q < NW; ++q) sum += part[q][threadIdx.x];
+      rc[tc[0] + ci + cx * (cj + cy * ck)] = sum;
     }
   }
-#pragma unroll
-  for (int o = 1; o < NCH; o <<= 1) v += __shfl_xor(v, o, 64);
-  if (I < g1.N && q == 0) rc[I] = v;
 }
 
 // y = omega D^-1 r (pre-smoothing from zero) after the PCG initialisation.
@@ -501,6 +517,14 @@ int mg_build(piso_ctx* c) {
       c->mg_g1.NB = 0;
       c->mg_g1.tab = d_tab1;
       c->mg_g1.fmap = nullptr;
+      // fine-grid restriction tiles: 64 fine x-cells (32 aggregates) of one coarse row
+      c->mg_tiles.nb = B;
+      c->mg_tiles.off[0] = 0;
+      for (int b = 0; b < B; ++b) {
+        const int nseg = (cur.dims[b][0] + 63) / 64;
+        c->mg_tiles.nseg[b] = nseg;
+        c->mg_tiles.off[b + 1] = c->mg_tiles.off[b] + nseg * nx.dims[b][1] * nx.dims[b][2];
+      }
     }
     c->mg.push_back(L);
     nbr_f.swap(nbr);
@@ -543,11 +567,11 @@ int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r,
   const R om = (R)kMgOmega;
   const Grid& g1 = c->mg_g1;
   if (c->dim == 2)
-    launch_timed(c, s, kTimeMgDown0, k_mg_down0<R, 2>, grid_cells(4 * g1.N), c->grid, g1, Pf, y, r,
-                 (R*)c->mg[0].r, (const CgState*)st);
+    launch_timed_wg(c, s, kTimeMgDown0, k_mg_down0<R, 2>, c->mg_tiles.off[c->nblocks], 128, c->grid, g1,
+                    c->mg_tiles, Pf, y, r, (R*)c->mg[0].r, (const CgState*)st);
   else
-    launch_timed(c, s, kTimeMgDown0, k_mg_down0<R, 3>, grid_cells(8 * g1.N), c->grid, g1, Pf, y, r,
-                 (R*)c->mg[0].r, (const CgState*)st);
+    launch_timed_wg(c, s, kTimeMgDown0, k_mg_down0<R, 3>, c->mg_tiles.off[c->nblocks], 256, c->grid, g1,
+                    c->mg_tiles, Pf, y, r, (R*)c->mg[0].r, (const CgState*)st);
   // launches of at most kMgPinGroups work-groups run on one XCD (see mg_group)
   auto pinned = [](int groups) { return groups <= kMgPinGroups ? 1 : 0; };
   auto grid_of = [](int groups, int pin) { return pin ? 8 * groups : groups; };
