@@ -126,7 +126,9 @@ struct piso_ctx {
   hipGraphExec_t cg_graph[2] = {nullptr, nullptr};   // recorded iteration pair: Jacobi, multigrid
   hipStream_t cap_stream = nullptr;                 // stream used only for recording
   bool use_graphs = true;
-  int pcg_hint[2] = {0, 0};                         // iterations of the last solve: Jacobi, multigrid
+  // iterations of the last solve per preconditioner (Jacobi, multigrid) and kind: plain
+  // solves, then the first, second and later MIXED refinement sweeps
+  int pcg_hint[2][4] = {};
   std::vector<piso::MgLevel> mg;  // coarse levels 1..L of the pressure preconditioner
   piso::Grid mg_g1{};             // level 1 as a block table (offsets, dims, division magic)
   piso::MgTiles mg_tiles{};       // work-group tiles of the fine-grid restriction

@@ -731,7 +731,7 @@ static int pcg_graph(piso_ctx* c, const PcgOps<R>& o, hipGraphExec_t* out) {
 template <typename R, typename BT>
 static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const BT* b,
                    const double* mean, double sign, R* x, double rtol, int max_iter, int check_every,
-                   int precond, int* iters_out, double* rel_out, int* status_out) {
+                   int precond, int* iters_out, double* rel_out, int* status_out, int hint_slot = 0) {
   const int N = c->N, G = grid_red(N, c->red_grid);
   CgState* st = c->cg;
   PcgOps<R> o;
@@ -783,7 +783,7 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
   }
   // the first chunk covers three quarters of the previous solve's iterations (solves of
   // one step and of consecutive steps take similar counts), later chunks check_every
-  int& hint = c->pcg_hint[o.mg ? 1 : 0];
+  int& hint = c->pcg_hint[o.mg ? 1 : 0][hint_slot];
   int chunk = std::max(check_every, (3 * hint / 4) & ~1);
   int launched = 0;
   while (!c->h_cg->done && launched < max_iter) {
@@ -882,7 +882,8 @@ int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const float* Pf, const floa
     // never for more than inner_rtol, the floor the float iteration reliably reaches
     const double tol_in = std::min(0.5, std::max(o->inner_rtol, 0.5 * o->rtol / rel));
     int rc = pcg_run<float, float>(c, s, Pf, Dinv, r32, nullptr, 1.0, e32, tol_in, o->max_iter,
-                                   o->check_every, o->precond, &iters, &rel_in, &st_in);
+                                   o->check_every, o->precond, &iters, &rel_in, &st_in,
+                                   1 + std::min(sweeps, 2));
     if (rc) return rc;
     if (st_in < 0) {
       status = st_in;
