@@ -614,6 +614,10 @@ int piso_create(const piso_domain_desc* desc, int32_t precision, piso_ctx** out)
     if (desc->block_cells[3 * b] % 4 != 0) c->quad = false;
   if (const char* e = std::getenv("PISO_NO_QUAD")) c->quad = (e[0] == '0');
   if (const char* e = std::getenv("PISO_NO_GRAPH")) c->use_graphs = (e[0] == '0');
+  if (const char* e = std::getenv("PISO_CG_GROUPS")) {
+    const int v = std::atoi(e);
+    c->cg_grid = v < 0 ? 0 : (v > kRedGrid ? kRedGrid : v);
+  }
   *out = c;
   return PISO_OK;
 }

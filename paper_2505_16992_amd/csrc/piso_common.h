@@ -149,13 +149,27 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], double* partials
 }
 
 // Sum of the G partials of NV values, identical in every thread of every work-group.
+// The loads are issued U trips of kWG at a time before their adds (a loop with the add
+// in it waits for each load in turn, about a microsecond per trip when the partials come
+// from another XCD); U shrinks with NV to bound the registers.  The per-thread order of
+// the adds is w ascending.
 template <int NV>
 __device__ __forceinline__ void reduce_partials(const double* __restrict__ partials, int G, double (&out)[NV]) {
+  constexpr int U = NV == 1 ? 8 : (NV == 2 ? 4 : 2);
 #pragma unroll
   for (int q = 0; q < NV; ++q) out[q] = 0.0;
-  for (int w = threadIdx.x; w < G; w += kWG) {
+  for (int w0 = 0; w0 < G; w0 += U * kWG) {
+    double v[NV][U];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) out[q] += partials[q * G + w];
+    for (int c = 0; c < U; ++c) {
+      const int w = w0 + (int)threadIdx.x + c * kWG;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) v[q][c] = w < G ? partials[q * G + w] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+#pragma unroll
+      for (int c = 0; c < U; ++c) out[q] += v[q][c];
   }
   wg_sum_all<NV>(out);
 }

@@ -86,9 +86,12 @@ struct MgTiles {
   int nseg[kMaxBlocks];
 };
 
-constexpr int kMgCoarse = 256;      // stop coarsening at this many cells (one work-group solves it)
+constexpr int kMgCoarse = 2048;     // stop coarsening at this many cells (one work-group solves it)
+constexpr int kMgCoarseThreads = 1024;   // that work-group: kMgCoarse / kMgCoarseThreads cells per thread
 constexpr int kMgMaxLevels = 16;
-constexpr int kMgCoarseSweeps = 24; // damped Jacobi sweeps on the coarsest level
+constexpr int kMgCoarseSteps3 = 16;   // Chebyshev steps on the coarsest level, 3D
+constexpr int kMgCoarseSteps2 = 32;   // and 2D (cheaper steps, slower Jacobi-type convergence)
+constexpr double kMgChebRatio = 100.0;   // their interval [2 / ratio, 2] of the spectrum of D^-1 M
 constexpr double kMgOmega = 0.8;    // Jacobi damping of the smoother
 constexpr int kMgPinGroups = 64;    // coarse-level launches up to this many work-groups run on one XCD
 
@@ -153,6 +156,7 @@ struct piso_ctx {
   piso::BiState* h_bi = nullptr;
   double* h_scal = nullptr;        // pinned [8]
   int red_grid = 512;              // work-groups of the reduction kernels
+  int cg_grid = 0;                 // work-groups of the PCG kernels (0: chosen from the size)
   std::vector<void*> allocs;
   piso::Timing timing;
   std::string err;

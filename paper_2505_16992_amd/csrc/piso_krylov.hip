@@ -100,22 +100,24 @@ __global__ void __launch_bounds__(kWG)
 k_cg_spmv(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
           const R* __restrict__ dold, R* __restrict__ dnew, R* __restrict__ q, CgState* st,
           const double* __restrict__ partB, double* __restrict__ partA, int Gp, int par) {
-  if (st->done) return;
-  const int kd = st->k;
+  // the state and the partials are loaded together, before the first wait
+  const int done = st->done, kd = st->k, max_k = st->max_k;
+  const double tol2bb = st->tol2 * st->bb, rz_old = st->rz[par ^ 1];
   double t[2];
   reduce_partials<2>(partB, Gp, t);
+  if (done) return;
   const double rz = t[0], rr = t[1];
-  if (!std::isfinite(rz) || !std::isfinite(rr) || rr <= st->tol2 * st->bb || kd >= st->max_k) {
+  if (!std::isfinite(rz) || !std::isfinite(rr) || rr <= tol2bb || kd >= max_k) {
     if (lead()) {
       st->rr = rr;
       st->iters = kd;
       if (!std::isfinite(rz) || !std::isfinite(rr)) st->status = PISO_E_NAN;
-      else if (!(rr <= st->tol2 * st->bb)) st->status = PISO_NOT_CONVERGED;
+      else if (!(rr <= tol2bb)) st->status = PISO_NOT_CONVERGED;
       st->done = 1;
     }
     return;
   }
-  const R beta = kd == 0 ? R(0) : (R)(rz / st->rz[par ^ 1]);
+  const R beta = kd == 0 ? R(0) : (R)(rz / rz_old);
   if (lead()) {
     st->rz[par] = rz;
     st->rr = rr;
@@ -147,9 +149,11 @@ __global__ void __launch_bounds__(kWG)
 k_cg_update(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restrict__ r,
             const R* __restrict__ dnew, const R* __restrict__ q, CgState* st, const double* __restrict__ partA,
             double* __restrict__ partB, int Gp, int par, R* __restrict__ y, R omega) {
-  if (st->done) return;
+  const int done = st->done;
+  const double rzp = st->rz[par];
   double t[1];
   reduce_partials<1>(partA, Gp, t);
+  if (done) return;
   const double dq = t[0];
   if (!(dq > 0.0) || !std::isfinite(dq)) {
     if (lead()) {
@@ -159,7 +163,7 @@ k_cg_update(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restrict_
     }
     return;
   }
-  const R alpha = (R)(st->rz[par] / dq);
+  const R alpha = (R)(rzp / dq);
   if (lead()) st->k = st->k + 1;   // no other work-group reads the index in this kernel
   int beg, end;
   chunk_range(N, beg, end);
@@ -184,22 +188,24 @@ __global__ void __launch_bounds__(kWG)
 k_cg_spmv_q(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
             const R* __restrict__ dold, R* __restrict__ dnew, R* __restrict__ q, CgState* st,
             const double* __restrict__ partB, double* __restrict__ partA, int Gp, int par) {
-  if (st->done) return;
-  const int kd = st->k;
+  // the state and the partials are loaded together, before the first wait
+  const int done = st->done, kd = st->k, max_k = st->max_k;
+  const double tol2bb = st->tol2 * st->bb, rz_old = st->rz[par ^ 1];
   double t[2];
   reduce_partials<2>(partB, Gp, t);
+  if (done) return;
   const double rz = t[0], rr = t[1];
-  if (!std::isfinite(rz) || !std::isfinite(rr) || rr <= st->tol2 * st->bb || kd >= st->max_k) {
+  if (!std::isfinite(rz) || !std::isfinite(rr) || rr <= tol2bb || kd >= max_k) {
     if (lead()) {
       st->rr = rr;
       st->iters = kd;
       if (!std::isfinite(rz) || !std::isfinite(rr)) st->status = PISO_E_NAN;
-      else if (!(rr <= st->tol2 * st->bb)) st->status = PISO_NOT_CONVERGED;
+      else if (!(rr <= tol2bb)) st->status = PISO_NOT_CONVERGED;
       st->done = 1;
     }
     return;
   }
-  const R beta = kd == 0 ? R(0) : (R)(rz / st->rz[par ^ 1]);
+  const R beta = kd == 0 ? R(0) : (R)(rz / rz_old);
   if (lead()) {
     st->rz[par] = rz;
     st->rr = rr;
@@ -239,9 +245,11 @@ __global__ void __launch_bounds__(kWG)
 k_cg_update_q(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restrict__ r,
               const R* __restrict__ dnew, const R* __restrict__ q, CgState* st, const double* __restrict__ partA,
               double* __restrict__ partB, int Gp, int par, R* __restrict__ y, R omega) {
-  if (st->done) return;
+  const int done = st->done;
+  const double rzp = st->rz[par];
   double t[1];
   reduce_partials<1>(partA, Gp, t);
+  if (done) return;
   const double dq = t[0];
   if (!(dq > 0.0) || !std::isfinite(dq)) {
     if (lead()) {
@@ -251,7 +259,7 @@ k_cg_update_q(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restric
     }
     return;
   }
-  const R alpha = (R)(st->rz[par] / dq);
+  const R alpha = (R)(rzp / dq);
   if (lead()) st->k = st->k + 1;   // no other work-group reads the index in this kernel
   int beg, end;
   quad_range(N >> 2, beg, end);
@@ -728,11 +736,25 @@ static int pcg_graph(piso_ctx* c, const PcgOps<R>& o, hipGraphExec_t* out) {
   return PISO_OK;
 }
 
+// Work-groups of the PCG kernels.  Every work-group of a kernel re-reduces the previous
+// kernel's per-group partials, so more groups cost a longer prologue; fewer groups leave
+// the chip idle.  Measured on the 96^3, 192x128x192, 256^2 and cylinder workloads: best
+// with whole loop trips of 256 work units (quads or cells) per group, as few trips as
+// keep the grid at or below 1536 groups, and at least 256 groups (then 64 units each).
+static int pcg_groups(const piso_ctx* c) {
+  if (c->cg_grid > 0) return c->cg_grid;
+  const long units = c->quad ? (long)c->N / 4 : (long)c->N;
+  const long trips = std::max(1L, (units + 256L * 1536 - 1) / (256L * 1536));
+  long g = (units + 256 * trips - 1) / (256 * trips);
+  if (g < 256) g = std::min(256L, (units + 63) / 64);
+  return (int)std::max(1L, std::min(g, (long)kRedGrid));
+}
+
 template <typename R, typename BT>
 static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const BT* b,
                    const double* mean, double sign, R* x, double rtol, int max_iter, int check_every,
                    int precond, int* iters_out, double* rel_out, int* status_out, int hint_slot = 0) {
-  const int N = c->N, G = grid_red(N, c->red_grid);
+  const int N = c->N, G = pcg_groups(c);
   CgState* st = c->cg;
   PcgOps<R> o;
   o.Pf = (const R*)c->g_Pf;

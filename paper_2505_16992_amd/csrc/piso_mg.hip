@@ -139,115 +139,193 @@ k_mg_prescale(int N, const R* __restrict__ Dinv, const R* __restrict__ r, R omeg
   if (P < N) y[P] = omega * Dinv[P] * r[P];
 }
 
-// Restriction between coarse levels (graph form).  One thread per (aggregate, child)
-// so that the loads of different children are in flight together; a graph row is read
-// as independent loads (up to kMgRowMax slots unrolled), and the NCH lanes of an
-// aggregate are summed with a fixed butterfly of shuffles (deterministic).
-constexpr int kMgRowMax = 8;
+constexpr int kMgRowMax = 8;   // graph-row slots held in registers
 
-template <typename R>
+// Graph row of cell P (0 <= P < n): neighbours q[s] (-1 where absent) and weights w[s]
+// of the first KR <= kMgRowMax slots (0 beyond the row; a slot inside the row with q < 0 keeps
+// its weight, callers use it with a zero difference).  The loads are unconditional
+// (slot index clamped into the row) and nothing waits for them here, so that all of
+// them are in flight together.
+template <typename R, int KR>
+__device__ __forceinline__ void mg_row(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, int P,
+                                       int (&q)[KR], R (&w)[KR]) {
+  const int Kc = K < KR ? K : KR;   // K >= 1: every level has a slot
+#pragma unroll
+  for (int s = 0; s < KR; ++s) {
+    const int sc = s < Kc ? s : Kc - 1;
+    const int qv = nbr[sc * n + P];
+    const R wv = W[sc * n + P];
+    q[s] = s < Kc ? qv : -1;
+    w[s] = s < Kc ? wv : R(0);
+  }
+}
+
+// r_P - (M x)_P for the pre-smoothed x = omega D^-1 r (absent slots add w (xP - xP) = 0).
+template <typename R, int KR>
 __device__ __forceinline__ R mg_row_residual(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W,
                                              const R* __restrict__ Dinv, const R* __restrict__ r, int P, R omega) {
+  int q[KR];
+  R w[KR];
+  mg_row<R, KR>(n, K, nbr, W, P, q, w);
   const R rP = r[P];
   const R xP = omega * Dinv[P] * rP;
-  int q[kMgRowMax];
-#pragma unroll
-  for (int s = 0; s < kMgRowMax; ++s) q[s] = s < K ? nbr[s * n + P] : -1;
   R res = rP;
 #pragma unroll
-  for (int s = 0; s < kMgRowMax; ++s)
-    if (q[s] >= 0) res -= W[s * n + P] * (xP - omega * Dinv[q[s]] * r[q[s]]);
-  for (int s = kMgRowMax; s < K; ++s) {
+  for (int s = 0; s < KR; ++s) {
+    const int Q = q[s] >= 0 ? q[s] : P;
+    res -= w[s] * (xP - omega * Dinv[Q] * r[Q]);
+  }
+  for (int s = KR; s < K; ++s) {
     const int Q = nbr[s * n + P];
     if (Q >= 0) res -= W[s * n + P] * (xP - omega * Dinv[Q] * r[Q]);
   }
   return res;
 }
 
-template <typename R, int NCH>
+// Restriction between coarse levels (graph form).  One thread per (aggregate, child)
+// so that the loads of different children are in flight together, and the NCH lanes
+// of an aggregate are summed with a fixed butterfly of shuffles (deterministic).  The
+// solver state is tested once the first loads are in flight.
+template <typename R, int NCH, int KR>
 __global__ void __launch_bounds__(kWG)
 k_mg_down(int nf, int Kf, const int* __restrict__ nbr, const R* __restrict__ W, const R* __restrict__ Dinv,
           const R* __restrict__ r, const int* __restrict__ child, int nc, R omega, R* __restrict__ rc,
           const CgState* st, int pin) {
-  if (st->done) return;
+  const int done = st->done;
   const int wg = mg_group(pin);
   if (wg < 0) return;
   const int t = wg * kWG + threadIdx.x;
   const int I = t / NCH, q = t % NCH;
-  R v = R(0);
-  if (I < nc) {
-    const int P = child[q * nc + I];
-    if (P >= 0) v = mg_row_residual<R>(nf, Kf, nbr, W, Dinv, r, P, omega);
-  }
+  const int P = I < nc ? child[q * nc + I] : -1;
+  if (done) return;
+  R v = mg_row_residual<R, KR>(nf, Kf, nbr, W, Dinv, r, P >= 0 ? P : 0, omega);
+  if (P < 0) v = R(0);
 #pragma unroll
   for (int o = 1; o < NCH; o <<= 1) v += __shfl_xor(v, o, 64);
   if (I < nc && q == 0) rc[I] = v;
 }
 
-// Coarsest level (n <= kMgCoarse cells, one work-group): e = sweeps damped Jacobi sweeps
-// from zero.
-// The cell's graph row is held in registers (up to kMgRowMax slots) so that a sweep
-// touches only the shared iterate.
-
-template <typename R>
-__global__ void __launch_bounds__(kMgCoarse)
+// Coarsest level (n <= kMgCoarse cells, one work-group of kMgCoarseThreads): e = B r with
+// B the Chebyshev iteration of `steps` steps from zero, preconditioned by D^-1, for the
+// interval [lo, hi] of the spectrum of D^-1 M.  M is a weighted graph Laplacian, so that
+// spectrum lies in [0, 2]: with hi = 2 the error polynomial p (p(0) = 1) has |p| < 1 on
+// (0, 2], hence B is a fixed symmetric positive definite map on the range of M and the
+// outer CG stays a plain PCG; eigenvalues below lo are damped less, not amplified.
+// Recurrence (theta = (hi + lo) / 2, delta = (hi - lo) / 2, sigma = theta / delta):
+//   x = 0, s = r, d = D^-1 r / theta, rho = 1 / sigma;  per step
+//   x += d, s -= M d, rho' = 1 / (2 sigma - rho), d = rho' rho d + (2 rho' / delta) D^-1 s.
+// Thread t owns cells t + c kMgCoarseThreads with their graph rows in registers (KR
+// slots; longer rows read the rest from global memory); d is exchanged through a double
+// buffer in LDS, one barrier per step.  The steps are bound by LDS reads (a row's
+// neighbours), so only present slots and cells are read.
+template <typename R, int KR>
+__global__ void __launch_bounds__(kMgCoarseThreads)
 k_mg_coarse(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, const R* __restrict__ Dinv,
-            const R* __restrict__ r, R omega, int sweeps, R* __restrict__ e, const CgState* st) {
-  if (st->done) return;
-  __shared__ R xs[2][kMgCoarse];   // iterate of the previous sweep / of this sweep
-  const int I = threadIdx.x;
-  const bool on = I < n;
-  const R rI = on ? r[I] : R(0);
-  const R dI = on ? Dinv[I] : R(0);
-  int q[kMgRowMax];
-  R w[kMgRowMax];
+            const R* __restrict__ r, R theta, R delta, int steps, R* __restrict__ e, const CgState* st) {
+  constexpr int C = kMgCoarse / kMgCoarseThreads;
+  const int done = st->done;   // tested once the row loads are in flight
+  __shared__ R ds[2][kMgCoarse];
+  int q[C][KR];
+  R w[C][KR];
+  R x[C], res[C], dv[C], di[C];
+  const R sigma = theta / delta;
+  R rho = R(1) / sigma;
+  // every load is unconditional (indices clamped into the arrays, results masked after),
+  // so that all of them are in flight together
+  const int Kc = K < KR ? K : KR;   // K >= 1: every level has a slot
 #pragma unroll
-  for (int s = 0; s < kMgRowMax; ++s) {
-    q[s] = (on && s < K) ? nbr[s * n + I] : -1;
-    w[s] = q[s] >= 0 ? W[s * n + I] : R(0);
-    if (q[s] < 0) q[s] = I;   // an absent slot contributes w (x - x) = 0
-  }
-  R x = omega * dI * rI;
-  xs[0][I] = x;
-  __syncthreads();
-  for (int it = 1; it < sweeps; ++it) {
-    const R* xo = xs[(it + 1) & 1];
-    R mx = R(0);
+  for (int c = 0; c < C; ++c) {
+    const int I = (int)threadIdx.x + c * kMgCoarseThreads;
+    const bool on = I < n;
+    const int Ic = on ? I : 0;
 #pragma unroll
-    for (int s = 0; s < kMgRowMax; ++s) mx += w[s] * (x - xo[q[s]]);
-    for (int s = kMgRowMax; s < K; ++s) {   // rows longer than the register block
-      const int Q = on ? nbr[s * n + I] : -1;
-      if (Q >= 0) mx += W[s * n + I] * (x - xo[Q]);
+    for (int s = 0; s < KR; ++s) {
+      const int sc = s < Kc ? s : Kc - 1;
+      const bool have = on && s < Kc;
+      const int qv = nbr[sc * n + Ic];
+      const R wv = W[sc * n + Ic];
+      q[c][s] = have ? qv : -1;
+      w[c][s] = have ? wv : R(0);
     }
-    x += omega * dI * (rI - mx);
-    xs[it & 1][I] = x;   // the other buffer: nobody reads it during this sweep
+    res[c] = r[Ic];
+    di[c] = Dinv[Ic];
+  }
+  if (done) return;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int I = (int)threadIdx.x + c * kMgCoarseThreads;
+    const bool on = I < n;
+    if (!on) res[c] = di[c] = R(0);
+#pragma unroll
+    for (int s = 0; s < KR; ++s)
+      if (q[c][s] < 0) {   // an absent slot contributes w (d - d) = 0
+        q[c][s] = on ? I : 0;
+        w[c][s] = R(0);
+      }
+    x[c] = R(0);
+    dv[c] = di[c] * res[c] / theta;
+    if (on) ds[0][I] = dv[c];
+  }
+  __syncthreads();
+  for (int it = 0; it < steps; ++it) {
+    const R* dold = ds[it & 1];
+    R* dnew = ds[(it + 1) & 1];
+    const R rn = R(1) / (R(2) * sigma - rho);
+    const R a = rn * rho, b = R(2) * rn / delta;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int I = (int)threadIdx.x + c * kMgCoarseThreads;
+      if (I < n) {
+        R md = R(0);
+#pragma unroll
+        for (int s = 0; s < KR; ++s)
+          if (s < K) md += w[c][s] * (dv[c] - dold[q[c][s]]);
+        for (int s = KR; s < K; ++s) {   // rows longer than the register block
+          const int Q = nbr[s * n + I];
+          if (Q >= 0) md += W[s * n + I] * (dv[c] - dold[Q]);
+        }
+        x[c] += dv[c];
+        res[c] -= md;
+        dv[c] = a * dv[c] + b * di[c] * res[c];
+        dnew[I] = dv[c];   // the other buffer: nobody reads it during this step
+      }
+    }
+    rho = rn;
     __syncthreads();
   }
-  if (on) e[I] = x;
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int I = (int)threadIdx.x + c * kMgCoarseThreads;
+    if (I < n) e[I] = x[c];
+  }
 }
 
 // Prolongation and post-smoothing on a coarse level: with z = omega D^-1 r + ec[parent],
 // e = z + omega D^-1 (r - M z).  The row's loads are issued together (unrolled slots).
-template <typename R>
+template <typename R, int KR>
 __global__ void __launch_bounds__(kWG)
 k_mg_up(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, const R* __restrict__ Dinv,
         const R* __restrict__ r, const int* __restrict__ parent, const R* __restrict__ ec, R omega,
         R* __restrict__ e, const CgState* st, int pin) {
-  if (st->done) return;
+  const int done = st->done;   // tested once the first loads are in flight
   const int wg = mg_group(pin);
   if (wg < 0) return;
   const int P = wg * kWG + threadIdx.x;
   if (P >= n) return;
+  int q[KR];
+  R w[KR];
+  mg_row<R, KR>(n, K, nbr, W, P, q, w);
   const R rP = r[P], dP = Dinv[P];
-  const R zP = omega * dP * rP + ec[parent[P]];
-  int q[kMgRowMax];
-#pragma unroll
-  for (int s = 0; s < kMgRowMax; ++s) q[s] = s < K ? nbr[s * n + P] : -1;
+  const int pP = parent[P];
+  if (done) return;
+  const R zP = omega * dP * rP + ec[pP];
   R mz = R(0);
 #pragma unroll
-  for (int s = 0; s < kMgRowMax; ++s)
-    if (q[s] >= 0) mz += W[s * n + P] * (zP - (omega * Dinv[q[s]] * r[q[s]] + ec[parent[q[s]]]));
-  for (int s = kMgRowMax; s < K; ++s) {
+  for (int s = 0; s < KR; ++s) {
+    const int Q = q[s] >= 0 ? q[s] : P;   // absent slots add w (zP - zP) = 0
+    mz += w[s] * (zP - (omega * Dinv[Q] * r[Q] + ec[parent[Q]]));
+  }
+  for (int s = KR; s < K; ++s) {
     const int Q = nbr[s * n + P];
     if (Q >= 0) mz += W[s * n + P] * (zP - (omega * Dinv[Q] * r[Q] + ec[parent[Q]]));
   }
@@ -579,26 +657,26 @@ int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r,
     const MgLevel& F = c->mg[l - 1];
     const MgLevel& C = c->mg[l];
     const int gw = grid_cells((1 << c->dim) * C.n), pin = pinned(gw);
-    if (c->dim == 2)
-      launch_timed(c, s, kTimeMgCoarse, k_mg_down<R, 4>, grid_of(gw, pin), F.n, F.K, (const int*)F.nbr,
-                   (const R*)F.W, (const R*)F.Dinv, (const R*)F.r, (const int*)C.child, C.n, om, (R*)C.r,
-                   (const CgState*)st, pin);
-    else
-      launch_timed(c, s, kTimeMgCoarse, k_mg_down<R, 8>, grid_of(gw, pin), F.n, F.K, (const int*)F.nbr,
-                   (const R*)F.W, (const R*)F.Dinv, (const R*)F.r, (const int*)C.child, C.n, om, (R*)C.r,
-                   (const CgState*)st, pin);
+    auto kern = c->dim == 2 ? (F.K <= 4 ? k_mg_down<R, 4, 4> : (F.K <= 6 ? k_mg_down<R, 4, 6> : k_mg_down<R, 4, 8>))
+                            : (F.K <= 4 ? k_mg_down<R, 8, 4> : (F.K <= 6 ? k_mg_down<R, 8, 6> : k_mg_down<R, 8, 8>));
+    launch_timed(c, s, kTimeMgCoarse, kern, grid_of(gw, pin), F.n, F.K, (const int*)F.nbr, (const R*)F.W,
+                 (const R*)F.Dinv, (const R*)F.r, (const int*)C.child, C.n, om, (R*)C.r, (const CgState*)st, pin);
   }
   {
     const MgLevel& L = c->mg[nl - 1];
-    launch_timed_wg(c, s, kTimeMgCoarse, k_mg_coarse<R>, 1, kMgCoarse, L.n, L.K, (const int*)L.nbr,
-                    (const R*)L.W, (const R*)L.Dinv, (const R*)L.r, om, (int)kMgCoarseSweeps, (R*)L.e,
-                    (const CgState*)st);
+    const double lo = 2.0 / kMgChebRatio, hi = 2.0;
+    const R th = (R)(0.5 * (hi + lo)), de = (R)(0.5 * (hi - lo));
+    const int steps = c->dim == 3 ? kMgCoarseSteps3 : kMgCoarseSteps2;
+    auto kern = L.K <= 4 ? k_mg_coarse<R, 4> : (L.K <= 6 ? k_mg_coarse<R, 6> : k_mg_coarse<R, 8>);
+    launch_timed_wg(c, s, kTimeMgCoarse, kern, 1, kMgCoarseThreads, L.n, L.K, (const int*)L.nbr, (const R*)L.W,
+                    (const R*)L.Dinv, (const R*)L.r, th, de, steps, (R*)L.e, (const CgState*)st);
   }
   for (int l = nl - 2; l >= 0; --l) {
     const MgLevel& F = c->mg[l];
     const MgLevel& C = c->mg[l + 1];
     const int gw = grid_cells(F.n), pin = pinned(gw);
-    launch_timed(c, s, kTimeMgCoarse, k_mg_up<R>, grid_of(gw, pin), F.n, F.K, (const int*)F.nbr, (const R*)F.W,
+    auto kern = F.K <= 4 ? k_mg_up<R, 4> : (F.K <= 6 ? k_mg_up<R, 6> : k_mg_up<R, 8>);
+    launch_timed(c, s, kTimeMgCoarse, kern, grid_of(gw, pin), F.n, F.K, (const int*)F.nbr, (const R*)F.W,
                  (const R*)F.Dinv, (const R*)F.r, (const int*)C.parent, (const R*)C.e, om, (R*)F.e,
                  (const CgState*)st, pin);
   }
