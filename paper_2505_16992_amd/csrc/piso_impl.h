@@ -91,6 +91,7 @@ constexpr int kMgCoarseThreads = 1024;   // that work-group: kMgCoarse / kMgCoar
 constexpr int kMgMaxLevels = 16;
 constexpr int kMgCoarseSteps3 = 16;   // Chebyshev steps on the coarsest level, 3D
 constexpr int kMgCoarseSteps2 = 32;   // and 2D (cheaper steps, slower Jacobi-type convergence)
+constexpr int kMgCoarseStepsMax = 32;
 constexpr double kMgChebRatio = 100.0;   // their interval [2 / ratio, 2] of the spectrum of D^-1 M
 constexpr double kMgOmega = 0.8;    // Jacobi damping of the smoother
 constexpr int kMgPinGroups = 64;    // coarse-level launches up to this many work-groups run on one XCD

@@ -213,90 +213,129 @@ k_mg_down(int nf, int Kf, const int* __restrict__ nbr, const R* __restrict__ W, 
 // outer CG stays a plain PCG; eigenvalues below lo are damped less, not amplified.
 // Recurrence (theta = (hi + lo) / 2, delta = (hi - lo) / 2, sigma = theta / delta):
 //   x = 0, s = r, d = D^-1 r / theta, rho = 1 / sigma;  per step
-//   x += d, s -= M d, rho' = 1 / (2 sigma - rho), d = rho' rho d + (2 rho' / delta) D^-1 s.
+//   x += d, s -= M d, rho' = 1 / (2 sigma - rho), d = rho' rho d + (2 rho' / delta) D^-1 s,
+// with the step coefficients a = rho' rho and b = 2 rho' / delta computed on the host.
 // Thread t owns cells t + c kMgCoarseThreads with their graph rows in registers (KR
 // slots; longer rows read the rest from global memory); d is exchanged through a double
-// buffer in LDS, one barrier per step.  The steps are bound by LDS reads (a row's
-// neighbours), so only present slots and cells are read.
+// buffer in LDS, one barrier per step.  One work-group does all the arithmetic, so a
+// step is bound by its VALU work: the LDS addresses are fixed before the steps and the
+// buffer roles at compile time.  (M d)_I is summed as w_s (d_I - d_q(s)), which is exact
+// zero for a constant d.
+// Constants span the null space of M (the pressure operator is pure Neumann and the
+// grid connected).  The restricted right-hand side has a rounding-size constant part
+// which p(0) = 1 leaves in the residual and the iteration amplifies into x (by about
+// 80 at 16 steps); in FP32 the iterates of the outer CG then carry a large constant and
+// lose their precision.  The coarse solve is therefore Pi B Pi with Pi the projection
+// onto zero mean, applied to r and to x (fixed order sums in double): still symmetric
+// and positive semi-definite, and unchanged on zero-mean input in exact arithmetic.
+template <typename R>
+struct MgCheb {
+  R inv_theta;
+  R a[kMgCoarseStepsMax], b[kMgCoarseStepsMax];
+};
+
+template <typename R, int KR>
+__device__ __forceinline__ void mg_cheb_step(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W,
+                                             const R* dold, R* dnew, R a, R b, const int (&q)[2][KR],
+                                             const R (&w)[2][KR], const R (&di)[2], R (&x)[2], R (&res)[2],
+                                             R (&dv)[2]) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int I = (int)threadIdx.x + c * kMgCoarseThreads;
+    if (I < n) {
+      R md = R(0);
+#pragma unroll
+      for (int s = 0; s < KR; ++s) md += w[c][s] * (dv[c] - dold[q[c][s]]);
+      for (int s = KR; s < K; ++s) {   // rows longer than the register block
+        const int Q = nbr[s * n + I];
+        if (Q >= 0) md += W[s * n + I] * (dv[c] - dold[Q]);
+      }
+      x[c] += dv[c];
+      res[c] -= md;
+      dv[c] = a * dv[c] + b * di[c] * res[c];
+      dnew[I] = dv[c];   // the other buffer: nobody reads it during this step
+    }
+  }
+}
+
+// Sum over the coarse work-group of two values per thread (fixed order), in every thread.
+__device__ __forceinline__ double mg_coarse_sum(double v, double* lds /* [kMgCoarseThreads / 64] */) {
+  constexpr int NW = kMgCoarseThreads / 64;
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) t += lds[w];
+  __syncthreads();   // lds is reused by the next call
+  return t;
+}
+
 template <typename R, int KR>
 __global__ void __launch_bounds__(kMgCoarseThreads)
 k_mg_coarse(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, const R* __restrict__ Dinv,
-            const R* __restrict__ r, R theta, R delta, int steps, R* __restrict__ e, const CgState* st) {
-  constexpr int C = kMgCoarse / kMgCoarseThreads;
+            const R* __restrict__ r, MgCheb<R> cc, int steps, R* __restrict__ e, const CgState* st) {
+  static_assert(kMgCoarse == 2 * kMgCoarseThreads, "two cells per thread");
   const int done = st->done;   // tested once the row loads are in flight
   __shared__ R ds[2][kMgCoarse];
-  int q[C][KR];
-  R w[C][KR];
-  R x[C], res[C], dv[C], di[C];
-  const R sigma = theta / delta;
-  R rho = R(1) / sigma;
+  int q[2][KR];
+  R w[2][KR];
+  R x[2], res[2], dv[2], di[2];
   // every load is unconditional (indices clamped into the arrays, results masked after),
   // so that all of them are in flight together
   const int Kc = K < KR ? K : KR;   // K >= 1: every level has a slot
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
+  for (int c = 0; c < 2; ++c) {
     const int I = (int)threadIdx.x + c * kMgCoarseThreads;
-    const bool on = I < n;
-    const int Ic = on ? I : 0;
+    const int Ic = I < n ? I : 0;
 #pragma unroll
     for (int s = 0; s < KR; ++s) {
       const int sc = s < Kc ? s : Kc - 1;
-      const bool have = on && s < Kc;
-      const int qv = nbr[sc * n + Ic];
-      const R wv = W[sc * n + Ic];
-      q[c][s] = have ? qv : -1;
-      w[c][s] = have ? wv : R(0);
+      q[c][s] = nbr[sc * n + Ic];
+      w[c][s] = W[sc * n + Ic];
     }
     res[c] = r[Ic];
     di[c] = Dinv[Ic];
   }
   if (done) return;
+  __shared__ double red[kMgCoarseThreads / 64];
+  {
+    const int I1 = (int)threadIdx.x + kMgCoarseThreads;
+    if ((int)threadIdx.x >= n) res[0] = R(0);
+    if (I1 >= n) res[1] = R(0);
+    const R mean = (R)(mg_coarse_sum((double)res[0] + (double)res[1], red) / n);
+    if ((int)threadIdx.x < n) res[0] -= mean;
+    if (I1 < n) res[1] -= mean;
+  }
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
+  for (int c = 0; c < 2; ++c) {
     const int I = (int)threadIdx.x + c * kMgCoarseThreads;
     const bool on = I < n;
     if (!on) res[c] = di[c] = R(0);
 #pragma unroll
     for (int s = 0; s < KR; ++s)
-      if (q[c][s] < 0) {   // an absent slot contributes w (d - d) = 0
+      if (!on || s >= Kc || q[c][s] < 0) {   // absent slot: weight 0 on the cell itself
         q[c][s] = on ? I : 0;
         w[c][s] = R(0);
       }
     x[c] = R(0);
-    dv[c] = di[c] * res[c] / theta;
+    dv[c] = di[c] * res[c] * cc.inv_theta;
     if (on) ds[0][I] = dv[c];
   }
   __syncthreads();
-  for (int it = 0; it < steps; ++it) {
-    const R* dold = ds[it & 1];
-    R* dnew = ds[(it + 1) & 1];
-    const R rn = R(1) / (R(2) * sigma - rho);
-    const R a = rn * rho, b = R(2) * rn / delta;
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      const int I = (int)threadIdx.x + c * kMgCoarseThreads;
-      if (I < n) {
-        R md = R(0);
-#pragma unroll
-        for (int s = 0; s < KR; ++s)
-          if (s < K) md += w[c][s] * (dv[c] - dold[q[c][s]]);
-        for (int s = KR; s < K; ++s) {   // rows longer than the register block
-          const int Q = nbr[s * n + I];
-          if (Q >= 0) md += W[s * n + I] * (dv[c] - dold[Q]);
-        }
-        x[c] += dv[c];
-        res[c] -= md;
-        dv[c] = a * dv[c] + b * di[c] * res[c];
-        dnew[I] = dv[c];   // the other buffer: nobody reads it during this step
-      }
-    }
-    rho = rn;
+  int it = 0;
+  for (; it + 1 < steps; it += 2) {   // buffer roles fixed at compile time
+    mg_cheb_step<R, KR>(n, K, nbr, W, ds[0], ds[1], cc.a[it], cc.b[it], q, w, di, x, res, dv);
+    __syncthreads();
+    mg_cheb_step<R, KR>(n, K, nbr, W, ds[1], ds[0], cc.a[it + 1], cc.b[it + 1], q, w, di, x, res, dv);
     __syncthreads();
   }
+  if (it < steps) mg_cheb_step<R, KR>(n, K, nbr, W, ds[0], ds[1], cc.a[it], cc.b[it], q, w, di, x, res, dv);
+  const R mean = (R)(mg_coarse_sum((double)x[0] + (double)x[1], red) / n);   // x is 0 off the level
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
+  for (int c = 0; c < 2; ++c) {
     const int I = (int)threadIdx.x + c * kMgCoarseThreads;
-    if (I < n) e[I] = x[c];
+    if (I < n) e[I] = x[c] - mean;
   }
 }
 
@@ -638,6 +677,23 @@ int mg_prescale(piso_ctx* c, hipStream_t s, const R* Dinv, const R* r, R* y) {
   return mg_check(c, "k_mg_prescale");
 }
 
+// Chebyshev step coefficients of the coarsest solve (see k_mg_coarse), in double.
+template <typename R>
+static MgCheb<R> mg_cheb_coef(int steps) {
+  const double lo = 2.0 / kMgChebRatio, hi = 2.0;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  MgCheb<R> cc{};
+  cc.inv_theta = (R)(1.0 / theta);
+  double rho = 1.0 / sigma;
+  for (int i = 0; i < steps && i < kMgCoarseStepsMax; ++i) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    cc.a[i] = (R)(rn * rho);
+    cc.b[i] = (R)(2.0 * rn / delta);
+    rho = rn;
+  }
+  return cc;
+}
+
 template <typename R>
 int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, const R* y, R* z, CgState* st,
              double* partB, int G) {
@@ -664,12 +720,11 @@ int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r,
   }
   {
     const MgLevel& L = c->mg[nl - 1];
-    const double lo = 2.0 / kMgChebRatio, hi = 2.0;
-    const R th = (R)(0.5 * (hi + lo)), de = (R)(0.5 * (hi - lo));
     const int steps = c->dim == 3 ? kMgCoarseSteps3 : kMgCoarseSteps2;
+    const MgCheb<R> cc = mg_cheb_coef<R>(steps);
     auto kern = L.K <= 4 ? k_mg_coarse<R, 4> : (L.K <= 6 ? k_mg_coarse<R, 6> : k_mg_coarse<R, 8>);
     launch_timed_wg(c, s, kTimeMgCoarse, kern, 1, kMgCoarseThreads, L.n, L.K, (const int*)L.nbr, (const R*)L.W,
-                    (const R*)L.Dinv, (const R*)L.r, th, de, steps, (R*)L.e, (const CgState*)st);
+                    (const R*)L.Dinv, (const R*)L.r, cc, steps, (R*)L.e, (const CgState*)st);
   }
   for (int l = nl - 2; l >= 0; --l) {
     const MgLevel& F = c->mg[l];
