@@ -286,9 +286,11 @@ def main():
         model = {
             # Pf (d), operand (z, or r and Dinv), d_old -> d_new, q
             "cg_stencil": ("k_cg_spmv_q" if quad else "k_cg_spmv", N * ((d + 4) if mg else (d + 5)) * es),
-            # x, r, d_new, q, Dinv -> x, r (+ y = omega Dinv r for the multigrid)
-            "cg_update": ("k_cg_update_q" if quad else "k_cg_update", N * (8 if mg else 7) * es),
-            # r, y, Pf (d) -> level-1 residual
+            # x, r, d_new, q, Dinv -> x, r (Jacobi)
+            "cg_update": ("k_cg_update_q" if quad else "k_cg_update", N * 7 * es),
+            # multigrid: x, r, d_new, q, Dinv, Pf (d) -> x, r', y, level-1 residual
+            "cg_update_restrict": ("k_mg_down0uq" if quad else "k_mg_down0u", N * (d + 8) * es + (N // nch) * es),
+            # r, y, Pf (d) -> level-1 residual (first V-cycle of a solve)
             "mg_down0": ("k_mg_down0", N * (d + 2) * es + (N // nch) * es),
             # y, r, Dinv, Pf (d), level-1 correction -> z
             "mg_up0": ("k_mg_up0_q" if quad else "k_mg_up0", N * (d + 4) * es + (N // nch) * es),

@@ -340,7 +340,8 @@ typedef enum {
   PISO_TIME_MG_DOWN0 = 2,    /* multigrid restriction from the fine grid */
   PISO_TIME_MG_UP0 = 3,      /* multigrid prolongation and smoothing on the fine grid */
   PISO_TIME_MG_COARSE = 4,   /* multigrid kernels on the coarse levels */
-  PISO_TIME_KINDS = 5
+  PISO_TIME_CG_UPDATE_MG = 5, /* multigrid PCG: x, r update fused with the fine-grid restriction */
+  PISO_TIME_KINDS = 6
 } piso_time_kind;
 
 int piso_set_timing(piso_ctx* ctx, int32_t enable);

@@ -18,7 +18,7 @@ PISO_OK, PISO_NOT_CONVERGED, PISO_BREAKDOWN = 0, 1, 2
 PISO_E_ARG, PISO_E_TOPOLOGY, PISO_E_HIP, PISO_E_NAN, PISO_E_OOM = -1, -2, -3, -4, -5
 PISO_SIDE_CONNECT, PISO_SIDE_DIRICHLET = 0, 1
 PISO_PRECOND_JACOBI, PISO_PRECOND_MG = 0, 1
-TIME_KINDS = ("cg_stencil", "cg_update", "mg_down0", "mg_up0", "mg_coarse")
+TIME_KINDS = ("cg_stencil", "cg_update", "mg_down0", "mg_up0", "mg_coarse", "cg_update_restrict")
 
 
 class SideDesc(C.Structure):

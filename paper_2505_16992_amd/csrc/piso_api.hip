@@ -243,7 +243,7 @@ int alloc_workspaces(piso_ctx* c) {
       {&c->w_rhs, N * 8}, {&c->w_us, D * N * e}, {&c->w_u1, D * N * e}, {&c->w_p1, N * e},
       {&c->w_h1, D * N * e}, {&c->w_tg, D * D * N * e}, {&c->w_tgp, D * N * e},
       {(void**)&c->w_rhs64, N * 8}, {(void**)&c->w_p64, N * 8}, {&c->m_r32, N * 4}, {&c->m_e32, N * 4},
-      {&c->k_r, N * e}, {&c->k_q, N * e}, {&c->k_d0, N * e}, {&c->k_d1, N * e},
+      {&c->k_r, N * e}, {&c->k_r2, N * e}, {&c->k_q, N * e}, {&c->k_d0, N * e}, {&c->k_d1, N * e},
       {&c->g_Pf, D * N * e}, {&c->g_Dinv, N * e}, {&c->g_x, N * e},
       {&c->b_r, D * N * e}, {&c->b_rh, D * N * e}, {&c->b_p0, D * N * e}, {&c->b_p1, D * N * e},
       {&c->b_v0, D * N * e}, {&c->b_v1, D * N * e}, {&c->b_s, D * N * e}, {&c->b_t, D * N * e},

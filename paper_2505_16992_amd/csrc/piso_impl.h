@@ -48,7 +48,8 @@ constexpr int kTimeCgUpdate = 1;    // PCG x, r update
 constexpr int kTimeMgDown0 = 2;     // multigrid restriction from the fine grid
 constexpr int kTimeMgUp0 = 3;       // multigrid prolongation and smoothing on the fine grid
 constexpr int kTimeMgCoarse = 4;    // multigrid kernels on the coarse levels
-constexpr int kTimeKinds = 5;
+constexpr int kTimeCgUpdateMg = 5;  // PCG update fused with the fine-grid restriction
+constexpr int kTimeKinds = 6;
 
 struct Timing {
   bool enabled = false;
@@ -84,6 +85,15 @@ struct MgTiles {
   int nb;
   int off[kMaxBlocks + 1];
   int nseg[kMaxBlocks];
+};
+
+// Work-groups of the quad-vectorised fused update and restriction: per block, the first
+// group and the number of units (an x-quad of 4 fine cells in one aggregate row and
+// plane, handled by 2^(d-1) threads: one per fine row and plane parity).
+struct MgQuadTiles {
+  int nb;
+  int off[kMaxBlocks + 1];
+  int units[kMaxBlocks];
 };
 
 constexpr int kMgCoarse = 2048;     // stop coarsening at this many cells (one work-group solves it)
@@ -123,6 +133,7 @@ struct piso_ctx {
   double* w_p64 = nullptr;        // [N] (MIXED)
   void *m_r32 = nullptr, *m_e32 = nullptr;   // float [N] (MIXED refinement)
   void *k_r = nullptr, *k_q = nullptr, *k_d0 = nullptr, *k_d1 = nullptr;   // PCG [N]
+  void* k_r2 = nullptr;           // second residual buffer of the multigrid PCG [N]
   void* k_z = nullptr;            // PCG preconditioned residual [N] (multigrid)
   void* k_y = nullptr;            // omega D^-1 r, the multigrid pre-smoothing [N]
   // PCG operands copied into context-owned buffers (graph-stable pointers)
@@ -136,6 +147,7 @@ struct piso_ctx {
   std::vector<piso::MgLevel> mg;  // coarse levels 1..L of the pressure preconditioner
   piso::Grid mg_g1{};             // level 1 as a block table (offsets, dims, division magic)
   piso::MgTiles mg_tiles{};       // work-group tiles of the fine-grid restriction
+  piso::MgQuadTiles mg_qtiles{};  // the same for the quad-vectorised fused update (nx % 4 == 0)
   // Dirichlet faces: owning cell and side (2 * axis + high), and the boundary cells
   // with their faces (ascending) for deterministic gathers
   int *out_bcell = nullptr, *out_bside = nullptr, *out_bc_cell = nullptr, *out_bc_ptr = nullptr,
@@ -306,6 +318,13 @@ int mg_prescale(piso_ctx* c, hipStream_t s, const R* Dinv, const R* r, R* y);
 template <typename R>
 int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, const R* y, R* z, CgState* st,
              double* partB, int G);
+// One PCG update (alpha from the Gp partials of d.q in partA, x += alpha d, rout = rin -
+// alpha q, y = omega D^-1 rout) fused with the fine-grid restriction, then the rest of
+// the V-cycle as mg_apply on rout.
+template <typename R>
+int mg_update_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, R* x, const R* rin, R* rout,
+                    const R* dnew, const R* q, R* y, R* z, CgState* st, const double* partA, int Gp, int par,
+                    double* partB, int G);
 
 // ---- advective outflow boundary (piso_outflow.hip) ----
 struct OutflowUm {

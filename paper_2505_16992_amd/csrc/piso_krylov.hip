@@ -144,11 +144,13 @@ k_cg_spmv(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R*
   write_partials<1>(acc, partA);
 }
 
-template <typename R, bool RED = true>
+// Jacobi PCG update: x += alpha d, r -= alpha q, partials of r.D^-1 r and r.r (the
+// multigrid PCG fuses its update with the fine-grid restriction instead).
+template <typename R>
 __global__ void __launch_bounds__(kWG)
 k_cg_update(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restrict__ r,
             const R* __restrict__ dnew, const R* __restrict__ q, CgState* st, const double* __restrict__ partA,
-            double* __restrict__ partB, int Gp, int par, R* __restrict__ y, R omega) {
+            double* __restrict__ partB, int Gp, int par) {
   const int done = st->done;
   const double rzp = st->rz[par];
   double t[1];
@@ -172,14 +174,10 @@ k_cg_update(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restrict_
     x[P] += alpha * dnew[P];
     const R rn = r[P] - alpha * q[P];
     r[P] = rn;
-    if (RED) {
-      acc[0] += (double)rn * (double)(Dinv[P] * rn);
-      acc[1] += (double)rn * (double)rn;
-    } else {
-      y[P] = omega * Dinv[P] * rn;   // multigrid pre-smoothing of the new residual
-    }
+    acc[0] += (double)rn * (double)(Dinv[P] * rn);
+    acc[1] += (double)rn * (double)rn;
   }
-  if (RED) write_partials<2>(acc, partB);
+  write_partials<2>(acc, partB);
 }
 
 
@@ -240,11 +238,11 @@ k_cg_spmv_q(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const 
   write_partials<1>(acc, partA);
 }
 
-template <typename R, bool RED = true>
+template <typename R>
 __global__ void __launch_bounds__(kWG)
 k_cg_update_q(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restrict__ r,
               const R* __restrict__ dnew, const R* __restrict__ q, CgState* st, const double* __restrict__ partA,
-              double* __restrict__ partB, int Gp, int par, R* __restrict__ y, R omega) {
+              double* __restrict__ partB, int Gp, int par) {
   const int done = st->done;
   const double rzp = st->rz[par];
   double t[1];
@@ -274,22 +272,15 @@ k_cg_update_q(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restric
       rv.v[e] -= alpha * qv.v[e];
     }
     const Q4<R> Dv = ldq(Dinv, P);
-    if constexpr (RED) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        acc[0] += (double)rv.v[e] * (double)(Dv.v[e] * rv.v[e]);
-        acc[1] += (double)rv.v[e] * (double)rv.v[e];
-      }
-    } else {
-      Q4<R> yv;   // multigrid pre-smoothing of the new residual
-#pragma unroll
-      for (int e = 0; e < 4; ++e) yv.v[e] = omega * Dv.v[e] * rv.v[e];
-      stq(y, P, yv);
+    for (int e = 0; e < 4; ++e) {
+      acc[0] += (double)rv.v[e] * (double)(Dv.v[e] * rv.v[e]);
+      acc[1] += (double)rv.v[e] * (double)rv.v[e];
     }
     stq(x, P, xv);
     stq(r, P, rv);
   }
-  if constexpr (RED) write_partials<2>(acc, partB);
+  write_partials<2>(acc, partB);
 }
 
 // MIXED form: r64 = b64 - M x64 in double with b64 = -(rhs64 - mean) and the float face
@@ -650,7 +641,7 @@ struct PcgOps {
   const R* Pf;
   const R* Dinv;
   R* x;
-  R *r, *q, *d0, *d1, *z, *y;
+  R *r, *r2, *q, *d0, *d1, *z, *y;   // r2: second residual buffer (multigrid: r alternates by parity)
   double *pA, *pB;
   int G;
   bool mg, quad;
@@ -664,7 +655,6 @@ static int pcg_iteration(piso_ctx* c, hipStream_t s, const PcgOps<R>& o, int par
   R* dold = par ? o.d1 : o.d0;
   R* dnew = par ? o.d0 : o.d1;
   const R* opnd = o.mg ? (const R*)o.z : (const R*)o.r;
-  const R om = (R)kMgOmega;
   const double* pBc = o.pB;
   if (o.quad) {
     if (c->dim == 2) {
@@ -682,12 +672,9 @@ static int pcg_iteration(piso_ctx* c, hipStream_t s, const PcgOps<R>& o, int par
         launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 3>, G, c->grid, o.Pf, o.Dinv, opnd, (const R*)dold,
                      dnew, o.q, st, pBc, o.pA, G, par);
     }
-    if (o.mg)
-      launch_timed(c, s, kTimeCgUpdate, k_cg_update_q<R, false>, G, N, o.Dinv, o.x, o.r, (const R*)dnew,
-                   (const R*)o.q, st, (const double*)o.pA, o.pB, G, par, o.y, om);
-    else
+    if (!o.mg)
       launch_timed(c, s, kTimeCgUpdate, k_cg_update_q<R>, G, N, o.Dinv, o.x, o.r, (const R*)dnew, (const R*)o.q,
-                   st, (const double*)o.pA, o.pB, G, par, o.y, om);
+                   st, (const double*)o.pA, o.pB, G, par);
   } else {
     if (c->dim == 2) {
       if (o.mg)
@@ -704,14 +691,15 @@ static int pcg_iteration(piso_ctx* c, hipStream_t s, const PcgOps<R>& o, int par
         launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 3>, G, c->grid, o.Pf, o.Dinv, opnd, (const R*)dold, dnew,
                      o.q, st, pBc, o.pA, G, par);
     }
-    if (o.mg)
-      launch_timed(c, s, kTimeCgUpdate, k_cg_update<R, false>, G, N, o.Dinv, o.x, o.r, (const R*)dnew,
-                   (const R*)o.q, st, (const double*)o.pA, o.pB, G, par, o.y, om);
-    else
+    if (!o.mg)
       launch_timed(c, s, kTimeCgUpdate, k_cg_update<R>, G, N, o.Dinv, o.x, o.r, (const R*)dnew, (const R*)o.q, st,
-                   (const double*)o.pA, o.pB, G, par, o.y, om);
+                   (const double*)o.pA, o.pB, G, par);
   }
-  if (o.mg) return mg_apply<R>(c, s, o.Pf, o.Dinv, (const R*)o.r, (const R*)o.y, o.z, st, o.pB, G);
+  // multigrid: the update is fused with the fine-grid restriction; the residual moves
+  // between r (even iterations read it) and r2 (odd ones)
+  if (o.mg)
+    return mg_update_apply<R>(c, s, o.Pf, o.Dinv, o.x, par ? (const R*)o.r2 : (const R*)o.r, par ? o.r : o.r2,
+                              (const R*)dnew, (const R*)o.q, o.y, o.z, st, (const double*)o.pA, G, par, o.pB, G);
   return check(c, "PCG iteration");
 }
 
@@ -761,6 +749,7 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
   o.Dinv = (const R*)c->g_Dinv;
   o.x = (R*)c->g_x;
   o.r = (R*)c->k_r;
+  o.r2 = (R*)c->k_r2;
   o.q = (R*)c->k_q;
   o.d0 = (R*)c->k_d0;
   o.d1 = (R*)c->k_d1;

@@ -131,6 +131,285 @@ k_mg_down0(Grid g, Grid g1, MgTiles tl, const R* __restrict__ Pf, const R* __res
   }
 }
 
+// The PCG update fused with the fine-grid restriction (multigrid PCG iterations):
+//   alpha = (r.z) / (d.q),  x += alpha d,  r' = r - alpha q,  y = omega D^-1 r',
+// then rc[I] = sum over the children P of aggregate I of r'_P - (M y)_P as in k_mg_down0.
+// y on the far side of a face leaving the aggregate is recomputed from r, q and D^-1
+// there (the same expressions as at P).  The residual is double-buffered (rin -> rout)
+// so that no work-group reads a value that another one has already overwritten; x is
+// updated in place (only at P).  Every work-group re-reduces the stencil kernel's
+// partials of d.q; the lead thread advances the iteration index (no other work-group
+// reads it in this kernel) and records a breakdown.  Same tiles as k_mg_down0.
+template <typename R, int D>
+__global__ void __launch_bounds__(64 << (D - 1))
+k_mg_down0u(Grid g, Grid g1, MgTiles tl, const R* __restrict__ Pf, const R* __restrict__ Dinv,
+            R* __restrict__ x, const R* __restrict__ rin, R* __restrict__ rout, const R* __restrict__ dnew,
+            const R* __restrict__ q, R* __restrict__ y, R omega, R* __restrict__ rc, CgState* st,
+            const double* __restrict__ partA, int Gp, int par) {
+  constexpr int NW = 1 << (D - 1);
+  const int done = st->done;
+  const double rzp = st->rz[par];
+  double t[1];
+  {
+    // reduce_partials for a work-group of NW waves
+    constexpr int WGS = 64 * NW;
+    __shared__ double red[NW];
+    double v = 0.0;
+    for (int w0 = 0; w0 < Gp; w0 += 4 * WGS) {
+      double u[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int w = w0 + (int)threadIdx.x + c * WGS;
+        u[c] = w < Gp ? partA[w] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v += u[c];
+    }
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double tt = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) tt += red[w];
+    t[0] = tt;
+  }
+  if (done) return;
+  const double dq = t[0];
+  if (!(dq > 0.0) || !std::isfinite(dq)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->status = std::isfinite(dq) ? PISO_BREAKDOWN : PISO_E_NAN;
+      st->iters = st->k;
+      st->done = 1;
+    }
+    return;
+  }
+  const R alpha = (R)(rzp / dq);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->k = st->k + 1;
+  __shared__ R part[NW][32];
+  const int tile = xcd_logical_group();
+  int b = 0;
+  for (int qq = 1; qq < tl.nb; ++qq) b += tile >= tl.off[qq] ? 1 : 0;
+  int lt = tile - tl.off[b];
+  const int* tf = g.tab + b * kTabStride;
+  const int* tc = g1.tab + b * kTabStride;
+  const int n[3] = {tf[1], tf[2], tf[3]};
+  const int cx = tc[1], cy = tc[2];
+  const int nseg = tl.nseg[b];
+  const int seg = lt % nseg;
+  lt /= nseg;
+  const int cj = lt % cy, ck = lt / cy;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int bit[3] = {lane & 1, w & 1, (w >> 1) & 1};
+  Cell c;
+  c.b = b;
+  c.i = seg * 64 + lane;
+  c.j = 2 * cj + bit[1];
+  c.k = 2 * ck + bit[2];
+  R v = R(0);
+  if (c.i < n[0] && c.j < n[1] && c.k < n[2]) {
+    const int N = g.N;
+    const int pos[3] = {c.i, c.j, c.k};
+    const int P = tf[0] + c.i + n[0] * (c.j + n[1] * c.k);
+    const R rn = rin[P] - alpha * q[P];
+    const R yP = omega * Dinv[P] * rn;
+    x[P] += alpha * dnew[P];
+    rout[P] = rn;
+    y[P] = yP;
+    R res = rn;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        const bool internal = sd ? (bit[j] == 0 && pos[j] + 1 < n[j]) : (bit[j] == 1);
+        if (internal) continue;
+        const int F = neighbour(g, c, P, j, sd);
+        if (F >= 0) {
+          const R wf = sd ? Pf[(size_t)j * N + P] : Pf[(size_t)j * N + F];
+          const R yF = omega * Dinv[F] * (rin[F] - alpha * q[F]);
+          res -= wf * (yP - yF);
+        }
+      }
+    }
+    v = res;
+  }
+  v += __shfl_xor(v, 1, 64);
+  if (!(lane & 1)) part[w][lane >> 1] = v;
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    const int ci = seg * 32 + threadIdx.x;
+    if (ci < cx) {
+      R sum = part[0][threadIdx.x];
+#pragma unroll
+      for (int qq = 1; qq < NW; ++qq) sum += part[qq][threadIdx.x];
+      rc[tc[0] + ci + cx * (cj + cy * ck)] = sum;
+    }
+  }
+}
+
+// Quad-vectorised form of k_mg_down0u (every block has nx % 4 == 0).  Thread layout:
+// lane = p + NP u with NP = 2^(d-1) parities p = (row parity) + 2 (plane parity) and u a
+// unit, an x-quad of 4 fine cells (two aggregates in x) of one aggregate row and plane;
+// units run x-quad fastest, then aggregate rows, then planes, per block.  All streams at
+// the thread's own cells move as 16-byte (float) vectors.  Faces leaving an aggregate:
+// in x, the faces of cells 0 and 3 of the quad to the neighbouring quads (their y comes
+// from the neighbouring lane when it holds that quad, else it is recomputed from memory)
+// and the face between cells 1 and 2 (two aggregates of the same quad); in y and z the
+// face to the next row or plane away from the aggregate's other fine row or plane (both
+// faces when the aggregate is one fine cell thick).  The NP parity lanes of a unit add
+// their aggregate sums with shuffles, and the lane of parity 0 writes the two aggregates.
+template <typename R, int D>
+__global__ void __launch_bounds__(kWG)
+k_mg_down0uq(Grid g, Grid g1, MgQuadTiles tl, const R* __restrict__ Pf, const R* __restrict__ Dinv,
+             R* __restrict__ x, const R* __restrict__ rin, R* __restrict__ rout, const R* __restrict__ dnew,
+             const R* __restrict__ q, R* __restrict__ y, R omega, R* __restrict__ rc, CgState* st,
+             const double* __restrict__ partA, int Gp, int par) {
+  constexpr int NP = 1 << (D - 1);
+  const int done = st->done;
+  const double rzp = st->rz[par];
+  double t[1];
+  reduce_partials<1>(partA, Gp, t);
+  if (done) return;
+  const double dq = t[0];
+  if (!(dq > 0.0) || !std::isfinite(dq)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->status = std::isfinite(dq) ? PISO_BREAKDOWN : PISO_E_NAN;
+      st->iters = st->k;
+      st->done = 1;
+    }
+    return;
+  }
+  const R alpha = (R)(rzp / dq);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->k = st->k + 1;   // no other group reads it here
+  const int N = g.N;
+  const int grp = xcd_logical_group();
+  int b = 0;
+  for (int qq = 1; qq < tl.nb; ++qq) b += grp >= tl.off[qq] ? 1 : 0;
+  const int* tf = g.tab + b * kTabStride;
+  const int* tc = g1.tab + b * kTabStride;
+  const int nx = tf[1], ny = tf[2], nz = tf[3], wrap = tf[kTabWrap];
+  const int cx = tc[1], cy = tc[2];
+  const int nxq = nx >> 2;
+  const int lane = threadIdx.x & 63, p = lane & (NP - 1);
+  const int u = (grp - tl.off[b]) * (kWG / NP) + ((int)threadIdx.x / NP);
+  const int xq = u % nxq, rest = u / nxq;
+  const int cj = rest % cy, ck = rest / cy;
+  const int j = 2 * cj + (p & 1), k = D == 3 ? 2 * ck + (p >> 1) : 0;
+  const bool valid = u < tl.units[b] && j < ny && k < nz;
+  const int i0 = 4 * xq;
+  const int P0 = valid ? tf[0] + i0 + nx * (j + ny * k) : 0;
+  // own cells: update, y, store
+  Q4<R> yq, res;
+  Q4<R> px;
+  if (valid) {
+    Q4<R> xv = ldq(x, P0);
+    const Q4<R> dv = ldq(dnew, P0), rv = ldq(rin, P0), qv = ldq(q, P0), Dv = ldq(Dinv, P0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      xv.v[e] += alpha * dv.v[e];
+      res.v[e] = rv.v[e] - alpha * qv.v[e];
+      yq.v[e] = omega * Dv.v[e] * res.v[e];
+    }
+    stq(x, P0, xv);
+    stq(rout, P0, res);
+    stq(y, P0, yq);
+    px = ldq(Pf, P0);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) yq.v[e] = res.v[e] = px.v[e] = R(0);
+  }
+  // y of one cell recomputed from memory (neighbours this thread's lanes do not hold)
+  auto y1 = [&](int F) { return omega * Dinv[F] * (rin[F] - alpha * q[F]); };
+  // x faces: cell 0 to the left quad, cells 1 | 2 inside, cell 3 to the right quad
+  const R yl_lane = __shfl_up(yq.v[3], NP, 64), pl_lane = __shfl_up(px.v[3], NP, 64);
+  const R yr_lane = __shfl_down(yq.v[0], NP, 64);
+  if (valid) {
+    // left: face coefficient stored at the left cell
+    int F = -1;
+    R yl = R(0), pl = R(0);
+    if (i0 > 0) {
+      if (lane >= NP && xq > 0) {
+        yl = yl_lane;
+        pl = pl_lane;
+        F = P0 - 1;
+      } else {
+        F = P0 - 1;
+        yl = y1(F);
+        pl = Pf[F];
+      }
+    } else {
+      F = (wrap & 1) ? P0 + nx - 1 : g.fmap[tf[4] + j + ny * k];
+      if (F >= 0) {
+        yl = y1(F);
+        pl = Pf[F];
+      }
+    }
+    if (F >= 0) res.v[0] -= pl * (yq.v[0] - yl);
+    // between the quad's two aggregates
+    res.v[1] -= px.v[1] * (yq.v[1] - yq.v[2]);
+    res.v[2] -= px.v[1] * (yq.v[2] - yq.v[1]);
+    // right: own face coefficient
+    int Fr = -1;
+    R yr = R(0);
+    if (i0 + 4 < nx) {
+      Fr = P0 + 4;
+      yr = (lane + NP < 64 && xq + 1 < nxq) ? yr_lane : y1(Fr);
+    } else {
+      Fr = (wrap & 2) ? P0 + 4 - nx : g.fmap[tf[5] + j + ny * k];
+      if (Fr >= 0) yr = y1(Fr);
+    }
+    if (Fr >= 0) res.v[3] -= px.v[3] * (yq.v[3] - yr);
+    // y and z faces
+#pragma unroll
+    for (int a = 1; a < D; ++a) {
+      const int pos = a == 1 ? j : k;
+      const int n = a == 1 ? ny : nz;
+      const int bit = pos & 1;
+      const int stride = a == 1 ? nx : nx * ny;
+      const R* Pa = Pf + (size_t)a * N;
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        const bool internal = sd ? (bit == 0 && pos + 1 < n) : (bit == 1);
+        if (internal) continue;
+        const bool in = sd ? pos + 1 < n : pos > 0;
+        const bool wr = ((wrap >> (2 * a + sd)) & 1) != 0;
+        if (in || wr) {
+          const int Pn = sd ? (in ? P0 + stride : P0 - (n - 1) * stride) : (in ? P0 - stride : P0 + (n - 1) * stride);
+          const Q4<R> rn = ldq(rin, Pn), qn = ldq(q, Pn), Dn = ldq(Dinv, Pn);
+          const Q4<R> wf = ldq(Pa, sd ? P0 : Pn);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const R yn = omega * Dn.v[e] * (rn.v[e] - alpha * qn.v[e]);
+            res.v[e] -= wf.v[e] * (yq.v[e] - yn);
+          }
+        } else {
+          const int base = tf[4 + 2 * a + sd] + (a == 1 ? i0 + nx * k : i0 + nx * j);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int F2 = g.fmap[base + e];
+            if (F2 >= 0) {
+              const R wf = sd ? Pa[P0 + e] : Pa[F2];
+              res.v[e] -= wf * (yq.v[e] - y1(F2));
+            }
+          }
+        }
+      }
+    }
+  }
+  // aggregates A (cells 0, 1) and B (cells 2, 3): sum over the NP parity lanes
+  R sa = valid ? res.v[0] + res.v[1] : R(0);
+  R sb = valid ? res.v[2] + res.v[3] : R(0);
+#pragma unroll
+  for (int o = 1; o < NP; o <<= 1) {
+    sa += __shfl_xor(sa, o, 64);
+    sb += __shfl_xor(sb, o, 64);
+  }
+  if (p == 0 && u < tl.units[b]) {
+    const int I = tc[0] + 2 * xq + cx * (cj + cy * ck);
+    rc[I] = sa;
+    rc[I + 1] = sb;
+  }
+}
+
 // y = omega D^-1 r (pre-smoothing from zero) after the PCG initialisation.
 template <typename R>
 __global__ void __launch_bounds__(kWG)
@@ -642,6 +921,16 @@ int mg_build(piso_ctx* c) {
         c->mg_tiles.nseg[b] = nseg;
         c->mg_tiles.off[b + 1] = c->mg_tiles.off[b] + nseg * nx.dims[b][1] * nx.dims[b][2];
       }
+      // quad tiles: units of one x-quad per aggregate row and plane, kWG / 2^(d-1) per group
+      const int upw = kWG >> (D - 1);
+      c->mg_qtiles.nb = B;
+      c->mg_qtiles.off[0] = 0;
+      for (int b = 0; b < B; ++b) {
+        const long long units = (long long)(cur.dims[b][0] / 4) * nx.dims[b][1] * nx.dims[b][2];
+        if (units > INT32_MAX / 2) return fail(c, PISO_E_ARG, "multigrid: block too large");
+        c->mg_qtiles.units[b] = (int)units;
+        c->mg_qtiles.off[b + 1] = c->mg_qtiles.off[b] + (int)((units + upw - 1) / upw);
+      }
     }
     c->mg.push_back(L);
     nbr_f.swap(nbr);
@@ -694,18 +983,15 @@ static MgCheb<R> mg_cheb_coef(int steps) {
   return cc;
 }
 
+// The V-cycle after the fine-grid restriction (level-1 residual in mg[0].r): coarse
+// levels, coarsest solve, prolongations, and the fine-grid prolongation and smoothing
+// into z with the partial sums of r.z and r.r.
 template <typename R>
-int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, const R* y, R* z, CgState* st,
-             double* partB, int G) {
+static int mg_tail(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, const R* y, R* z,
+                   CgState* st, double* partB, int G) {
   const int nl = (int)c->mg.size();
   const R om = (R)kMgOmega;
   const Grid& g1 = c->mg_g1;
-  if (c->dim == 2)
-    launch_timed_wg(c, s, kTimeMgDown0, k_mg_down0<R, 2>, c->mg_tiles.off[c->nblocks], 128, c->grid, g1,
-                    c->mg_tiles, Pf, y, r, (R*)c->mg[0].r, (const CgState*)st);
-  else
-    launch_timed_wg(c, s, kTimeMgDown0, k_mg_down0<R, 3>, c->mg_tiles.off[c->nblocks], 256, c->grid, g1,
-                    c->mg_tiles, Pf, y, r, (R*)c->mg[0].r, (const CgState*)st);
   // launches of at most kMgPinGroups work-groups run on one XCD (see mg_group)
   auto pinned = [](int groups) { return groups <= kMgPinGroups ? 1 : 0; };
   auto grid_of = [](int groups, int pin) { return pin ? 8 * groups : groups; };
@@ -759,6 +1045,46 @@ int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r,
   return mg_check(c, "multigrid V-cycle");
 }
 
+template <typename R>
+int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, const R* y, R* z, CgState* st,
+             double* partB, int G) {
+  const int tiles = c->mg_tiles.off[c->nblocks];
+  if (c->dim == 2)
+    launch_timed_wg(c, s, kTimeMgDown0, k_mg_down0<R, 2>, tiles, 128, c->grid, c->mg_g1, c->mg_tiles, Pf, y, r,
+                    (R*)c->mg[0].r, (const CgState*)st);
+  else
+    launch_timed_wg(c, s, kTimeMgDown0, k_mg_down0<R, 3>, tiles, 256, c->grid, c->mg_g1, c->mg_tiles, Pf, y, r,
+                    (R*)c->mg[0].r, (const CgState*)st);
+  return mg_tail<R>(c, s, Pf, Dinv, r, y, z, st, partB, G);
+}
+
+template <typename R>
+int mg_update_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, R* x, const R* rin, R* rout,
+                    const R* dnew, const R* q, R* y, R* z, CgState* st, const double* partA, int Gp, int par,
+                    double* partB, int G) {
+  const R om = (R)kMgOmega;
+  const bool quad = c->quad && ((((uintptr_t)Pf) | ((uintptr_t)Dinv) | ((uintptr_t)x) | ((uintptr_t)rin) |
+                                 ((uintptr_t)rout) | ((uintptr_t)dnew) | ((uintptr_t)q) | ((uintptr_t)y)) & 15u) == 0;
+  if (quad) {
+    const int groups = c->mg_qtiles.off[c->nblocks];
+    if (c->dim == 2)
+      launch_timed(c, s, kTimeCgUpdateMg, k_mg_down0uq<R, 2>, groups, c->grid, c->mg_g1, c->mg_qtiles, Pf, Dinv, x,
+                   rin, rout, dnew, q, y, om, (R*)c->mg[0].r, st, partA, Gp, par);
+    else
+      launch_timed(c, s, kTimeCgUpdateMg, k_mg_down0uq<R, 3>, groups, c->grid, c->mg_g1, c->mg_qtiles, Pf, Dinv, x,
+                   rin, rout, dnew, q, y, om, (R*)c->mg[0].r, st, partA, Gp, par);
+  } else {
+    const int tiles = c->mg_tiles.off[c->nblocks];
+    if (c->dim == 2)
+      launch_timed_wg(c, s, kTimeCgUpdateMg, k_mg_down0u<R, 2>, tiles, 128, c->grid, c->mg_g1, c->mg_tiles, Pf,
+                      Dinv, x, rin, rout, dnew, q, y, om, (R*)c->mg[0].r, st, partA, Gp, par);
+    else
+      launch_timed_wg(c, s, kTimeCgUpdateMg, k_mg_down0u<R, 3>, tiles, 256, c->grid, c->mg_g1, c->mg_tiles, Pf,
+                      Dinv, x, rin, rout, dnew, q, y, om, (R*)c->mg[0].r, st, partA, Gp, par);
+  }
+  return mg_tail<R>(c, s, Pf, Dinv, (const R*)rout, (const R*)y, z, st, partB, G);
+}
+
 template int mg_setup<float>(piso_ctx*, hipStream_t, const float*);
 template int mg_setup<double>(piso_ctx*, hipStream_t, const double*);
 template int mg_prescale<float>(piso_ctx*, hipStream_t, const float*, const float*, float*);
@@ -767,5 +1093,11 @@ template int mg_apply<float>(piso_ctx*, hipStream_t, const float*, const float*,
                              CgState*, double*, int);
 template int mg_apply<double>(piso_ctx*, hipStream_t, const double*, const double*, const double*, const double*,
                               double*, CgState*, double*, int);
+template int mg_update_apply<float>(piso_ctx*, hipStream_t, const float*, const float*, float*, const float*, float*,
+                                    const float*, const float*, float*, float*, CgState*, const double*, int, int,
+                                    double*, int);
+template int mg_update_apply<double>(piso_ctx*, hipStream_t, const double*, const double*, double*, const double*,
+                                     double*, const double*, const double*, double*, double*, CgState*,
+                                     const double*, int, int, double*, int);
 
 }  // namespace piso
