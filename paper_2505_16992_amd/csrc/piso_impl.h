@@ -99,7 +99,7 @@ struct MgQuadTiles {
 constexpr int kMgCoarse = 2048;     // stop coarsening at this many cells (one work-group solves it)
 constexpr int kMgCoarseThreads = 1024;   // that work-group: kMgCoarse / kMgCoarseThreads cells per thread
 constexpr int kMgMaxLevels = 16;
-constexpr int kMgCoarseSteps3 = 16;   // Chebyshev steps on the coarsest level, 3D
+constexpr int kMgCoarseSteps3 = 12;   // Chebyshev steps on the coarsest level, 3D
 constexpr int kMgCoarseSteps2 = 32;   // and 2D (cheaper steps, slower Jacobi-type convergence)
 constexpr int kMgCoarseStepsMax = 32;
 constexpr double kMgChebRatio = 100.0;   // their interval [2 / ratio, 2] of the spectrum of D^-1 M

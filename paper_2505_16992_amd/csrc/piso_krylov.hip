@@ -724,18 +724,21 @@ static int pcg_graph(piso_ctx* c, const PcgOps<R>& o, hipGraphExec_t* out) {
   return PISO_OK;
 }
 
-// Work-groups of the PCG kernels.  Every work-group of a kernel re-reduces the previous
+// Work-groups of the Krylov kernels.  Every work-group of a kernel re-reduces the previous
 // kernel's per-group partials, so more groups cost a longer prologue; fewer groups leave
 // the chip idle.  Measured on the 96^3, 192x128x192, 256^2 and cylinder workloads: best
 // with whole loop trips of 256 work units (quads or cells) per group, as few trips as
 // keep the grid at or below 1536 groups, and at least 256 groups (then 64 units each).
-static int pcg_groups(const piso_ctx* c) {
-  if (c->cg_grid > 0) return c->cg_grid;
-  const long units = c->quad ? (long)c->N / 4 : (long)c->N;
+static int solver_groups(long units) {
   const long trips = std::max(1L, (units + 256L * 1536 - 1) / (256L * 1536));
   long g = (units + 256 * trips - 1) / (256 * trips);
   if (g < 256) g = std::min(256L, (units + 63) / 64);
   return (int)std::max(1L, std::min(g, (long)kRedGrid));
+}
+
+static int pcg_groups(const piso_ctx* c) {
+  if (c->cg_grid > 0) return c->cg_grid;
+  return solver_groups(c->quad ? (long)c->N / 4 : (long)c->N);
 }
 
 template <typename R, typename BT>
@@ -922,7 +925,7 @@ int velocity_solve(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* 
                    const piso_solve_opts* o, piso_solve_info* info) {
   if (o->precond != PISO_PRECOND_JACOBI)
     return fail(c, PISO_E_ARG, "velocity solve: only the Jacobi preconditioner is available");
-  const int N = c->N, G = grid_red(N, c->red_grid), D = c->dim;
+  const int N = c->N, G = solver_groups(N), D = c->dim;   // cell-per-thread kernels
   R* r = (R*)c->b_r;
   R* rh = (R*)c->b_rh;
   R* pb[2] = {(R*)c->b_p0, (R*)c->b_p1};

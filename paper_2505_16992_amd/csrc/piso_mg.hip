@@ -497,16 +497,17 @@ k_mg_down(int nf, int Kf, const int* __restrict__ nbr, const R* __restrict__ W, 
 // Thread t owns cells t + c kMgCoarseThreads with their graph rows in registers (KR
 // slots; longer rows read the rest from global memory); d is exchanged through a double
 // buffer in LDS, one barrier per step.  One work-group does all the arithmetic, so a
-// step is bound by its VALU work: the LDS addresses are fixed before the steps and the
-// buffer roles at compile time.  (M d)_I is summed as w_s (d_I - d_q(s)), which is exact
-// zero for a constant d.
+// step is bound by its VALU work: the LDS addresses are fixed before the steps, the
+// buffer roles at compile time, and (M d)_I = d_I sum_s w_s - sum_s w_s d_q(s) takes one
+// fused multiply-add per slot.
 // Constants span the null space of M (the pressure operator is pure Neumann and the
 // grid connected).  The restricted right-hand side has a rounding-size constant part
-// which p(0) = 1 leaves in the residual and the iteration amplifies into x (by about
-// 80 at 16 steps); in FP32 the iterates of the outer CG then carry a large constant and
-// lose their precision.  The coarse solve is therefore Pi B Pi with Pi the projection
-// onto zero mean, applied to r and to x (fixed order sums in double): still symmetric
-// and positive semi-definite, and unchanged on zero-mean input in exact arithmetic.
+// which p(0) = 1 leaves in the residual and the iteration amplifies into x (by
+// q(0) = -p'(0), about 60 at 12 steps and 160 at 32); in FP32 the iterates of the outer CG then carry a large constant and
+// lose their precision (and the form of M d above turns a large constant in d into
+// noise).  The coarse solve is therefore Pi B Pi with Pi the projection onto zero mean,
+// applied to r and to x (fixed order sums in double): still symmetric and positive
+// semi-definite, and unchanged on zero-mean input in exact arithmetic.
 template <typename R>
 struct MgCheb {
   R inv_theta;
@@ -516,15 +517,15 @@ struct MgCheb {
 template <typename R, int KR>
 __device__ __forceinline__ void mg_cheb_step(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W,
                                              const R* dold, R* dnew, R a, R b, const int (&q)[2][KR],
-                                             const R (&w)[2][KR], const R (&di)[2], R (&x)[2], R (&res)[2],
-                                             R (&dv)[2]) {
+                                             const R (&w)[2][KR], const R (&wsum)[2], const R (&di)[2], R (&x)[2],
+                                             R (&res)[2], R (&dv)[2]) {
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const int I = (int)threadIdx.x + c * kMgCoarseThreads;
     if (I < n) {
-      R md = R(0);
+      R md = dv[c] * wsum[c];
 #pragma unroll
-      for (int s = 0; s < KR; ++s) md += w[c][s] * (dv[c] - dold[q[c][s]]);
+      for (int s = 0; s < KR; ++s) md -= w[c][s] * dold[q[c][s]];
       for (int s = KR; s < K; ++s) {   // rows longer than the register block
         const int Q = nbr[s * n + I];
         if (Q >= 0) md += W[s * n + I] * (dv[c] - dold[Q]);
@@ -559,7 +560,7 @@ k_mg_coarse(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, 
   __shared__ R ds[2][kMgCoarse];
   int q[2][KR];
   R w[2][KR];
-  R x[2], res[2], dv[2], di[2];
+  R x[2], res[2], dv[2], di[2], wsum[2];
   // every load is unconditional (indices clamped into the arrays, results masked after),
   // so that all of them are in flight together
   const int Kc = K < KR ? K : KR;   // K >= 1: every level has a slot
@@ -591,12 +592,15 @@ k_mg_coarse(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, 
     const int I = (int)threadIdx.x + c * kMgCoarseThreads;
     const bool on = I < n;
     if (!on) res[c] = di[c] = R(0);
+    wsum[c] = R(0);
 #pragma unroll
-    for (int s = 0; s < KR; ++s)
+    for (int s = 0; s < KR; ++s) {
       if (!on || s >= Kc || q[c][s] < 0) {   // absent slot: weight 0 on the cell itself
         q[c][s] = on ? I : 0;
         w[c][s] = R(0);
       }
+      wsum[c] += w[c][s];   // register slots only: longer rows use the difference form
+    }
     x[c] = R(0);
     dv[c] = di[c] * res[c] * cc.inv_theta;
     if (on) ds[0][I] = dv[c];
@@ -604,12 +608,12 @@ k_mg_coarse(int n, int K, const int* __restrict__ nbr, const R* __restrict__ W, 
   __syncthreads();
   int it = 0;
   for (; it + 1 < steps; it += 2) {   // buffer roles fixed at compile time
-    mg_cheb_step<R, KR>(n, K, nbr, W, ds[0], ds[1], cc.a[it], cc.b[it], q, w, di, x, res, dv);
+    mg_cheb_step<R, KR>(n, K, nbr, W, ds[0], ds[1], cc.a[it], cc.b[it], q, w, wsum, di, x, res, dv);
     __syncthreads();
-    mg_cheb_step<R, KR>(n, K, nbr, W, ds[1], ds[0], cc.a[it + 1], cc.b[it + 1], q, w, di, x, res, dv);
+    mg_cheb_step<R, KR>(n, K, nbr, W, ds[1], ds[0], cc.a[it + 1], cc.b[it + 1], q, w, wsum, di, x, res, dv);
     __syncthreads();
   }
-  if (it < steps) mg_cheb_step<R, KR>(n, K, nbr, W, ds[0], ds[1], cc.a[it], cc.b[it], q, w, di, x, res, dv);
+  if (it < steps) mg_cheb_step<R, KR>(n, K, nbr, W, ds[0], ds[1], cc.a[it], cc.b[it], q, w, wsum, di, x, res, dv);
   const R mean = (R)(mg_coarse_sum((double)x[0] + (double)x[1], red) / n);   // x is 0 off the level
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
