@@ -228,6 +228,7 @@ def main():
             gus[-1] = torch.ones_like(u0)
         dS = torch.zeros_like(S)
         gu, gp = None, None
+        ctx.adjoint_reset()   # adjoint pressure solves warm-start within this rollout only
         for q in range(n_steps - 1, -1, -1):
             gin = gus[q] if gu is None else gus[q] + gu
             g = ctx.step_backward(tapes[q], us[q], ps[q], nu, ub, case.dt, gin, gp, opts, want=("u", "p", "S"))

@@ -136,7 +136,12 @@ typedef struct {
   int32_t grad_p_in_predictor;     /* 1: b = b_u - grad p^n (eq. implEuler1); 0: b = b_u */
   int32_t grad_path_flags;         /* backward only: 1 = skip the adjoint velocity solve,
                                       2 = skip the adjoint pressure solves (Sec. 2.4) */
-  int32_t reserved;
+  int32_t adjoint_warm_start;      /* backward only: 1 = each adjoint pressure solve of
+                                      piso_step_backward starts from the solution of the same
+                                      corrector's solve in the previous call (consecutive steps
+                                      of a backward rollout have similar adjoint pressures);
+                                      0 = from zero.  The result then depends on that history
+                                      within the solver tolerance; piso_adjoint_reset clears it. */
 } piso_step_opts;
 
 typedef struct {
@@ -273,6 +278,13 @@ int piso_step_backward(piso_ctx* ctx, void* stream, const void* tape, const void
                        double dt, const void* du_np1, const void* dp_np1, void* du_n, void* dp_n,
                        void* dS, void* dnu, void* du_b, const piso_step_opts* opts,
                        piso_step_info* info);
+
+/* Forget the adjoint pressure solutions kept for adjoint_warm_start: the next
+ * piso_step_backward starts its adjoint pressure solves from zero.  Call at the start of
+ * every backward rollout whose gradients must not depend on earlier calls (results are
+ * then a function of the rollout alone, e.g. bit-identical with and without
+ * checkpointing). */
+int piso_adjoint_reset(piso_ctx* ctx);
 
 /* Advective outflow boundary (App. A.4, eq. advOut), applied between steps: on the
  * Dirichlet faces with outflow[f] != 0 (device int32 [NB]) the value is advanced

@@ -50,7 +50,7 @@ class SolveInfo(C.Structure):
 class StepOpts(C.Structure):
     _fields_ = [("vel", SolveOpts), ("pres", SolveOpts), ("n_correctors", C.c_int32),
                 ("grad_p_in_predictor", C.c_int32), ("grad_path_flags", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("adjoint_warm_start", C.c_int32)]
 
 
 class StepInfo(C.Structure):
@@ -107,6 +107,7 @@ _SIGS = {
     "piso_stats_finalize": (I32, [VP, VP, I32, VP, VP, VP]),
     "piso_stats_backward": (I32, [VP, VP, VP, I32, VP, VP, VP, VP]),
     "piso_set_timing": (I32, [VP, I32]),
+    "piso_adjoint_reset": (I32, [VP]),
     "piso_get_timing": (I32, [VP, I32, C.POINTER(F64), C.POINTER(C.c_int64)]),
 }
 

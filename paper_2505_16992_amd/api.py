@@ -195,6 +195,11 @@ class Context:
         out = {"u": du, "p": dp, "S": dS, "nu": dnu, "u_b": dub}
         return (out, inf.as_dict()) if info else out
 
+    def adjoint_reset(self):
+        """Start the next step_backward's adjoint pressure solves from zero (see
+        adjoint_warm_start in the step options)."""
+        return self._check(self.lib.piso_adjoint_reset(self.h), "piso_adjoint_reset")
+
     # ---------------------------------------------------------------- fine-grained calls
     def assemble(self, sys, u, p, nu, S, u_b, dt, grad_p_in_predictor=1):
         nu_t, nf = self._nu(nu)
@@ -376,6 +381,23 @@ class PisoStep(torch.autograd.Function):
         g = pctx.step_backward(tape, u, p, nu, u_b if fctx.has_ub else None, fctx.dt, du1, dp1, fctx.opts)
         return (None, None, None, g["u"], g["p"], g["S"], g["nu"].reshape(nu.shape),
                 g["u_b"] if fctx.has_ub else None)
+
+
+class _AdjointReset(torch.autograd.Function):
+    """Identity on the final state of a rollout whose backward runs before any step's
+    backward of that rollout: it clears the context's adjoint warm-start history, so the
+    rollout's gradients depend on the rollout alone (e.g. bit-identical with and without
+    checkpointing)."""
+
+    @staticmethod
+    def forward(fctx, pctx: Context, *xs):
+        fctx.pctx = pctx
+        return tuple(x.view_as(x) for x in xs)
+
+    @staticmethod
+    def backward(fctx, *gs):
+        fctx.pctx.adjoint_reset()
+        return (None,) + tuple(gs)
 
 
 class _Segment(torch.autograd.Function):
@@ -580,6 +602,14 @@ def rollout(pctx: Context, u0, p0, S, nu, u_b, dt, n_steps: int, checkpoint_ever
             done += 1
         if return_all:
             traj.append((u, p) if outflow is None else (u, p, ub))
+    if n_steps > 0 and torch.is_grad_enabled():
+        last = _AdjointReset.apply(pctx, u, p) if outflow is None else _AdjointReset.apply(pctx, u, p, ub)
+        if outflow is None:
+            u, p = last
+        else:
+            u, p, ub = last
+        if return_all:
+            traj[-1] = tuple(last)
     if return_all:
         return traj
     return (u, p) if outflow is None else (u, p, ub)

@@ -250,7 +250,7 @@ int alloc_workspaces(piso_ctx* c) {
       {&c->a_g, D * N * e}, {&c->a_uin, D * N * e}, {&c->a_lam, N * e}, {&c->a_pbar, N * e},
       {&c->a_mu, D * N * e}, {&c->a_dh, D * N * e}, {&c->a_dA, N * e}, {&c->a_dC, 2 * D * N * e},
       {&c->a_dbu, D * N * e}, {&c->a_db, D * N * e}, {&c->a_dp1, N * e}, {&c->a_dnu, N * e},
-      {&c->a_ybar, D * N * e}, {&c->a_cbar, D * D * N * e}, {&c->w_zb, D * (size_t)std::max(c->NB, 1) * e},
+      {&c->a_ybar, D * N * e}, {&c->a_cbar, D * D * N * e}, {&c->a_lam_hist[0], N * 8}, {&c->a_lam_hist[1], N * 8}, {&c->w_zb, D * (size_t)std::max(c->NB, 1) * e},
       {(void**)&c->partials, (size_t)kPartRegions * kRedGrid * sizeof(double)},
       {(void**)&c->mean, 8 * sizeof(double)}, {(void**)&c->cg, sizeof(CgState)}, {(void**)&c->bi, sizeof(BiState)},
   };
@@ -327,24 +327,47 @@ int do_pressure(piso_ctx* c, hipStream_t s, const R* A, const R* C, const R* bu,
   return pressure_solve<R, R>(c, s, Pf, Dinv, rhs, c->mean, p, o, info);
 }
 
-// Zero-mean lambda of P lambda = g - mean(g) (pressure adjoint), x0 = 0.
+// Zero-mean lambda of P lambda = g - mean(g) (pressure adjoint).  x0 = 0, or with
+// hist = 0 / 1 the kept solution of that corrector's previous adjoint solve when there is
+// one; a solve that ends with status >= 0 is kept for the next call.
 template <typename R>
 int do_pressure_adjoint(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* g, R* lam,
-                        const piso_solve_opts* o, piso_solve_info* info) {
+                        const piso_solve_opts* o, piso_solve_info* info, int hist = -1) {
   const int N = c->N;
+  const bool warm = hist >= 0 && c->lam_hist_valid[hist];
+  piso_solve_info tmp{};
+  piso_solve_info* inf = info ? info : &tmp;
   if (c->prec == PISO_MIXED) {
     if constexpr (std::is_same<R, float>::value) {
       if (int rc = launch_copy<float, double>(c, s, g, c->w_rhs64, N)) return rc;
       if (int rc = launch_sum<double, double>(c, s, c->w_rhs64, N, 1.0 / N, c->mean)) return rc;
-      PISO_HIP(c, hipMemsetAsync(c->w_p64, 0, sizeof(double) * N, s));
-      if (int rc = pressure_solve_mixed(c, s, Pf, Dinv, c->w_rhs64, c->mean, c->w_p64, o, info)) return rc;
-      return launch_copy<double, float>(c, s, c->w_p64, lam, N);
+      if (warm)
+        PISO_HIP(c, hipMemcpyAsync(c->w_p64, c->a_lam_hist[hist], sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+      else
+        PISO_HIP(c, hipMemsetAsync(c->w_p64, 0, sizeof(double) * N, s));
+      const int rc = pressure_solve_mixed(c, s, Pf, Dinv, c->w_rhs64, c->mean, c->w_p64, o, inf);
+      if (rc < 0) return rc;
+      if (hist >= 0 && inf->status >= 0) {
+        PISO_HIP(c, hipMemcpyAsync(c->a_lam_hist[hist], c->w_p64, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+        c->lam_hist_valid[hist] = true;
+      }
+      if (int rc2 = launch_copy<double, float>(c, s, c->w_p64, lam, N)) return rc2;
+      return rc;
     }
     return fail(c, PISO_E_ARG, "MIXED requires float storage");
   }
   if (int rc = launch_sum<R, double>(c, s, g, N, 1.0 / N, c->mean)) return rc;
-  PISO_HIP(c, hipMemsetAsync(lam, 0, sizeof(R) * N, s));
-  return pressure_solve<R, R>(c, s, Pf, Dinv, g, c->mean, lam, o, info);
+  if (warm)
+    PISO_HIP(c, hipMemcpyAsync(lam, c->a_lam_hist[hist], sizeof(R) * N, hipMemcpyDeviceToDevice, s));
+  else
+    PISO_HIP(c, hipMemsetAsync(lam, 0, sizeof(R) * N, s));
+  const int rc = pressure_solve<R, R>(c, s, Pf, Dinv, g, c->mean, lam, o, inf);
+  if (rc < 0) return rc;
+  if (hist >= 0 && inf->status >= 0) {
+    PISO_HIP(c, hipMemcpyAsync(c->a_lam_hist[hist], lam, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
+    c->lam_hist_valid[hist] = true;
+  }
+  return rc;
 }
 
 // Divergence-free gradient modification (eq. SgradPsgrad): p_S from P(A = 1) p_S =
@@ -442,12 +465,12 @@ template <typename R>
 int do_corrector_bwd(piso_ctx* c, hipStream_t s, const R* A, const R* C, const R* Pf, const R* Dinv,
                      const R* h, const R* u_in, const R* p_lag, const R* p, const R* du_c, R* pbar,
                      R* du_in_out, R* p_lag_bar, R* dA, R* dC, R* dbu, R* dub, bool skip_solve,
-                     const piso_solve_opts* o, piso_solve_info* info) {
+                     const piso_solve_opts* o, piso_solve_info* info, int hist) {
   if (int rc = launch_correct_bwd<R>(c, s, A, p, du_c, pbar, dA)) return rc;
   R* lam = nullptr;
   if (!skip_solve) {
     lam = (R*)c->a_lam;
-    int rc = do_pressure_adjoint<R>(c, s, Pf, Dinv, pbar, lam, o, info);
+    int rc = do_pressure_adjoint<R>(c, s, Pf, Dinv, pbar, lam, o, info, hist);
     if (rc < 0) return rc;
     if ((rc = launch_pface_bwd<R>(c, s, A, lam, p, dA))) return rc;
   } else if (info) {
@@ -513,15 +536,16 @@ int do_step_backward(piso_ctx* c, hipStream_t s, const void* tape, const R* u_n,
   piso_solve_info pi[2]{}, vi{};
   // corrector 2: output u***, p**; inputs u**, lag p*
   PISO_HIP(c, hipMemsetAsync(uin, 0, sizeof(R) * D * N, s));
+  const int warm = o->adjoint_warm_start ? 1 : 0;
   int rc = do_corrector_bwd<R>(c, s, t.A, t.C, t.Pf, t.Dinv, t.h2, t.u1, t.p1, t.p2, duc, pbar, uin, dp1, dA, dC, dbu,
-                               dub, skipP, &o->pres, &pi[1]);
+                               dub, skipP, &o->pres, &pi[1], warm ? 1 : -1);
   if (rc < 0) return rc;
   // corrector 1: output u**, p*; inputs u*, lag p^n
   PISO_HIP(c, hipMemcpyAsync(duc, uin, sizeof(R) * D * N, hipMemcpyDeviceToDevice, s));
   PISO_HIP(c, hipMemcpyAsync(pbar, dp1, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
   PISO_HIP(c, hipMemsetAsync(uin, 0, sizeof(R) * D * N, s));
   rc = do_corrector_bwd<R>(c, s, t.A, t.C, t.Pf, t.Dinv, t.h1, t.us, p_n, t.p1, duc, pbar, uin, dp_n, dA, dC, dbu, dub,
-                           skipP, &o->pres, &pi[0]);
+                           skipP, &o->pres, &pi[0], warm ? 0 : -1);
   if (rc < 0) return rc;
   // velocity solve: mu = C^-T du*, db = mu, dC -= mu (x) u*
   if (!skipV) {
@@ -678,6 +702,7 @@ void piso_default_step_opts(int32_t precision, piso_step_opts* o) {
   o->n_correctors = 2;
   o->grad_p_in_predictor = 1;
   o->grad_path_flags = 0;
+  o->adjoint_warm_start = 1;
 }
 
 #define CTX_ENTER()                                  \
@@ -887,6 +912,12 @@ int piso_step_backward(piso_ctx* c, void* stream, const void* tape, const void* 
       (const R*)dp_np1, (R*)du_n, (R*)dp_n, (R*)dS, (R*)dnu, (R*)du_b, o, info
   return DISPATCH_R(do_step_backward<double>(ARGS(double)), do_step_backward<float>(ARGS(float)));
 #undef ARGS
+}
+
+int piso_adjoint_reset(piso_ctx* c) {
+  if (!c) return PISO_E_ARG;
+  c->lam_hist_valid[0] = c->lam_hist_valid[1] = false;
+  return PISO_OK;
 }
 
 int piso_outflow_update(piso_ctx* c, void* stream, const void* u_n, const void* u_b, const int32_t* outflow,

@@ -134,6 +134,10 @@ struct piso_ctx {
   void *m_r32 = nullptr, *m_e32 = nullptr;   // float [N] (MIXED refinement)
   void *k_r = nullptr, *k_q = nullptr, *k_d0 = nullptr, *k_d1 = nullptr;   // PCG [N]
   void* k_r2 = nullptr;           // second residual buffer of the multigrid PCG [N]
+  // adjoint pressure solutions of the last piso_step_backward per corrector (8 bytes per
+  // cell: the working type, or double for MIXED), the warm start of the next call
+  void* a_lam_hist[2] = {nullptr, nullptr};
+  bool lam_hist_valid[2] = {false, false};
   void* k_z = nullptr;            // PCG preconditioned residual [N] (multigrid)
   void* k_y = nullptr;            // omega D^-1 r, the multigrid pre-smoothing [N]
   // PCG operands copied into context-owned buffers (graph-stable pointers)

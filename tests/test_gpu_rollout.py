@@ -165,3 +165,44 @@ def test_gradient_path_flags(api):
         gr = step_vjp(geo, rec, w, np.zeros(geo.N), **kw)
         assert rel(host(g["S"]), gr["S"]) < 1e-8, flags
         assert rel(host(g["u"]), gr["u_n"]) < 1e-8, flags
+
+
+def test_adjoint_warm_start(api):
+    """The adjoint pressure solves of step_backward start from the previous call's
+    solutions (adjoint_warm_start, the default): a repeated call converges at once and
+    agrees to solver tolerance; adjoint_reset restores the cold-start result bit for bit;
+    with the option off every call is cold."""
+    say("test_adjoint_warm_start")
+    case = small_cases()["channel_q"]
+    ctx = api.Context(case.domain, "f64")
+    _, (u, p, S, ub, nu) = _inputs(ctx, case, 8)
+    o = tight_opts(ctx)
+    assert o.adjoint_warm_start == 1
+    tape = ctx.new_tape()
+    ctx.step(u, p, nu, S, ub, case.dt, o, tape=tape)
+    rng = np.random.default_rng(9)
+    du1 = dev(rng.standard_normal(u.shape), ctx.dtype)
+    dp1 = dev(rng.standard_normal(p.shape), ctx.dtype)
+
+    def bwd():
+        g, inf = ctx.step_backward(tape, u, p, nu, ub, case.dt, du1, dp1, o, info=True)
+        return {k: host(v) for k, v in g.items() if v is not None}, [q["iters"] for q in inf["pres"]]
+
+    ctx.adjoint_reset()
+    g1, it1 = bwd()
+    g2, it2 = bwd()
+    say("adjoint pressure iterations cold %s, warm repeat %s" % (it1, it2))
+    assert all(b < a for a, b in zip(it1, it2))
+    for k in g1:
+        assert rel(g2[k], g1[k]) < 1e-9
+    ctx.adjoint_reset()
+    g3, it3 = bwd()
+    assert it3 == it1
+    for k in g1:
+        assert np.array_equal(g3[k], g1[k])
+    o.adjoint_warm_start = 0
+    g4, it4 = bwd()
+    g5, it5 = bwd()
+    assert it4 == it1 and it5 == it1
+    for k in g1:
+        assert np.array_equal(g4[k], g1[k]) and np.array_equal(g5[k], g1[k])
