@@ -438,7 +438,9 @@ int do_step(piso_ctx* c, hipStream_t s, const R* u_n, const R* p_n, const R* nu,
     R* pk = last ? p2 : p1;
     R* uk = last ? u_np1 : u1;
     if (pk != p_lag) PISO_HIP(c, hipMemcpyAsync(pk, p_lag, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
+    c->pcg_kind = kPcgFwd1 + std::min(k, 1);
     rc = do_pressure<R>(c, s, A, C, bu, Pf, Dinv, u_in, ub, p_lag, h, nullptr, pk, &o->pres, &pi[std::min(k, 1)]);
+    c->pcg_kind = kPcgOther;
     if (rc < 0) return rc;
     rc = launch_correct<R>(c, s, A, h, pk, Pf, p_lag, uk, nullptr);
     if (rc) return rc;
@@ -537,15 +539,19 @@ int do_step_backward(piso_ctx* c, hipStream_t s, const void* tape, const R* u_n,
   // corrector 2: output u***, p**; inputs u**, lag p*
   PISO_HIP(c, hipMemsetAsync(uin, 0, sizeof(R) * D * N, s));
   const int warm = o->adjoint_warm_start ? 1 : 0;
+  c->pcg_kind = kPcgAdj1 + 1;
   int rc = do_corrector_bwd<R>(c, s, t.A, t.C, t.Pf, t.Dinv, t.h2, t.u1, t.p1, t.p2, duc, pbar, uin, dp1, dA, dC, dbu,
                                dub, skipP, &o->pres, &pi[1], warm ? 1 : -1);
+  c->pcg_kind = kPcgOther;
   if (rc < 0) return rc;
   // corrector 1: output u**, p*; inputs u*, lag p^n
   PISO_HIP(c, hipMemcpyAsync(duc, uin, sizeof(R) * D * N, hipMemcpyDeviceToDevice, s));
   PISO_HIP(c, hipMemcpyAsync(pbar, dp1, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
   PISO_HIP(c, hipMemsetAsync(uin, 0, sizeof(R) * D * N, s));
+  c->pcg_kind = kPcgAdj1;
   rc = do_corrector_bwd<R>(c, s, t.A, t.C, t.Pf, t.Dinv, t.h1, t.us, p_n, t.p1, duc, pbar, uin, dp_n, dA, dC, dbu, dub,
                            skipP, &o->pres, &pi[0], warm ? 0 : -1);
+  c->pcg_kind = kPcgOther;
   if (rc < 0) return rc;
   // velocity solve: mu = C^-T du*, db = mu, dC -= mu (x) u*
   if (!skipV) {

@@ -43,6 +43,10 @@ constexpr int kPartS = 22;       // one-shot sums                  (2)
 constexpr int kPartRegions = 24;
 
 // Kernel classes of the solver timing (piso_get_timing).
+// Kinds of pressure solve, for the iteration-count estimates of the host read-backs:
+// forward correctors 1 and 2, adjoint correctors 1 and 2, everything else.
+constexpr int kPcgFwd1 = 0, kPcgAdj1 = 2, kPcgOther = 4;
+
 constexpr int kTimeCgStencil = 0;   // PCG stencil kernel (direction update and M d)
 constexpr int kTimeCgUpdate = 1;    // PCG x, r update
 constexpr int kTimeMgDown0 = 2;     // multigrid restriction from the fine grid
@@ -147,7 +151,10 @@ struct piso_ctx {
   bool use_graphs = true;
   // iterations of the last solve per preconditioner (Jacobi, multigrid) and kind: plain
   // solves, then the first, second and later MIXED refinement sweeps
-  int pcg_hint[2][4] = {};
+  // [kind][slot]: kind = the solve's place in a step (kPcgKinds below), slot = plain
+  // solve, then the first, second and later MIXED refinement sweeps
+  int pcg_hint[2][5][4] = {};
+  int pcg_kind = 4;               // kind of the next pressure solves (set around them)
   std::vector<piso::MgLevel> mg;  // coarse levels 1..L of the pressure preconditioner
   piso::Grid mg_g1{};             // level 1 as a block table (offsets, dims, division magic)
   piso::MgTiles mg_tiles{};       // work-group tiles of the fine-grid restriction

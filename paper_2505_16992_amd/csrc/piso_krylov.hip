@@ -186,9 +186,18 @@ __global__ void __launch_bounds__(kWG)
 k_cg_spmv_q(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
             const R* __restrict__ dold, R* __restrict__ dnew, R* __restrict__ q, CgState* st,
             const double* __restrict__ partB, double* __restrict__ partA, int Gp, int par) {
-  // the state and the partials are loaded together, before the first wait
+  // the state, the partials and this thread's first quad of the operand streams are
+  // loaded together, before the first wait (at one trip per thread the prologue's
+  // latency then overlaps the main loads)
   const int done = st->done, kd = st->k, max_k = st->max_k;
   const double tol2bb = st->tol2 * st->bb, rz_old = st->rz[par ^ 1];
+  int beg, end;
+  quad_range(g.N >> 2, beg, end);
+  const int qd0 = beg + (int)threadIdx.x;
+  const int P00 = qd0 < end ? qd0 << 2 : 0;   // unconditional (clamped) loads: no branch to wait at
+  const Q4<R> b0 = ldq(r, P00), c0 = ldq(dold, P00);
+  Q4<R> a0{};
+  if constexpr (!ZOP) a0 = ldq(Dinv, P00);
   double t[2];
   reduce_partials<2>(partB, Gp, t);
   if (done) return;
@@ -222,13 +231,17 @@ k_cg_spmv_q(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const 
     return o;
   };
   auto d1 = [&](int P, bool, int, int, int) { return (ZOP ? r[P] : Dinv[P] * r[P]) + beta * dold[P]; };
-  int beg, end;
-  quad_range(g.N >> 2, beg, end);
   double acc[1] = {0.0};
-  for (int qd = beg + (int)threadIdx.x; qd < end; qd += kWG) {
+  for (int qd = qd0; qd < end; qd += kWG) {
     const int P0 = qd << 2;
     const Cell c = locate(g, P0);
-    const Q4<R> dP = dq(P0, c.j, c.k);
+    Q4<R> dP;
+    if (qd == qd0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) dP.v[e] = (ZOP ? b0.v[e] : a0.v[e] * b0.v[e]) + beta * c0.v[e];
+    } else {
+      dP = dq(P0, c.j, c.k);
+    }
     const Q4<R> M = quad_stencil<R, D>(g, c, P0, Pf, dP, dq, d1);
     stq(dnew, P0, dP);
     stq(q, P0, M);
@@ -322,6 +335,25 @@ k_finalize2(const double* __restrict__ partials, int G, double* __restrict__ out
     out[0] = t[0];
     out[1] = t[1];
   }
+}
+
+// x = 0 when the right-hand side is zero (set by k_cg_check), decided on the device so
+// that the host need not wait for the initial state.
+template <typename R>
+__global__ void __launch_bounds__(kWG) k_cg_zero_if(int N, const CgState* st, R* __restrict__ x) {
+  if (!st->zero_rhs) return;
+  const int P = cell_of_thread(N);
+  if (P >= 0) x[P] = R(0);
+}
+
+// x_c = 0 for the components whose right-hand side is zero (set by k_bi_check).
+template <typename R, int D>
+__global__ void __launch_bounds__(kWG) k_bi_zero_if(int N, const BiState* st, R* __restrict__ x) {
+  const int P = cell_of_thread(N);
+  if (P < 0) return;
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+    if (st->bb[c] == 0.0) x[(size_t)c * N + P] = R(0);
 }
 
 __global__ void __launch_bounds__(kWG) k_mix_add(int N, double* __restrict__ x64, const float* __restrict__ e) {
@@ -783,9 +815,10 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
     if (int rc = mg_prescale<R>(c, s, o.Dinv, (const R*)o.r, o.y)) return rc;
     if (int rc = mg_apply<R>(c, s, o.Pf, o.Dinv, (const R*)o.r, (const R*)o.y, o.z, st, o.pB, G)) return rc;
   }
-  PISO_HIP(c, hipMemcpyAsync(c->h_cg, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-  PISO_HIP(c, hipStreamSynchronize(s));
-  if (c->h_cg->zero_rhs) PISO_HIP(c, hipMemsetAsync(o.x, 0, es * (size_t)N, s));
+  // no read-back here: a zero right-hand side is handled on the device, and iterations
+  // launched after convergence return at once
+  k_cg_zero_if<R><<<grid_cells(N), kWG, 0, s>>>(N, st, o.x);
+  c->h_cg->done = 0;
   // chunks of an even number of iterations: the recorded pair keeps the slot parity
   if (check_every < 2) check_every = 2;
   check_every += check_every & 1;
@@ -795,10 +828,13 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
   if (use_graph && !*gx) {
     if (int rc = pcg_graph<R>(c, o, gx)) return rc;
   }
-  // the first chunk covers three quarters of the previous solve's iterations (solves of
-  // one step and of consecutive steps take similar counts), later chunks check_every
-  int& hint = c->pcg_hint[o.mg ? 1 : 0][hint_slot];
-  int chunk = std::max(check_every, (3 * hint / 4) & ~1);
+  // the first chunk covers the iterations of the previous solve of the same kind less two
+  // (solves of one kind in consecutive steps take similar counts, different kinds do
+  // not; an iteration launched after convergence costs about as much as a read-back),
+  // later chunks check_every
+  const int kind = c->pcg_kind >= 0 && c->pcg_kind <= kPcgOther ? c->pcg_kind : kPcgOther;
+  int& hint = c->pcg_hint[o.mg ? 1 : 0][kind][hint_slot];
+  int chunk = std::max(check_every, (hint - 2) & ~1);
   int launched = 0;
   while (!c->h_cg->done && launched < max_iter) {
     const int n = std::min(chunk, max_iter - launched + 1);
@@ -954,11 +990,11 @@ int velocity_solve(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* 
   } while (0)
   BI_LAUNCH(k_bi_init, c->grid, A, C, b, x, r, rh, pb[0], vb[0], p3);
   BI_CHECK(1, 0);
+  // zero right-hand sides are handled on the device (no read-back before the iterations)
+  if (D == 2) k_bi_zero_if<R, 2><<<grid_cells(N), kWG, 0, s>>>(N, st, x);
+  else k_bi_zero_if<R, 3><<<grid_cells(N), kWG, 0, s>>>(N, st, x);
   if (int rc = check(c, "k_bi_init")) return rc;
-  PISO_HIP(c, hipMemcpyAsync(c->h_bi, st, sizeof(BiState), hipMemcpyDeviceToHost, s));
-  PISO_HIP(c, hipStreamSynchronize(s));
-  for (int q = 0; q < D; ++q)
-    if (c->h_bi->bb[q] == 0.0) PISO_HIP(c, hipMemsetAsync(x + (size_t)q * N, 0, sizeof(R) * (size_t)N, s));
+  c->h_bi->all_done = 0;
   int it = 0;
   const int ce = o->check_every < 1 ? 4 : o->check_every;
   while (!c->h_bi->all_done && it < o->max_iter) {

@@ -266,20 +266,6 @@ k_mg_down0uq(Grid g, Grid g1, MgQuadTiles tl, const R* __restrict__ Pf, const R*
   constexpr int NP = 1 << (D - 1);
   const int done = st->done;
   const double rzp = st->rz[par];
-  double t[1];
-  reduce_partials<1>(partA, Gp, t);
-  if (done) return;
-  const double dq = t[0];
-  if (!(dq > 0.0) || !std::isfinite(dq)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      st->status = std::isfinite(dq) ? PISO_BREAKDOWN : PISO_E_NAN;
-      st->iters = st->k;
-      st->done = 1;
-    }
-    return;
-  }
-  const R alpha = (R)(rzp / dq);
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->k = st->k + 1;   // no other group reads it here
   const int N = g.N;
   const int grp = xcd_logical_group();
   int b = 0;
@@ -297,12 +283,28 @@ k_mg_down0uq(Grid g, Grid g1, MgQuadTiles tl, const R* __restrict__ Pf, const R*
   const bool valid = u < tl.units[b] && j < ny && k < nz;
   const int i0 = 4 * xq;
   const int P0 = valid ? tf[0] + i0 + nx * (j + ny * k) : 0;
+  // own-cell streams are loaded (unconditionally, P0 = 0 when not valid) before the
+  // partials of d.q, so that the prologue's latency overlaps them
+  Q4<R> xv = ldq(x, P0);
+  const Q4<R> dv = ldq(dnew, P0), rv = ldq(rin, P0), qv = ldq(q, P0), Dv = ldq(Dinv, P0);
+  Q4<R> px = ldq(Pf, P0);
+  double t[1];
+  reduce_partials<1>(partA, Gp, t);
+  if (done) return;
+  const double dq = t[0];
+  if (!(dq > 0.0) || !std::isfinite(dq)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->status = std::isfinite(dq) ? PISO_BREAKDOWN : PISO_E_NAN;
+      st->iters = st->k;
+      st->done = 1;
+    }
+    return;
+  }
+  const R alpha = (R)(rzp / dq);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->k = st->k + 1;   // no other group reads it here
   // own cells: update, y, store
   Q4<R> yq, res;
-  Q4<R> px;
   if (valid) {
-    Q4<R> xv = ldq(x, P0);
-    const Q4<R> dv = ldq(dnew, P0), rv = ldq(rin, P0), qv = ldq(q, P0), Dv = ldq(Dinv, P0);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       xv.v[e] += alpha * dv.v[e];
@@ -312,7 +314,6 @@ k_mg_down0uq(Grid g, Grid g1, MgQuadTiles tl, const R* __restrict__ Pf, const R*
     stq(x, P0, xv);
     stq(rout, P0, res);
     stq(y, P0, yq);
-    px = ldq(Pf, P0);
   } else {
 #pragma unroll
     for (int e = 0; e < 4; ++e) yq.v[e] = res.v[e] = px.v[e] = R(0);
