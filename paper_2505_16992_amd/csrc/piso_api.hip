@@ -439,8 +439,10 @@ int do_step(piso_ctx* c, hipStream_t s, const R* u_n, const R* p_n, const R* nu,
     R* uk = last ? u_np1 : u1;
     if (pk != p_lag) PISO_HIP(c, hipMemcpyAsync(pk, p_lag, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
     c->pcg_kind = kPcgFwd1 + std::min(k, 1);
+    c->pcg_same_op = k > 0;   // the correctors of a step share P_f and D^-1
     rc = do_pressure<R>(c, s, A, C, bu, Pf, Dinv, u_in, ub, p_lag, h, nullptr, pk, &o->pres, &pi[std::min(k, 1)]);
     c->pcg_kind = kPcgOther;
+    c->pcg_same_op = false;
     if (rc < 0) return rc;
     rc = launch_correct<R>(c, s, A, h, pk, Pf, p_lag, uk, nullptr);
     if (rc) return rc;
@@ -549,9 +551,11 @@ int do_step_backward(piso_ctx* c, hipStream_t s, const void* tape, const R* u_n,
   PISO_HIP(c, hipMemcpyAsync(pbar, dp1, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
   PISO_HIP(c, hipMemsetAsync(uin, 0, sizeof(R) * D * N, s));
   c->pcg_kind = kPcgAdj1;
+  c->pcg_same_op = !skipP;   // the second adjoint solve of the step: the same tape P_f
   rc = do_corrector_bwd<R>(c, s, t.A, t.C, t.Pf, t.Dinv, t.h1, t.us, p_n, t.p1, duc, pbar, uin, dp_n, dA, dC, dbu, dub,
                            skipP, &o->pres, &pi[0], warm ? 0 : -1);
   c->pcg_kind = kPcgOther;
+  c->pcg_same_op = false;
   if (rc < 0) return rc;
   // velocity solve: mu = C^-T du*, db = mu, dC -= mu (x) u*
   if (!skipV) {

@@ -155,6 +155,15 @@ struct piso_ctx {
   // solve, then the first, second and later MIXED refinement sweeps
   int pcg_hint[2][5][4] = {};
   int pcg_kind = 4;               // kind of the next pressure solves (set around them)
+  // The PCG copies P_f and D^-1 into g_Pf / g_Dinv and builds the coarse operators from
+  // them.  A caller that knows the operator has not changed since the last solve (the
+  // second corrector of a step, the second adjoint solve, later MIXED sweeps) sets
+  // pcg_same_op around the solve; the setup is then skipped when it was made from the
+  // same buffer, element size and preconditioner.
+  bool pcg_same_op = false;
+  const void* pcg_op_src = nullptr;
+  int pcg_op_es = 0;
+  bool pcg_op_mg = false;
   std::vector<piso::MgLevel> mg;  // coarse levels 1..L of the pressure preconditioner
   piso::Grid mg_g1{};             // level 1 as a block table (offsets, dims, division magic)
   piso::MgTiles mg_tiles{};       // work-group tiles of the fine-grid restriction

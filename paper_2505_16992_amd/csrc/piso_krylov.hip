@@ -798,13 +798,21 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
   o.mg = precond == PISO_PRECOND_MG && !c->mg.empty();
   o.quad = c->quad;   // the context's buffers are 256-byte aligned
   const size_t es = sizeof(R);
-  PISO_HIP(c, hipMemcpyAsync((void*)o.Pf, Pf, es * (size_t)c->dim * N, hipMemcpyDeviceToDevice, s));
-  PISO_HIP(c, hipMemcpyAsync((void*)o.Dinv, Dinv, es * (size_t)N, hipMemcpyDeviceToDevice, s));
+  const bool reuse = c->pcg_same_op && c->pcg_op_src == (const void*)Pf && c->pcg_op_es == (int)es &&
+                     (c->pcg_op_mg || !o.mg);
+  if (!reuse) {
+    c->pcg_op_src = nullptr;   // invalid until the setup below is enqueued
+    PISO_HIP(c, hipMemcpyAsync((void*)o.Pf, Pf, es * (size_t)c->dim * N, hipMemcpyDeviceToDevice, s));
+    PISO_HIP(c, hipMemcpyAsync((void*)o.Dinv, Dinv, es * (size_t)N, hipMemcpyDeviceToDevice, s));
+    if (o.mg) {
+      if (int rc = mg_setup<R>(c, s, o.Pf)) return rc;
+    }
+    c->pcg_op_src = Pf;
+    c->pcg_op_es = (int)es;
+    c->pcg_op_mg = o.mg;
+  }
   PISO_HIP(c, hipMemcpyAsync(o.x, x, es * (size_t)N, hipMemcpyDeviceToDevice, s));
   const double tol2 = rtol * rtol;
-  if (o.mg) {
-    if (int rc = mg_setup<R>(c, s, o.Pf)) return rc;
-  }
   if (c->dim == 2)
     k_cg_init<R, BT, 2><<<G, kWG, 0, s>>>(c->grid, o.Pf, o.Dinv, b, mean, sign, o.x, o.r, o.d0, o.pB);
   else
@@ -931,9 +939,12 @@ int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const float* Pf, const floa
     // ask the inner solve only for the reduction still missing (with a margin of 2), but
     // never for more than inner_rtol, the floor the float iteration reliably reaches
     const double tol_in = std::min(0.5, std::max(o->inner_rtol, 0.5 * o->rtol / rel));
+    const bool same = c->pcg_same_op;
+    c->pcg_same_op = same || sweeps > 0;   // later sweeps: same operator
     int rc = pcg_run<float, float>(c, s, Pf, Dinv, r32, nullptr, 1.0, e32, tol_in, o->max_iter,
                                    o->check_every, o->precond, &iters, &rel_in, &st_in,
                                    1 + std::min(sweeps, 2));
+    c->pcg_same_op = same;
     if (rc) return rc;
     if (st_in < 0) {
       status = st_in;
