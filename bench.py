@@ -26,7 +26,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2505_16992_amd", "csrc")
-DIGEST_SOURCES = ["piso_common.h", "piso_quad.h", "piso_krylov.hip", "piso_mg.hip"]
+DIGEST_SOURCES = ["piso_common.h", "piso_quad.h", "piso_krylov.hip", "piso_mg.hip", "piso_line.hip"]
 
 
 def kernel_digest():
@@ -284,6 +284,7 @@ def main():
         quad = all(b[0] % 4 == 0 for b in dom.blocks)
         nch = 2 ** d
         # algorithmic bytes per launch of each fine-grid kernel class (each stream once)
+        line = mg and bool(ctx.mg_line_axis)
         model = {
             # Pf (d), operand (z, or r and Dinv), d_old -> d_new, q
             "cg_stencil": ("k_cg_spmv_q" if quad else "k_cg_spmv", N * ((d + 4) if mg else (d + 5)) * es),
@@ -296,6 +297,13 @@ def main():
             # y, r, Dinv, Pf (d), level-1 correction -> z
             "mg_up0": ("k_mg_up0_q" if quad else "k_mg_up0", N * (d + 4) * es + (N // nch) * es),
         }
+        if line:
+            # line smoothing: the update kernel smooths (x, r, d_new, q, Dinv, Pf along the
+            # line -> x, r', y) and the restriction runs every iteration; the first
+            # pre-smoothing of a solve reads r, Dinv, Pf along the line and writes y
+            model["cg_update_restrict"] = ("k_line_pre", N * 9 * es)
+            model["mg_smooth0"] = ("k_line_pre", N * 4 * es)
+            model["mg_up0"] = ("k_line_post", N * (d + 4) * es + (N // nch) * es)
         per = {}
         for k, (ms, n) in tm.items():
             if n:
@@ -319,6 +327,7 @@ def main():
             it_ms = sum(ms for ms, _ in tm.values()) / max(iters, 1)
             it_bytes = sum(model[k][1] * tm[k][1] for k in fine) / max(iters, 1)
             pcg = {"preconditioner": "multigrid" if mg else "jacobi",
+                   "fine_smoother": ("lines along %s" % "xyz"[ctx.mg_line_axis]) if mg and ctx.mg_line_axis else "point",
                    "mg_levels": [n for n, _ in ctx.mg_levels] if mg else [],
                    "iteration_us": round(1e3 * it_ms, 3),
                    "fine_bytes_per_iteration": int(it_bytes),

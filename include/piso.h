@@ -192,6 +192,14 @@ int piso_sizes(const piso_ctx* ctx, int64_t* n_cells, int64_t* n_bfaces, int64_t
  * slots per cell slots[l-1] (host arrays of at least 16 entries, may be NULL). */
 int piso_mg_info(const piso_ctx* ctx, int32_t* n_levels, int64_t* cells, int32_t* slots);
 
+/* Fine-level smoother of the multigrid preconditioner: *line_axis = 0 for damped point
+ * Jacobi, or 1 (y) / 2 (z) for damped line Jacobi along that axis (tridiagonal solves
+ * along the lines).  Lines are chosen at context creation for single-block grids whose
+ * metric weight along one transverse axis is on average more than 3x the largest other
+ * (a grid stretched towards walls normal to that axis); PISO_MG_LINE=0 in the
+ * environment at creation keeps point Jacobi. */
+int piso_mg_smoother(const piso_ctx* ctx, int32_t* line_axis);
+
 /* Default options for a precision: vel rtol 1e-10 (F64) / 1e-7, Jacobi; pres rtol 1e-10
  * (F64), 1e-6 (F32), 1e-8 (MIXED, inner floor 1e-5), multigrid-preconditioned, read back every
  * 4 iterations; 2 correctors, grad_p_in_predictor = 1. */
@@ -352,8 +360,10 @@ typedef enum {
   PISO_TIME_MG_DOWN0 = 2,    /* multigrid restriction from the fine grid */
   PISO_TIME_MG_UP0 = 3,      /* multigrid prolongation and smoothing on the fine grid */
   PISO_TIME_MG_COARSE = 4,   /* multigrid kernels on the coarse levels */
-  PISO_TIME_CG_UPDATE_MG = 5, /* multigrid PCG: x, r update fused with the fine-grid restriction */
-  PISO_TIME_KINDS = 6
+  PISO_TIME_CG_UPDATE_MG = 5, /* multigrid PCG: x, r update fused with the fine-grid
+                                 pre-smoothing (point smoothing: and the restriction) */
+  PISO_TIME_MG_SMOOTH0 = 6,  /* line smoothing: first pre-smoothing of a solve on the fine grid */
+  PISO_TIME_KINDS = 7
 } piso_time_kind;
 
 int piso_set_timing(piso_ctx* ctx, int32_t enable);

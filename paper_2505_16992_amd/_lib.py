@@ -18,7 +18,8 @@ PISO_OK, PISO_NOT_CONVERGED, PISO_BREAKDOWN = 0, 1, 2
 PISO_E_ARG, PISO_E_TOPOLOGY, PISO_E_HIP, PISO_E_NAN, PISO_E_OOM = -1, -2, -3, -4, -5
 PISO_SIDE_CONNECT, PISO_SIDE_DIRICHLET = 0, 1
 PISO_PRECOND_JACOBI, PISO_PRECOND_MG = 0, 1
-TIME_KINDS = ("cg_stencil", "cg_update", "mg_down0", "mg_up0", "mg_coarse", "cg_update_restrict")
+TIME_KINDS = ("cg_stencil", "cg_update", "mg_down0", "mg_up0", "mg_coarse", "cg_update_restrict",
+              "mg_smooth0")
 
 
 class SideDesc(C.Structure):
@@ -108,6 +109,7 @@ _SIGS = {
     "piso_stats_backward": (I32, [VP, VP, VP, I32, VP, VP, VP, VP]),
     "piso_set_timing": (I32, [VP, I32]),
     "piso_adjoint_reset": (I32, [VP]),
+    "piso_mg_smoother": (I32, [VP, C.POINTER(I32)]),
     "piso_get_timing": (I32, [VP, I32, C.POINTER(F64), C.POINTER(C.c_int64)]),
 }
 

@@ -86,6 +86,9 @@ class Context:
         cells_l, slots_l = (C.c_int64 * 16)(), (C.c_int32 * 16)()
         self.lib.piso_mg_info(h, C.byref(nl), cells_l, slots_l)
         self.mg_levels = [(int(cells_l[q]), int(slots_l[q])) for q in range(nl.value)]
+        la = C.c_int32(0)
+        self._check(self.lib.piso_mg_smoother(self.h, C.byref(la)), "piso_mg_smoother")
+        self.mg_line_axis = int(la.value)   # 0: point Jacobi on the fine level, 1/2: lines along y/z
 
     def __del__(self):
         h = getattr(self, "h", None)

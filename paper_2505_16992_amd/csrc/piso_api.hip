@@ -631,6 +631,7 @@ int piso_create(const piso_domain_desc* desc, int32_t precision, piso_ctx** out)
   if (!rc) rc = precision == PISO_F64 ? upload_metrics<double>(c, desc) : upload_metrics<float>(c, desc);
   if (!rc) rc = alloc_workspaces(c);
   if (!rc) rc = mg_build(c);
+  if (!rc && !c->mg.empty()) rc = line_choose(c, desc);
   if (!rc) rc = outflow_build(c);
   if (rc) {
     g_create_error = c->err;
@@ -691,6 +692,12 @@ int piso_mg_info(const piso_ctx* c, int32_t* n_levels, int64_t* cells, int32_t* 
     if (cells) cells[l] = c->mg[l].n;
     if (slots) slots[l] = c->mg[l].K;
   }
+  return PISO_OK;
+}
+
+int piso_mg_smoother(const piso_ctx* c, int32_t* line_axis) {
+  if (!c || !line_axis) return PISO_E_ARG;
+  *line_axis = c->mg_line_axis;
   return PISO_OK;
 }
 

@@ -52,8 +52,9 @@ constexpr int kTimeCgUpdate = 1;    // PCG x, r update
 constexpr int kTimeMgDown0 = 2;     // multigrid restriction from the fine grid
 constexpr int kTimeMgUp0 = 3;       // multigrid prolongation and smoothing on the fine grid
 constexpr int kTimeMgCoarse = 4;    // multigrid kernels on the coarse levels
-constexpr int kTimeCgUpdateMg = 5;  // PCG update fused with the fine-grid restriction
-constexpr int kTimeKinds = 6;
+constexpr int kTimeCgUpdateMg = 5;  // PCG update fused with the fine-grid pre-smoothing
+constexpr int kTimeMgSmooth0 = 6;   // first fine-grid pre-smoothing of a solve (line smoother)
+constexpr int kTimeKinds = 7;
 
 struct Timing {
   bool enabled = false;
@@ -168,6 +169,8 @@ struct piso_ctx {
   piso::Grid mg_g1{};             // level 1 as a block table (offsets, dims, division magic)
   piso::MgTiles mg_tiles{};       // work-group tiles of the fine-grid restriction
   piso::MgQuadTiles mg_qtiles{};  // the same for the quad-vectorised fused update (nx % 4 == 0)
+  int mg_line_axis = 0;           // fine-level line smoothing along this axis (0: point Jacobi)
+  int mg_line_L = 0;              // cells per line segment (8 segments per line)
   // Dirichlet faces: owning cell and side (2 * axis + high), and the boundary cells
   // with their faces (ascending) for deterministic gathers
   int *out_bcell = nullptr, *out_bside = nullptr, *out_bc_cell = nullptr, *out_bc_ptr = nullptr,
@@ -345,6 +348,23 @@ template <typename R>
 int mg_update_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, R* x, const R* rin, R* rout,
                     const R* dnew, const R* q, R* y, R* z, CgState* st, const double* partA, int Gp, int par,
                     double* partB, int G);
+
+// ---- fine-level line smoothing (piso_line.hip) ----
+// Chooses the line axis for a single-block grid whose metric is strongly anisotropic
+// along one transverse axis (y or z), else leaves point Jacobi.
+int line_choose(piso_ctx* c, const piso_domain_desc* desc);
+// Work-groups of the line kernels (64 lines each); their partial sums use this count.
+int line_groups(const piso_ctx* c);
+// y = omega T^-1 r' (T: tridiagonal part of M along the line axis), after the PCG update
+// x += alpha d, r' = rin - alpha q into rout when `update`, else r' = rin.
+template <typename R>
+int line_pre(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, R* x, const R* rin, R* rout, const R* dnew,
+             const R* q, R* y, CgState* st, const double* partA, int Gp, int par, bool update);
+// z = z1 + omega T^-1 (r - M z1), z1 = y + e1[parent]; partial sums of r.z, r.r into partB
+// (line_groups work-groups).
+template <typename R>
+int line_post(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, const R* y, const R* e1, R* z,
+              double* partB, CgState* st);
 
 // ---- advective outflow boundary (piso_outflow.hip) ----
 struct OutflowUm {

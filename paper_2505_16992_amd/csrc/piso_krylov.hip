@@ -676,7 +676,8 @@ struct PcgOps {
   R *r, *r2, *q, *d0, *d1, *z, *y;   // r2: second residual buffer (multigrid: r alternates by parity)
   double *pA, *pB;
   int G;
-  bool mg, quad;
+  int Gz;          // work-groups whose partial sums of r.z, r.r the V-cycle leaves (G, or the line kernels')
+  bool mg, quad, line;
 };
 
 // One PCG iteration with slot parity par (the direction buffers alternate with it).
@@ -692,14 +693,14 @@ static int pcg_iteration(piso_ctx* c, hipStream_t s, const PcgOps<R>& o, int par
     if (c->dim == 2) {
       if (o.mg)
         launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 2, true>, G, c->grid, o.Pf, o.Dinv, opnd,
-                     (const R*)dold, dnew, o.q, st, pBc, o.pA, G, par);
+                     (const R*)dold, dnew, o.q, st, pBc, o.pA, o.Gz, par);
       else
         launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 2>, G, c->grid, o.Pf, o.Dinv, opnd, (const R*)dold,
                      dnew, o.q, st, pBc, o.pA, G, par);
     } else {
       if (o.mg)
         launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 3, true>, G, c->grid, o.Pf, o.Dinv, opnd,
-                     (const R*)dold, dnew, o.q, st, pBc, o.pA, G, par);
+                     (const R*)dold, dnew, o.q, st, pBc, o.pA, o.Gz, par);
       else
         launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 3>, G, c->grid, o.Pf, o.Dinv, opnd, (const R*)dold,
                      dnew, o.q, st, pBc, o.pA, G, par);
@@ -711,14 +712,14 @@ static int pcg_iteration(piso_ctx* c, hipStream_t s, const PcgOps<R>& o, int par
     if (c->dim == 2) {
       if (o.mg)
         launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 2, true>, G, c->grid, o.Pf, o.Dinv, opnd, (const R*)dold,
-                     dnew, o.q, st, pBc, o.pA, G, par);
+                     dnew, o.q, st, pBc, o.pA, o.Gz, par);
       else
         launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 2>, G, c->grid, o.Pf, o.Dinv, opnd, (const R*)dold, dnew,
                      o.q, st, pBc, o.pA, G, par);
     } else {
       if (o.mg)
         launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 3, true>, G, c->grid, o.Pf, o.Dinv, opnd, (const R*)dold,
-                     dnew, o.q, st, pBc, o.pA, G, par);
+                     dnew, o.q, st, pBc, o.pA, o.Gz, par);
       else
         launch_timed(c, s, kTimeCgStencil, k_cg_spmv<R, 3>, G, c->grid, o.Pf, o.Dinv, opnd, (const R*)dold, dnew,
                      o.q, st, pBc, o.pA, G, par);
@@ -729,6 +730,15 @@ static int pcg_iteration(piso_ctx* c, hipStream_t s, const PcgOps<R>& o, int par
   }
   // multigrid: the update is fused with the fine-grid restriction; the residual moves
   // between r (even iterations read it) and r2 (odd ones)
+  if (o.mg && o.line) {
+    // line smoothing: the update with the line pre-smoothing, then the V-cycle on r'
+    const R* rin = par ? (const R*)o.r2 : (const R*)o.r;
+    R* rout = par ? o.r : o.r2;
+    if (int rc = line_pre<R>(c, s, o.Pf, o.Dinv, o.x, rin, rout, (const R*)dnew, (const R*)o.q, o.y, st,
+                             (const double*)o.pA, G, par, true))
+      return rc;
+    return mg_apply<R>(c, s, o.Pf, o.Dinv, (const R*)rout, (const R*)o.y, o.z, st, o.pB, G);
+  }
   if (o.mg)
     return mg_update_apply<R>(c, s, o.Pf, o.Dinv, o.x, par ? (const R*)o.r2 : (const R*)o.r, par ? o.r : o.r2,
                               (const R*)dnew, (const R*)o.q, o.y, o.z, st, (const double*)o.pA, G, par, o.pB, G);
@@ -797,6 +807,8 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
   // partials); the stencil kernel then forms d from z instead of Dinv r
   o.mg = precond == PISO_PRECOND_MG && !c->mg.empty();
   o.quad = c->quad;   // the context's buffers are 256-byte aligned
+  o.line = o.mg && c->mg_line_axis != 0;
+  o.Gz = o.line ? line_groups(c) : G;
   const size_t es = sizeof(R);
   const bool reuse = c->pcg_same_op && c->pcg_op_src == (const void*)Pf && c->pcg_op_es == (int)es &&
                      (c->pcg_op_mg || !o.mg);
@@ -820,7 +832,13 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
   k_cg_check<<<1, kWG, 0, s>>>(o.pB, G, 1, max_iter, tol2, st);
   if (int rc = check(c, "k_cg_init")) return rc;
   if (o.mg) {
-    if (int rc = mg_prescale<R>(c, s, o.Dinv, (const R*)o.r, o.y)) return rc;
+    if (o.line) {
+      if (int rc = line_pre<R>(c, s, o.Pf, o.Dinv, o.x, (const R*)o.r, o.r, nullptr, nullptr, o.y, st, nullptr, 0, 0,
+                               false))
+        return rc;
+    } else {
+      if (int rc = mg_prescale<R>(c, s, o.Dinv, (const R*)o.r, o.y)) return rc;
+    }
     if (int rc = mg_apply<R>(c, s, o.Pf, o.Dinv, (const R*)o.r, (const R*)o.y, o.z, st, o.pB, G)) return rc;
   }
   // no read-back here: a zero right-hand side is handled on the device, and iterations
@@ -856,7 +874,7 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
       }
     }
     launched += n + (n & 1);
-    k_cg_check<<<1, kWG, 0, s>>>(o.pB, G, 0, max_iter, tol2, st);
+    k_cg_check<<<1, kWG, 0, s>>>(o.pB, o.Gz, 0, max_iter, tol2, st);
     if (int rc = check(c, "k_cg iteration")) return rc;
     PISO_HIP(c, hipMemcpyAsync(c->h_cg, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
     PISO_HIP(c, hipStreamSynchronize(s));

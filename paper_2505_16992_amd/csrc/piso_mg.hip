@@ -1026,6 +1026,7 @@ static int mg_tail(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
                  (const R*)F.Dinv, (const R*)F.r, (const int*)C.parent, (const R*)C.e, om, (R*)F.e,
                  (const CgState*)st, pin);
   }
+  if (c->mg_line_axis) return line_post<R>(c, s, Pf, Dinv, r, y, (const R*)c->mg[0].e, z, partB, st);
   {
     const MgLevel& L1 = c->mg[0];
     const bool quad = c->quad && ((((uintptr_t)Pf) | ((uintptr_t)Dinv) | ((uintptr_t)r) | ((uintptr_t)y) |
