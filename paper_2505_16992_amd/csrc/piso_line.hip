@@ -66,57 +66,65 @@ __device__ __forceinline__ double line_wg_sum(double v, double* lds /* [kLineWav
   return t;
 }
 
+// Load from a uniform base at a 32-bit byte offset (the host keeps line smoothing to
+// grids whose fields are below 4 GiB): the base stays in scalar registers and loads at
+// the same cell share one offset register across arrays.
+template <typename R>
+__device__ __forceinline__ R ldo(const R* __restrict__ base, uint32_t off) {
+  return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(base) + off);
+}
+
+// Reciprocal of a pivot: the hardware reciprocal (1 ulp) in FP32, exact in FP64.
+template <typename R>
+__device__ __forceinline__ R line_rcp(R x) {
+  if constexpr (sizeof(R) == 4) return __builtin_amdgcn_rcpf(x);
+  else return R(1) / x;
+}
+
 // Solve T w = d on the lines of this work-group.  Each thread holds its segment's
 // coefficients a (lower), b (diagonal), c (upper) and right-hand side d for k <= L cells
-// (k = 0: no cells); on return d holds w.  All threads of the work-group call it.
+// (k = 0: no cells); on return d holds w.  Cells t >= k must carry a = 0, finite b > 0,
+// c and d: they are then decoupled from the segment and the recursions run over all L
+// cells without branches.  All threads of the work-group call it.
 template <typename R, int L>
 __device__ __forceinline__ void line_solve(const R (&a)[L], const R (&b)[L], const R (&c)[L], R (&d)[L], int k,
                                            int nseg, R* sh /* [kLineLanes][kLineSegs][6] */,
                                            R* sif /* [kLineLanes][kLineSegs][2] */) {
   const int lane = threadIdx.x % kLineLanes, m = threadIdx.x / kLineLanes;
   R cp[L], V[L], G[L];
-  // forward elimination (the segment's first lower and last upper couplings are the
-  // right-hand sides of V and G)
-  R prev_cp = R(0), prev_u = R(0), prev_v = R(0), prev_g = R(0);
+  // forward elimination; the segment's first lower coupling a[0] and last upper coupling
+  // c[k-1] are the right-hand sides of V and G (G is zero above cell k-1 until then)
+  R pc = R(0), pu = R(0), pv = R(1);
 #pragma unroll
   for (int t = 0; t < L; ++t) {
-    if (t < k) {
-      const R at = t > 0 ? a[t] : R(0);
-      const R inv = R(1) / (b[t] - at * prev_cp);
-      cp[t] = t < k - 1 ? c[t] * inv : R(0);
-      d[t] = (d[t] - at * prev_u) * inv;
-      V[t] = (t == 0 ? -a[0] : -at * prev_v) * inv;
-      G[t] = (t == k - 1 ? -c[t] : -at * prev_g) * inv;
-      prev_cp = cp[t];
-      prev_u = d[t];
-      prev_v = V[t];
-      prev_g = G[t];
-    } else {
-      cp[t] = V[t] = G[t] = R(0);
-    }
+    const R inv = line_rcp(b[t] - a[t] * pc);
+    const bool last = t == k - 1;
+    cp[t] = last ? R(0) : c[t] * inv;
+    d[t] = (d[t] - a[t] * pu) * inv;
+    V[t] = -a[t] * pv * inv;
+    G[t] = last ? -c[t] * inv : R(0);
+    pc = cp[t];
+    pu = d[t];
+    pv = V[t];
   }
-  // back substitution
+  // back substitution (cp[k-1] = 0 cuts the cells above the segment off)
 #pragma unroll
   for (int t = L - 2; t >= 0; --t) {
-    if (t < k - 1) {
-      d[t] -= cp[t] * d[t + 1];
-      V[t] -= cp[t] * V[t + 1];
-      G[t] -= cp[t] * G[t + 1];
-    }
+    d[t] -= cp[t] * d[t + 1];
+    V[t] -= cp[t] * V[t + 1];
+    G[t] -= cp[t] * G[t + 1];
   }
   // segment end values through LDS
-  R* e = sh + ((size_t)lane * kLineSegs + m) * 6;
-  if (k > 0) {
-    R uf = d[0], vf = V[0], gf = G[0], ul = d[0], vl = V[0], gl = G[0];
+  R ul = d[0], vl = V[0], gl = G[0];
 #pragma unroll
-    for (int t = 1; t < L; ++t)
-      if (t == k - 1) {
-        ul = d[t];
-        vl = V[t];
-        gl = G[t];
-      }
-    e[0] = uf; e[1] = vf; e[2] = gf; e[3] = ul; e[4] = vl; e[5] = gl;
+  for (int t = 1; t < L; ++t) {
+    const bool last = t == k - 1;
+    ul = last ? d[t] : ul;
+    vl = last ? V[t] : vl;
+    gl = last ? G[t] : gl;
   }
+  R* e = sh + ((size_t)lane * kLineSegs + m) * 6;
+  e[0] = d[0]; e[1] = V[0]; e[2] = G[0]; e[3] = ul; e[4] = vl; e[5] = gl;
   __syncthreads();
   // interface recurrence, one thread per line: l_{m-1} = al + be f_m, f_m = A_m + B_m f_{m+1}
   if (m == 0) {
@@ -159,14 +167,50 @@ __device__ __forceinline__ void line_solve(const R (&a)[L], const R (&b)[L], con
     }
   }
   __syncthreads();
+  // segments past the line's end read values never written: only their cells use them
   const R* ii = sif + ((size_t)lane * kLineSegs + m) * 2;
-  const R lp = k > 0 ? ii[0] : R(0), fn = k > 0 ? ii[1] : R(0);
+  const R lp = ii[0], fn = ii[1];
 #pragma unroll
-  for (int t = 0; t < L; ++t)
-    if (t < k) d[t] += V[t] * lp + G[t] * fn;
+  for (int t = 0; t < L; ++t) d[t] += V[t] * lp + G[t] * fn;
 }
 
 }  // namespace
+
+// Where a thread's cells lie.  Cells past the line's end (a ragged or empty last
+// segment, a lane past the last line) are clamped to the line's last cell, a line past
+// the last one to line 0: every load stays in bounds and needs no condition; such cells
+// are masked in the arithmetic and never stored.
+struct LineCells {
+  int k;       // cells of the segment (0..L)
+  int lp0;     // position of the segment's first cell along the line
+  int pl0;     // first cell of the line
+  int ci, co;  // the line's x and other transverse coordinate
+  int nseg;    // segments of a line
+};
+
+template <int L>
+__device__ __forceinline__ LineCells line_cells(const LineGeo& geo, int la) {
+  LineCells q;
+  const int lane = threadIdx.x % kLineLanes, m = threadIdx.x / kLineLanes;
+  const int l = xcd_logical_group() * kLineLanes + lane;
+  const bool lv = l < geo.nlines;
+  const int li = lv ? l : 0;
+  q.nseg = (geo.n + L - 1) / L;
+  q.lp0 = m * L;
+  int k = geo.n - q.lp0;
+  q.k = lv ? (k < 0 ? 0 : (k > L ? L : k)) : 0;
+  q.pl0 = line_base(geo, la, li);
+  q.ci = li % geo.nx;
+  q.co = li / geo.nx;
+  return q;
+}
+
+// cell t of the segment (clamped into the line)
+template <int L>
+__device__ __forceinline__ int line_cell(const LineGeo& geo, const LineCells& q, int t) {
+  const int lp = q.lp0 + t;
+  return q.pl0 + (lp < geo.n ? lp : geo.n - 1) * geo.stride;
+}
 
 // Pre-smoothing from zero on the fine level, y = omega T^-1 r', with the PCG update in
 // front of it when UPD (alpha from the Gp partials of d.q, x += alpha d, r' = rin -
@@ -182,31 +226,29 @@ k_line_pre(Grid g, int la, const R* __restrict__ Pf, const R* __restrict__ Dinv,
   const int done = st->done;
   const double rzp = UPD ? st->rz[par] : 0.0;
   const LineGeo geo = line_geo(g, la);
-  const int lane = threadIdx.x % kLineLanes, m = threadIdx.x / kLineLanes;
-  const int l = xcd_logical_group() * kLineLanes + lane;
-  const int nseg = (geo.n + L - 1) / L;
-  int k = geo.n - m * L;
-  k = l < geo.nlines ? (k < 0 ? 0 : (k > L ? L : k)) : 0;
-  const int P0 = l < geo.nlines ? line_base(geo, la, l) + m * L * geo.stride : 0;
+  const LineCells lc = line_cells<L>(geo, la);
+  const int k = lc.k;
   const R* Pa = Pf + (size_t)la * g.N;
+  constexpr uint32_t es = sizeof(R);
   R a[L], b[L], c[L], d[L];
   R xv[L], dv[L], qv[L];
-  // loads first (clamped to cell 0 where there is no cell), then the partials
+  uint32_t off[L];
+  // loads first, then the partials
 #pragma unroll
   for (int t = 0; t < L; ++t) {
-    const bool on = t < k;
-    const int P = on ? P0 + t * geo.stride : 0;
-    const int j = m * L + t;
-    b[t] = Dinv[P];
-    d[t] = rin[P];
-    a[t] = Pa[on && j > 0 ? P - geo.stride : 0];
-    c[t] = Pa[P];
+    off[t] = (uint32_t)line_cell<L>(geo, lc, t) * es;
+    b[t] = ldo(Dinv, off[t]);
+    d[t] = ldo(rin, off[t]);
+    c[t] = ldo(Pa, off[t]);
     if constexpr (UPD) {
-      xv[t] = x[P];
-      dv[t] = dnew[P];
-      qv[t] = q[P];
+      xv[t] = ldo(x, off[t]);
+      dv[t] = ldo(dnew, off[t]);
+      qv[t] = ldo(q, off[t]);
     }
   }
+  // the face below the segment (its weight is stored at the cell below)
+  const int lpb = lc.lp0 > 0 ? (lc.lp0 < geo.n ? lc.lp0 : geo.n) - 1 : 0;
+  const R wlo = ldo(Pa, (uint32_t)(lc.pl0 + lpb * geo.stride) * es);
   R alpha = R(0);
   if constexpr (UPD) {
     double v = 0.0;
@@ -235,36 +277,39 @@ k_line_pre(Grid g, int la, const R* __restrict__ Pf, const R* __restrict__ Dinv,
   } else {
     if (done) return;
   }
+  // T along the line: the lower coupling of cell t is the upper one of cell t-1; no
+  // coupling across the line's ends (walls, or a wrap left out of T)
+  R cl = wlo;
 #pragma unroll
   for (int t = 0; t < L; ++t) {
-    const int j = m * L + t;
-    if (t < k) {
-      const int P = P0 + t * geo.stride;
-      if constexpr (UPD) {
-        d[t] = d[t] - alpha * qv[t];
-        x[P] = xv[t] + alpha * dv[t];
-        rout[P] = d[t];
+    const int lp = lc.lp0 + t;
+    if constexpr (UPD) d[t] = d[t] - alpha * qv[t];
+    const R up = c[t];
+    a[t] = (t < k && lp > 0) ? -cl : R(0);
+    c[t] = lp + 1 < geo.n ? -up : R(0);
+    b[t] = line_rcp(b[t]);
+    cl = up;
+  }
+  if constexpr (UPD) {
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      if (t < k) {
+        *reinterpret_cast<R*>(reinterpret_cast<char*>(x) + off[t]) = xv[t] + alpha * dv[t];
+        *reinterpret_cast<R*>(reinterpret_cast<char*>(rout) + off[t]) = d[t];
       }
-      b[t] = R(1) / b[t];
-      a[t] = j > 0 ? -a[t] : R(0);
-      c[t] = j < geo.n - 1 ? -c[t] : R(0);
-    } else {
-      a[t] = c[t] = d[t] = R(0);
-      b[t] = R(1);
     }
   }
-  line_solve<R, L>(a, b, c, d, k, nseg, sh, sif);
+  line_solve<R, L>(a, b, c, d, k, lc.nseg, sh, sif);
 #pragma unroll
   for (int t = 0; t < L; ++t)
-    if (t < k) y[P0 + t * geo.stride] = omega * d[t];
+    if (t < k) *reinterpret_cast<R*>(reinterpret_cast<char*>(y) + off[t]) = omega * d[t];
 }
 
 // Fine-level prolongation and post-smoothing with the line smoother:
 // z1 = y + e1[parent], z = z1 + omega T^-1 (r - M z1); partial sums of r.z and r.r.
-// M z1 on the segment: along the line from the thread's own cells (memory at the segment
-// ends), across x from the neighbouring lanes (memory at the group's edges), across the
-// other transverse axis from memory.  The block's sides are walls or wrap onto the
-// block (the host checks this before choosing lines).
+// A face that does not exist (a wall) is given the cell itself as neighbour: its term
+// of M z1 is then exactly zero.  The block's sides are walls or wrap onto the block (the
+// host checks this before choosing lines).
 template <typename R, int L>
 __global__ void __launch_bounds__(kLineThreads)
 k_line_post(Grid g, Grid g1, int la, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
@@ -275,115 +320,108 @@ k_line_post(Grid g, Grid g1, int la, const R* __restrict__ Pf, const R* __restri
   __shared__ double red[kLineWaves];
   if (st->done) return;
   const LineGeo geo = line_geo(g, la);
-  const int lane = threadIdx.x % kLineLanes, m = threadIdx.x / kLineLanes;
-  const int l = xcd_logical_group() * kLineLanes + lane;
-  const int nseg = (geo.n + L - 1) / L;
-  int k = geo.n - m * L;
-  k = l < geo.nlines ? (k < 0 ? 0 : (k > L ? L : k)) : 0;
-  const int P0 = l < geo.nlines ? line_base(geo, la, l) + m * L * geo.stride : 0;
-  const int N = g.N;
-  const int* t1 = g1.tab;
+  const LineCells lc = line_cells<L>(geo, la);
+  const int k = lc.k, n = geo.n, nx = geo.nx, ci = lc.ci, co = lc.co;
   const int wrap = g.tab[kTabWrap];
-  const int nx = geo.nx;
-  // the line's fixed coordinates: x = ci, the other transverse one = co along axis ot
-  const int li = l < geo.nlines ? l : 0;
-  const int ci = li % nx, co = li / nx;
-  const int ot = la == 1 ? 2 : 1;
+  const int ot = la == 1 ? 2 : 1;                      // the other transverse axis
   const int no = ot == 1 ? geo.ny : geo.nz;
   const int so = ot == 1 ? nx : nx * geo.ny;
-  const bool has_ot = g.dim == 3 || ot == 1;
-  auto par_of = [&](int i, int lp, int op) {   // aggregate of the cell (x, line, other)
-    const int j = la == 1 ? lp : op, kk = la == 1 ? op : lp;
-    return t1[0] + (i >> 1) + t1[1] * ((j >> 1) + t1[2] * (kk >> 1));
-  };
-  const R* Pa = Pf + (size_t)la * N;
-  const R* Px = Pf;
-  const R* Po = Pf + (size_t)ot * N;
-  // every load is issued before the stencil (indices clamped: a face that does not exist
-  // reads the cell itself and is masked afterwards), so that nothing waits in a branch
+  const bool has_ot = g.dim == 3;
+  // neighbour offsets (cells) of the thread's line, 0 where the face does not exist
   const bool xl_in = ci > 0, xr_in = ci + 1 < nx;
-  const bool xl_on = xl_in || (wrap & 1), xr_on = xr_in || (wrap & 2);
-  const int cil = xl_in ? ci - 1 : nx - 1, cir = xr_in ? ci + 1 : 0;
+  const bool xl_on = xl_in || (wrap & 1), xr_on = xr_in || ((wrap >> 1) & 1);
+  const int dxl = xl_in ? -1 : (xl_on ? nx - 1 : 0);
+  const int dxr = xr_in ? 1 : (xr_on ? 1 - nx : 0);
   const bool om_in = co > 0, op_in = co + 1 < no;
   const bool om_on = has_ot && (om_in || ((wrap >> (2 * ot)) & 1));
   const bool op_on = has_ot && (op_in || ((wrap >> (2 * ot + 1)) & 1));
-  const int com = om_in ? co - 1 : no - 1, cop = op_in ? co + 1 : 0;
+  const int dom = om_on ? (om_in ? -so : (no - 1) * so) : 0;
+  const int dop = op_on ? (op_in ? so : -(no - 1) * so) : 0;
+  // aggregate (coarse cell) of fine cell (i, line position lp, other o): the coarse grid
+  // halves every axis of the block
+  const int* t1 = g1.tab;
+  const int cs = la == 1 ? t1[1] : t1[1] * t1[2];     // coarse stride along the line
+  const int cso = la == 1 ? t1[1] * t1[2] : t1[1];    // along the other transverse axis
+  const int cil = xl_on ? (xl_in ? ci - 1 : nx - 1) : ci, cir = xr_on ? (xr_in ? ci + 1 : 0) : ci;
+  const int com = om_on ? (om_in ? co - 1 : no - 1) : co, cop = op_on ? (op_in ? co + 1 : 0) : co;
+  const int cb = t1[0] + (ci >> 1) + (co >> 1) * cso;
+  const int cbl = t1[0] + (cil >> 1) + (co >> 1) * cso, cbr = t1[0] + (cir >> 1) + (co >> 1) * cso;
+  const int cbm = t1[0] + (ci >> 1) + (com >> 1) * cso, cbp = t1[0] + (ci >> 1) + (cop >> 1) * cso;
+  const R* Pa = Pf + (size_t)la * g.N;
+  const R* Px = Pf;
+  const R* Po = Pf + (size_t)(has_ot ? ot : 0) * g.N;
+  constexpr uint32_t es = sizeof(R);
   R b[L], d[L], z1[L], rv[L], pa[L], px[L];
-  R zxl[L], zxr[L], wxl[L], zom[L], zop[L], wom[L], wop[L];
+  R yxl[L], yxr[L], wxl[L], yom[L], yop[L], wom[L], wop[L];
+  R eo[L / 2], exl[L / 2], exr[L / 2], eom[L / 2], eop[L / 2];
+  uint32_t off[L];
 #pragma unroll
   for (int t = 0; t < L; ++t) {
-    const bool on = t < k;
-    const int P = on ? P0 + t * geo.stride : 0;
-    const int lp = on ? m * L + t : 0;
-    rv[t] = r[P];
-    b[t] = Dinv[P];
-    pa[t] = Pa[P];
-    px[t] = Px[P];
-    z1[t] = y[P] + ec[on ? par_of(ci, lp, co) : 0];
-    const int FL = on && xl_on ? (xl_in ? P - 1 : P + nx - 1) : P;
-    const int FR = on && xr_on ? (xr_in ? P + 1 : P + 1 - nx) : P;
-    zxl[t] = y[FL] + ec[on ? par_of(cil, lp, co) : 0];
-    zxr[t] = y[FR] + ec[on ? par_of(cir, lp, co) : 0];
-    wxl[t] = Px[FL];
-    const int FM = on && om_on ? (om_in ? P - so : P + (no - 1) * so) : P;
-    const int FP = on && op_on ? (op_in ? P + so : P - (no - 1) * so) : P;
-    zom[t] = y[FM] + ec[on && has_ot ? par_of(ci, lp, com) : 0];
-    zop[t] = y[FP] + ec[on && has_ot ? par_of(ci, lp, cop) : 0];
-    wom[t] = Po[FM];
-    wop[t] = Po[P];
+    const int P = line_cell<L>(geo, lc, t);
+    off[t] = (uint32_t)P * es;
+    rv[t] = ldo(r, off[t]);
+    b[t] = ldo(Dinv, off[t]);
+    pa[t] = ldo(Pa, off[t]);
+    px[t] = ldo(Px, off[t]);
+    z1[t] = ldo(y, off[t]);
+    yxl[t] = ldo(y, (uint32_t)(P + dxl) * es);
+    wxl[t] = ldo(Px, (uint32_t)(P + dxl) * es);
+    yxr[t] = ldo(y, (uint32_t)(P + dxr) * es);
+    yom[t] = ldo(y, (uint32_t)(P + dom) * es);
+    wom[t] = ldo(Po, (uint32_t)(P + dom) * es);
+    yop[t] = ldo(y, (uint32_t)(P + dop) * es);
+    wop[t] = ldo(Po, off[t]);
   }
-  // along the line at the segment's two ends (the rest comes from the thread's own cells)
-  const int lp0 = m * L, lpk = m * L + (k > 0 ? k - 1 : 0);
-  const bool lo_in = lp0 > 0, hi_in = lpk + 1 < geo.n;
-  const bool lo_on = k > 0 && (lo_in || ((wrap >> (2 * la)) & 1));
-  const bool hi_on = k > 0 && (hi_in || ((wrap >> (2 * la + 1)) & 1));
-  // (a segment past the line's end has no cells and P0 beyond it: it reads cell 0)
-  const int Pb = k > 0 ? P0 : 0;
-  const int Pk = Pb + (k > 0 ? k - 1 : 0) * geo.stride;
-  const int FLo = lo_on ? (lo_in ? P0 - geo.stride : P0 + (geo.n - 1) * geo.stride) : Pb;
-  const int FHi = hi_on ? (hi_in ? Pk + geo.stride : Pk - (geo.n - 1) * geo.stride) : Pk;
-  const R zlo = y[FLo] + ec[k > 0 ? par_of(ci, lo_in ? lp0 - 1 : geo.n - 1, co) : 0];
-  const R zhi = y[FHi] + ec[k > 0 ? par_of(ci, hi_in ? lpk + 1 : 0, co) : 0];
-  const R wlo0 = Pa[FLo];
-  // x neighbours held by the adjacent lanes of the same segment (width-32 shuffles)
-  const bool left_lane = lane > 0 && xl_in, right_lane = lane + 1 < kLineLanes && xr_in;
+  // the coarse correction is shared by the two cells of a pair (L and lp0 are even)
+#pragma unroll
+  for (int h = 0; h < L / 2; ++h) {
+    const int lp = lc.lp0 + 2 * h;
+    const int cc = ((lp < n ? lp : n - 1) >> 1) * cs;
+    eo[h] = ldo(ec, (uint32_t)(cb + cc) * es);
+    exl[h] = ldo(ec, (uint32_t)(cbl + cc) * es);
+    exr[h] = ldo(ec, (uint32_t)(cbr + cc) * es);
+    eom[h] = ldo(ec, (uint32_t)(cbm + cc) * es);
+    eop[h] = ldo(ec, (uint32_t)(cbp + cc) * es);
+  }
+  // along the line beyond the segment's ends (the cell itself where that face does not
+  // exist, or for a segment without cells)
+  const int lpk = lc.lp0 + (k > 0 ? k - 1 : 0);
+  const int lpo = lc.lp0 > 0 ? (lc.lp0 < n ? lc.lp0 : n) - 1 : (((wrap >> (2 * la)) & 1) ? n - 1 : 0);
+  const int lph = k == 0 ? 0 : (lpk + 1 < n ? lpk + 1 : (((wrap >> (2 * la + 1)) & 1) ? 0 : lpk));
+  const int Plo = lc.pl0 + lpo * geo.stride, Phi = lc.pl0 + lph * geo.stride;
+  const R zlo = ldo(y, (uint32_t)Plo * es) + ldo(ec, (uint32_t)(cb + (lpo >> 1) * cs) * es);
+  const R zhi = ldo(y, (uint32_t)Phi * es) + ldo(ec, (uint32_t)(cb + (lph >> 1) * cs) * es);
+  const R wlo = ldo(Pa, (uint32_t)Plo * es);
   R a[L], c[L];
 #pragma unroll
+  for (int t = 0; t < L; ++t) z1[t] += eo[t / 2];
+#pragma unroll
   for (int t = 0; t < L; ++t) {
-    const R zl = __shfl(z1[t], lane > 0 ? lane - 1 : lane, kLineLanes);
-    const R pl = __shfl(px[t], lane > 0 ? lane - 1 : lane, kLineLanes);
-    const R zr = __shfl(z1[t], lane + 1 < kLineLanes ? lane + 1 : lane, kLineLanes);
-    if (t < k) {
-      const int lp = m * L + t;
-      R mz = R(0);
-      if (xl_on) mz += (left_lane ? pl : wxl[t]) * (z1[t] - (left_lane ? zl : zxl[t]));
-      if (xr_on) mz += px[t] * (z1[t] - (right_lane ? zr : zxr[t]));
-      if (om_on) mz += wom[t] * (z1[t] - zom[t]);
-      if (op_on) mz += wop[t] * (z1[t] - zop[t]);
-      // along the line (the lower face's weight is stored at the lower cell)
-      const R wlo = t > 0 ? pa[t - 1] : wlo0;
-      if (t > 0 || lo_on) mz += wlo * (z1[t] - (t > 0 ? z1[t - 1] : zlo));
-      if (t + 1 < k || hi_on) mz += pa[t] * (z1[t] - (t + 1 < k ? z1[t + 1] : zhi));
-      d[t] = rv[t] - mz;
-      // T: tridiagonal part along the line (couplings across a wrap left out)
-      b[t] = R(1) / b[t];
-      a[t] = lp > 0 ? -wlo : R(0);
-      c[t] = lp + 1 < geo.n ? -pa[t] : R(0);
-    } else {
-      a[t] = c[t] = d[t] = R(0);
-      b[t] = R(1);
-    }
+    const int lp = lc.lp0 + t;
+    const int h = t / 2;
+    const R z = z1[t];
+    R mz = wxl[t] * (z - (yxl[t] + exl[h]));
+    mz += px[t] * (z - (yxr[t] + exr[h]));
+    mz += wom[t] * (z - (yom[t] + eom[h]));
+    mz += wop[t] * (z - (yop[t] + eop[h]));
+    // along the line: the lower face's weight is stored at the lower cell
+    const R wl = t > 0 ? pa[t - 1] : wlo;
+    mz += wl * (z - (t > 0 ? z1[t - 1] : zlo));
+    mz += pa[t] * (z - (t + 1 < k ? z1[t + 1] : zhi));
+    d[t] = rv[t] - mz;
+    // T: tridiagonal part along the line (couplings across a wrap left out)
+    b[t] = line_rcp(b[t]);
+    a[t] = (t < k && lp > 0) ? -wl : R(0);
+    c[t] = lp + 1 < n ? -pa[t] : R(0);
   }
-  line_solve<R, L>(a, b, c, d, k, nseg, sh, sif);
+  line_solve<R, L>(a, b, c, d, k, lc.nseg, sh, sif);
   double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll
   for (int t = 0; t < L; ++t) {
-    if (t < k) {
-      const R zo = z1[t] + omega * d[t];
-      z[P0 + t * geo.stride] = zo;
-      acc0 += (double)rv[t] * (double)zo;
-      acc1 += (double)rv[t] * (double)rv[t];
-    }
+    const R zo = z1[t] + omega * d[t];
+    acc0 += t < k ? (double)rv[t] * (double)zo : 0.0;
+    acc1 += t < k ? (double)rv[t] * (double)rv[t] : 0.0;
+    if (t < k) *reinterpret_cast<R*>(reinterpret_cast<char*>(z) + off[t]) = zo;
   }
   const double s0 = line_wg_sum(acc0, red);
   const double s1 = line_wg_sum(acc1, red);
@@ -451,7 +489,9 @@ int line_choose(piso_ctx* c, const piso_domain_desc* desc) {
     for (int f = 0; f < faces; ++f)
       if (c->h_fmap[(size_t)c->h_tab[4 + side] + f] >= 0) plain_sides = false;
   }
-  bool on = best > 3.0 && L > 0 && groups <= kRedGrid && plain_sides;
+  // the kernels address fields with 32-bit byte offsets
+  const bool small = (size_t)N * sizeof(double) < (size_t(1) << 32);
+  bool on = best > 3.0 && L > 0 && groups <= kRedGrid && plain_sides && small;
   if (const char* e = std::getenv("PISO_MG_LINE")) on = on && e[0] != '0';
   if (on) {
     c->mg_line_axis = axis;
