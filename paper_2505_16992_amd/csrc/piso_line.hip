@@ -491,8 +491,10 @@ int line_choose(piso_ctx* c, const piso_domain_desc* desc) {
   }
   // the kernels address fields with 32-bit byte offsets
   const bool small = (size_t)N * sizeof(double) < (size_t(1) << 32);
-  bool on = best > 3.0 && L > 0 && groups <= kRedGrid && plain_sides && small;
-  if (const char* e = std::getenv("PISO_MG_LINE")) on = on && e[0] != '0';
+  const bool fits = axis > 0 && L > 0 && groups <= kRedGrid && plain_sides && small;
+  bool on = fits && best > 3.0;
+  // PISO_MG_LINE=0: point Jacobi; =1: lines wherever the grid allows them
+  if (const char* e = std::getenv("PISO_MG_LINE")) on = e[0] == '0' ? false : (e[0] == '1' ? fits : on);
   if (on) {
     c->mg_line_axis = axis;
     c->mg_line_L = L;
