@@ -304,6 +304,8 @@ def main():
             model["cg_update_restrict"] = ("k_line_pre", N * 9 * es)
             model["mg_smooth0"] = ("k_line_pre", N * 4 * es)
             model["mg_up0"] = ("k_line_post", N * (d + 4) * es + (N // nch) * es)
+            if quad and len(dom.blocks) == 1:
+                model["mg_down0"] = ("k_line_restrict", N * (d + 2) * es + (N // nch) * es)
         per = {}
         for k, (ms, n) in tm.items():
             if n:

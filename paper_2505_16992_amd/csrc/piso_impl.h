@@ -353,7 +353,7 @@ int mg_update_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, R* x
 // Chooses the line axis for a single-block grid whose metric is strongly anisotropic
 // along one transverse axis (y or z), else leaves point Jacobi.
 int line_choose(piso_ctx* c, const piso_domain_desc* desc);
-// Work-groups of the line kernels (64 lines each); their partial sums use this count.
+// Work-groups of the line kernels (32 lines each); their partial sums use this count.
 int line_groups(const piso_ctx* c);
 // y = omega T^-1 r' (T: tridiagonal part of M along the line axis), after the PCG update
 // x += alpha d, r' = rin - alpha q into rout when `update`, else r' = rin.
@@ -365,6 +365,10 @@ int line_pre(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, R* x, const
 template <typename R>
 int line_post(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, const R* y, const R* e1, R* z,
               double* partB, CgState* st);
+// Level-1 residual R (r - M y) into mg[0].r in the quad layout; returns 1 without
+// launching where that layout does not apply (the tile kernel is used then).
+template <typename R>
+int line_restrict(piso_ctx* c, hipStream_t s, const R* Pf, const R* r, const R* y, CgState* st);
 
 // ---- advective outflow boundary (piso_outflow.hip) ----
 struct OutflowUm {

@@ -21,6 +21,7 @@
 #include <string>
 
 #include "piso_impl.h"
+#include "piso_quad.h"
 
 namespace piso {
 
@@ -431,6 +432,85 @@ k_line_post(Grid g, Grid g1, int la, const R* __restrict__ Pf, const R* __restri
   }
 }
 
+// Fine-grid restriction with line smoothing (y from the line solve, stored by
+// k_line_pre): rc[I] = sum over the children P of aggregate I of r'_P - (M y)_P.  Faces
+// between two children of I cancel in the sum; a face that leaves the aggregate
+// through a wall takes the cell itself as neighbour, which makes its term exactly zero.
+// Single block with nx % 4 == 0 whose sides are walls or wrap onto it (checked by the
+// host).  Unit: one x-quad (two aggregates along x) of one coarse row and plane, one
+// thread per fine row and plane parity of the unit (2^(d-1)); the aggregate sums are
+// added across those threads by shuffles.  All loads are unconditional (rows past an
+// odd extent are clamped to the last row and masked).
+template <typename R, int D>
+__global__ void __launch_bounds__(kWG)
+k_line_restrict(Grid g, Grid g1, int units, const R* __restrict__ Pf, const R* __restrict__ y,
+                const R* __restrict__ r, R* __restrict__ rc, const CgState* st) {
+  if (st->done) return;
+  constexpr int NP = 1 << (D - 1);
+  const int* tf = g.tab;
+  const int* tc = g1.tab;
+  const int N = g.N;
+  const int nx = tf[1], ny = tf[2], nz = tf[3], wrap = tf[kTabWrap];
+  const int cx = tc[1], cy = tc[2];
+  const int nxq = nx >> 2;
+  const int p = (int)threadIdx.x & (NP - 1);
+  const int u0 = xcd_logical_group() * (kWG / NP) + (int)threadIdx.x / NP;
+  const bool uv = u0 < units;
+  const int u = uv ? u0 : 0;
+  const int xq = u % nxq, rest = u / nxq;
+  const int cj = rest % cy, ck = rest / cy;
+  const int jj = 2 * cj + (p & 1), kk = D == 3 ? 2 * ck + (p >> 1) : 0;
+  const bool valid = uv && jj < ny && kk < nz;
+  const int j = jj < ny ? jj : ny - 1, k = kk < nz ? kk : nz - 1;
+  const int i0 = 4 * xq;
+  const int P0 = tf[0] + i0 + nx * (j + ny * k);
+  const Q4<R> yq = ldq(y, P0), rq = ldq(r, P0), px = ldq(Pf, P0);
+  // x faces that leave the quad's aggregates: left of cell 0 (weight stored at the left
+  // cell) and right of cell 3; the face between cells 1 and 2 separates the two
+  const int dl = i0 > 0 ? -1 : ((wrap & 1) ? nx - 1 : 0);
+  const int dr = i0 + 4 < nx ? 4 : ((wrap & 2) ? 4 - nx : 3);
+  const R yl = y[P0 + dl], pl = Pf[P0 + dl], yr = y[P0 + dr];
+  R res[4];
+  res[0] = rq.v[0] - pl * (yq.v[0] - yl);
+  res[1] = rq.v[1] - px.v[1] * (yq.v[1] - yq.v[2]);
+  res[2] = rq.v[2] - px.v[1] * (yq.v[2] - yq.v[1]);
+  res[3] = rq.v[3] - px.v[3] * (yq.v[3] - yr);
+  // y (and z) faces: the one on the side away from the aggregate's other row, and for
+  // the last row of an odd extent (an aggregate one row thick) the upper one as well
+#pragma unroll
+  for (int a = 1; a < D; ++a) {
+    const int pos = a == 1 ? j : k;
+    const int n = a == 1 ? ny : nz;
+    const int stride = a == 1 ? nx : nx * ny;
+    const int bit = pos & 1;
+    const R* Pa = Pf + (size_t)a * N;
+    const int dlo = pos > 0 ? -stride : (((wrap >> (2 * a)) & 1) ? (n - 1) * stride : 0);
+    const int dhi = pos + 1 < n ? stride : (((wrap >> (2 * a + 1)) & 1) ? -(n - 1) * stride : 0);
+    const int dm = bit ? dhi : dlo;
+    const Q4<R> yn = ldq(y, P0 + dm), wn = ldq(Pa, bit ? P0 : P0 + dm);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) res[e] -= wn.v[e] * (yq.v[e] - yn.v[e]);
+    if (n & 1) {   // the same for every thread
+      const int dx = (bit == 0 && pos + 1 == n) ? dhi : 0;
+      const Q4<R> yx = ldq(y, P0 + dx), wx = ldq(Pa, P0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) res[e] -= wx.v[e] * (yq.v[e] - yx.v[e]);
+    }
+  }
+  R sa = valid ? res[0] + res[1] : R(0);
+  R sb = valid ? res[2] + res[3] : R(0);
+#pragma unroll
+  for (int o = 1; o < NP; o <<= 1) {
+    sa += __shfl_xor(sa, o, 64);
+    sb += __shfl_xor(sb, o, 64);
+  }
+  if (p == 0 && uv) {
+    const int I = tc[0] + 2 * xq + cx * (cj + cy * ck);
+    rc[I] = sa;
+    rc[I + 1] = sb;
+  }
+}
+
 // ------------------------------------------------------------------ host
 
 int line_groups(const piso_ctx* c) {
@@ -555,6 +635,26 @@ int line_post(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r
   return PISO_OK;
 }
 
+// The restriction for line smoothing in the quad layout; 1 (nothing launched) where
+// the grid or the operands do not allow it (the caller then uses the tile kernel).
+template <typename R>
+int line_restrict(piso_ctx* c, hipStream_t s, const R* Pf, const R* r, const R* y, CgState* st) {
+  if (!c->mg_line_axis || !c->quad || c->nblocks != 1) return 1;
+  if ((((uintptr_t)Pf) | ((uintptr_t)r) | ((uintptr_t)y)) & 15u) return 1;
+  const int groups = c->mg_qtiles.off[1];
+  const int units = c->mg_qtiles.units[0];
+  R* rc = (R*)c->mg[0].r;
+  if (c->dim == 2)
+    launch_timed_wg(c, s, kTimeMgDown0, k_line_restrict<R, 2>, groups, kWG, c->grid, c->mg_g1, units, Pf, y, r, rc,
+                    (const CgState*)st);
+  else
+    launch_timed_wg(c, s, kTimeMgDown0, k_line_restrict<R, 3>, groups, kWG, c->grid, c->mg_g1, units, Pf, y, r, rc,
+                    (const CgState*)st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, PISO_E_HIP, std::string("k_line_restrict: ") + hipGetErrorString(e));
+  return PISO_OK;
+}
+
 template int line_pre<float>(piso_ctx*, hipStream_t, const float*, const float*, float*, const float*, float*,
                              const float*, const float*, float*, CgState*, const double*, int, int, bool);
 template int line_pre<double>(piso_ctx*, hipStream_t, const double*, const double*, double*, const double*, double*,
@@ -563,5 +663,8 @@ template int line_post<float>(piso_ctx*, hipStream_t, const float*, const float*
                               const float*, float*, double*, CgState*);
 template int line_post<double>(piso_ctx*, hipStream_t, const double*, const double*, const double*, const double*,
                                const double*, double*, double*, CgState*);
+
+template int line_restrict<float>(piso_ctx*, hipStream_t, const float*, const float*, const float*, CgState*);
+template int line_restrict<double>(piso_ctx*, hipStream_t, const double*, const double*, const double*, CgState*);
 
 }  // namespace piso

@@ -1054,6 +1054,9 @@ static int mg_tail(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
 template <typename R>
 int mg_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, const R* y, R* z, CgState* st,
              double* partB, int G) {
+  const int lr = line_restrict<R>(c, s, Pf, r, y, st);
+  if (lr < 0) return lr;
+  if (lr == 0) return mg_tail<R>(c, s, Pf, Dinv, r, y, z, st, partB, G);
   const int tiles = c->mg_tiles.off[c->nblocks];
   if (c->dim == 2)
     launch_timed_wg(c, s, kTimeMgDown0, k_mg_down0<R, 2>, tiles, 128, c->grid, c->mg_g1, c->mg_tiles, Pf, y, r,
