@@ -82,6 +82,11 @@ struct MgLevel {
   void* Dinv = nullptr;   // [n] inverse of the diagonal sum_s W[s][I] (0 if isolated)
   void* r = nullptr;      // [n] restricted residual
   void* e = nullptr;      // [n] correction
+  // single-block grids: the level's extents and the division magic for nx and nx * ny
+  // (slots are the directions 2 * axis + side there)
+  int dims[3] = {0, 0, 0};
+  uint32_t mx_lo = 0, mx_hi = 0, mxy_lo = 0, mxy_hi = 0;
+  int mx_sh = 0, mxy_sh = 0;
 };
 
 // Tiles of the fine-grid restriction: per block, the first tile and the number of
@@ -169,6 +174,7 @@ struct piso_ctx {
   piso::Grid mg_g1{};             // level 1 as a block table (offsets, dims, division magic)
   piso::MgTiles mg_tiles{};       // work-group tiles of the fine-grid restriction
   piso::MgQuadTiles mg_qtiles{};  // the same for the quad-vectorised fused update (nx % 4 == 0)
+  bool mg_struct = false;         // single block: coarse levels indexed by position
   int mg_line_axis = 0;           // fine-level line smoothing along this axis (0: point Jacobi)
   int mg_line_L = 0;              // cells per line segment (8 segments per line)
   // Dirichlet faces: owning cell and side (2 * axis + high), and the boundary cells

@@ -485,6 +485,116 @@ k_mg_down(int nf, int Kf, const int* __restrict__ nbr, const R* __restrict__ W, 
   if (I < nc && q == 0) rc[I] = v;
 }
 
+// Single-block levels: the cell at (i, j, k) of extents n, its neighbour in direction
+// (axis a, side) as a cell index and its coordinate along a (the cell itself where no
+// face leaves that way: its weight is 0 there).
+struct MgBox {
+  int n[3];
+  int wrap;
+};
+
+__device__ __forceinline__ void mg_box_nb(const MgBox& bx, const int (&pos)[3], int P, int a, int side, int& Q,
+                                          int& qa) {
+  const int st = a == 0 ? 1 : (a == 1 ? bx.n[0] : bx.n[0] * bx.n[1]);
+  const int p = pos[a], n = bx.n[a];
+  if (side) qa = p + 1 < n ? p + 1 : (((bx.wrap >> (2 * a + 1)) & 1) ? 0 : p);
+  else qa = p > 0 ? p - 1 : (((bx.wrap >> (2 * a)) & 1) ? n - 1 : p);
+  Q = P + (qa - p) * st;
+}
+
+__device__ __forceinline__ void mg_box_pos(const MgBox& bx, int P, uint64_t mx, int sx, uint64_t mxy, int sxy, int D,
+                                           int (&pos)[3]) {
+  const uint32_t jk = fast_div((uint32_t)P, mx, sx);
+  pos[0] = P - (int)jk * bx.n[0];
+  if (D == 3) {
+    pos[2] = (int)fast_div((uint32_t)P, mxy, sxy);
+    pos[1] = (int)jk - pos[2] * bx.n[1];
+  } else {
+    pos[1] = (int)jk;
+    pos[2] = 0;
+  }
+}
+
+// k_mg_down on a single block: children, neighbours and their positions by arithmetic,
+// so that all loads of a thread are independent (one memory latency instead of a chain
+// of child, neighbour and value loads).  Same sums, in the same slot order.
+template <typename R, int D>
+__global__ void __launch_bounds__(kWG)
+k_mg_down_s(MgBox fb, const R* __restrict__ W, const R* __restrict__ Dinv, const R* __restrict__ r, MgBox cb,
+            uint64_t cmx, int csx, uint64_t cmxy, int csxy, int nc, R omega, R* __restrict__ rc, const CgState* st,
+            int pin) {
+  constexpr int NCH = 1 << D, K = 2 * D;
+  const int done = st->done;
+  const int wg = mg_group(pin);
+  if (wg < 0) return;
+  const int t = wg * kWG + threadIdx.x;
+  const int I0 = t / NCH, q = t % NCH;
+  const int I = I0 < nc ? I0 : 0;
+  int cpos[3];
+  mg_box_pos(cb, I, cmx, csx, cmxy, csxy, D, cpos);
+  const int ch[3] = {2 * cpos[0] + (q & 1), 2 * cpos[1] + ((q >> 1) & 1), D == 3 ? 2 * cpos[2] + (q >> 2) : 0};
+  const bool ok = I0 < nc && ch[0] < fb.n[0] && ch[1] < fb.n[1] && ch[2] < fb.n[2];
+  // a child past an odd extent is replaced by the aggregate's first child and masked
+  const int pos[3] = {ok ? ch[0] : 2 * cpos[0], ok ? ch[1] : 2 * cpos[1], ok ? ch[2] : 2 * cpos[2]};
+  const int nf = fb.n[0] * fb.n[1] * fb.n[2];
+  const int P = pos[0] + fb.n[0] * (pos[1] + fb.n[1] * pos[2]);
+  R w[K], rq[K], dq[K];
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    int Q, qa;
+    mg_box_nb(fb, pos, P, s / 2, s & 1, Q, qa);
+    w[s] = W[s * nf + P];
+    rq[s] = r[Q];
+    dq[s] = Dinv[Q];
+  }
+  const R rP = r[P], xP = omega * Dinv[P] * rP;
+  if (done) return;
+  R res = rP;
+#pragma unroll
+  for (int s = 0; s < K; ++s) res -= w[s] * (xP - omega * dq[s] * rq[s]);
+  R v = ok ? res : R(0);
+#pragma unroll
+  for (int o = 1; o < NCH; o <<= 1) v += __shfl_xor(v, o, 64);
+  if (I0 < nc && q == 0) rc[I0] = v;
+}
+
+// k_mg_up on a single block, parents and neighbours by arithmetic.
+template <typename R, int D>
+__global__ void __launch_bounds__(kWG)
+k_mg_up_s(MgBox fb, uint64_t mx, int sx, uint64_t mxy, int sxy, const R* __restrict__ W, const R* __restrict__ Dinv,
+          const R* __restrict__ r, MgBox cb, const R* __restrict__ ec, R omega, R* __restrict__ e, const CgState* st,
+          int pin) {
+  constexpr int K = 2 * D;
+  const int done = st->done;
+  const int wg = mg_group(pin);
+  if (wg < 0) return;
+  const int n = fb.n[0] * fb.n[1] * fb.n[2];
+  const int P = wg * kWG + threadIdx.x;
+  if (P >= n) return;
+  int pos[3];
+  mg_box_pos(fb, P, mx, sx, mxy, sxy, D, pos);
+  const int cst[3] = {1, cb.n[0], cb.n[0] * cb.n[1]};
+  const int pP = (pos[0] >> 1) + cb.n[0] * ((pos[1] >> 1) + cb.n[1] * (pos[2] >> 1));
+  R w[K], rq[K], dq[K], eq[K];
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    const int a = s / 2;
+    int Q, qa;
+    mg_box_nb(fb, pos, P, a, s & 1, Q, qa);
+    w[s] = W[s * n + P];
+    rq[s] = r[Q];
+    dq[s] = Dinv[Q];
+    eq[s] = ec[pP + ((qa >> 1) - (pos[a] >> 1)) * cst[a]];
+  }
+  const R rP = r[P], dP = Dinv[P], eP = ec[pP];
+  if (done) return;
+  const R zP = omega * dP * rP + eP;
+  R mz = R(0);
+#pragma unroll
+  for (int s = 0; s < K; ++s) mz += w[s] * (zP - (omega * dq[s] * rq[s] + eq[s]));
+  e[P] = zP + omega * dP * (rP - mz);
+}
+
 // Coarsest level (n <= kMgCoarse cells, one work-group of kMgCoarseThreads): e = B r with
 // B the Chebyshev iteration of `steps` steps from zero, preconditioned by D^-1, for the
 // interval [lo, hi] of the spectrum of D^-1 M.  M is a weighted graph Laplacian, so that
@@ -830,13 +940,19 @@ int mg_build(piso_ctx* c) {
             child[(size_t)q * nx.n + I] = P;
           }
     }
-    // coarse adjacency and contribution lists (fixed traversal order)
+    // coarse adjacency and contribution lists (fixed traversal order).  On a single
+    // block a finer face in direction (axis, side) leaves an aggregate towards the
+    // aggregate next to it in the same direction, so there the slots are the directions
+    // 2 * axis + side on every level, as on the fine grid (-1 and weight 0 where no face
+    // leaves that way); with several blocks they are numbered as neighbours are found.
+    const bool by_dir = B == 1;
     std::vector<int> nb_off(nx.n + 1, 0), nb_list;
     std::vector<int> pr_off(nx.n + 1, 0), pr_slot, pr_face;
     nb_list.reserve((size_t)nx.n * 2 * D);
     int K = 0;
     for (int I = 0; I < nx.n; ++I) {
       const size_t nb0 = nb_list.size(), pr0 = pr_slot.size();
+      if (by_dir) nb_list.resize(nb0 + 2 * D, -1);
       for (int q = 0; q < NCH; ++q) {
         const int P = child[(size_t)q * nx.n + I];
         if (P < 0) continue;
@@ -846,11 +962,18 @@ int mg_build(piso_ctx* c) {
           const int J = parent[Q];
           if (J == I) continue;
           int slot = -1;
-          for (size_t u = nb0; u < nb_list.size(); ++u)
-            if (nb_list[u] == J) slot = (int)(u - nb0);
-          if (slot < 0) {
-            slot = (int)(nb_list.size() - nb0);
-            nb_list.push_back(J);
+          if (by_dir) {
+            slot = s;
+            if (nb_list[nb0 + s] >= 0 && nb_list[nb0 + s] != J)
+              return fail(c, PISO_E_ARG, "multigrid: aggregate with two neighbours in one direction");
+            nb_list[nb0 + s] = J;
+          } else {
+            for (size_t u = nb0; u < nb_list.size(); ++u)
+              if (nb_list[u] == J) slot = (int)(u - nb0);
+            if (slot < 0) {
+              slot = (int)(nb_list.size() - nb0);
+              nb_list.push_back(J);
+            }
           }
           long long face;
           if (level == 1) {
@@ -885,6 +1008,11 @@ int mg_build(piso_ctx* c) {
     MgLevel L;
     L.n = nx.n;
     L.K = K;
+    if (by_dir) {
+      for (int a = 0; a < 3; ++a) L.dims[a] = nx.dims[0][a];
+      div_magic((uint32_t)L.dims[0], L.mx_lo, L.mx_hi, L.mx_sh);
+      div_magic((uint32_t)(L.dims[0] * L.dims[1]), L.mxy_lo, L.mxy_hi, L.mxy_sh);
+    }
     if (int rc = upload(c, (void**)&L.nbr, nbr)) return rc;
     if (int rc = upload(c, (void**)&L.child, child)) return rc;
     if (int rc = upload(c, (void**)&L.parent, parent)) return rc;
@@ -942,6 +1070,9 @@ int mg_build(piso_ctx* c) {
     cur = nx;
   }
   if (!c->mg.empty() && c->mg.back().n > kMgCoarse) c->mg.clear();   // cannot happen: blocks <= 16
+  // PISO_MG_GRAPH=1 keeps the table-driven kernels on single-block grids
+  c->mg_struct = B == 1 && !c->mg.empty();
+  if (const char* e = std::getenv("PISO_MG_GRAPH")) c->mg_struct = c->mg_struct && e[0] != '1';
   if (!c->mg.empty()) {
     if (int rc = dev_alloc(c, &c->k_z, (size_t)c->N * c->esz)) return rc;
     if (int rc = dev_alloc(c, &c->k_y, (size_t)c->N * c->esz)) return rc;
@@ -1000,10 +1131,20 @@ static int mg_tail(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
   // launches of at most kMgPinGroups work-groups run on one XCD (see mg_group)
   auto pinned = [](int groups) { return groups <= kMgPinGroups ? 1 : 0; };
   auto grid_of = [](int groups, int pin) { return pin ? 8 * groups : groups; };
+  const int wrap = c->h_tab[kTabWrap];
+  auto box = [&](const MgLevel& L) { return MgBox{{L.dims[0], L.dims[1], L.dims[2]}, wrap}; };
+  auto m64 = [](uint32_t lo, uint32_t hi) { return (uint64_t)lo | ((uint64_t)hi << 32); };
   for (int l = 1; l < nl; ++l) {
     const MgLevel& F = c->mg[l - 1];
     const MgLevel& C = c->mg[l];
     const int gw = grid_cells((1 << c->dim) * C.n), pin = pinned(gw);
+    if (c->mg_struct) {
+      auto ks = c->dim == 2 ? k_mg_down_s<R, 2> : k_mg_down_s<R, 3>;
+      launch_timed(c, s, kTimeMgCoarse, ks, grid_of(gw, pin), box(F), (const R*)F.W, (const R*)F.Dinv,
+                   (const R*)F.r, box(C), m64(C.mx_lo, C.mx_hi), C.mx_sh, m64(C.mxy_lo, C.mxy_hi), C.mxy_sh, C.n, om,
+                   (R*)C.r, (const CgState*)st, pin);
+      continue;
+    }
     auto kern = c->dim == 2 ? (F.K <= 4 ? k_mg_down<R, 4, 4> : (F.K <= 6 ? k_mg_down<R, 4, 6> : k_mg_down<R, 4, 8>))
                             : (F.K <= 4 ? k_mg_down<R, 8, 4> : (F.K <= 6 ? k_mg_down<R, 8, 6> : k_mg_down<R, 8, 8>));
     launch_timed(c, s, kTimeMgCoarse, kern, grid_of(gw, pin), F.n, F.K, (const int*)F.nbr, (const R*)F.W,
@@ -1021,6 +1162,13 @@ static int mg_tail(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
     const MgLevel& F = c->mg[l];
     const MgLevel& C = c->mg[l + 1];
     const int gw = grid_cells(F.n), pin = pinned(gw);
+    if (c->mg_struct) {
+      auto ks = c->dim == 2 ? k_mg_up_s<R, 2> : k_mg_up_s<R, 3>;
+      launch_timed(c, s, kTimeMgCoarse, ks, grid_of(gw, pin), box(F), m64(F.mx_lo, F.mx_hi), F.mx_sh,
+                   m64(F.mxy_lo, F.mxy_hi), F.mxy_sh, (const R*)F.W, (const R*)F.Dinv, (const R*)F.r, box(C),
+                   (const R*)C.e, om, (R*)F.e, (const CgState*)st, pin);
+      continue;
+    }
     auto kern = F.K <= 4 ? k_mg_up<R, 4> : (F.K <= 6 ? k_mg_up<R, 6> : k_mg_up<R, 8>);
     launch_timed(c, s, kTimeMgCoarse, kern, grid_of(gw, pin), F.n, F.K, (const int*)F.nbr, (const R*)F.W,
                  (const R*)F.Dinv, (const R*)F.r, (const int*)C.parent, (const R*)C.e, om, (R*)F.e,
