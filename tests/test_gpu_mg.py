@@ -186,3 +186,26 @@ def test_graph_replay_matches_eager(prec, monkeypatch):
             outs.append(res)
         for (ue, pe), (ug, pg) in zip(*outs):
             assert torch.equal(ue, ug) and torch.equal(pe, pg)
+
+
+@pytest.mark.parametrize("name", ["channel_q", "channel", "tgv16", "cavity12"])
+def test_position_indexed_levels_match_tables(name, monkeypatch):
+    """Single-block grids run the coarse levels with position-indexed kernels; the
+    table-driven kernels on the same direction-ordered graphs (PISO_MG_GRAPH=1) give the
+    same FP64 step to solver tolerance with iteration counts within one."""
+    api = _api()
+    case = small_cases()[name]
+    u, p, S, ub, nu = random_state(case, seed=16)
+    out = []
+    for env in (None, "1"):
+        if env:
+            monkeypatch.setenv("PISO_MG_GRAPH", env)
+        ctx = api.Context(case.domain, "f64")
+        monkeypatch.delenv("PISO_MG_GRAPH", raising=False)
+        t = ctx.dtype
+        o = tight_opts(ctx)
+        u1, p1, info = ctx.step(dev(u, t), dev(p, t), dev(nu, t), dev(S, t), dev(ub, t), case.dt, o, info=True)
+        out.append((host(u1), host(p1), [q["iters"] for q in info["pres"]]))
+    say("%s: iters position-indexed %s, tables %s" % (name, out[0][2], out[1][2]))
+    assert rel(out[0][0], out[1][0]) < 1e-10 and rel_p(out[0][1], out[1][1]) < 1e-9
+    assert all(abs(a - b) <= 1 for a, b in zip(out[0][2], out[1][2]))
