@@ -113,7 +113,9 @@ constexpr int kMgCoarseSteps3 = 12;   // Chebyshev steps on the coarsest level, 
 constexpr int kMgCoarseSteps2 = 32;   // and 2D (cheaper steps, slower Jacobi-type convergence)
 constexpr int kMgCoarseStepsMax = 32;
 constexpr double kMgChebRatio = 100.0;   // their interval [2 / ratio, 2] of the spectrum of D^-1 M
-constexpr double kMgOmega = 0.8;    // Jacobi damping of the smoother
+constexpr double kMgOmega = 0.8;        // damping of the fine-level smoother
+constexpr double kMgOmegaCoarse = 0.9;  // damping of the Jacobi sweeps on the coarse levels (< 1:
+                                        // the V-cycle stays symmetric positive definite)
 constexpr int kMgPinGroups = 64;    // coarse-level launches up to this many work-groups run on one XCD
 
 }  // namespace piso

@@ -1126,7 +1126,7 @@ template <typename R>
 static int mg_tail(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, const R* y, R* z,
                    CgState* st, double* partB, int G) {
   const int nl = (int)c->mg.size();
-  const R om = (R)kMgOmega;
+  const R om = (R)kMgOmega, omc = (R)kMgOmegaCoarse;
   const Grid& g1 = c->mg_g1;
   // launches of at most kMgPinGroups work-groups run on one XCD (see mg_group)
   auto pinned = [](int groups) { return groups <= kMgPinGroups ? 1 : 0; };
@@ -1141,14 +1141,14 @@ static int mg_tail(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
     if (c->mg_struct) {
       auto ks = c->dim == 2 ? k_mg_down_s<R, 2> : k_mg_down_s<R, 3>;
       launch_timed(c, s, kTimeMgCoarse, ks, grid_of(gw, pin), box(F), (const R*)F.W, (const R*)F.Dinv,
-                   (const R*)F.r, box(C), m64(C.mx_lo, C.mx_hi), C.mx_sh, m64(C.mxy_lo, C.mxy_hi), C.mxy_sh, C.n, om,
+                   (const R*)F.r, box(C), m64(C.mx_lo, C.mx_hi), C.mx_sh, m64(C.mxy_lo, C.mxy_hi), C.mxy_sh, C.n, omc,
                    (R*)C.r, (const CgState*)st, pin);
       continue;
     }
     auto kern = c->dim == 2 ? (F.K <= 4 ? k_mg_down<R, 4, 4> : (F.K <= 6 ? k_mg_down<R, 4, 6> : k_mg_down<R, 4, 8>))
                             : (F.K <= 4 ? k_mg_down<R, 8, 4> : (F.K <= 6 ? k_mg_down<R, 8, 6> : k_mg_down<R, 8, 8>));
     launch_timed(c, s, kTimeMgCoarse, kern, grid_of(gw, pin), F.n, F.K, (const int*)F.nbr, (const R*)F.W,
-                 (const R*)F.Dinv, (const R*)F.r, (const int*)C.child, C.n, om, (R*)C.r, (const CgState*)st, pin);
+                 (const R*)F.Dinv, (const R*)F.r, (const int*)C.child, C.n, omc, (R*)C.r, (const CgState*)st, pin);
   }
   {
     const MgLevel& L = c->mg[nl - 1];
@@ -1166,12 +1166,12 @@ static int mg_tail(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
       auto ks = c->dim == 2 ? k_mg_up_s<R, 2> : k_mg_up_s<R, 3>;
       launch_timed(c, s, kTimeMgCoarse, ks, grid_of(gw, pin), box(F), m64(F.mx_lo, F.mx_hi), F.mx_sh,
                    m64(F.mxy_lo, F.mxy_hi), F.mxy_sh, (const R*)F.W, (const R*)F.Dinv, (const R*)F.r, box(C),
-                   (const R*)C.e, om, (R*)F.e, (const CgState*)st, pin);
+                   (const R*)C.e, omc, (R*)F.e, (const CgState*)st, pin);
       continue;
     }
     auto kern = F.K <= 4 ? k_mg_up<R, 4> : (F.K <= 6 ? k_mg_up<R, 6> : k_mg_up<R, 8>);
     launch_timed(c, s, kTimeMgCoarse, kern, grid_of(gw, pin), F.n, F.K, (const int*)F.nbr, (const R*)F.W,
-                 (const R*)F.Dinv, (const R*)F.r, (const int*)C.parent, (const R*)C.e, om, (R*)F.e,
+                 (const R*)F.Dinv, (const R*)F.r, (const int*)C.parent, (const R*)C.e, omc, (R*)F.e,
                  (const CgState*)st, pin);
   }
   if (c->mg_line_axis) return line_post<R>(c, s, Pf, Dinv, r, y, (const R*)c->mg[0].e, z, partB, st);
