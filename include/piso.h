@@ -175,7 +175,16 @@ typedef struct {
  * resolution, opposite sides, same orientation), J > 0; returns PISO_E_TOPOLOGY
  * otherwise.  Derives alpha_jk = J T_j . T_k (App. A.3.3) on the device and detects
  * non-orthogonal grids (max |alpha_jk| / alpha_jj > 1e-12).  Uses the current HIP device.
- * On failure *out is NULL and piso_create_error() returns the message. */
+ * On failure *out is NULL and piso_create_error() returns the message.
+ *
+ * Environment read at creation (all optional; for measurement and comparison):
+ *   PISO_MG_LINE=0     point Jacobi on the fine multigrid level; =1 lines wherever the
+ *                      grid allows them (see piso_mg_smoother)
+ *   PISO_MG_GRAPH=1    table-driven coarse-level kernels on single-block grids too
+ *   PISO_NO_QUAD=1     no vectorised (four cells per thread) kernels
+ *   PISO_NO_GRAPH=1    launch the PCG iterations one by one instead of replaying a graph
+ *   PISO_CG_GROUPS=n   work-groups of the Krylov kernels (0 or unset: sized to the grid,
+ *                      at most 2048) */
 int piso_create(const piso_domain_desc* desc, int32_t precision, piso_ctx** out);
 void piso_destroy(piso_ctx* ctx);
 const char* piso_last_error(const piso_ctx* ctx);
@@ -195,9 +204,10 @@ int piso_mg_info(const piso_ctx* ctx, int32_t* n_levels, int64_t* cells, int32_t
 /* Fine-level smoother of the multigrid preconditioner: *line_axis = 0 for damped point
  * Jacobi, or 1 (y) / 2 (z) for damped line Jacobi along that axis (tridiagonal solves
  * along the lines).  Lines are chosen at context creation for single-block grids whose
- * metric weight along one transverse axis is on average more than 3x the largest other
- * (a grid stretched towards walls normal to that axis); PISO_MG_LINE=0 in the
- * environment at creation keeps point Jacobi. */
+ * sides are walls or wrap onto the block and whose metric weight along one transverse
+ * axis is on average more than 3x the largest other (a grid stretched towards walls
+ * normal to that axis); PISO_MG_LINE=0 in the environment at creation keeps point
+ * Jacobi, PISO_MG_LINE=1 takes lines wherever the grid allows them. */
 int piso_mg_smoother(const piso_ctx* ctx, int32_t* line_axis);
 
 /* Default options for a precision: vel rtol 1e-10 (F64) / 1e-7, Jacobi; pres rtol 1e-10

@@ -647,7 +647,7 @@ int piso_create(const piso_domain_desc* desc, int32_t precision, piso_ctx** out)
   c->quad = true;
   for (int b = 0; b < c->nblocks; ++b)
     if (desc->block_cells[3 * b] % 4 != 0) c->quad = false;
-  if (const char* e = std::getenv("PISO_NO_QUAD")) c->quad = (e[0] == '0');
+  if (const char* e = std::getenv("PISO_NO_QUAD")) c->quad = c->quad && e[0] == '0';   // can only turn it off
   if (const char* e = std::getenv("PISO_NO_GRAPH")) c->use_graphs = (e[0] == '0');
   if (const char* e = std::getenv("PISO_CG_GROUPS")) {
     const int v = std::atoi(e);
