@@ -12,12 +12,17 @@
 //
 // GPU layout.  A work-group owns 32 lines (consecutive lines, x fastest, so that the 32
 // lanes of a half-wave load 128 contiguous bytes of a row) and cuts each line into S = 8
-// segments of L cells, one per half-wave (32 lines per group keeps more than one group
-// per CU at 96^3).  A thread eliminates its segment with the Thomas algorithm for three right-hand
-// sides (the line's right-hand side and the two couplings to the neighbouring segments),
-// so that w = U + V w_prev_last + G w_next_first on the segment; the first and last
-// values of the segments go through LDS, one thread per line solves the two-term
-// recurrence for the segment interface values, and every thread reconstructs its cells.
+// segments of L cells, one per half-wave (288 groups at 96^3; 16 lines of 16 shorter
+// segments per group spread better over the CUs but ran slower).  A thread eliminates its
+// segment with the Thomas algorithm for three right-hand sides (the line's right-hand
+// side and the two couplings to the neighbouring segments), so that
+// w = U + V w_prev_last + G w_next_first on the segment; the first and last values of
+// the segments go through LDS, one thread per line solves the two-term recurrence for
+// the segment interface values, and every thread reconstructs its cells.
+//
+// Kernels: k_line_pre (the PCG update fused with the pre-smoothing), k_line_restrict (the
+// restriction of r' - M y to level 1, which needs y of other groups' lines) and
+// k_line_post (prolongation fused with the post-smoothing and the partial sums of r.z).
 #include <string>
 
 #include "piso_impl.h"
