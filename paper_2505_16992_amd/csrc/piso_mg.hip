@@ -16,12 +16,14 @@
 // refreshed from Pf before every solve (P depends on A, eq. pMatDiscrete).
 //
 // One application z = B r is a V-cycle from a zero guess: on each level one damped
-// Jacobi sweep before and one after the coarse correction (omega = 0.8), a fixed
-// number of damped Jacobi sweeps on the coarsest level (<= 256 cells, one work-group).
-// Every step is a fixed linear map and the pre- and post-smoothers are the same
-// symmetric operator, so B is symmetric positive definite on the range of M and the
-// outer CG keeps its theory.  The pre-smoothing result omega D^-1 r is never stored:
-// the kernels that need it at a neighbour recompute it from r and D^-1.
+// Jacobi sweep before and one after the coarse correction (omega = 0.8 on the fine
+// level, 0.9 on the coarse ones; on stretched single-block grids the fine level smooths
+// along lines instead, in piso_line.hip), and on the coarsest level (<= 2048 cells, one
+// work-group) a fixed Chebyshev iteration.  Every step is a fixed linear map and the
+// pre- and post-smoothers are the same symmetric operator, so B is symmetric positive
+// definite on the range of M and the outer CG keeps its theory.  On the coarse levels
+// the pre-smoothing result omega D^-1 r is never stored: the kernels that need it at a
+// neighbour recompute it from r and D^-1.
 #include <algorithm>
 #include <array>
 #include <cmath>
