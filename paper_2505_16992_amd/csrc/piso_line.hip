@@ -558,7 +558,9 @@ int line_choose(piso_ctx* c, const piso_domain_desc* desc) {
   }
   const int n = c->h_tab[1 + axis];
   int L = 0;
-  for (int cand : {4, 8, 12, 16, 24, 32})
+  // lines of at most 128 cells: longer segments than 16 cells no longer fit the
+  // registers (FP64 spills from 24 on)
+  for (int cand : {4, 8, 12, 16})
     if (cand * kLineSegs >= n) {
       L = cand;
       break;
@@ -599,9 +601,7 @@ static void launch_pre_L(piso_ctx* c, hipStream_t s, int G, const R* Pf, const R
     case 4: PRE(4); break;
     case 8: PRE(8); break;
     case 12: PRE(12); break;
-    case 16: PRE(16); break;
-    case 24: PRE(24); break;
-    default: PRE(32); break;
+    default: PRE(16); break;
   }
 #undef PRE
 }
@@ -630,9 +630,7 @@ int line_post(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r
     case 4: POST(4); break;
     case 8: POST(8); break;
     case 12: POST(12); break;
-    case 16: POST(16); break;
-    case 24: POST(24); break;
-    default: POST(32); break;
+    default: POST(16); break;
   }
 #undef POST
   hipError_t e = hipGetLastError();
