@@ -205,10 +205,10 @@ int piso_mg_info(const piso_ctx* ctx, int32_t* n_levels, int64_t* cells, int32_t
  * Jacobi, or 1 (y) / 2 (z) for damped line Jacobi along that axis (tridiagonal solves
  * along the lines).  Lines are chosen at context creation for single-block grids whose
  * sides are walls or wrap onto the block, with lines of at most 128 cells, and whose
- * metric weight along one transverse
- * axis is on average more than 3x the largest other (a grid stretched towards walls
- * normal to that axis); PISO_MG_LINE=0 in the environment at creation keeps point
- * Jacobi, PISO_MG_LINE=1 takes lines wherever the grid allows them. */
+ * metric weight along one transverse axis is on average more than 3x the largest other
+ * (a grid stretched towards walls normal to that axis); PISO_MG_LINE=0 in the
+ * environment at creation keeps point Jacobi, PISO_MG_LINE=1 takes lines wherever the
+ * grid allows them. */
 int piso_mg_smoother(const piso_ctx* ctx, int32_t* line_axis);
 
 /* Default options for a precision: vel rtol 1e-10 (F64) / 1e-7, Jacobi; pres rtol 1e-10
