@@ -204,3 +204,20 @@ def test_errors(api):
     with pytest.raises(api.PisoError) as e:
         api.Context(cases.Domain(2, [(3, 4, 1), (3, 5, 1)], sides, T, J, cc), "f64")
     assert e.value.code == -2                       # PISO_E_TOPOLOGY
+
+
+@pytest.mark.parametrize("name,value", [("channel", "0"), ("channel_q", "1")])
+def test_no_quad_switch(api, name, value, monkeypatch):
+    """PISO_NO_QUAD can only turn the vectorised kernels off: "0" on a grid with
+    nx % 4 != 0 still runs the scalar kernels, "1" on a grid that allows the vectorised
+    ones runs the scalar kernels instead; the FP64 step matches the oracle either way."""
+    say("test_no_quad_switch", name, value)
+    monkeypatch.setenv("PISO_NO_QUAD", value)
+    case, ctx, (u, p, S, ub, nu), (ud, pd, Sd, ubd, nud) = _setup(api, name)
+    monkeypatch.delenv("PISO_NO_QUAD")
+    u1, p1, info = ctx.step(ud, pd, nud, Sd, ubd, case.dt, tight_opts(ctx), info=True)
+    torch.cuda.synchronize()
+    ref = oracle_step(Geometry(case.domain), u, p, nu, S, case.dt, ub)
+    assert info["vel"]["status"] == 0 and info["pres"][1]["status"] == 0, info
+    assert rel(host(u1), ref.u2) < 1e-9
+    assert rel_p(host(p1), ref.p2) < 1e-9
