@@ -247,6 +247,7 @@ int alloc_workspaces(piso_ctx* c) {
       {&c->g_Pf, D * N * e}, {&c->g_Dinv, N * e}, {&c->g_x, N * e},
       {&c->b_r, D * N * e}, {&c->b_rh, D * N * e}, {&c->b_p0, D * N * e}, {&c->b_p1, D * N * e},
       {&c->b_v0, D * N * e}, {&c->b_v1, D * N * e}, {&c->b_s, D * N * e}, {&c->b_t, D * N * e},
+      {&c->b_iA, N * e},
       {&c->a_g, D * N * e}, {&c->a_uin, D * N * e}, {&c->a_lam, N * e}, {&c->a_pbar, N * e},
       {&c->a_mu, D * N * e}, {&c->a_dh, D * N * e}, {&c->a_dA, N * e}, {&c->a_dC, 2 * D * N * e},
       {&c->a_dbu, D * N * e}, {&c->a_db, D * N * e}, {&c->a_dp1, N * e}, {&c->a_dnu, N * e},

@@ -187,6 +187,7 @@ struct piso_ctx {
   void *out_star = nullptr, *out_contrib = nullptr;   // [d][NB] working precision
   void *b_r = nullptr, *b_rh = nullptr, *b_p0 = nullptr, *b_p1 = nullptr, *b_v0 = nullptr,
        *b_v1 = nullptr, *b_s = nullptr, *b_t = nullptr;                    // BiCGStab [d][N]
+  void* b_iA = nullptr;   // BiCGStab: 1 / A, formed once per solve [N]
   // adjoint workspaces
   void *a_g = nullptr, *a_uin = nullptr, *a_lam = nullptr, *a_pbar = nullptr, *a_mu = nullptr,
        *a_dh = nullptr, *a_dA = nullptr, *a_dC = nullptr, *a_dbu = nullptr, *a_db = nullptr,

@@ -378,6 +378,14 @@ __device__ __forceinline__ R coef_m(const R* __restrict__ C, int j, int Fm, int 
   return TRANS ? C[(size_t)j * N + Fm] : C[(size_t)(D + j) * N + Fm];
 }
 
+// 1 / A once per solve (the same correctly rounded quotient the iterations would form
+// per neighbour).
+template <typename R>
+__global__ void __launch_bounds__(kWG) k_bi_recip(int N, const R* __restrict__ A, R* __restrict__ iA) {
+  const int P = cell_of_thread(N);
+  if (P >= 0) iA[P] = R(1) / A[P];
+}
+
 template <typename R, int D, bool TRANS>
 __global__ void __launch_bounds__(kWG)
 k_bi_init(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __restrict__ b,
@@ -466,7 +474,7 @@ k_bi_check(const double* __restrict__ part3, int G, int first, int k_total, doub
 
 template <typename R, int D, bool TRANS>
 __global__ void __launch_bounds__(kWG)
-k_bi_1(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __restrict__ r,
+k_bi_1(Grid g, const R* __restrict__ iA, const R* __restrict__ C, const R* __restrict__ r,
        const R* __restrict__ rh, const R* __restrict__ p_old, const R* __restrict__ v_old,
        R* __restrict__ p_new, R* __restrict__ v_new, BiState* st, const double* __restrict__ part3,
        double* __restrict__ part1, int Gp, int k) {
@@ -523,8 +531,8 @@ k_bi_1(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __rest
     for (int j = 0; j < D; ++j) {
       cp[j] = Fp[j] >= 0 ? coef_p<R, D, TRANS>(C, j, P, N) : R(0);
       cm[j] = Fm[j] >= 0 ? coef_m<R, D, TRANS>(C, j, Fm[j], N) : R(0);
-      iAp[j] = Fp[j] >= 0 ? R(1) / A[Fp[j]] : R(0);
-      iAm[j] = Fm[j] >= 0 ? R(1) / A[Fm[j]] : R(0);
+      iAp[j] = Fp[j] >= 0 ? iA[Fp[j]] : R(0);
+      iAm[j] = Fm[j] >= 0 ? iA[Fm[j]] : R(0);
     }
 #pragma unroll
     for (int c = 0; c < D; ++c) {
@@ -548,7 +556,7 @@ k_bi_1(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __rest
 
 template <typename R, int D, bool TRANS>
 __global__ void __launch_bounds__(kWG)
-k_bi_2(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __restrict__ r,
+k_bi_2(Grid g, const R* __restrict__ iA, const R* __restrict__ C, const R* __restrict__ r,
        const R* __restrict__ v, R* __restrict__ s, R* __restrict__ t, BiState* st,
        const double* __restrict__ part1, double* __restrict__ part2, int Gp, int k) {
   if (st->all_done) return;
@@ -592,8 +600,8 @@ k_bi_2(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __rest
     for (int j = 0; j < D; ++j) {
       cp[j] = Fp[j] >= 0 ? coef_p<R, D, TRANS>(C, j, P, N) : R(0);
       cm[j] = Fm[j] >= 0 ? coef_m<R, D, TRANS>(C, j, Fm[j], N) : R(0);
-      iAp[j] = Fp[j] >= 0 ? R(1) / A[Fp[j]] : R(0);
-      iAm[j] = Fm[j] >= 0 ? R(1) / A[Fm[j]] : R(0);
+      iAp[j] = Fp[j] >= 0 ? iA[Fp[j]] : R(0);
+      iAm[j] = Fm[j] >= 0 ? iA[Fm[j]] : R(0);
     }
 #pragma unroll
     for (int c = 0; c < D; ++c) {
@@ -618,7 +626,7 @@ k_bi_2(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __rest
 
 template <typename R, int D>
 __global__ void __launch_bounds__(kWG)
-k_bi_3(int N, const R* __restrict__ A, R* __restrict__ x, R* __restrict__ r, const R* __restrict__ rh,
+k_bi_3(int N, const R* __restrict__ iAv, R* __restrict__ x, R* __restrict__ r, const R* __restrict__ rh,
        const R* __restrict__ p, const R* __restrict__ s, const R* __restrict__ t, BiState* st,
        const double* __restrict__ part2, double* __restrict__ part3, int Gp, int k) {
   if (st->all_done) return;
@@ -641,7 +649,7 @@ k_bi_3(int N, const R* __restrict__ A, R* __restrict__ x, R* __restrict__ r, con
 #pragma unroll
   for (int q = 0; q < 2 * D; ++q) acc[q] = 0.0;
   for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
-    const R iA = R(1) / A[P];
+    const R iA = iAv[P];
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       if (!act[c]) continue;
@@ -1017,6 +1025,8 @@ int velocity_solve(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* 
     if (D == 2) k_bi_check<2><<<1, kWG, 0, s>>>(p3, G, FIRST, KT, tol2, st);      \
     else k_bi_check<3><<<1, kWG, 0, s>>>(p3, G, FIRST, KT, tol2, st);             \
   } while (0)
+  R* iA = (R*)c->b_iA;
+  k_bi_recip<R><<<grid_cells(N), kWG, 0, s>>>(N, A, iA);
   BI_LAUNCH(k_bi_init, c->grid, A, C, b, x, r, rh, pb[0], vb[0], p3);
   BI_CHECK(1, 0);
   // zero right-hand sides are handled on the device (no read-back before the iterations)
@@ -1033,10 +1043,10 @@ int velocity_solve(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* 
       R* pn = pb[(it + 1) & 1];
       R* vo = vb[it & 1];
       R* vn = vb[(it + 1) & 1];
-      BI_LAUNCH(k_bi_1, c->grid, A, C, r, rh, po, vo, pn, vn, st, p3, p1, G, it);
-      BI_LAUNCH(k_bi_2, c->grid, A, C, r, vn, sb, tb, st, p1, p2, G, it);
-      if (D == 2) k_bi_3<R, 2><<<G, kWG, 0, s>>>(N, A, x, r, rh, pn, sb, tb, st, p2, p3, G, it);
-      else k_bi_3<R, 3><<<G, kWG, 0, s>>>(N, A, x, r, rh, pn, sb, tb, st, p2, p3, G, it);
+      BI_LAUNCH(k_bi_1, c->grid, iA, C, r, rh, po, vo, pn, vn, st, p3, p1, G, it);
+      BI_LAUNCH(k_bi_2, c->grid, iA, C, r, vn, sb, tb, st, p1, p2, G, it);
+      if (D == 2) k_bi_3<R, 2><<<G, kWG, 0, s>>>(N, iA, x, r, rh, pn, sb, tb, st, p2, p3, G, it);
+      else k_bi_3<R, 3><<<G, kWG, 0, s>>>(N, iA, x, r, rh, pn, sb, tb, st, p2, p3, G, it);
     }
     BI_CHECK(0, it);
     if (int rc = check(c, "k_bi iteration")) return rc;
