@@ -526,13 +526,20 @@ k_bi_1(Grid g, const R* __restrict__ iA, const R* __restrict__ C, const R* __res
   for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
     int Fp[D], Fm[D];
     faces_of<D>(g, P, Fp, Fm);
+    // a face without a neighbour cell (a Dirichlet side) reads the cell itself with
+    // coefficient 0: every load is unconditional and its term adds exactly nothing
     R cp[D], cm[D], iAp[D], iAm[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      cp[j] = Fp[j] >= 0 ? coef_p<R, D, TRANS>(C, j, P, N) : R(0);
-      cm[j] = Fm[j] >= 0 ? coef_m<R, D, TRANS>(C, j, Fm[j], N) : R(0);
-      iAp[j] = Fp[j] >= 0 ? iA[Fp[j]] : R(0);
-      iAm[j] = Fm[j] >= 0 ? iA[Fm[j]] : R(0);
+      const bool hp = Fp[j] >= 0, hm = Fm[j] >= 0;
+      Fp[j] = hp ? Fp[j] : P;
+      Fm[j] = hm ? Fm[j] : P;
+      const R cpv = coef_p<R, D, TRANS>(C, j, P, N), cmv = coef_m<R, D, TRANS>(C, j, Fm[j], N);
+      const R ipv = iA[Fp[j]], imv = iA[Fm[j]];
+      cp[j] = hp ? cpv : R(0);
+      cm[j] = hm ? cmv : R(0);
+      iAp[j] = hp ? ipv : R(0);
+      iAm[j] = hm ? imv : R(0);
     }
 #pragma unroll
     for (int c = 0; c < D; ++c) {
@@ -543,8 +550,8 @@ k_bi_1(Grid g, const R* __restrict__ iA, const R* __restrict__ C, const R* __res
       R v = pP;   // A_P (p_P / A_P)
 #pragma unroll
       for (int j = 0; j < D; ++j) {
-        if (Fp[j] >= 0) v += cp[j] * pn(Fp[j]) * iAp[j];
-        if (Fm[j] >= 0) v += cm[j] * pn(Fm[j]) * iAm[j];
+        v += cp[j] * pn(Fp[j]) * iAp[j];
+        v += cm[j] * pn(Fm[j]) * iAm[j];
       }
       p_new[o + P] = pP;
       v_new[o + P] = v;
@@ -595,13 +602,20 @@ k_bi_2(Grid g, const R* __restrict__ iA, const R* __restrict__ C, const R* __res
   for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
     int Fp[D], Fm[D];
     faces_of<D>(g, P, Fp, Fm);
+    // a face without a neighbour cell (a Dirichlet side) reads the cell itself with
+    // coefficient 0: every load is unconditional and its term adds exactly nothing
     R cp[D], cm[D], iAp[D], iAm[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      cp[j] = Fp[j] >= 0 ? coef_p<R, D, TRANS>(C, j, P, N) : R(0);
-      cm[j] = Fm[j] >= 0 ? coef_m<R, D, TRANS>(C, j, Fm[j], N) : R(0);
-      iAp[j] = Fp[j] >= 0 ? iA[Fp[j]] : R(0);
-      iAm[j] = Fm[j] >= 0 ? iA[Fm[j]] : R(0);
+      const bool hp = Fp[j] >= 0, hm = Fm[j] >= 0;
+      Fp[j] = hp ? Fp[j] : P;
+      Fm[j] = hm ? Fm[j] : P;
+      const R cpv = coef_p<R, D, TRANS>(C, j, P, N), cmv = coef_m<R, D, TRANS>(C, j, Fm[j], N);
+      const R ipv = iA[Fp[j]], imv = iA[Fm[j]];
+      cp[j] = hp ? cpv : R(0);
+      cm[j] = hm ? cmv : R(0);
+      iAp[j] = hp ? ipv : R(0);
+      iAm[j] = hm ? imv : R(0);
     }
 #pragma unroll
     for (int c = 0; c < D; ++c) {
@@ -612,8 +626,8 @@ k_bi_2(Grid g, const R* __restrict__ iA, const R* __restrict__ C, const R* __res
       R tv = sP;
 #pragma unroll
       for (int j = 0; j < D; ++j) {
-        if (Fp[j] >= 0) tv += cp[j] * sv(Fp[j]) * iAp[j];
-        if (Fm[j] >= 0) tv += cm[j] * sv(Fm[j]) * iAm[j];
+        tv += cp[j] * sv(Fp[j]) * iAp[j];
+        tv += cm[j] * sv(Fm[j]) * iAm[j];
       }
       s[o + P] = sP;
       t[o + P] = tv;
