@@ -51,10 +51,12 @@ k_cg_init(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const BT
     const R b = (R)(sign * ((double)bsrc[P] - mu));
     const R xP = x[P];
     R Mx = R(0);
+    // a face without a neighbour cell reads the cell itself: its term is exactly zero
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      if (Fp[j] >= 0) Mx += Pf[(size_t)j * N + P] * (xP - x[Fp[j]]);
-      if (Fm[j] >= 0) Mx += Pf[(size_t)j * N + Fm[j]] * (xP - x[Fm[j]]);
+      const int Fpj = Fp[j] >= 0 ? Fp[j] : P, Fmj = Fm[j] >= 0 ? Fm[j] : P;
+      Mx += Pf[(size_t)j * N + P] * (xP - x[Fpj]);
+      Mx += Pf[(size_t)j * N + Fmj] * (xP - x[Fmj]);
     }
     const R rv = b - Mx;
     r[P] = rv;
@@ -400,11 +402,16 @@ k_bi_init(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __r
   for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
     int Fp[D], Fm[D];
     faces_of<D>(g, P, Fp, Fm);
+    // a face without a neighbour cell reads the cell itself with coefficient 0
     R cp[D], cm[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      cp[j] = Fp[j] >= 0 ? coef_p<R, D, TRANS>(C, j, P, N) : R(0);
-      cm[j] = Fm[j] >= 0 ? coef_m<R, D, TRANS>(C, j, Fm[j], N) : R(0);
+      const bool hp = Fp[j] >= 0, hm = Fm[j] >= 0;
+      Fp[j] = hp ? Fp[j] : P;
+      Fm[j] = hm ? Fm[j] : P;
+      const R cpv = coef_p<R, D, TRANS>(C, j, P, N), cmv = coef_m<R, D, TRANS>(C, j, Fm[j], N);
+      cp[j] = hp ? cpv : R(0);
+      cm[j] = hm ? cmv : R(0);
     }
     const R AP = A[P];
 #pragma unroll
@@ -413,8 +420,8 @@ k_bi_init(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __r
       R Cx = AP * xc[P];
 #pragma unroll
       for (int j = 0; j < D; ++j) {
-        if (Fp[j] >= 0) Cx += cp[j] * xc[Fp[j]];
-        if (Fm[j] >= 0) Cx += cm[j] * xc[Fm[j]];
+        Cx += cp[j] * xc[Fp[j]];
+        Cx += cm[j] * xc[Fm[j]];
       }
       const R bv = b[(size_t)c * N + P];
       const R rv = bv - Cx;
