@@ -207,19 +207,18 @@ k_h(Grid g, const R* __restrict__ JT, const R* __restrict__ A, const R* __restri
   R acc[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) acc[i] = bu[(size_t)i * N + P];
+  // a face without a neighbour cell (a Dirichlet side, whose value is in bu) reads the
+  // cell itself with coefficient 0: every load is unconditional, the term is zero
 #pragma unroll
   for (int j = 0; j < D; ++j) {
-    const int Fp = neighbour(g, c, P, j, 1);
-    if (Fp >= 0) {
-      const R cp = C[(size_t)j * N + P];
+    const int F0 = neighbour(g, c, P, j, 1), F1 = neighbour(g, c, P, j, 0);
+    const int Fp = F0 >= 0 ? F0 : P, Fm = F1 >= 0 ? F1 : P;
+    const R cpv = C[(size_t)j * N + P], cmv = C[(size_t)(D + j) * N + Fm];
+    const R cp = F0 >= 0 ? cpv : R(0), cm = F1 >= 0 ? cmv : R(0);
 #pragma unroll
-      for (int i = 0; i < D; ++i) acc[i] -= cp * u[(size_t)i * N + Fp];
-    }
-    const int Fm = neighbour(g, c, P, j, 0);
-    if (Fm >= 0) {
-      const R cm = C[(size_t)(D + j) * N + Fm];
-#pragma unroll
-      for (int i = 0; i < D; ++i) acc[i] -= cm * u[(size_t)i * N + Fm];
+    for (int i = 0; i < D; ++i) {
+      acc[i] -= cp * u[(size_t)i * N + Fp];
+      acc[i] -= cm * u[(size_t)i * N + Fm];
     }
   }
   const R iA = R(1) / A[P];
