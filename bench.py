@@ -9,12 +9,15 @@ HBM before the timed region.  Prints one JSON line.
     python bench.py [--gpus 1] [--steps 16] [--warmup 2] [--precision f32|mixed|f64]
                     [--workload channel96|channel192|cavity256|tgv32|cylinder5|pcg256]
                     [--no-cpu-baseline]
+    python bench.py --pcg-micro 200 [--workload channel256] [--precision f32|f64|mixed] [--precond mg|jacobi]
+    python bench.py --triad
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -75,6 +78,10 @@ def make_case(name):
         return cases.cylinder_oh()
     if name == "pcg256":
         return cases.channel(256, 256, 256)
+    m = re.fullmatch(r"channel(\d+)x(\d+)x(\d+)", name) or re.fullmatch(r"channel(\d+)", name)
+    if m:
+        dims = [int(g) for g in m.groups()]
+        return cases.channel(*(dims * 3 if len(dims) == 1 else dims))
     raise SystemExit("unknown workload " + name)
 
 
@@ -145,6 +152,150 @@ def time_extras(ctx, case, precision, u0, S):
     return out
 
 
+def pcg_roofline(ctx, dom, opts, tm, workload, precision):
+    """(roofline, pressure_cg) records from per-class kernel times tm = {class: (ms,
+    launches)}: algorithmic bytes per launch of each fine-grid kernel class (each stream
+    moved once) over its average duration; the roofline names the class with the
+    largest total time."""
+    N, d, es = ctx.N, ctx.dim, ctx.elem_bytes
+    if ctx.precision == "mixed":
+        es = 4   # the inner PCG iterations of the refinement run in FP32
+    mg = opts.pres.precond == 1 and bool(ctx.mg_levels)
+    quad = all(b[0] % 4 == 0 for b in dom.blocks)
+    nch = 2 ** d
+    line = mg and bool(ctx.mg_line_axis)
+    model = {
+        # Pf (d), operand (z, or r and Dinv), d_old -> d_new, q
+        "cg_stencil": ("k_cg_spmv_q" if quad else "k_cg_spmv", N * ((d + 4) if mg else (d + 5)) * es),
+        # x, r, d_new, q, Dinv -> x, r (Jacobi)
+        "cg_update": ("k_cg_update_q" if quad else "k_cg_update", N * 7 * es),
+        # multigrid: x, r, d_new, q, Dinv, Pf (d) -> x, r', y, level-1 residual
+        "cg_update_restrict": ("k_mg_down0uq" if quad else "k_mg_down0u", N * (d + 8) * es + (N // nch) * es),
+        # r, y, Pf (d) -> level-1 residual (first V-cycle of a solve)
+        "mg_down0": ("k_mg_down0", N * (d + 2) * es + (N // nch) * es),
+        # y, r, Dinv, Pf (d), level-1 correction -> z
+        "mg_up0": ("k_mg_up0_q" if quad else "k_mg_up0", N * (d + 4) * es + (N // nch) * es),
+    }
+    if line:
+        # line smoothing: the update kernel smooths (x, r, d_new, q, Dinv, Pf along the
+        # line -> x, r', y) and the restriction runs every iteration; the first
+        # pre-smoothing of a solve reads r, Dinv, Pf along the line and writes y
+        model["cg_update_restrict"] = ("k_line_pre", N * 9 * es)
+        model["mg_smooth0"] = ("k_line_pre", N * 4 * es)
+        model["mg_up0"] = ("k_line_post", N * (d + 4) * es + (N // nch) * es)
+        if quad and len(dom.blocks) == 1:
+            model["mg_down0"] = ("k_line_restrict", N * (d + 2) * es + (N // nch) * es)
+    per = {}
+    for k, (ms, n) in tm.items():
+        if n:
+            per[k] = {"avg_us": round(1e3 * ms / n, 3), "launches": n, "total_ms": round(ms, 3)}
+            if k in model:
+                per[k]["kernel"] = model[k][0]
+                per[k]["bytes_per_launch"] = model[k][1]
+                per[k]["GBps"] = round(model[k][1] / (ms / n * 1e-3) / 1e9, 1)
+    fine = [k for k in model if k in per]
+    if not fine:
+        return None, None
+    dom_k = max(fine, key=lambda k: per[k]["total_ms"])
+    kname, kbytes = model[dom_k]
+    avg = tm[dom_k][0] / tm[dom_k][1]
+    ach = kbytes / (avg * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": kname, "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
+            "traffic": counter_traffic(kname, workload, precision),
+            "avg_launch_us": round(avg * 1e3, 3), "bytes_per_launch": kbytes,
+            "launches": tm[dom_k][1]}
+    iters = tm["cg_stencil"][1]
+    it_ms = sum(ms for ms, _ in tm.values()) / max(iters, 1)
+    it_bytes = sum(model[k][1] * tm[k][1] for k in fine) / max(iters, 1)
+    pcg = {"preconditioner": "multigrid" if mg else "jacobi",
+           "fine_smoother": ("lines along %s" % "xyz"[ctx.mg_line_axis]) if mg and ctx.mg_line_axis else "point",
+           "mg_levels": [n for n, _ in ctx.mg_levels] if mg else [],
+           "iteration_us": round(1e3 * it_ms, 3),
+           "fine_bytes_per_iteration": int(it_bytes),
+           "GBps": round(it_bytes / (it_ms * 1e-3) / 1e9, 1),
+           "kernels": per}
+    return roof, pcg
+
+
+def pcg_micro(ctx, case, precision, workload, iters, precond):
+    """Pressure-CG bandwidth on the pressure system of corrector 1 of step 1: a fixed
+    number of PCG iterations (independent of convergence), timed as a whole and per
+    kernel class, then the same system solved from p = 0 to a relative residual of 1e-8."""
+    import torch
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=ctx.dtype, device="cuda")
+    u0, p0, S, ub = dev(case.u0), dev(case.p0), dev(case.S), dev(case.u_b)
+    nu = dev(np.array([case.nu]))
+    opts = ctx.default_opts()
+    opts.pres.precond = precond
+    sys_ = ctx.new_system()
+    ctx.assemble(sys_, u0, p0, nu, S, ub, case.dt)
+    us = u0.clone()
+    ctx.solve_velocity(sys_, us, opts.vel)
+    fixed = type(opts.pres)()
+    fixed.rtol, fixed.max_iter, fixed.check_every, fixed.precond = 1e-30, iters, iters, precond
+    fixed.inner_rtol, fixed.max_refine = 1e-30, 0
+    p = torch.zeros_like(p0)
+    out = {"mode": "pcg_micro", "workload": workload, "cells": ctx.N, "precision": precision,
+           "preconditioner": "multigrid" if precond == 1 else "jacobi"}
+    if precision != "mixed":
+        ctx.solve_pressure(sys_, us, ub, p0, p, fixed)     # warm-up (graph recording, setup)
+        torch.cuda.synchronize()
+        reps = 3
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            p.zero_()
+            inf = ctx.solve_pressure(sys_, us, ub, p0, p, fixed)
+        b.record()
+        torch.cuda.synchronize()
+        out["fixed_iters"] = inf["iters"]
+        out["fixed_solve_ms"] = round(a.elapsed_time(b) / reps, 4)
+        ctx.set_timing(True)
+        p.zero_()
+        ctx.solve_pressure(sys_, us, ub, p0, p, fixed)
+        torch.cuda.synchronize()
+        tm = ctx.get_timing()
+        ctx.set_timing(False)
+        roof, pcg = pcg_roofline(ctx, case.domain, opts, tm, workload, precision)
+        out["roofline"], out["pressure_cg"] = roof, pcg
+    # to a relative residual of 1e-8 from p = 0
+    tol = type(opts.pres)()
+    tol.rtol, tol.max_iter, tol.check_every, tol.precond = 1e-8, 20000, 4, precond
+    tol.inner_rtol, tol.max_refine = opts.pres.inner_rtol, opts.pres.max_refine
+    p.zero_()
+    ctx.solve_pressure(sys_, us, ub, p0, p, tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.zero_()
+    inf = ctx.solve_pressure(sys_, us, ub, p0, p, tol)
+    torch.cuda.synchronize()
+    out["solve_1e-8"] = {"ms": round(1e3 * (time.perf_counter() - t0), 3), "iters": inf["iters"],
+                         "refinements": inf["refinements"], "rel_residual": inf["rel_residual"]}
+    return out
+
+
+def stream_triad(gib=4.0, reps=20):
+    """STREAM-type triad a = b + s c on float32 arrays of `gib` GiB each (torch's
+    elementwise kernel): the achievable HBM ceiling beside the 8 TB/s peak."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    b = torch.ones(n, dtype=torch.float32, device="cuda")
+    c = torch.ones(n, dtype=torch.float32, device="cuda")
+    a = torch.empty_like(b)
+    torch.add(b, c, alpha=3.0, out=a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.add(b, c, alpha=3.0, out=a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"mode": "stream_triad", "bytes_per_call": 3 * n * 4, "ms": round(ms, 4),
+            "GBps": round(3 * n * 4 / (ms * 1e-3) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +310,12 @@ def main():
     ap.add_argument("--kernel-digest", action="store_true", help="print the CG kernel source digest")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of 256 MiB (counter calibration)")
+    ap.add_argument("--pcg-micro", type=int, default=0, metavar="ITERS",
+                    help="only the pressure-CG microbenchmark: ITERS fixed PCG iterations on the "
+                         "corrector-1 system of step 1, then the same system solved to 1e-8")
+    ap.add_argument("--precond", default="mg", choices=["mg", "jacobi"],
+                    help="pressure preconditioner of --pcg-micro")
+    ap.add_argument("--triad", action="store_true", help="only the STREAM-type triad ceiling")
     ap.add_argument("--pres-rtol", type=float, default=None,
                     help="pressure tolerance (equal-residual comparisons of the precision forms)")
     args = ap.parse_args()
@@ -187,9 +344,16 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration": {"read_bytes": x.numel() * 4, "write_bytes": y.numel() * 4}}))
         return
+    if args.triad:
+        print(json.dumps(stream_triad()), flush=True)
+        return
     case = make_case(args.workload)
     dom = case.domain
     ctx = api.Context(dom, args.precision)
+    if args.pcg_micro:
+        print(json.dumps(pcg_micro(ctx, case, args.precision, args.workload, args.pcg_micro,
+                                   1 if args.precond == "mg" else 0)), flush=True)
+        return
     dt_t = ctx.dtype
     N, d = ctx.N, ctx.dim
     log("workload %s N=%d precision %s dt=%.3e" % (args.workload, N, args.precision, case.dt))
@@ -279,62 +443,7 @@ def main():
         torch.cuda.synchronize()
         tm = ctx.get_timing()
         ctx.set_timing(False)
-        es = ctx.elem_bytes
-        mg = opts.pres.precond == 1 and bool(ctx.mg_levels)
-        quad = all(b[0] % 4 == 0 for b in dom.blocks)
-        nch = 2 ** d
-        # algorithmic bytes per launch of each fine-grid kernel class (each stream once)
-        line = mg and bool(ctx.mg_line_axis)
-        model = {
-            # Pf (d), operand (z, or r and Dinv), d_old -> d_new, q
-            "cg_stencil": ("k_cg_spmv_q" if quad else "k_cg_spmv", N * ((d + 4) if mg else (d + 5)) * es),
-            # x, r, d_new, q, Dinv -> x, r (Jacobi)
-            "cg_update": ("k_cg_update_q" if quad else "k_cg_update", N * 7 * es),
-            # multigrid: x, r, d_new, q, Dinv, Pf (d) -> x, r', y, level-1 residual
-            "cg_update_restrict": ("k_mg_down0uq" if quad else "k_mg_down0u", N * (d + 8) * es + (N // nch) * es),
-            # r, y, Pf (d) -> level-1 residual (first V-cycle of a solve)
-            "mg_down0": ("k_mg_down0", N * (d + 2) * es + (N // nch) * es),
-            # y, r, Dinv, Pf (d), level-1 correction -> z
-            "mg_up0": ("k_mg_up0_q" if quad else "k_mg_up0", N * (d + 4) * es + (N // nch) * es),
-        }
-        if line:
-            # line smoothing: the update kernel smooths (x, r, d_new, q, Dinv, Pf along the
-            # line -> x, r', y) and the restriction runs every iteration; the first
-            # pre-smoothing of a solve reads r, Dinv, Pf along the line and writes y
-            model["cg_update_restrict"] = ("k_line_pre", N * 9 * es)
-            model["mg_smooth0"] = ("k_line_pre", N * 4 * es)
-            model["mg_up0"] = ("k_line_post", N * (d + 4) * es + (N // nch) * es)
-            if quad and len(dom.blocks) == 1:
-                model["mg_down0"] = ("k_line_restrict", N * (d + 2) * es + (N // nch) * es)
-        per = {}
-        for k, (ms, n) in tm.items():
-            if n:
-                per[k] = {"avg_us": round(1e3 * ms / n, 3), "launches": n, "total_ms": round(ms, 3)}
-                if k in model:
-                    per[k]["kernel"] = model[k][0]
-                    per[k]["bytes_per_launch"] = model[k][1]
-                    per[k]["GBps"] = round(model[k][1] / (ms / n * 1e-3) / 1e9, 1)
-        fine = [k for k in model if k in per]
-        if fine:
-            dom_k = max(fine, key=lambda k: per[k]["total_ms"])
-            kname, kbytes = model[dom_k]
-            avg = tm[dom_k][0] / tm[dom_k][1]
-            ach = kbytes / (avg * 1e-3) / 1e9
-            roof = {"bound": "hbm", "kernel": kname, "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
-                    "traffic": counter_traffic(kname, args.workload, args.precision),
-                    "avg_launch_us": round(avg * 1e3, 3), "bytes_per_launch": kbytes,
-                    "launches": tm[dom_k][1]}
-            iters = tm["cg_stencil"][1]
-            it_ms = sum(ms for ms, _ in tm.values()) / max(iters, 1)
-            it_bytes = sum(model[k][1] * tm[k][1] for k in fine) / max(iters, 1)
-            pcg = {"preconditioner": "multigrid" if mg else "jacobi",
-                   "fine_smoother": ("lines along %s" % "xyz"[ctx.mg_line_axis]) if mg and ctx.mg_line_axis else "point",
-                   "mg_levels": [n for n, _ in ctx.mg_levels] if mg else [],
-                   "iteration_us": round(1e3 * it_ms, 3),
-                   "fine_bytes_per_iteration": int(it_bytes),
-                   "GBps": round(it_bytes / (it_ms * 1e-3) / 1e9, 1),
-                   "kernels": per}
+        roof, pcg = pcg_roofline(ctx, dom, opts, tm, args.workload, args.precision)
         log("timing %s" % tm)
 
     extras = None

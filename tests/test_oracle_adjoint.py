@@ -6,7 +6,9 @@
 * central finite differences on a larger grid;
 * the step is affine in the source S, so a finite change of S is predicted exactly
   by the S-gradient;
-* a two-step rollout chains step gradients.
+* a two-step rollout chains step gradients;
+* the gradient-path flags of Sec. 2.4: each skipped adjoint solve equals the complex
+  step of a forward whose corresponding solution is frozen (a stop-gradient).
 """
 import numpy as np
 import pytest
@@ -128,3 +130,59 @@ def test_gradient_path_flags_are_partial_sums():
     g2 = w / rec.A
     g1 = -np.stack([rec.H.T @ g2[i] for i in range(2)]) / rec.A
     assert np.max(np.abs(none["S"] - (g2 + g1))) < 1e-14 * np.max(np.abs(g2))
+
+
+def _frozen_solve_step(monkeypatch, velocity, pressure):
+    """The forward oracle with the chosen linear solves taken as constants under the
+    complex step: the solve is applied to the real parts of its operator and right-hand
+    side only, so its solution carries no imaginary part (a stop-gradient)."""
+    import oracle.piso as op
+    sv, spr = op.solve_velocity, op.solve_pressure
+    if velocity:
+        monkeypatch.setattr(op, "solve_velocity",
+                            lambda H, A, b, mode="direct", rtol=1e-13, x0=None, lu=None:
+                            sv(H.real, A.real, b.real, mode, rtol))
+    if pressure:
+        monkeypatch.setattr(op, "solve_pressure",
+                            lambda Pm, rhs, mode="direct", rtol=1e-13, x0=None:
+                            spr(Pm.real, rhs.real, mode, rtol))
+    return op.step
+
+
+@pytest.mark.parametrize("idx", range(len(CASES)))
+@pytest.mark.parametrize("flags", [1, 2, 3])
+def test_gradient_path_flags_complex_step(monkeypatch, idx, flags):
+    """Sec. 2.4 (eq. jnone): skipping the backward velocity solve (flag 1) is the gradient
+    of the step with u* held constant, skipping the backward pressure solves (flag 2) the
+    gradient with p* and p** held constant.  Pinned by the complex step of a forward in
+    which exactly those solutions are frozen."""
+    case = CASES[idx]()
+    geo = Geometry(case.domain)
+    u, p, S, ub, nu = _state(case, 300 + idx)
+    rng = np.random.default_rng(400 + idx)
+    rec = step(geo, u, p, nu, S, case.dt, ub)
+    wu = rng.standard_normal(u.shape)
+    wp = rng.standard_normal(p.shape)
+    g = step_vjp(geo, rec, wu, wp, skip_velocity_solve=bool(flags & 1), skip_pressure_solve=bool(flags & 2))
+    v = [rng.standard_normal(x.shape) for x in (u, p, S, ub)] + [case.nu * rng.standard_normal(nu.shape)]
+    frozen = _frozen_solve_step(monkeypatch, bool(flags & 1), bool(flags & 2))
+    h = 1e-30
+    rc = frozen(geo, u + 1j * h * v[0], p + 1j * h * v[1], nu + 1j * h * v[4], S + 1j * h * v[2],
+                case.dt, ub + 1j * h * v[3])
+    jv = (np.sum(wu * rc.u2.imag) + np.sum(wp * rc.p2.imag)) / h
+    vjp = (np.sum(g["u_n"] * v[0]) + np.sum(g["p_n"] * v[1]) + np.sum(g["S"] * v[2])
+           + np.sum(g["u_b"] * v[3]) + np.sum(g["nu"] * v[4]))
+    assert abs(jv - vjp) <= 1e-12 * abs(jv)
+    # the frozen paths carry part of the full gradient, so the pin is not vacuous
+    full = step_vjp(geo, rec, wu, wp)
+    vjp_full = (np.sum(full["u_n"] * v[0]) + np.sum(full["p_n"] * v[1]) + np.sum(full["S"] * v[2])
+                + np.sum(full["u_b"] * v[3]) + np.sum(full["nu"] * v[4]))
+    assert abs(vjp_full - vjp) > 1e-6 * abs(vjp_full)
+    # and each input's gradient on its own (a mistake confined to one input's path)
+    for k, key in enumerate(("u_n", "p_n", "S", "u_b", "nu")):
+        args = [u, p, S, ub, nu]
+        args = [a + 1j * h * v[q] if q == k else a for q, a in enumerate(args)]
+        r1 = frozen(geo, args[0], args[1], args[4], args[2], case.dt, args[3])
+        jv_k = (np.sum(wu * r1.u2.imag) + np.sum(wp * r1.p2.imag)) / h
+        vjp_k = np.sum(g[key] * v[k])
+        assert abs(jv_k - vjp_k) <= 1e-12 * max(abs(jv), 1e-300), key
