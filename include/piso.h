@@ -27,8 +27,8 @@
  *   - Dirichlet boundary values u_b are [d][NB]: Dirichlet segments in the order they
  *     were given to piso_create, faces of a segment in tangential order (first
  *     tangential axis fastest).
- *   - element type of every field, intermediate and gradient: double for PISO_F64,
- *     float for PISO_F32 and PISO_MIXED.
+ *   - element type of every field, intermediate and gradient: float for PISO_F32,
+ *     double for PISO_F64 and PISO_MIXED.
  *
  * Pointers: "device" pointers must point to memory of the device that was current at
  * piso_create; "host" pointers are read during the call only.  The caller owns every
@@ -59,8 +59,11 @@ typedef struct piso_ctx piso_ctx;
 typedef enum {
   PISO_F64 = 0,    /* all storage and arithmetic in double */
   PISO_F32 = 1,    /* float storage and stencil arithmetic; Krylov dot products in double */
-  PISO_MIXED = 2   /* as F32, plus a double residual and iterative refinement of the
-                      pressure solve (double pressure accumulator, float inner PCG) */
+  PISO_MIXED = 2   /* double storage and double stencil arithmetic outside the Krylov
+                      iterations; both linear solves run as iterative refinement: the
+                      residual of the double system in double, a float inner Krylov solve
+                      (float operator copies, float vectors, double dot products) for the
+                      correction, the correction added in double */
 } piso_precision;
 
 typedef enum {
@@ -112,12 +115,14 @@ typedef enum {
 
 typedef struct {
   double rtol;                     /* stop when ||b - M x||_2 <= rtol ||b||_2 (per component) */
-  int32_t max_iter;                /* Krylov iterations (MIXED pressure: inner iterations per sweep) */
+  int32_t max_iter;                /* Krylov iterations (MIXED: inner iterations per sweep) */
   int32_t check_every;             /* iterations between convergence read-backs */
-  double inner_rtol;               /* MIXED pressure only: smallest inner float PCG tolerance;
+  double inner_rtol;               /* MIXED only: smallest inner float Krylov tolerance;
                                       each sweep asks for the residual reduction still
                                       needed (with a factor-2 margin), but not below this */
-  int32_t max_refine;              /* MIXED pressure only: refinement sweeps */
+  int32_t max_refine;              /* MIXED only: refinement sweeps (0: the initial guess is
+                                      returned with PISO_NOT_CONVERGED unless it already
+                                      meets rtol) */
   int32_t precond;                 /* piso_precond; PISO_PRECOND_MG is accepted for the pressure
                                       only (PISO_E_ARG for the velocity solve) */
 } piso_solve_opts;
@@ -211,8 +216,9 @@ int piso_mg_info(const piso_ctx* ctx, int32_t* n_levels, int64_t* cells, int32_t
  * grid allows them. */
 int piso_mg_smoother(const piso_ctx* ctx, int32_t* line_axis);
 
-/* Default options for a precision: vel rtol 1e-10 (F64) / 1e-7, Jacobi; pres rtol 1e-10
- * (F64), 1e-6 (F32), 1e-8 (MIXED, inner floor 1e-5), multigrid-preconditioned, read back every
+/* Default options for a precision: vel rtol 1e-7 (F32) / 1e-10 (F64, MIXED), Jacobi;
+ * pres rtol 1e-10 (F64), 1e-6 (F32), 1e-8 (MIXED), multigrid-preconditioned; MIXED inner
+ * floors 1e-5 and at most 20 (pressure) / 10 (velocity) refinement sweeps; read back every
  * 4 iterations; 2 correctors, grad_p_in_predictor = 1. */
 void piso_default_step_opts(int32_t precision, piso_step_opts* opts);
 

@@ -54,7 +54,7 @@ class Context:
         self.precision = precision
         self.prec = _PREC[precision]
         self.dim = int(domain.dim)
-        self.dtype = torch.float64 if self.prec == L.PISO_F64 else torch.float32
+        self.dtype = torch.float32 if self.prec == L.PISO_F32 else torch.float64   # MIXED stores double
         cells = np.array([list(b) for b in domain.blocks], dtype=np.int32).reshape(-1)
         sides = (L.SideDesc * len(domain.sides))()
         for q, s in enumerate(domain.sides):
@@ -76,6 +76,7 @@ class Context:
         if rc != 0:
             raise PisoError(rc, self.lib.piso_create_error().decode())
         self.h = h
+        self._adj_owner = None   # the rollout (or step) whose backward wrote the warm-start history
         self.device = torch.device("cuda", torch.cuda.current_device())
         n, nb, tb, eb = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
         no = C.c_int32()
@@ -201,6 +202,7 @@ class Context:
     def adjoint_reset(self):
         """Start the next step_backward's adjoint pressure solves from zero (see
         adjoint_warm_start in the step options)."""
+        self._adj_owner = None
         return self._check(self.lib.piso_adjoint_reset(self.h), "piso_adjoint_reset")
 
     # ---------------------------------------------------------------- fine-grained calls
@@ -362,17 +364,31 @@ class Context:
 
 # ===================================================================== autograd
 
+def _adjoint_owner(pctx: Context, owner):
+    """Before a backward step: the context's adjoint warm-start history (the adjoint
+    pressure solutions of its last backward step) is kept only for the backward pass
+    that wrote it.  Every rollout, and every stand-alone step, is its own owner; the
+    first backward step of another owner clears the history, so gradients depend on
+    the rollout (or step) alone, whatever was differentiated before and whichever of
+    its states the loss uses."""
+    if pctx._adj_owner is not owner:
+        pctx.adjoint_reset()
+        pctx._adj_owner = owner
+
+
 class PisoStep(torch.autograd.Function):
     """One differentiable PISO step: (u, p, S, nu, u_b) -> (u^{n+1}, p^{n+1}).
 
     The forward keeps a tape of the intermediates; the backward runs the hand-written
-    adjoint (transposed solves and per-operation adjoints)."""
+    adjoint (transposed solves and per-operation adjoints).  `owner` groups the steps
+    of one rollout for the adjoint warm start (None: a stand-alone step)."""
 
     @staticmethod
-    def forward(fctx, pctx: Context, opts, dt, u, p, S, nu, u_b):
+    def forward(fctx, pctx: Context, opts, dt, owner, u, p, S, nu, u_b):
         tape = pctx.new_tape()
         u1, p1 = pctx.step(u, p, nu, S, u_b, dt, opts, tape=tape)
         fctx.pctx, fctx.opts, fctx.dt = pctx, opts, dt
+        fctx.owner = owner if owner is not None else object()
         fctx.save_for_backward(tape, u, p, nu, u_b if u_b is not None else torch.empty(0))
         fctx.has_ub = u_b is not None
         return u1, p1
@@ -381,26 +397,10 @@ class PisoStep(torch.autograd.Function):
     def backward(fctx, du1, dp1):
         tape, u, p, nu, u_b = fctx.saved_tensors
         pctx = fctx.pctx
+        _adjoint_owner(pctx, fctx.owner)
         g = pctx.step_backward(tape, u, p, nu, u_b if fctx.has_ub else None, fctx.dt, du1, dp1, fctx.opts)
-        return (None, None, None, g["u"], g["p"], g["S"], g["nu"].reshape(nu.shape),
+        return (None, None, None, None, g["u"], g["p"], g["S"], g["nu"].reshape(nu.shape),
                 g["u_b"] if fctx.has_ub else None)
-
-
-class _AdjointReset(torch.autograd.Function):
-    """Identity on the final state of a rollout whose backward runs before any step's
-    backward of that rollout: it clears the context's adjoint warm-start history, so the
-    rollout's gradients depend on the rollout alone (e.g. bit-identical with and without
-    checkpointing)."""
-
-    @staticmethod
-    def forward(fctx, pctx: Context, *xs):
-        fctx.pctx = pctx
-        return tuple(x.view_as(x) for x in xs)
-
-    @staticmethod
-    def backward(fctx, *gs):
-        fctx.pctx.adjoint_reset()
-        return (None,) + tuple(gs)
 
 
 class _Segment(torch.autograd.Function):
@@ -408,11 +408,11 @@ class _Segment(torch.autograd.Function):
     (step checkpointing): memory O(1 state + k tapes) per segment."""
 
     @staticmethod
-    def forward(fctx, pctx: Context, opts, dt, k, u, p, S, nu, u_b):
+    def forward(fctx, pctx: Context, opts, dt, k, owner, u, p, S, nu, u_b):
         uu, pp = u, p
         for _ in range(k):
             uu, pp = pctx.step(uu, pp, nu, S, u_b, dt, opts)
-        fctx.pctx, fctx.opts, fctx.dt, fctx.k = pctx, opts, dt, k
+        fctx.pctx, fctx.opts, fctx.dt, fctx.k, fctx.owner = pctx, opts, dt, k, owner
         fctx.has_ub = u_b is not None
         fctx.save_for_backward(u, p, S, nu, u_b if u_b is not None else torch.empty(0))
         return uu, pp
@@ -433,6 +433,7 @@ class _Segment(torch.autograd.Function):
         dnu = torch.zeros_like(nu.reshape(-1))
         dub = torch.zeros_like(ub) if ub is not None else None
         gu, gp = du, dp
+        _adjoint_owner(pctx, fctx.owner)
         for q in range(k - 1, -1, -1):
             un, pn = states[q]
             g = pctx.step_backward(tapes[q], un, pn, nu, ub, dt, gu, gp, opts)
@@ -442,7 +443,7 @@ class _Segment(torch.autograd.Function):
             if dub is not None:
                 dub += g["u_b"]
             tapes[q] = None
-        return None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), dub
+        return None, None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), dub
 
 
 class OutflowUpdate(torch.autograd.Function):
@@ -466,12 +467,13 @@ class _OutflowSegment(torch.autograd.Function):
     values: (u, p, S, nu, u_b) -> (u^{n+k}, p^{n+k}, u_b^{n+k})."""
 
     @staticmethod
-    def forward(fctx, pctx: Context, opts, dt, k, mask, u_m, u, p, S, nu, u_b):
+    def forward(fctx, pctx: Context, opts, dt, k, owner, mask, u_m, u, p, S, nu, u_b):
         uu, pp, bb = u, p, u_b
         for _ in range(k):
             bb = pctx.outflow_update(uu, bb, mask, u_m, dt)
             uu, pp = pctx.step(uu, pp, nu, S, bb, dt, opts)
         fctx.pctx, fctx.opts, fctx.dt, fctx.k, fctx.mask, fctx.u_m = pctx, opts, dt, k, mask, u_m
+        fctx.owner = owner
         fctx.save_for_backward(u, p, S, nu, u_b)
         return uu, pp, bb
 
@@ -493,6 +495,7 @@ class _OutflowSegment(torch.autograd.Function):
         dnu = torch.zeros_like(nu.reshape(-1))
         gu, gp = du, dp
         gb = dbb.contiguous() if dbb is not None else torch.zeros_like(u_b)
+        _adjoint_owner(pctx, fctx.owner)
         for q in range(k - 1, -1, -1):
             un, pn, bprev = states[q]
             g = pctx.step_backward(tapes[q], un, pn, nu, used[q], dt, gu, gp, opts)
@@ -502,7 +505,7 @@ class _OutflowSegment(torch.autograd.Function):
             gb, gu = pctx.outflow_update_backward(un, bprev, mask, u_m, dt, gb_used, du=g["u"])
             gp = g["p"]
             tapes[q] = None
-        return None, None, None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), gb
+        return None, None, None, None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), gb
 
 
 class PlaneStatistics(torch.autograd.Function):
@@ -560,7 +563,7 @@ def divfree_gradient_hook(pctx: Context, S, lam, opts=None):
 
 def step(pctx: Context, u, p, S, nu, u_b, dt, opts=None):
     """Differentiable single step (keeps its tape until backward)."""
-    return PisoStep.apply(pctx, opts if opts is not None else pctx.default_opts(), dt, u, p, S, nu, u_b)
+    return PisoStep.apply(pctx, opts if opts is not None else pctx.default_opts(), dt, None, u, p, S, nu, u_b)
 
 
 def rollout(pctx: Context, u0, p0, S, nu, u_b, dt, n_steps: int, checkpoint_every: int = 0, opts=None,
@@ -569,10 +572,16 @@ def rollout(pctx: Context, u0, p0, S, nu, u_b, dt, n_steps: int, checkpoint_ever
     stores only the state at the start of each k-step segment and recomputes the
     segment's tapes in the backward.  warmup steps run first without a tape.
 
+    return_all: the list of states after every step (k = 0), or after every segment
+    (k > 0: the states inside a segment are not kept, only its last one).  The adjoint
+    pressure solves of the rollout's backward warm-start from each other but never
+    from another rollout's (or step's) backward.
+
     outflow = (mask, u_m): before every step the Dirichlet values of the masked faces
     are advanced by the advective outflow update (the boundary values then become part
     of the state; the result gains a third entry, the final u_b)."""
     o = opts if opts is not None else pctx.default_opts()
+    owner = object()   # the backward steps of this rollout share the adjoint warm start
     u, p, ub = u0, p0, u_b
     if outflow is not None:
         mask, u_m = outflow
@@ -590,29 +599,21 @@ def rollout(pctx: Context, u0, p0, S, nu, u_b, dt, n_steps: int, checkpoint_ever
         if outflow is not None:
             if checkpoint_every > 0:
                 k = min(checkpoint_every, n_steps - done)
-                u, p, ub = _OutflowSegment.apply(pctx, o, dt, k, mask, u_m, u, p, S, nu, ub)
+                u, p, ub = _OutflowSegment.apply(pctx, o, dt, k, owner, mask, u_m, u, p, S, nu, ub)
                 done += k
             else:
                 ub = OutflowUpdate.apply(pctx, mask, u_m, dt, u, ub)
-                u, p = PisoStep.apply(pctx, o, dt, u, p, S, nu, ub)
+                u, p = PisoStep.apply(pctx, o, dt, owner, u, p, S, nu, ub)
                 done += 1
         elif checkpoint_every > 0:
             k = min(checkpoint_every, n_steps - done)
-            u, p = _Segment.apply(pctx, o, dt, k, u, p, S, nu, ub)
+            u, p = _Segment.apply(pctx, o, dt, k, owner, u, p, S, nu, ub)
             done += k
         else:
-            u, p = PisoStep.apply(pctx, o, dt, u, p, S, nu, ub)
+            u, p = PisoStep.apply(pctx, o, dt, owner, u, p, S, nu, ub)
             done += 1
         if return_all:
             traj.append((u, p) if outflow is None else (u, p, ub))
-    if n_steps > 0 and torch.is_grad_enabled():
-        last = _AdjointReset.apply(pctx, u, p) if outflow is None else _AdjointReset.apply(pctx, u, p, ub)
-        if outflow is None:
-            u, p = last
-        else:
-            u, p, ub = last
-        if return_all:
-            traj[-1] = tuple(last)
     if return_all:
         return traj
     return (u, p) if outflow is None else (u, p, ub)

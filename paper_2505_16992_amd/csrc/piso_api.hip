@@ -237,12 +237,15 @@ int upload_metrics(piso_ctx* c, const piso_domain_desc* d) {
 
 int alloc_workspaces(piso_ctx* c) {
   const size_t N = c->N, D = c->dim, e = c->esz;
+  const size_t mx = c->prec == PISO_MIXED ? 1 : 0;   // the MIXED refinement buffers
   struct { void** p; size_t bytes; } L[] = {
       {&c->w_A, N * e}, {&c->w_C, 2 * D * N * e}, {&c->w_bu, D * N * e}, {&c->w_b, D * N * e},
       {&c->w_Pf, D * N * e}, {&c->w_Dinv, N * e}, {&c->w_h, D * N * e}, {&c->w_W, D * N * e},
       {&c->w_rhs, N * 8}, {&c->w_us, D * N * e}, {&c->w_u1, D * N * e}, {&c->w_p1, N * e},
       {&c->w_h1, D * N * e}, {&c->w_tg, D * D * N * e}, {&c->w_tgp, D * N * e},
-      {(void**)&c->w_rhs64, N * 8}, {(void**)&c->w_p64, N * 8}, {&c->m_r32, N * 4}, {&c->m_e32, N * 4},
+      {&c->m_r32, mx * D * N * 4}, {&c->m_e32, mx * D * N * 4}, {&c->x_Pf32, mx * D * N * 4},
+      {&c->x_Dinv32, mx * N * 4}, {&c->x_A32, mx * N * 4}, {&c->x_C32, mx * 2 * D * N * 4},
+      {(void**)&c->mix_scal, 8 * sizeof(double)},
       {&c->k_r, N * e}, {&c->k_r2, N * e}, {&c->k_q, N * e}, {&c->k_d0, N * e}, {&c->k_d1, N * e},
       {&c->g_Pf, D * N * e}, {&c->g_Dinv, N * e}, {&c->g_x, N * e},
       {&c->b_r, D * N * e}, {&c->b_rh, D * N * e}, {&c->b_p0, D * N * e}, {&c->b_p1, D * N * e},
@@ -312,17 +315,6 @@ int do_pressure(piso_ctx* c, hipStream_t s, const R* A, const R* C, const R* bu,
                 piso_solve_info* info) {
   R* W = (R*)c->w_W;
   if (int rc = launch_h<R>(c, s, A, C, bu, u_in, h, W)) return rc;
-  if (c->prec == PISO_MIXED) {
-    if constexpr (std::is_same<R, float>::value) {
-      if (int rc = launch_div<float, double>(c, s, W, ub, A, p_lag, c->w_rhs64, c->mean)) return rc;
-      if (rhs_out)
-        if (int rc = launch_copy<double, float>(c, s, c->w_rhs64, rhs_out, c->N)) return rc;
-      if (int rc = launch_copy<float, double>(c, s, p, c->w_p64, c->N)) return rc;
-      if (int rc = pressure_solve_mixed(c, s, Pf, Dinv, c->w_rhs64, c->mean, c->w_p64, o, info)) return rc;
-      return launch_copy<double, float>(c, s, c->w_p64, p, c->N);
-    }
-    return fail(c, PISO_E_ARG, "MIXED requires float storage");
-  }
   R* rhs = rhs_out ? rhs_out : (R*)c->w_rhs;
   if (int rc = launch_div<R, R>(c, s, W, ub, A, p_lag, rhs, c->mean)) return rc;
   return pressure_solve<R, R>(c, s, Pf, Dinv, rhs, c->mean, p, o, info);
@@ -338,25 +330,6 @@ int do_pressure_adjoint(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, 
   const bool warm = hist >= 0 && c->lam_hist_valid[hist];
   piso_solve_info tmp{};
   piso_solve_info* inf = info ? info : &tmp;
-  if (c->prec == PISO_MIXED) {
-    if constexpr (std::is_same<R, float>::value) {
-      if (int rc = launch_copy<float, double>(c, s, g, c->w_rhs64, N)) return rc;
-      if (int rc = launch_sum<double, double>(c, s, c->w_rhs64, N, 1.0 / N, c->mean)) return rc;
-      if (warm)
-        PISO_HIP(c, hipMemcpyAsync(c->w_p64, c->a_lam_hist[hist], sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-      else
-        PISO_HIP(c, hipMemsetAsync(c->w_p64, 0, sizeof(double) * N, s));
-      const int rc = pressure_solve_mixed(c, s, Pf, Dinv, c->w_rhs64, c->mean, c->w_p64, o, inf);
-      if (rc < 0) return rc;
-      if (hist >= 0 && inf->status >= 0) {
-        PISO_HIP(c, hipMemcpyAsync(c->a_lam_hist[hist], c->w_p64, sizeof(double) * N, hipMemcpyDeviceToDevice, s));
-        c->lam_hist_valid[hist] = true;
-      }
-      if (int rc2 = launch_copy<double, float>(c, s, c->w_p64, lam, N)) return rc2;
-      return rc;
-    }
-    return fail(c, PISO_E_ARG, "MIXED requires float storage");
-  }
   if (int rc = launch_sum<R, double>(c, s, g, N, 1.0 / N, c->mean)) return rc;
   if (warm)
     PISO_HIP(c, hipMemcpyAsync(lam, c->a_lam_hist[hist], sizeof(R) * N, hipMemcpyDeviceToDevice, s));
@@ -390,20 +363,9 @@ int do_divfree(piso_ctx* c, hipStream_t s, const R* S, const R* gS, double lam, 
   if (int rc = launch_pcoef<R>(c, s, A, Pf, Dinv)) return rc;
   if (int rc = launch_jt_field<R>(c, s, S, W)) return rc;
   PISO_HIP(c, hipMemsetAsync(plag, 0, sizeof(R) * N, s));
-  if (c->prec == PISO_MIXED) {
-    if constexpr (std::is_same<R, float>::value) {
-      if (int rc = launch_div<float, double>(c, s, W, zb, A, plag, c->w_rhs64, c->mean)) return rc;
-      PISO_HIP(c, hipMemsetAsync(c->w_p64, 0, sizeof(double) * N, s));
-      if (int rc = pressure_solve_mixed(c, s, Pf, Dinv, c->w_rhs64, c->mean, c->w_p64, o, info)) return rc;
-      if (int rc = launch_copy<double, float>(c, s, c->w_p64, p, N)) return rc;
-    } else {
-      return fail(c, PISO_E_ARG, "MIXED requires float storage");
-    }
-  } else {
-    PISO_HIP(c, hipMemsetAsync(p, 0, sizeof(R) * N, s));
-    if (int rc = launch_div<R, R>(c, s, W, zb, A, plag, (R*)c->w_rhs, c->mean)) return rc;
-    if (int rc = pressure_solve<R, R>(c, s, Pf, Dinv, (const R*)c->w_rhs, c->mean, p, o, info)) return rc;
-  }
+  PISO_HIP(c, hipMemsetAsync(p, 0, sizeof(R) * N, s));
+  if (int rc = launch_div<R, R>(c, s, W, zb, A, plag, (R*)c->w_rhs, c->mean)) return rc;
+  if (int rc = pressure_solve<R, R>(c, s, Pf, Dinv, (const R*)c->w_rhs, c->mean, p, o, info)) return rc;
   if (lam == 0.0) return launch_copy<R, R>(c, s, gS, g_out, c->dim * N);
   if (int rc = launch_fill<R>(c, s, N, (R)(-1.0 / lam), A)) return rc;
   return launch_correct<R>(c, s, A, gS, p, Pf, nullptr, g_out, nullptr);
@@ -581,17 +543,6 @@ int do_step_backward(piso_ctx* c, hipStream_t s, const void* tape, const R* u_n,
   return st;
 }
 
-struct DevGuard {
-  int prev = -1;
-  explicit DevGuard(int dev) {
-    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
-    else prev = -1;
-  }
-  ~DevGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
-
 }  // namespace
 
 // ====================================================================== C-ABI
@@ -624,12 +575,12 @@ int piso_create(const piso_domain_desc* desc, int32_t precision, piso_ctx** out)
   c->dim = desc->dim;
   c->nblocks = desc->n_blocks;
   c->prec = precision;
-  c->esz = precision == PISO_F64 ? 8 : 4;
+  c->esz = precision == PISO_F32 ? 4 : 8;   // MIXED stores its fields in double
   int rc = hipGetDevice(&c->device) == hipSuccess ? PISO_OK : fail(c, PISO_E_HIP, "hipGetDevice failed");
   if (!rc) rc = build_topology(c, desc);
   if (!rc) rc = upload(c, (void**)&c->d_tab, c->h_tab);
   if (!rc) rc = upload(c, (void**)&c->d_fmap, c->h_fmap);
-  if (!rc) rc = precision == PISO_F64 ? upload_metrics<double>(c, desc) : upload_metrics<float>(c, desc);
+  if (!rc) rc = c->esz == 8 ? upload_metrics<double>(c, desc) : upload_metrics<float>(c, desc);
   if (!rc) rc = alloc_workspaces(c);
   if (!rc) rc = mg_build(c);
   if (!rc && !c->mg.empty()) rc = line_choose(c, desc);
@@ -705,7 +656,7 @@ int piso_mg_smoother(const piso_ctx* c, int32_t* line_axis) {
 void piso_default_step_opts(int32_t precision, piso_step_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
-  o->vel.rtol = precision == PISO_F64 ? 1e-10 : 1e-7;
+  o->vel.rtol = precision == PISO_F32 ? 1e-7 : 1e-10;
   o->vel.max_iter = 500;
   o->vel.check_every = 4;
   o->pres.rtol = precision == PISO_F64 ? 1e-10 : (precision == PISO_MIXED ? 1e-8 : 1e-6);
@@ -715,8 +666,8 @@ void piso_default_step_opts(int32_t precision, piso_step_opts* o) {
   o->vel.precond = PISO_PRECOND_JACOBI;
   o->pres.inner_rtol = 1e-5;
   o->pres.max_refine = 20;
-  o->vel.inner_rtol = 1e-3;
-  o->vel.max_refine = 0;
+  o->vel.inner_rtol = 1e-5;
+  o->vel.max_refine = 10;
   o->n_correctors = 2;
   o->grad_p_in_predictor = 1;
   o->grad_path_flags = 0;
@@ -728,7 +679,7 @@ void piso_default_step_opts(int32_t precision, piso_step_opts* o) {
   DevGuard dg_(c->device);                           \
   hipStream_t s = (hipStream_t)stream
 
-#define DISPATCH_R(CALL_F64, CALL_F32) (c->prec == PISO_F64 ? (CALL_F64) : (CALL_F32))
+#define DISPATCH_R(CALL_F64, CALL_F32) (c->esz == 8 ? (CALL_F64) : (CALL_F32))
 
 int piso_assemble(piso_ctx* c, void* stream, const void* u_n, const void* p_n, const void* nu, int32_t nu_is_field,
                   const void* S, const void* u_b, double dt, int32_t gradp, const piso_system* sys) {
@@ -811,7 +762,7 @@ int piso_correct_backward(piso_ctx* c, void* stream, const piso_system* sys, con
   CTX_ENTER();
   REQUIRE(sys && sys->A && p && du_out, "piso_correct_backward: null pointer");
   const int n = c->dim * c->N;
-  if (c->prec == PISO_F64) {
+  if (c->esz == 8) {
     if (dh)
       if (int rc = launch_axpy<double>(c, s, n, 1.0, (const double*)du_out, (double*)dh)) return rc;
     return launch_correct_bwd<double>(c, s, (const double*)sys->A, (const double*)p, (const double*)du_out,
@@ -860,7 +811,7 @@ int piso_solve_pressure_backward(piso_ctx* c, void* stream, const piso_system* s
     if (int rc = launch_outer_bwd<R>(c, s, (const R*)sys->C, gv, (const R*)u_in, (R*)du_in, (R*)g->dC, nullptr))   \
       return rc;                                                                                                    \
   } while (0)
-  if (c->prec == PISO_F64) BODY(double);
+  if (c->esz == 8) BODY(double);
   else BODY(float);
 #undef BODY
   if (info) *info = tmp;
@@ -889,7 +840,7 @@ int piso_solve_velocity_backward(piso_ctx* c, void* stream, const piso_system* s
       return rc;                                                                                                   \
     if ((rc = launch_axpy<R>(c, s, D * N, R(1), mu, (R*)g->db))) return rc;                                        \
   } while (0)
-  if (c->prec == PISO_F64) BODY(double);
+  if (c->esz == 8) BODY(double);
   else BODY(float);
 #undef BODY
   if (info) *info = tmp;
@@ -913,7 +864,7 @@ int piso_assemble_backward(piso_ctx* c, void* stream, const void* u_n, const voi
     return do_assemble_bwd<R>(c, s, (const R*)u_n, (const R*)nu, nu_is_field, (const R*)u_b, dt, (const R*)g->dA,  \
                               (const R*)g->dC, dbu, (R*)du_n, (R*)dS, (R*)dnu, (R*)du_b);                         \
   } while (0)
-  if (c->prec == PISO_F64) BODY(double);
+  if (c->esz == 8) BODY(double);
   else BODY(float);
 #undef BODY
 }

@@ -122,7 +122,7 @@ constexpr int kMgPinGroups = 64;    // coarse-level launches up to this many wor
 
 struct piso_ctx {
   int dim = 0, nblocks = 0, N = 0, NB = 0, prec = 0, device = 0;
-  size_t esz = 8;                 // element bytes of the working precision
+  size_t esz = 8;                 // element bytes of the stored fields: 4 for F32, else 8
   bool diagT = false, nonorth = false;
   bool quad = false;              // every block has nx % 4 == 0: vectorised CG kernels
   piso::Grid grid{};
@@ -141,13 +141,16 @@ struct piso_ctx {
   void* w_tg = nullptr;           // [d*d][N] tangential gradients (non-orthogonal)
   void* w_tgp = nullptr;          // [d][N]
   void* w_zb = nullptr;           // [d][max(NB,1)] zeros (boundary values of a source field)
-  double* w_rhs64 = nullptr;      // [N] (MIXED)
-  double* w_p64 = nullptr;        // [N] (MIXED)
-  void *m_r32 = nullptr, *m_e32 = nullptr;   // float [N] (MIXED refinement)
+  // MIXED: float copies of the step's operators for the inner solves, and the float
+  // residual and correction of the refinement (velocity: [d][N], pressure: [N])
+  void *x_Pf32 = nullptr, *x_Dinv32 = nullptr, *x_A32 = nullptr, *x_C32 = nullptr;
+  void *m_r32 = nullptr, *m_e32 = nullptr;
+  const void* mix_op_src = nullptr;   // double P_f the float pressure operator was rounded from
+  double* mix_scal = nullptr;         // [8] device scalars of the refinement residuals
   void *k_r = nullptr, *k_q = nullptr, *k_d0 = nullptr, *k_d1 = nullptr;   // PCG [N]
   void* k_r2 = nullptr;           // second residual buffer of the multigrid PCG [N]
   // adjoint pressure solutions of the last piso_step_backward per corrector (8 bytes per
-  // cell: the working type, or double for MIXED), the warm start of the next call
+  // cell), the warm start of the next call
   void* a_lam_hist[2] = {nullptr, nullptr};
   bool lam_hist_valid[2] = {false, false};
   void* k_z = nullptr;            // PCG preconditioned residual [N] (multigrid)
@@ -208,6 +211,18 @@ struct piso_ctx {
 };
 
 namespace piso {
+
+// Makes the context's device current for the duration of a call.
+struct DevGuard {
+  int prev = -1;
+  explicit DevGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DevGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
 
 inline int fail(piso_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
@@ -405,13 +420,27 @@ int stats_backward(piso_ctx* c, hipStream_t s, const R* u, int axis, const doubl
 template <typename R, typename BT>
 int pressure_solve(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const BT* rhs,
                    const double* mean, R* x, const piso_solve_opts* o, piso_solve_info* info);
-// MIXED form: double residual of (Pf float) with rhs64, refinement of the double x64.
-int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const float* Pf, const float* Dinv,
+// MIXED form: double residual with the double Pf and rhs64, inner float PCG, refinement
+// of the double x64 (pressure_solve<double, double> comes here in a MIXED context).
+int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const double* Pf, const double* Dinv,
                          const double* rhs64, const double* mean, double* x64,
                          const piso_solve_opts* o, piso_solve_info* info);
 template <typename R>
 int velocity_solve(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* C, const R* b, R* x,
                    const piso_solve_opts* o, piso_solve_info* info);
+// Workspace of one BiCGStab solve (F64 / F32 contexts): the vectors r, r-hat, p (two),
+// v (two), s, t ([d][N] each) and 1/A ([N]) in the context's element type, the
+// partial-sum regions (3, 6 and 9 values of kRedGrid doubles each) and the solver state.
+struct BiWork {
+  void *r, *rh, *p0, *p1, *v0, *v1, *s, *t, *iA;
+  double *part1, *part2, *part3;
+  BiState* st;
+};
+BiWork bi_work_ctx(piso_ctx* c);   // the context's own workspaces
+template <typename R>
+int velocity_solve_ws(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* C, const R* b, R* x,
+                      const piso_solve_opts* o, piso_solve_info* info, const BiWork& w);
+
 
 // ---- adjoint launch wrappers (piso_bwd.hip) ----
 template <typename R>

@@ -9,6 +9,7 @@
 // every check_every iterations, through a one-work-group check kernel.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "piso_impl.h"
 #include "piso_quad.h"
@@ -298,17 +299,18 @@ k_cg_update_q(int N, const R* __restrict__ Dinv, R* __restrict__ x, R* __restric
   write_partials<2>(acc, partB);
 }
 
-// MIXED form: r64 = b64 - M x64 in double with b64 = -(rhs64 - mean) and the float face
-// coefficients, r32 = (float) r64; partials of r.r and b.b.
+// MIXED form: r64 = b64 - M x64 in double, with b64 = -(rhs64 - mean) and the double
+// face coefficients (the operator of the step), r32 = (float) r64; partials of r.r and
+// b.b.
 template <int D>
 __global__ void __launch_bounds__(kWG)
-k_mix_resid(Grid g, const float* __restrict__ Pf, const double* __restrict__ rhs64,
+k_mix_resid(Grid g, const double* __restrict__ Pf, const double* __restrict__ rhs64,
             const double* __restrict__ mean, const double* __restrict__ x64, float* __restrict__ r32,
             double* __restrict__ partials) {
   const int N = g.N;
   int beg, end;
   chunk_range(N, beg, end);
-  const double mu = mean[0];
+  const double mu = mean ? mean[0] : 0.0;
   double acc[2] = {0.0, 0.0};
   for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
     int Fp[D], Fm[D];
@@ -316,10 +318,12 @@ k_mix_resid(Grid g, const float* __restrict__ Pf, const double* __restrict__ rhs
     const double b = -(rhs64[P] - mu);
     const double xP = x64[P];
     double Mx = 0.0;
+    // a face without a neighbour cell reads the cell itself: its term is exactly zero
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      if (Fp[j] >= 0) Mx += (double)Pf[(size_t)j * N + P] * (xP - x64[Fp[j]]);
-      if (Fm[j] >= 0) Mx += (double)Pf[(size_t)j * N + Fm[j]] * (xP - x64[Fm[j]]);
+      const int Fpj = Fp[j] >= 0 ? Fp[j] : P, Fmj = Fm[j] >= 0 ? Fm[j] : P;
+      Mx += Pf[(size_t)j * N + P] * (xP - x64[Fpj]);
+      Mx += Pf[(size_t)j * N + Fmj] * (xP - x64[Fmj]);
     }
     const double rv = b - Mx;
     r32[P] = (float)rv;
@@ -329,13 +333,14 @@ k_mix_resid(Grid g, const float* __restrict__ Pf, const double* __restrict__ rhs
   write_partials<2>(acc, partials);
 }
 
+template <int NV>
 __global__ void __launch_bounds__(kWG)
-k_finalize2(const double* __restrict__ partials, int G, double* __restrict__ out) {
-  double t[2];
-  reduce_partials<2>(partials, G, t);
+k_finalize(const double* __restrict__ partials, int G, double* __restrict__ out) {
+  double t[NV];
+  reduce_partials<NV>(partials, G, t);
   if (threadIdx.x == 0) {
-    out[0] = t[0];
-    out[1] = t[1];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) out[q] = t[q];
   }
 }
 
@@ -358,8 +363,9 @@ __global__ void __launch_bounds__(kWG) k_bi_zero_if(int N, const BiState* st, R*
     if (st->bb[c] == 0.0) x[(size_t)c * N + P] = R(0);
 }
 
-__global__ void __launch_bounds__(kWG) k_mix_add(int N, double* __restrict__ x64, const float* __restrict__ e) {
-  const int P = cell_of_thread(N);
+// x64 += e over n elements (the refinement update of both MIXED solves).
+__global__ void __launch_bounds__(kWG) k_mix_add(int n, double* __restrict__ x64, const float* __restrict__ e) {
+  const int P = cell_of_thread(n);
   if (P < 0) return;
   x64[P] += (double)e[P];
 }
@@ -435,6 +441,51 @@ k_bi_init(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __r
     }
   }
   write_partials<3 * D>(acc, part3);
+}
+
+// MIXED form: r32 = (float)(b - C x) (C^T x with TRANS), formed in double with the
+// double coefficients of the step; partials of r_c.r_c and b_c.b_c per component.
+template <int D, bool TRANS>
+__global__ void __launch_bounds__(kWG)
+k_bi_mix_resid(Grid g, const double* __restrict__ A, const double* __restrict__ C, const double* __restrict__ b,
+               const double* __restrict__ x, float* __restrict__ r32, double* __restrict__ part) {
+  const int N = g.N;
+  int beg, end;
+  chunk_range(N, beg, end);
+  double acc[2 * D];
+#pragma unroll
+  for (int q = 0; q < 2 * D; ++q) acc[q] = 0.0;
+  for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
+    int Fp[D], Fm[D];
+    faces_of<D>(g, P, Fp, Fm);
+    double cp[D], cm[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const bool hp = Fp[j] >= 0, hm = Fm[j] >= 0;
+      Fp[j] = hp ? Fp[j] : P;
+      Fm[j] = hm ? Fm[j] : P;
+      const double cpv = coef_p<double, D, TRANS>(C, j, P, N), cmv = coef_m<double, D, TRANS>(C, j, Fm[j], N);
+      cp[j] = hp ? cpv : 0.0;
+      cm[j] = hm ? cmv : 0.0;
+    }
+    const double AP = A[P];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const double* xc = x + (size_t)c * N;
+      double Cx = AP * xc[P];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        Cx += cp[j] * xc[Fp[j]];
+        Cx += cm[j] * xc[Fm[j]];
+      }
+      const double bv = b[(size_t)c * N + P];
+      const double rv = bv - Cx;
+      r32[(size_t)c * N + P] = (float)rv;
+      acc[c] += rv * rv;
+      acc[D + c] += bv * bv;
+    }
+  }
+  write_partials<2 * D>(acc, part);
 }
 
 template <int D>
@@ -923,6 +974,9 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
 template <typename R, typename BT>
 int pressure_solve(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const BT* rhs,
                    const double* mean, R* x, const piso_solve_opts* o, piso_solve_info* info) {
+  if constexpr (std::is_same<R, double>::value && std::is_same<BT, double>::value) {
+    if (c->prec == PISO_MIXED) return pressure_solve_mixed(c, s, Pf, Dinv, rhs, mean, x, o, info);
+  }
   if (o->precond != PISO_PRECOND_JACOBI && o->precond != PISO_PRECOND_MG)
     return fail(c, PISO_E_ARG, "pressure solve: unknown preconditioner");
   int iters = 0, status = 0;
@@ -944,7 +998,10 @@ int pressure_solve(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
   return status < 0 ? status : PISO_OK;
 }
 
-int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const float* Pf, const float* Dinv,
+// MIXED form (pressure): the residual of the double system rhs64 - P x64 (the step's
+// double face coefficients) in double, an inner float PCG on the float-rounded operator
+// for the correction, x64 += e; repeated until the double relative residual is <= rtol.
+int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const double* Pf, const double* Dinv,
                          const double* rhs64, const double* mean, double* x64, const piso_solve_opts* o,
                          piso_solve_info* info) {
   if (o->precond != PISO_PRECOND_JACOBI && o->precond != PISO_PRECOND_MG)
@@ -952,7 +1009,17 @@ int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const float* Pf, const floa
   const int N = c->N, G = grid_red(N, c->red_grid);
   float* r32 = (float*)c->m_r32;
   float* e32 = (float*)c->m_e32;
+  float* Pf32 = (float*)c->x_Pf32;
+  float* Dinv32 = (float*)c->x_Dinv32;
   double* pS = part(c, kPartS);
+  // the float operator of the inner solves, rounded once per operator
+  const bool same = c->pcg_same_op && c->mix_op_src == (const void*)Pf;
+  if (!same) {
+    c->mix_op_src = nullptr;
+    if (int rc = launch_copy<double, float>(c, s, Pf, Pf32, c->dim * N)) return rc;
+    if (int rc = launch_copy<double, float>(c, s, Dinv, Dinv32, N)) return rc;
+    c->mix_op_src = Pf;
+  }
   int iters = 0, status = 0, sweeps = 0;
   double rel = 0.0;
   for (;;) {
@@ -960,12 +1027,12 @@ int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const float* Pf, const floa
       k_mix_resid<2><<<G, kWG, 0, s>>>(c->grid, Pf, rhs64, mean, x64, r32, pS);
     else
       k_mix_resid<3><<<G, kWG, 0, s>>>(c->grid, Pf, rhs64, mean, x64, r32, pS);
-    k_finalize2<<<1, kWG, 0, s>>>(pS, G, c->mean + 2);
+    k_finalize<2><<<1, kWG, 0, s>>>(pS, G, c->mean + 2);
     if (int rc = check(c, "k_mix_resid")) return rc;
     PISO_HIP(c, hipMemcpyAsync(c->h_scal, c->mean + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     PISO_HIP(c, hipStreamSynchronize(s));
     const double rr = c->h_scal[0], bb = c->h_scal[1];
-    if (!std::isfinite(rr)) {
+    if (!std::isfinite(rr) || !std::isfinite(bb)) {
       status = PISO_E_NAN;
       break;
     }
@@ -986,12 +1053,12 @@ int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const float* Pf, const floa
     // ask the inner solve only for the reduction still missing (with a margin of 2), but
     // never for more than inner_rtol, the floor the float iteration reliably reaches
     const double tol_in = std::min(0.5, std::max(o->inner_rtol, 0.5 * o->rtol / rel));
-    const bool same = c->pcg_same_op;
-    c->pcg_same_op = same || sweeps > 0;   // later sweeps: same operator
-    int rc = pcg_run<float, float>(c, s, Pf, Dinv, r32, nullptr, 1.0, e32, tol_in, o->max_iter,
+    const bool same_in = c->pcg_same_op;
+    c->pcg_same_op = same || sweeps > 0;   // later sweeps and correctors: same operator
+    int rc = pcg_run<float, float>(c, s, Pf32, Dinv32, r32, nullptr, 1.0, e32, tol_in, o->max_iter,
                                    o->check_every, o->precond, &iters, &rel_in, &st_in,
                                    1 + std::min(sweeps, 2));
-    c->pcg_same_op = same;
+    c->pcg_same_op = same_in;
     if (rc) return rc;
     if (st_in < 0) {
       status = st_in;
@@ -1014,22 +1081,52 @@ int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const float* Pf, const floa
   return status < 0 ? status : PISO_OK;
 }
 
+static int velocity_solve_mixed(piso_ctx* c, hipStream_t s, bool trans, const double* A, const double* C,
+                                const double* b, double* x, const piso_solve_opts* o, piso_solve_info* info);
+
 template <typename R>
 int velocity_solve(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* C, const R* b, R* x,
                    const piso_solve_opts* o, piso_solve_info* info) {
+  if constexpr (std::is_same<R, double>::value) {
+    if (c->prec == PISO_MIXED) return velocity_solve_mixed(c, s, trans, A, C, b, x, o, info);
+  }
+  return velocity_solve_ws<R>(c, s, trans, A, C, b, x, o, info, bi_work_ctx(c));
+}
+
+BiWork bi_work_ctx(piso_ctx* c) {
+  BiWork w;
+  w.r = c->b_r;
+  w.rh = c->b_rh;
+  w.p0 = c->b_p0;
+  w.p1 = c->b_p1;
+  w.v0 = c->b_v0;
+  w.v1 = c->b_v1;
+  w.s = c->b_s;
+  w.t = c->b_t;
+  w.iA = c->b_iA;
+  w.part1 = part(c, kPart1);
+  w.part2 = part(c, kPart2);
+  w.part3 = part(c, kPart3);
+  w.st = c->bi;
+  return w;
+}
+
+template <typename R>
+int velocity_solve_ws(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* C, const R* b, R* x,
+                      const piso_solve_opts* o, piso_solve_info* info, const BiWork& w) {
   if (o->precond != PISO_PRECOND_JACOBI)
     return fail(c, PISO_E_ARG, "velocity solve: only the Jacobi preconditioner is available");
   const int N = c->N, G = solver_groups(N), D = c->dim;   // cell-per-thread kernels
-  R* r = (R*)c->b_r;
-  R* rh = (R*)c->b_rh;
-  R* pb[2] = {(R*)c->b_p0, (R*)c->b_p1};
-  R* vb[2] = {(R*)c->b_v0, (R*)c->b_v1};
-  R* sb = (R*)c->b_s;
-  R* tb = (R*)c->b_t;
-  BiState* st = c->bi;
-  double* p1 = part(c, kPart1);
-  double* p2 = part(c, kPart2);
-  double* p3 = part(c, kPart3);
+  R* r = (R*)w.r;
+  R* rh = (R*)w.rh;
+  R* pb[2] = {(R*)w.p0, (R*)w.p1};
+  R* vb[2] = {(R*)w.v0, (R*)w.v1};
+  R* sb = (R*)w.s;
+  R* tb = (R*)w.t;
+  BiState* st = w.st;
+  double* p1 = w.part1;
+  double* p2 = w.part2;
+  double* p3 = w.part3;
   const double tol2 = o->rtol * o->rtol;
 #define BI_LAUNCH(KERNEL, ...)                                                    \
   do {                                                                            \
@@ -1046,7 +1143,7 @@ int velocity_solve(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* 
     if (D == 2) k_bi_check<2><<<1, kWG, 0, s>>>(p3, G, FIRST, KT, tol2, st);      \
     else k_bi_check<3><<<1, kWG, 0, s>>>(p3, G, FIRST, KT, tol2, st);             \
   } while (0)
-  R* iA = (R*)c->b_iA;
+  R* iA = (R*)w.iA;
   k_bi_recip<R><<<grid_cells(N), kWG, 0, s>>>(N, A, iA);
   BI_LAUNCH(k_bi_init, c->grid, A, C, b, x, r, rh, pb[0], vb[0], p3);
   BI_CHECK(1, 0);
@@ -1095,11 +1192,92 @@ int velocity_solve(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* 
   return status < 0 ? status : PISO_OK;
 }
 
+// MIXED form (velocity): the residuals b_c - C x_c (C^T with trans) of the double system
+// in double, an inner float BiCGStab on the float-rounded operator for the corrections,
+// x += e; repeated until every component's double relative residual is <= rtol.
+static int velocity_solve_mixed(piso_ctx* c, hipStream_t s, bool trans, const double* A, const double* C,
+                                const double* b, double* x, const piso_solve_opts* o, piso_solve_info* info) {
+  if (o->precond != PISO_PRECOND_JACOBI)
+    return fail(c, PISO_E_ARG, "velocity solve: only the Jacobi preconditioner is available");
+  const int N = c->N, D = c->dim, G = solver_groups(N);
+  float* A32 = (float*)c->x_A32;
+  float* C32 = (float*)c->x_C32;
+  float* r32 = (float*)c->m_r32;
+  float* e32 = (float*)c->m_e32;
+  double* p3 = part(c, kPart3);
+  if (int rc = launch_copy<double, float>(c, s, A, A32, N)) return rc;
+  if (int rc = launch_copy<double, float>(c, s, C, C32, 2 * D * N)) return rc;
+  int iters = 0, status = 0, sweeps = 0;
+  double rel = 0.0;
+  bool zero_done = false;
+  for (;;) {
+    if (D == 2) {
+      if (trans) k_bi_mix_resid<2, true><<<G, kWG, 0, s>>>(c->grid, A, C, b, x, r32, p3);
+      else k_bi_mix_resid<2, false><<<G, kWG, 0, s>>>(c->grid, A, C, b, x, r32, p3);
+      k_finalize<4><<<1, kWG, 0, s>>>(p3, G, c->mix_scal);
+    } else {
+      if (trans) k_bi_mix_resid<3, true><<<G, kWG, 0, s>>>(c->grid, A, C, b, x, r32, p3);
+      else k_bi_mix_resid<3, false><<<G, kWG, 0, s>>>(c->grid, A, C, b, x, r32, p3);
+      k_finalize<6><<<1, kWG, 0, s>>>(p3, G, c->mix_scal);
+    }
+    if (int rc = check(c, "k_bi_mix_resid")) return rc;
+    PISO_HIP(c, hipMemcpyAsync(c->h_scal, c->mix_scal, 2 * D * sizeof(double), hipMemcpyDeviceToHost, s));
+    PISO_HIP(c, hipStreamSynchronize(s));
+    rel = 0.0;
+    bool bad = false;
+    for (int q = 0; q < D; ++q) {
+      const double rr = c->h_scal[q], bb = c->h_scal[D + q];
+      if (!std::isfinite(rr) || !std::isfinite(bb)) bad = true;
+      else if (bb > 0.0) rel = std::max(rel, std::sqrt(rr / bb));
+      else if (!zero_done) {
+        // a zero right-hand side: the solution component is zero, and so its residual
+        PISO_HIP(c, hipMemsetAsync(x + (size_t)q * N, 0, sizeof(double) * (size_t)N, s));
+        PISO_HIP(c, hipMemsetAsync(r32 + (size_t)q * N, 0, sizeof(float) * (size_t)N, s));
+      }
+    }
+    zero_done = true;
+    if (bad) {
+      status = PISO_E_NAN;
+      break;
+    }
+    if (rel <= o->rtol) break;
+    if (sweeps >= o->max_refine) {
+      status = PISO_NOT_CONVERGED;
+      break;
+    }
+    PISO_HIP(c, hipMemsetAsync(e32, 0, sizeof(float) * (size_t)D * N, s));
+    piso_solve_opts in = *o;
+    in.rtol = std::min(0.5, std::max(o->inner_rtol, 0.5 * o->rtol / rel));
+    piso_solve_info ii{};
+    int rc = velocity_solve<float>(c, s, trans, A32, C32, r32, e32, &in, &ii);
+    if (rc < 0) {
+      status = rc;
+      break;
+    }
+    iters += ii.iters;
+    k_mix_add<<<grid_cells(D * N), kWG, 0, s>>>(D * N, x, e32);
+    if (int rc2 = check(c, "k_mix_add")) return rc2;
+    ++sweeps;
+  }
+  if (info) {
+    info->status = status;
+    info->iters = iters;
+    info->refinements = sweeps;
+    info->rel_residual = rel;
+  }
+  return status < 0 ? status : PISO_OK;
+}
+
 template int pressure_solve<float, float>(piso_ctx*, hipStream_t, const float*, const float*, const float*,
                                           const double*, float*, const piso_solve_opts*, piso_solve_info*);
 template int pressure_solve<double, double>(piso_ctx*, hipStream_t, const double*, const double*,
                                             const double*, const double*, double*, const piso_solve_opts*,
                                             piso_solve_info*);
+template int velocity_solve_ws<float>(piso_ctx*, hipStream_t, bool, const float*, const float*, const float*,
+                                      float*, const piso_solve_opts*, piso_solve_info*, const BiWork&);
+template int velocity_solve_ws<double>(piso_ctx*, hipStream_t, bool, const double*, const double*,
+                                       const double*, double*, const piso_solve_opts*, piso_solve_info*,
+                                       const BiWork&);
 template int velocity_solve<float>(piso_ctx*, hipStream_t, bool, const float*, const float*, const float*,
                                    float*, const piso_solve_opts*, piso_solve_info*);
 template int velocity_solve<double>(piso_ctx*, hipStream_t, bool, const double*, const double*,

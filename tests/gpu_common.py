@@ -34,6 +34,20 @@ def rel_p(a, b):
     return rel(a, b)
 
 
+def max_elem(a, b):
+    """Largest element-wise difference over the largest reference magnitude: an error
+    confined to a few cells (a wall row, a block seam) shows here, not in the L2 norm."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def max_elem_p(a, b):
+    a = np.asarray(a) - np.mean(a)
+    b = np.asarray(b) - np.mean(b)
+    return max_elem(a, b)
+
+
 def tight_opts(ctx, rtol_v=1e-12, rtol_p=1e-12):
     o = ctx.default_opts()
     o.vel.rtol = rtol_v

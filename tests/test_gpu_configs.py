@@ -14,7 +14,7 @@ import torch
 
 import cases
 from oracle.piso import Geometry, step as oracle_step
-from tests.gpu_common import dev, host, rel, rel_p, say
+from tests.gpu_common import dev, host, max_elem, max_elem_p, rel, rel_p, say
 
 pytestmark = pytest.mark.gpu
 
@@ -51,9 +51,11 @@ def test_cavity256_forms():
             assert info["pres"][1]["rel_residual"] <= o.pres.rtol
             if n in refs:
                 eu, ep = rel(host(ud), refs[n][0]), rel_p(host(pd), refs[n][1])
-                say("  %s step %d rel err u %.2e p %.2e" % (prec, n, eu, ep))
-                assert eu < (1e-9 if prec == "f64" else 1e-5)
-                assert ep < (1e-7 if prec == "f64" else 1e-4)
+                mu_, mp = max_elem(host(ud), refs[n][0]), max_elem_p(host(pd), refs[n][1])
+                say("  %s step %d rel err u %.2e p %.2e; max elem u %.2e p %.2e" % (prec, n, eu, ep, mu_, mp))
+                tol = 1e-9 if prec == "f64" else 1e-7
+                assert eu < tol and ep < tol
+                assert mu_ < 10 * tol and mp < 10 * tol
 
 
 @pytest.mark.timeout(900)
@@ -96,13 +98,52 @@ def test_cylinder5_checkpointed_adjoint_fd():
                 err = abs(fd - an) / max(abs(an), 1e-2)
                 worst = max(worst, err)
                 say("  FD cell (%d, %d): fd %.8e adjoint %.8e rel %.2e" % (comp, cell, fd, an, err))
-            assert worst < 1e-5
+            assert worst < 1e-6
             fd_cells = cells
     a, b = grads["f32"], grads["f64"]
     e_cells = max(abs(a[c, i] - b[c, i]) for c, i in fd_cells) / np.abs(b).max()
     e_all = rel(a, b)
     say("  FP32 vs FP64 adjoint: FD cells max %.2e (of max |grad|), field rel L2 %.2e" % (e_cells, e_all))
-    assert e_all < 1e-2
+    assert e_cells < 1e-3
+    assert e_all < 1e-5
+
+
+@pytest.mark.timeout(600)
+def test_cylinder5_forward_vs_oracle():
+    """Full-size 5-block cylinder (non-orthogonal transition blocks, side segments):
+    steps 1 and 2 from the impulsive start against the oracle's direct solves, in F64,
+    MIXED and F32.  F32 is the paper's form: its velocity meets 1e-5; its pressure is
+    limited by the FP32 storage of h and u* under the cancellation in div h (measured
+    2.8e-5 at step 2), so its stated pressure tolerance is 1e-4."""
+    api = _api()
+    case = cases.cylinder_oh()
+    geo = Geometry(case.domain)
+    say("cylinder5: oracle steps ...")
+    u, p = case.u0, case.p0
+    refs = []
+    for _ in range(2):
+        rec = oracle_step(geo, u, p, case.nu, case.S, case.dt, case.u_b)
+        u, p = rec.u2, rec.p2
+        refs.append((u.copy(), p.copy()))
+    say("cylinder5: oracle done")
+    tol = {"f64": (1e-9, 1e-9), "mixed": (1e-9, 1e-7), "f32": (1e-5, 1e-4)}
+    for prec in ("f64", "mixed", "f32"):
+        ctx = api.Context(case.domain, prec)
+        t = ctx.dtype
+        o = ctx.default_opts()
+        if prec == "f64":
+            o.vel.rtol = o.pres.rtol = 1e-12
+        ud, pd = dev(case.u0, t), dev(case.p0, t)
+        nu, S, ub = dev([case.nu], t), dev(case.S, t), dev(case.u_b, t)
+        for n in range(2):
+            ud, pd = ctx.step(ud, pd, nu, S, ub, case.dt, o)
+            hu, hp = host(ud), host(pd)
+            eu, ep = rel(hu, refs[n][0]), rel_p(hp, refs[n][1])
+            mu_, mp = max_elem(hu, refs[n][0]), max_elem_p(hp, refs[n][1])
+            say("  %s step %d rel err u %.2e p %.2e; max elem u %.2e p %.2e" % (prec, n + 1, eu, ep, mu_, mp))
+            tu, tp = tol[prec]
+            assert eu < tu and ep < tp
+            assert mu_ < 10 * tu and mp < 10 * tp
 
 
 @pytest.mark.timeout(1100)
@@ -122,9 +163,12 @@ def test_channel192_forms_and_checkpointed_rollout():
         u1, p1, info = ctx.step(dev(u, t), dev(case.p0, t), dev([case.nu], t), dev(case.S, t), dev(case.u_b, t),
                                 case.dt, o, info=True)
         eu, ep = rel(host(u1), ref.u2), rel_p(host(p1), ref.p2)
-        say("  %s rel err u %.2e p %.2e residual %.2e" % (prec, eu, ep, info["pres"][1]["rel_residual"]))
-        assert eu < (1e-9 if prec == "f64" else 1e-5)
-        assert ep < (1e-7 if prec == "f64" else 1e-4)
+        mu_, mp = max_elem(host(u1), ref.u2), max_elem_p(host(p1), ref.p2)
+        say("  %s rel err u %.2e p %.2e; max elem u %.2e p %.2e; residual %.2e"
+            % (prec, eu, ep, mu_, mp, info["pres"][1]["rel_residual"]))
+        tol = 1e-9 if prec == "f64" else 1e-7
+        assert eu < tol and ep < tol
+        assert mu_ < 10 * tol and mp < 10 * tol
     # 4-step forward+adjoint rollout with checkpointing (k = 1 and k = 4), MIXED
     ctx = api.Context(case.domain, "mixed")
     t = ctx.dtype

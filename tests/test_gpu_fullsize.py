@@ -7,7 +7,7 @@ import torch
 
 import cases
 from oracle.piso import Geometry, step as oracle_step
-from tests.gpu_common import dev, host, rel, rel_p, say
+from tests.gpu_common import dev, host, max_elem, max_elem_p, rel, rel_p, say
 
 pytestmark = pytest.mark.gpu
 
@@ -39,15 +39,19 @@ def test_channel96_step(channel96, prec):
     torch.cuda.synchronize()
     eu = [rel(host(u1)[i], ref.u2[i]) for i in range(3)]
     ep = rel_p(host(p1), ref.p2)
-    say("  %s rel err u %s p %.3e info %s" % (prec, ["%.2e" % e for e in eu], ep, info))
-    # FP32 storage of u*, A, C and h limits the pressure: rhs = div h is a difference of
-    # nearly cancelling face fluxes (|rhs| ~ 1e-3 |W| here), so a 1e-7 storage error
-    # becomes ~1e-4 in rhs and in p, whatever the pressure residual (the MIXED form
-    # reaches 1e-9); the FP64 form meets 1e-7.
-    tol_u = 1e-9 if prec == "f64" else 1e-5
-    tol_p = {"f64": 1e-7, "mixed": 1e-4, "f32": 2e-4}[prec]
-    assert max(eu) < tol_u
-    assert ep < tol_p
+    mu_ = max(max_elem(host(u1)[i], ref.u2[i]) for i in range(3))
+    mp = max_elem_p(host(p1), ref.p2)
+    say("  %s rel err u %s p %.3e; max elem u %.2e p %.2e; info %s"
+        % (prec, ["%.2e" % e for e in eu], ep, mu_, mp, info))
+    # F32 (the paper's form: FP32 storage of u*, A, C, h) is limited on the pressure by
+    # cancellation: rhs = div h is a difference of nearly cancelling face fluxes
+    # (|rhs| ~ 1e-3 |W| here), so a 1e-7 storage error becomes ~5e-5 in p whatever the
+    # residual; its stated tolerance is 1e-4 on p.  MIXED keeps double storage and
+    # refines both solves to the FP64 residual: it meets 1e-7.
+    tol_u = {"f64": 1e-9, "mixed": 1e-9, "f32": 1e-5}[prec]
+    tol_p = {"f64": 1e-9, "mixed": 1e-7, "f32": 1e-4}[prec]
+    assert max(eu) < tol_u and mu_ < 10 * tol_u
+    assert ep < tol_p and mp < 10 * tol_p
 
 
 @pytest.mark.timeout(300)
@@ -74,3 +78,91 @@ def test_channel96_source_gradient_affine(channel96):
     rhs = float((g["S"] * dS).sum())
     say("  affine check lhs %.12e rhs %.12e" % (lhs, rhs))
     assert abs(lhs - rhs) <= 1e-8 * abs(lhs)
+
+
+def _oracle_loss_gradient(case, recs, targets):
+    """dL/dS of the channel statistics loss over the rolled-out steps (plane means of u
+    and the uv covariance over x-z planes, averaged over the steps, squared error
+    against seeded targets), by the oracle's statistics adjoint and step adjoints."""
+    from oracle import stats as ost
+    from oracle.adjoint import step_vjp
+    geo = Geometry(case.domain)
+    dims = case.domain.blocks[0]
+    ny = dims[1]
+    u_hat, uv_hat = targets
+    st = ost.empty_state(ny, 3)
+    for r in recs:
+        st = ost.accumulate(st, r.u2, dims, 1)
+    mean, cov = ost.finalize(st)
+    mbar = np.zeros_like(mean)
+    cbar = np.zeros_like(cov)
+    mbar[:, 0] = 2.0 * (mean[:, 0] - u_hat) / ny
+    cbar[:, 1] = 2.0 * (cov[:, 1] - uv_hat) / ny
+    gus = [ost.stats_vjp(st, r.u2, dims, 1, mbar, cbar) for r in recs]
+    dS = np.zeros_like(case.S)
+    gu, gp = None, np.zeros(geo.N)
+    for q in range(len(recs) - 1, -1, -1):
+        gin = gus[q] if gu is None else gus[q] + gu
+        g = step_vjp(geo, recs[q], gin, gp, mode="iterative", rtol=1e-11)
+        gu, gp = g["u_n"], g["p_n"]
+        dS += g["S"]
+    return dS
+
+
+def _gpu_loss_gradient(ctx, case, u, n_steps, o, targets):
+    t = ctx.dtype
+    u0, p0, nu, S, ub = dev(u, t), dev(case.p0, t), dev([case.nu], t), dev(case.S, t), dev(case.u_b, t)
+    u_hat, uv_hat = (torch.as_tensor(x, dtype=torch.float64, device="cuda") for x in targets)
+    us, ps, tapes = [u0], [p0], []
+    for _ in range(n_steps):
+        tp = ctx.new_tape()
+        u1, p1 = ctx.step(us[-1], ps[-1], nu, S, ub, case.dt, o, tape=tp)
+        us.append(u1)
+        ps.append(p1)
+        tapes.append(tp)
+    state = ctx.stats_state(1)
+    for x in us[1:]:
+        ctx.stats_accumulate(x, state, 1)
+    mean, cov = ctx.stats_finalize(state, 1)
+    ny = mean.shape[0]
+    mbar, cbar = torch.zeros_like(mean), torch.zeros_like(cov)
+    mbar[:, 0] = 2.0 * (mean[:, 0] - u_hat) / ny
+    cbar[:, 1] = 2.0 * (cov[:, 1] - uv_hat) / ny
+    gus = [ctx.stats_backward(x, state, mbar, cbar, 1) for x in us[1:]]
+    dS = torch.zeros_like(S)
+    gu, gp = None, None
+    ctx.adjoint_reset()
+    for q in range(n_steps - 1, -1, -1):
+        gin = gus[q] if gu is None else gus[q] + gu
+        g = ctx.step_backward(tapes[q], us[q], ps[q], nu, ub, case.dt, gin, gp, o, want=("u", "p", "S"))
+        gu, gp = g["u"], g["p"]
+        dS += g["S"]
+    torch.cuda.synchronize()
+    return host(dS)
+
+
+@pytest.mark.timeout(1100)
+def test_channel96_loss_gradient_vs_oracle(channel96):
+    """The benchmark's gradient, dL/dS of the plane-statistics loss through a 2-step
+    rollout at 96^3, in every precision form against the oracle's FP64 adjoint chain
+    (iterative solves at rtol 1e-11).  F64 (solves at 1e-12) <= 1e-8; MIXED with its
+    default options <= 1e-7; F32 (the paper's form) <= 1e-5 (measured 3.4e-6)."""
+    import cases as C
+    from paper_2505_16992_amd import api
+    case, u, ref1 = channel96
+    say("test_channel96_loss_gradient_vs_oracle: oracle step 2 and adjoint chain ...")
+    geo = Geometry(case.domain)
+    ref2 = oracle_step(geo, ref1.u2, ref1.p2, case.nu, case.S, case.dt, case.u_b, mode="iterative", rtol=1e-11)
+    targets = C.channel_loss_targets(case)
+    g_ref = _oracle_loss_gradient(case, [ref1, ref2], targets)
+    say("oracle done")
+    tol = {"f64": 1e-8, "mixed": 1e-7, "f32": 1e-5}
+    for prec in ("f64", "mixed", "f32"):
+        ctx = api.Context(case.domain, prec)
+        o = ctx.default_opts()
+        if prec == "f64":
+            o.vel.rtol = o.pres.rtol = 1e-12
+        g = _gpu_loss_gradient(ctx, case, u, 2, o, targets)
+        e, m = rel(g, g_ref), max_elem(g, g_ref)
+        say("  %s dL/dS rel err %.2e max elem %.2e" % (prec, e, m))
+        assert e < tol[prec] and m < 10 * tol[prec]

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import cases
+from oracle.adjoint import step_vjp
 from oracle.piso import Geometry, step as oracle_step
 from tests.gpu_common import dev, host, random_state, rel, rel_p, say, small_cases, tight_opts
 
@@ -60,6 +61,8 @@ def line_cases():
         "zbox12x9x16": (_box((12, 9, 16), 2, (0,)), 2),
         # 2D, lines along y of 90 cells (12-cell segments), walls on every side
         "ybox2d20x90": (_box((20, 90), 1, (), extent=(4.0, 1.0)), 1),
+        # lines along y of 112 cells: 16-cell segments (the longest kind), the last ragged
+        "channel8x112x8": (cases.channel(8, 112, 8), 1),
     }
 
 
@@ -115,7 +118,8 @@ def test_line_step_single_precision(prec):
                                 ctx.default_opts(), info=True)
         eu, ep = rel(host(u1), ref.u2), rel_p(host(p1), ref.p2)
         say("%s %s: iters %s, rel err u %.2e p %.2e" % (name, prec, [q["iters"] for q in info["pres"]], eu, ep))
-        assert eu < 1e-5 and ep < 2e-4
+        # MIXED: FP64-level to its residuals (1e-10 velocity, 1e-8 pressure)
+        assert eu < (1e-7 if prec == "mixed" else 1e-5) and ep < (1e-6 if prec == "mixed" else 1e-5)
 
 
 def test_line_adjoint_matches_point_adjoint(monkeypatch):
@@ -148,3 +152,36 @@ def test_line_adjoint_matches_point_adjoint(monkeypatch):
         e = rel(grads[0][k], grads[1][k])
         say("grad %s: line vs point rel %.2e" % (k, e))
         assert e < 1e-9
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_line_adjoint_vs_oracle(prec):
+    """The adjoint of a step with 3D line smoothing (lines of 96 cells: 12-cell
+    segments) against the oracle's step_vjp: F64 <= 1e-8, F32 at the single-precision
+    adjoint tolerance 1e-5."""
+    api = _api()
+    case = cases.channel(16, 96, 8)
+    u, p, S, ub, nu = random_state(case, seed=35)
+    if prec == "f32":
+        u, p, S, ub, nu = [np.asarray(x, dtype=np.float32).astype(np.float64) for x in (u, p, S, ub, nu)]
+    rng = np.random.default_rng(36)
+    w = rng.standard_normal(u.shape)
+    wp = rng.standard_normal(p.shape)
+    if prec == "f32":
+        w, wp = w.astype(np.float32).astype(np.float64), wp.astype(np.float32).astype(np.float64)
+    ctx = api.Context(case.domain, prec)
+    assert ctx.mg_line_axis == 1
+    t = ctx.dtype
+    o = tight_opts(ctx) if prec == "f64" else ctx.default_opts()
+    tape = ctx.new_tape()
+    args = (dev(u, t), dev(p, t), dev(nu, t), dev(S, t), dev(ub, t))
+    ctx.step(*args, case.dt, o, tape=tape)
+    g = ctx.step_backward(tape, args[0], args[1], args[2], args[4], case.dt, dev(w, t), dev(wp, t), o)
+    geo = Geometry(case.domain)
+    ref = oracle_step(geo, u, p, nu, S, case.dt, ub)
+    gr = step_vjp(geo, ref, w, wp)
+    tol = 1e-8 if prec == "f64" else 1e-5
+    for k, key in (("u", "u_n"), ("p", "p_n"), ("S", "S"), ("nu", "nu"), ("u_b", "u_b")):
+        e = rel(host(g[k]), gr[key])
+        say("%s grad %s rel %.2e" % (prec, k, e))
+        assert e < tol, k

@@ -124,6 +124,47 @@ def test_step_backward_f64(api, name):
         assert rel(host(g["u_b"]), gr["u_b"]) < 1e-8
 
 
+# Single-precision adjoint against the FP64 oracle (inputs rounded to FP32 once, the
+# oracle takes the same values).  MIXED keeps double storage and refines both solves to
+# the FP64 residual, so its gradients meet the FP64 bound; F32 is the paper's form, whose
+# per-field error is stated here: every field within 1e-5 relative L2 of the oracle
+# (measured up to 1.4e-6 on these grids).
+SP_ADJ_TOL = {"mixed": 1e-8, "f32": 1e-5}
+
+
+@pytest.mark.parametrize("prec", ["f32", "mixed"])
+@pytest.mark.parametrize("name", CASES)
+def test_step_backward_single_precision(api, prec, name):
+    say("test_step_backward_single_precision", prec, name)
+    case = small_cases()[name]
+    ctx = api.Context(case.domain, prec)
+    u, p, S, ub, nu = [np.asarray(x, dtype=np.float32).astype(np.float64) for x in random_state(case, 3)]
+    t = ctx.dtype
+    ud, pd, Sd, ubd, nud = (dev(x, t) for x in (u, p, S, ub, nu))
+    o = ctx.default_opts()
+    if prec == "mixed":
+        o.vel.rtol = o.pres.rtol = 1e-12
+    tape = ctx.new_tape()
+    ctx.step(ud, pd, nud, Sd, ubd, case.dt, o, tape=tape)
+    rng = np.random.default_rng(4)
+    wu = rng.standard_normal(u.shape).astype(np.float32).astype(np.float64)
+    wp = rng.standard_normal(p.shape).astype(np.float32).astype(np.float64)
+    g = ctx.step_backward(tape, ud, pd, nud, ubd, case.dt, dev(wu, t), dev(wp, t), o)
+    torch.cuda.synchronize()
+    geo = Geometry(case.domain)
+    ref = oracle_step(geo, u, p, nu, S, case.dt, ub)
+    gr = step_vjp(geo, ref, wu, wp)
+    errs = {}
+    for k in ("u", "p", "S", "nu", "u_b"):
+        if k == "u_b" and not geo.nb:
+            continue
+        key = {"u": "u_n", "p": "p_n"}.get(k, k)
+        errs[k] = rel(host(g[k]), gr[key])
+    say("  rel err %s" % {k: "%.2e" % v for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v < SP_ADJ_TOL[prec], k
+
+
 def test_tgv_config_20_steps(api):
     """The first workload: 32x32 periodic TGV, nu = 0.01, dt = 0.01, 20 steps, FP64."""
     say("test_tgv_config_20_steps")
@@ -159,16 +200,16 @@ def test_step_single_precision(api, prec, name):
     o = ctx.default_opts()
     if prec == "f32":
         o.pres.rtol = 1e-6
-    d32 = torch.float32
-    u1, p1, info = ctx.step(dev(u, d32), dev(p, d32), dev(nu, d32), dev(S, d32), dev(ub, d32), case.dt, o,
-                            info=True)
+    t = ctx.dtype
+    u1, p1, info = ctx.step(dev(u, t), dev(p, t), dev(nu, t), dev(S, t), dev(ub, t), case.dt, o, info=True)
     torch.cuda.synchronize()
     ref = oracle_step(geo, u, p, nu, S, case.dt, ub)
     eu = rel(host(u1), ref.u2)
     ep = rel_p(host(p1), ref.p2)
     say("  rel err u %.3e p %.3e info %s" % (eu, ep, info))
-    assert eu < 1e-5
-    assert ep < (1e-5 if prec == "mixed" else 1e-4)
+    # MIXED refines both solves to the FP64 residual (1e-10 velocity, 1e-8 pressure)
+    assert eu < (1e-8 if prec == "mixed" else 1e-5)
+    assert ep < (1e-7 if prec == "mixed" else 1e-5)
     if prec == "mixed":
         assert info["pres"][1]["rel_residual"] <= 1e-8
 

@@ -206,3 +206,63 @@ def test_adjoint_warm_start(api):
     assert it4 == it1 and it5 == it1
     for k in g1:
         assert np.array_equal(g4[k], g1[k]) and np.array_equal(g5[k], g1[k])
+
+
+def test_adjoint_history_isolated_between_rollouts(api):
+    """The adjoint warm start never crosses from one backward pass to another: a
+    rollout's gradient is bit for bit the same whatever was differentiated before it,
+    also when the loss uses an earlier state than the last (then the rollout's final
+    step never runs its backward), and a stand-alone step's too."""
+    say("test_adjoint_history_isolated_between_rollouts")
+    case = small_cases()["channel_q"]
+    ctx = api.Context(case.domain, "f64")
+    _, (u, p, S, ub, nu) = _inputs(ctx, case, 13)
+    w = torch.randn_like(u)
+
+    def grads_mid(k):
+        S_ = S.clone().requires_grad_(True)
+        traj = api.rollout(ctx, u, p, S_, nu, ub, case.dt, 3, checkpoint_every=k, return_all=True)
+        (g,) = torch.autograd.grad((traj[0][0] * w).sum() + (traj[1][0] * w).sum(), [S_])
+        return g
+
+    def grads_other():
+        S_ = (2.0 * S).requires_grad_(True)
+        uT, _ = api.rollout(ctx, u, p, S_, nu, ub, case.dt, 3)
+        torch.autograd.grad((uT * uT).sum(), [S_])
+
+    def grads_step():
+        S_ = S.clone().requires_grad_(True)
+        u1, _ = api.step(ctx, u, p, S_, nu, ub, case.dt)
+        return torch.autograd.grad((u1 * w).sum(), [S_])[0]
+
+    for k in (0, 1):
+        a = grads_mid(k)
+        grads_other()
+        b = grads_mid(k)
+        assert torch.equal(a, b), k
+    a = grads_step()
+    grads_other()
+    b = grads_step()
+    assert torch.equal(a, b)
+
+
+def test_rollout_warmup(api):
+    """warmup steps run without a tape before the differentiated ones: the same final
+    state as running them by hand, and the gradient of the rollout that starts there."""
+    say("test_rollout_warmup")
+    case = small_cases()["cylinder_q"]
+    ctx = api.Context(case.domain, "f64")
+    _, (u, p, S, ub, nu) = _inputs(ctx, case, 14)
+    o = tight_opts(ctx)
+    w = torch.randn_like(u)
+    S1 = S.clone().requires_grad_(True)
+    uT, pT = api.rollout(ctx, u, p, S1, nu, ub, case.dt, 2, warmup=3, opts=o)
+    (g1,) = torch.autograd.grad((uT * w).sum(), [S1])
+    uu, pp = u, p
+    for _ in range(3):
+        uu, pp = ctx.step(uu, pp, nu, S, ub, case.dt, o)
+    S2 = S.clone().requires_grad_(True)
+    uT2, pT2 = api.rollout(ctx, uu, pp, S2, nu, ub, case.dt, 2, opts=o)
+    (g2,) = torch.autograd.grad((uT2 * w).sum(), [S2])
+    assert torch.equal(uT.detach(), uT2.detach()) and torch.equal(pT.detach(), pT2.detach())
+    assert torch.equal(g1, g2)
