@@ -236,6 +236,24 @@ int piso_assemble(piso_ctx* ctx, void* stream, const void* u_n, const void* p_n,
 int piso_solve_velocity(piso_ctx* ctx, void* stream, const piso_system* sys, void* u_star,
                         const piso_solve_opts* opts, piso_solve_info* info);
 
+/* For callers that cannot allocate device memory at the call (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): piso_solve_velocity
+ * with the same kernels and results, but its BiCGStab workspace (the vectors r, r-hat,
+ * p, p', v, v', s, t [d][N] and 1/A [N] in the context's element type, 18 partial-sum
+ * rows of 2048 doubles and the solver state) taken from one fixed device array of
+ * PISO_NOALLOC_SCRATCH_BYTES per GPU instead of the context's buffers.  The array is
+ * part of the library's device code: each GPU the library runs on holds its own copy
+ * until the process ends.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU race (serialise them, e.g. on one stream); nothing carries over
+ * from one call to the next.  Needs 256-byte-aligned (8 d + 1) N elements plus the
+ * partial sums and state within the array (an F64 3D grid: about 200 bytes per cell,
+ * 335k cells; F32 3D: about 670k cells): PISO_E_ARG beyond that, and for PISO_MIXED
+ * contexts (whose solves need the context's refinement buffers).  Calls no hipMalloc,
+ * hipFree or allocating library routine. */
+#define PISO_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+int piso_solve_velocity_noalloc(piso_ctx* ctx, void* stream, const piso_system* sys, void* u_star,
+                                const piso_solve_opts* opts, piso_solve_info* info);
+
 /* Pressure corrector: h = A^-1 (b_u - H u_in) (eq. pressureRHS), rhs = div h + Dirichlet
  * face flux + deferred non-orthogonal term of p_lag (eqs. pressureRHSdivDiscrete,
  * pressureRHSnonOrtho), then the zero-mean solution of P p = rhs - mean(rhs) by PCG on

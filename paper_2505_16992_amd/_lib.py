@@ -85,6 +85,8 @@ _SIGS = {
     "piso_assemble": (I32, [VP, VP, VP, VP, VP, I32, VP, VP, F64, I32, C.POINTER(System)]),
     "piso_solve_velocity": (I32, [VP, VP, C.POINTER(System), VP, C.POINTER(SolveOpts),
                                   C.POINTER(SolveInfo)]),
+    "piso_solve_velocity_noalloc": (I32, [VP, VP, C.POINTER(System), VP, C.POINTER(SolveOpts),
+                                          C.POINTER(SolveInfo)]),
     "piso_solve_pressure": (I32, [VP, VP, C.POINTER(System), VP, VP, VP, VP, C.POINTER(SolveOpts),
                                   C.POINTER(SolveInfo)]),
     "piso_correct": (I32, [VP, VP, C.POINTER(System), VP, VP, VP, VP, VP]),

@@ -220,6 +220,15 @@ class Context:
         self._check(rc, "piso_solve_velocity")
         return inf.as_dict()
 
+    def solve_velocity_noalloc(self, sys, u_star, opts: L.SolveOpts):
+        """solve_velocity with its workspace in the library's fixed per-GPU array (no
+        allocation during the call; calls on one GPU must not overlap)."""
+        inf = L.SolveInfo()
+        rc = self.lib.piso_solve_velocity_noalloc(self.h, _stream(), C.byref(self._sys(sys)), _ptr(u_star),
+                                                  C.byref(opts), C.byref(inf))
+        self._check(rc, "piso_solve_velocity_noalloc")
+        return inf.as_dict()
+
     def solve_pressure(self, sys, u_in, u_b, p_lag, p, opts: L.SolveOpts):
         inf = L.SolveInfo()
         rc = self.lib.piso_solve_pressure(self.h, _stream(), C.byref(self._sys(sys)), _ptr(u_in),

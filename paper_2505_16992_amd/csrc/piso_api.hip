@@ -577,6 +577,7 @@ int piso_create(const piso_domain_desc* desc, int32_t precision, piso_ctx** out)
   c->prec = precision;
   c->esz = precision == PISO_F32 ? 4 : 8;   // MIXED stores its fields in double
   int rc = hipGetDevice(&c->device) == hipSuccess ? PISO_OK : fail(c, PISO_E_HIP, "hipGetDevice failed");
+  if (!rc) rc = noalloc_bind(c);
   if (!rc) rc = build_topology(c, desc);
   if (!rc) rc = upload(c, (void**)&c->d_tab, c->h_tab);
   if (!rc) rc = upload(c, (void**)&c->d_fmap, c->h_fmap);

@@ -206,6 +206,7 @@ struct piso_ctx {
   int red_grid = 512;              // work-groups of the reduction kernels
   int cg_grid = 0;                 // work-groups of the PCG kernels (0: chosen from the size)
   std::vector<void*> allocs;
+  void* noalloc_scratch = nullptr;   // device address of the allocation-free entry's array
   piso::Timing timing;
   std::string err;
 };
@@ -440,7 +441,9 @@ BiWork bi_work_ctx(piso_ctx* c);   // the context's own workspaces
 template <typename R>
 int velocity_solve_ws(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* C, const R* b, R* x,
                       const piso_solve_opts* o, piso_solve_info* info, const BiWork& w);
-
+// The fixed device array of the allocation-free entry point on the context's device
+// (piso_noalloc.hip): its address, looked up once per device at context creation.
+int noalloc_bind(piso_ctx* c);
 
 // ---- adjoint launch wrappers (piso_bwd.hip) ----
 template <typename R>
