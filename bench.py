@@ -4,9 +4,12 @@ workload and the pressure-CG bandwidth against the MI355X HBM roofline.
 A timed step is one forward PISO step with its tape plus its adjoint step (the whole
 hot path); K steps form a K-step rollout whose loss is the plane-mean statistics loss
 of the channel workload, back-propagated through every step.  Inputs are resident in
-HBM before the timed region.  Prints one JSON line.
+HBM before the timed region.  Prints one JSON line.  The default form is MIXED (double
+storage, float Krylov iterations refined to the double residual): the form that meets
+1e-5 against the FP64 oracle on velocity and pressure at 96^3; the paper's FP32 form is
+timed beside it for context.
 
-    python bench.py [--gpus 1] [--steps 16] [--warmup 2] [--precision f32|mixed|f64]
+    python bench.py [--gpus 1] [--steps 16] [--warmup 2] [--precision mixed|f32|f64]
                     [--workload channel96|channel192|cavity256|tgv32|cylinder5|pcg256]
                     [--no-cpu-baseline]
     python bench.py --pcg-micro 200 [--workload channel256] [--precision f32|f64|mixed] [--precond mg|jacobi]
@@ -259,9 +262,11 @@ def pcg_micro(ctx, case, precision, workload, iters, precond):
         ctx.set_timing(False)
         roof, pcg = pcg_roofline(ctx, case.domain, opts, tm, workload, precision)
         out["roofline"], out["pressure_cg"] = roof, pcg
-    # to a relative residual of 1e-8 from p = 0
+    # to the equal-residual target 1e-8 from p = 0 (F32: to its own default 1e-6; the
+    # float recurrence does not reach 1e-8)
     tol = type(opts.pres)()
-    tol.rtol, tol.max_iter, tol.check_every, tol.precond = 1e-8, 20000, 4, precond
+    goal = 1e-6 if precision == "f32" else 1e-8
+    tol.rtol, tol.max_iter, tol.check_every, tol.precond = goal, 2000, 4, precond
     tol.inner_rtol, tol.max_refine = opts.pres.inner_rtol, opts.pres.max_refine
     p.zero_()
     ctx.solve_pressure(sys_, us, ub, p0, p, tol)
@@ -270,7 +275,7 @@ def pcg_micro(ctx, case, precision, workload, iters, precond):
     p.zero_()
     inf = ctx.solve_pressure(sys_, us, ub, p0, p, tol)
     torch.cuda.synchronize()
-    out["solve_1e-8"] = {"ms": round(1e3 * (time.perf_counter() - t0), 3), "iters": inf["iters"],
+    out["solve_to_rtol"] = {"rtol": goal, "ms": round(1e3 * (time.perf_counter() - t0), 3), "iters": inf["iters"],
                          "refinements": inf["refinements"], "rel_residual": inf["rel_residual"]}
     return out
 
@@ -340,9 +345,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="f32", choices=["f32", "mixed", "f64"])
+    ap.add_argument("--precision", default="mixed", choices=["f32", "mixed", "f64"])
     ap.add_argument("--workload", default="channel96")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f32-context", action="store_true",
+                    help="skip the FP32-form figures reported beside a MIXED run")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the per-call timings of the outflow, statistics and gradient-modification calls")
@@ -393,60 +400,65 @@ def main():
         print(json.dumps(pcg_micro(ctx, case, args.precision, args.workload, args.pcg_micro,
                                    1 if args.precond == "mg" else 0)), flush=True)
         return
-    dt_t = ctx.dtype
     N, d = ctx.N, ctx.dim
     log("workload %s N=%d precision %s dt=%.3e" % (args.workload, N, args.precision, case.dt))
-
-    def dev(x):
-        return torch.as_tensor(np.ascontiguousarray(x), dtype=dt_t, device="cuda")
-
-    u0, p0, S, ub = dev(case.u0), dev(case.p0), dev(case.S), dev(case.u_b)
-    nu = dev(np.array([case.nu]))
-    opts = ctx.default_opts()
-    if args.pres_rtol is not None:
-        opts.pres.rtol = args.pres_rtol
     K, W = args.steps, args.warmup
     is_channel = args.workload.startswith("channel") or args.workload == "pcg256"
+    targets = None
     if is_channel:
-        nx, ny, nz = dom.blocks[0]
         u_hat, uv_hat = cases.channel_loss_targets(case)
         targets = (torch.as_tensor(u_hat, dtype=torch.float64, device="cuda"),
                    torch.as_tensor(uv_hat, dtype=torch.float64, device="cuda"))
 
-    def fwd_adj(n_steps):
-        """n-step rollout with tapes, then its adjoint; returns (dS, info)."""
-        us, ps, tapes = [u0], [p0], []
-        infos = []
-        for _ in range(n_steps):
-            t = ctx.new_tape()
-            u1, p1, inf = ctx.step(us[-1], ps[-1], nu, S, ub, case.dt, opts, tape=t, info=True)
-            us.append(u1)
-            ps.append(p1)
-            tapes.append(t)
-            infos.append(inf)
-        if is_channel:
-            _, gus = stats_loss_grads(ctx, us[1:], targets)
-        else:
-            gus = [torch.zeros_like(u0) for _ in range(n_steps)]
-            gus[-1] = torch.ones_like(u0)
-        dS = torch.zeros_like(S)
-        gu, gp = None, None
-        ctx.adjoint_reset()   # adjoint pressure solves warm-start within this rollout only
-        for q in range(n_steps - 1, -1, -1):
-            gin = gus[q] if gu is None else gus[q] + gu
-            g = ctx.step_backward(tapes[q], us[q], ps[q], nu, ub, case.dt, gin, gp, opts, want=("u", "p", "S"))
-            gu, gp = g["u"], g["p"]
-            dS += g["S"]
-            tapes[q] = None
-        return dS, infos
+    def runner(cx):
+        """(fwd_adj, fwd, opts, S) for context cx: the workload's inputs in its precision."""
+        def dev(x):
+            return torch.as_tensor(np.ascontiguousarray(x), dtype=cx.dtype, device="cuda")
 
-    def fwd(n_steps):
-        u, p = u0, p0
-        infos = []
-        for _ in range(n_steps):
-            u, p, inf = ctx.step(u, p, nu, S, ub, case.dt, opts, info=True)
-            infos.append(inf)
-        return infos
+        u0, p0, S, ub = dev(case.u0), dev(case.p0), dev(case.S), dev(case.u_b)
+        nu = dev(np.array([case.nu]))
+        opts = cx.default_opts()
+        if args.pres_rtol is not None:
+            opts.pres.rtol = args.pres_rtol
+
+        def fwd_adj(n_steps):
+            """n-step rollout with tapes, then its adjoint; returns (dS, info)."""
+            us, ps, tapes = [u0], [p0], []
+            infos = []
+            for _ in range(n_steps):
+                t = cx.new_tape()
+                u1, p1, inf = cx.step(us[-1], ps[-1], nu, S, ub, case.dt, opts, tape=t, info=True)
+                us.append(u1)
+                ps.append(p1)
+                tapes.append(t)
+                infos.append(inf)
+            if is_channel:
+                _, gus = stats_loss_grads(cx, us[1:], targets)
+            else:
+                gus = [torch.zeros_like(u0) for _ in range(n_steps)]
+                gus[-1] = torch.ones_like(u0)
+            dS = torch.zeros_like(S)
+            gu, gp = None, None
+            cx.adjoint_reset()   # adjoint pressure solves warm-start within this rollout only
+            for q in range(n_steps - 1, -1, -1):
+                gin = gus[q] if gu is None else gus[q] + gu
+                g = cx.step_backward(tapes[q], us[q], ps[q], nu, ub, case.dt, gin, gp, opts, want=("u", "p", "S"))
+                gu, gp = g["u"], g["p"]
+                dS += g["S"]
+                tapes[q] = None
+            return dS, infos
+
+        def fwd(n_steps):
+            u, p = u0, p0
+            infos = []
+            for _ in range(n_steps):
+                u, p, inf = cx.step(u, p, nu, S, ub, case.dt, opts, info=True)
+                infos.append(inf)
+            return infos
+
+        return fwd_adj, fwd, opts, (u0, S)
+
+    fwd_adj, fwd, opts, (u0, S) = runner(ctx)
 
     # warm-up (untimed)
     if W:
@@ -485,6 +497,27 @@ def main():
         roof, pcg = pcg_roofline(ctx, dom, opts, tm, args.workload, args.precision)
         log("timing %s" % tm)
 
+    # the paper's own FP32 form on the same workload, for context (its pressure at 96^3 is
+    # 4.7e-5 from the FP64 oracle, beyond the 1e-5 the MIXED form meets)
+    f32_ctx = None
+    if args.precision == "mixed" and not args.no_f32_context:
+        cx = api.Context(dom, "f32")
+        fa, fw, o32, _ = runner(cx)
+        if W:
+            fa(W)
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        fa(K)
+        torch.cuda.synchronize()
+        a1 = time.perf_counter()
+        fw(K)
+        torch.cuda.synchronize()
+        a2 = time.perf_counter()
+        f32_ctx = {"fwd_adj_steps_per_s": round(K / (a1 - a0), 4), "fwd_steps_per_s": round(K / (a2 - a1), 4),
+                   "pres_rtol": o32.pres.rtol}
+        log("f32 context %s" % f32_ctx)
+        del cx
+
     extras = None
     if not args.no_extras and args.workload == "channel96":
         extras = time_extras(ctx, case, args.precision, u0, S)
@@ -519,6 +552,7 @@ def main():
         "pressure_cg": pcg,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "f32_form": f32_ctx,
         "extras": extras,
     }
     print(json.dumps(out), flush=True)

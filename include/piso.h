@@ -106,11 +106,24 @@ typedef struct {
 /* Preconditioner of a Krylov solve (piso_solve_opts.precond). */
 typedef enum {
   PISO_PRECOND_JACOBI = 0,  /* diagonal scaling (pressure CG and velocity BiCGStab) */
-  PISO_PRECOND_MG = 1       /* pressure CG only: one V-cycle of aggregation multigrid per
+  PISO_PRECOND_MG = 1,      /* pressure CG only: one V-cycle of aggregation multigrid per
                                iteration (2^d cells per aggregate inside each block, Galerkin
                                coarse operators, damped Jacobi smoothing).  The paper names
                                multigrid for the pressure as the way to a faster solver
                                (Sec. 6, App. A.6); the converged solution is the same. */
+  PISO_PRECOND_ILU0 = 2,    /* velocity BiCGStab only: ILU(0) of C in red-black order (App. A.6
+                               names ILU for BiCGStab).  Cells of one colour couple only to the
+                               other colour, so the factors need no fill-in except on the
+                               diagonal of the second colour: S_P = A_P - sum_F C_PF C_FP / A_F,
+                               and M^-1 r is two colour sweeps.  Needs a grid that two colours
+                               tile with every face between colours (even periodic extents,
+                               consistent across block connections): PISO_E_ARG otherwise. */
+  PISO_PRECOND_JACOBI_ILU0 = 3   /* velocity BiCGStab only: Jacobi first; if that solve ends
+                               without converging (max_iter, breakdown, or a non-finite
+                               residual) it is restarted with PISO_PRECOND_ILU0 (App. A.6:
+                               ILU only where the plain solve fails), from the last iterate,
+                               or from zero after a non-finite one.  On a grid that two
+                               colours cannot tile the Jacobi result stands. */
 } piso_precond;
 
 typedef struct {
@@ -123,15 +136,17 @@ typedef struct {
   int32_t max_refine;              /* MIXED only: refinement sweeps (0: the initial guess is
                                       returned with PISO_NOT_CONVERGED unless it already
                                       meets rtol) */
-  int32_t precond;                 /* piso_precond; PISO_PRECOND_MG is accepted for the pressure
-                                      only (PISO_E_ARG for the velocity solve) */
+  int32_t precond;                 /* piso_precond; PISO_PRECOND_MG for the pressure only,
+                                      PISO_PRECOND_ILU0 / _JACOBI_ILU0 for the velocity only
+                                      (PISO_E_ARG otherwise) */
 } piso_solve_opts;
 
 typedef struct {
   int32_t status;                  /* PISO_OK, PISO_NOT_CONVERGED, PISO_BREAKDOWN or < 0 */
   int32_t iters;                   /* Krylov iterations (summed over components / sweeps) */
   int32_t refinements;             /* MIXED: refinement sweeps */
-  int32_t reserved;
+  int32_t fallback;                /* velocity, PISO_PRECOND_JACOBI_ILU0: 1 if the ILU(0)
+                                      restart ran (iters then counts both solves) */
   double rel_residual;             /* final relative residual (max over components) */
 } piso_solve_info;
 
@@ -216,7 +231,8 @@ int piso_mg_info(const piso_ctx* ctx, int32_t* n_levels, int64_t* cells, int32_t
  * grid allows them. */
 int piso_mg_smoother(const piso_ctx* ctx, int32_t* line_axis);
 
-/* Default options for a precision: vel rtol 1e-7 (F32) / 1e-10 (F64, MIXED), Jacobi;
+/* Default options for a precision: vel rtol 1e-7 (F32) / 1e-10 (F64, MIXED), Jacobi with
+ * the ILU(0) restart on failure (PISO_PRECOND_JACOBI_ILU0);
  * pres rtol 1e-10 (F64), 1e-6 (F32), 1e-8 (MIXED), multigrid-preconditioned; MIXED inner
  * floors 1e-5 and at most 20 (pressure) / 10 (velocity) refinement sweeps; read back every
  * 4 iterations; 2 correctors, grad_p_in_predictor = 1. */
@@ -239,15 +255,16 @@ int piso_solve_velocity(piso_ctx* ctx, void* stream, const piso_system* sys, voi
 /* For callers that cannot allocate device memory at the call (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): piso_solve_velocity
  * with the same kernels and results, but its BiCGStab workspace (the vectors r, r-hat,
- * p, p', v, v', s, t [d][N] and 1/A [N] in the context's element type, 18 partial-sum
- * rows of 2048 doubles and the solver state) taken from one fixed device array of
+ * p, p', v, v', s, t, M^-1 p, M^-1 s [d][N], 1/A and the ILU(0) pivots [N] in the
+ * context's element type, 18 partial-sum rows of 2048 doubles and the solver state)
+ * taken from one fixed device array of
  * PISO_NOALLOC_SCRATCH_BYTES per GPU instead of the context's buffers.  The array is
  * part of the library's device code: each GPU the library runs on holds its own copy
  * until the process ends.  Every call on one GPU shares that GPU's array: calls that
  * overlap on one GPU race (serialise them, e.g. on one stream); nothing carries over
- * from one call to the next.  Needs 256-byte-aligned (8 d + 1) N elements plus the
- * partial sums and state within the array (an F64 3D grid: about 200 bytes per cell,
- * 335k cells; F32 3D: about 670k cells): PISO_E_ARG beyond that, and for PISO_MIXED
+ * from one call to the next.  Needs 256-byte-aligned (10 d + 2) N elements plus the
+ * partial sums and state within the array (an F64 3D grid: 256 bytes per cell, about
+ * 260k cells; F32 3D: about 520k cells): PISO_E_ARG beyond that, and for PISO_MIXED
  * contexts (whose solves need the context's refinement buffers).  Calls no hipMalloc,
  * hipFree or allocating library routine. */
 #define PISO_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
@@ -384,6 +401,59 @@ int piso_stats_finalize(piso_ctx* ctx, void* stream, int32_t axis, const double*
  * mean_bar_k / n + sum_{i<=j} cov_bar_ij (delta_ik (u_j - mu_j) + delta_jk (u_i - mu_i)) / n. */
 int piso_stats_backward(piso_ctx* ctx, void* stream, const void* u, int32_t axis, const double* state,
                         const double* mean_bar, const double* cov_bar, void* du);
+
+/* Arbitrary-order online (co)moments (Sec. 2.5: differentiable moments of any order
+ * accumulated without storing the sequence), for single-block contexts.  m variables per
+ * sample, given as fields x [m][N] of the context's element type (m in {2, 3, 4, 6}: the
+ * velocity components, or velocity and a vector such as grad p side by side), central
+ * comoments of every total order 2 .. order (order 2 .. 4, at most 32 multi-indices: m <= 6
+ * at order 2, m <= 4 at order 3, m <= 3 at order 4), per plane normal to `axis`.  State:
+ * caller-owned device doubles, n_planes records of record_len = 1 + m + n_alpha:
+ * [n, mu_0 .. mu_{m-1}, S_alpha] with S_alpha = sum over the plane's samples of
+ * prod_i (x_i - mu_i)^alpha_i; a multi-index is its sorted tuple of variable indices,
+ * stored by order and then lexicographically (order 2 first: (0,0), (0,1), .., the
+ * covariance pairs; then (0,0,0), (0,0,1), ..).  All zeros is the empty state.  Each step
+ * merges by the binomial expansion of the deviations about the combined mean (no raw
+ * moments).  PISO_E_ARG for other layouts.  Deterministic. */
+int piso_moments_size(const piso_ctx* ctx, int32_t axis, int32_t m, int32_t order, int64_t* n_planes,
+                      int64_t* record_len);
+int piso_moments_accumulate(piso_ctx* ctx, void* stream, const void* x, int32_t m, int32_t order, int32_t axis,
+                            double* state);
+/* mean [n_planes][m] and central moments S_alpha / n [n_planes][n_alpha], device doubles. */
+int piso_moments_finalize(piso_ctx* ctx, void* stream, int32_t m, int32_t order, int32_t axis,
+                          const double* state, double* mean, double* moments);
+/* For a non-empty final state and the gradients mean_bar, moments_bar of the finalized
+ * statistics, ADDS to dx [m][N] the gradient with respect to one accumulated field x:
+ * mean_bar_k / n + sum_alpha moments_bar_alpha (alpha_k / n)
+ * (dev^(alpha - e_k) - M_(alpha - e_k)), dev = x - mu, M of order 1 being zero. */
+int piso_moments_backward(piso_ctx* ctx, void* stream, const void* x, int32_t m, int32_t order, int32_t axis,
+                          const double* state, const double* mean_bar, const double* moments_bar, void* dx);
+
+/* Cell-centred gradient of a field phi [ncomp][N]: out [d][ncomp][N] with
+ * out[i][c] = sum_j T_ji (phi_c(P + e_j) - phi_c(P - e_j)) / 2; across a Dirichlet face
+ * the neighbour is the ghost 2 phi_b - phi_P with phi_b [ncomp][NB] the face values (a
+ * velocity and its u_b), or phi_P when phi_b is NULL (the pressure: the step's own
+ * gradient, boundary value p_b = p_P).  The inputs of the dissipation and
+ * pressure-gradient budget terms. */
+int piso_field_gradient(piso_ctx* ctx, void* stream, const void* phi, int32_t ncomp, const void* phi_b,
+                        void* out);
+
+/* Turbulent energy-budget terms of Sec. 2.5 per plane normal to `axis` (the other axes
+ * homogeneous; for grids whose metric is constant over each plane), from accumulated
+ * moment states: state_u of u (m = d, order_u >= 3), state_grad the d states of
+ * g_k = du/dx_k (m = d, order 2; [d][n_planes][record] contiguous), state_up of
+ * (u, grad p) side by side (m = 2 d, order 2); wall_mean host [2][d]: the mean velocity on
+ * the low and high wall of the axis (ignored on a periodic axis).  out [5][n_planes][d(d+1)/2]
+ * (i <= j): production P_ij = -(R_ia dU_j/dx_a + R_ja dU_i/dx_a), dissipation
+ * eps_ij = 2 sum_k cov(g_k,i, g_k,j), turbulent transport T_ij = -d<u_i'u_j'u_a'>/dx_a,
+ * viscous diffusion D_ij = d^2 R_ij/dx_a^2 (without nu, as printed), velocity
+ * pressure-gradient term Pi_ij = -(cov(u_i, dp/dx_j) + cov(u_j, dp/dx_i)).  Profile
+ * derivatives: T_aa (f_+ - f_-)/2 and (1/J)(alpha_+ (f_+ - f) + alpha_- (f_- - f)),
+ * alpha = J T_aa^2 with face weights lerp(alpha), from the plane's first cell; at a wall
+ * the ghost 2 f_w - f and the face weight 2 alpha, f_w the wall mean for U and zero for
+ * the fluctuation statistics.  Forward only. */
+int piso_budget(piso_ctx* ctx, void* stream, int32_t axis, int32_t order_u, const double* state_u,
+                const double* state_grad, const double* state_up, const double* wall_mean, double* out);
 
 /* Diagnostics used by tests and benchmarks.  While timing is enabled, the pressure
  * solver's kernels are launched with HIP events attached to the dispatch

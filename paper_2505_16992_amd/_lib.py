@@ -17,7 +17,7 @@ PISO_F64, PISO_F32, PISO_MIXED = 0, 1, 2
 PISO_OK, PISO_NOT_CONVERGED, PISO_BREAKDOWN = 0, 1, 2
 PISO_E_ARG, PISO_E_TOPOLOGY, PISO_E_HIP, PISO_E_NAN, PISO_E_OOM = -1, -2, -3, -4, -5
 PISO_SIDE_CONNECT, PISO_SIDE_DIRICHLET = 0, 1
-PISO_PRECOND_JACOBI, PISO_PRECOND_MG = 0, 1
+PISO_PRECOND_JACOBI, PISO_PRECOND_MG, PISO_PRECOND_ILU0, PISO_PRECOND_JACOBI_ILU0 = 0, 1, 2, 3
 TIME_KINDS = ("cg_stencil", "cg_update", "mg_down0", "mg_up0", "mg_coarse", "cg_update_restrict",
               "mg_smooth0")
 
@@ -41,11 +41,11 @@ class SolveOpts(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("refinements", C.c_int32),
-                ("reserved", C.c_int32), ("rel_residual", C.c_double)]
+                ("fallback", C.c_int32), ("rel_residual", C.c_double)]
 
     def as_dict(self):
         return {"status": self.status, "iters": self.iters, "refinements": self.refinements,
-                "rel_residual": self.rel_residual}
+                "fallback": self.fallback, "rel_residual": self.rel_residual}
 
 
 class StepOpts(C.Structure):
@@ -109,6 +109,12 @@ _SIGS = {
     "piso_stats_accumulate": (I32, [VP, VP, VP, I32, VP]),
     "piso_stats_finalize": (I32, [VP, VP, I32, VP, VP, VP]),
     "piso_stats_backward": (I32, [VP, VP, VP, I32, VP, VP, VP, VP]),
+    "piso_moments_size": (I32, [VP, I32, I32, I32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "piso_moments_accumulate": (I32, [VP, VP, VP, I32, I32, I32, VP]),
+    "piso_moments_finalize": (I32, [VP, VP, I32, I32, I32, VP, VP, VP]),
+    "piso_moments_backward": (I32, [VP, VP, VP, I32, I32, I32, VP, VP, VP, VP]),
+    "piso_field_gradient": (I32, [VP, VP, VP, I32, VP, VP]),
+    "piso_budget": (I32, [VP, VP, I32, I32, VP, VP, VP, C.POINTER(C.c_double), VP]),
     "piso_set_timing": (I32, [VP, I32]),
     "piso_adjoint_reset": (I32, [VP]),
     "piso_mg_smoother": (I32, [VP, C.POINTER(I32)]),

@@ -358,6 +358,67 @@ class Context:
                                                  _ptr(cb), _ptr(du)), "piso_stats_backward")
         return du
 
+    # ------------------------------------------------ arbitrary-order moments, budget terms
+    def moments_size(self, m, order, axis=1):
+        n, r = C.c_int64(), C.c_int64()
+        self._check(self.lib.piso_moments_size(self.h, int(axis), int(m), int(order), C.byref(n), C.byref(r)),
+                    "piso_moments_size")
+        return n.value, r.value
+
+    def moments_state(self, m, order, axis=1):
+        """Empty state of the order-`order` comoments of m variables (device float64)."""
+        n, r = self.moments_size(m, order, axis)
+        return torch.zeros(n, r, dtype=torch.float64, device=self.device)
+
+    def moments_accumulate(self, x, state, order, axis=1):
+        m = x.shape[0]
+        self._t(x, (m, self.N), "x")
+        self._check(self.lib.piso_moments_accumulate(self.h, _stream(), _ptr(x), int(m), int(order), int(axis),
+                                                     _ptr(state)), "piso_moments_accumulate")
+        return state
+
+    def moments_finalize(self, state, m, order, axis=1):
+        """(mean [n_planes, m], central moments [n_planes, n_alpha]) in the storage order
+        of the multi-indices (by order, then lexicographic tuples)."""
+        n, r = self.moments_size(m, order, axis)
+        mean = torch.empty(n, m, dtype=torch.float64, device=self.device)
+        mom = torch.empty(n, r - 1 - m, dtype=torch.float64, device=self.device)
+        self._check(self.lib.piso_moments_finalize(self.h, _stream(), int(m), int(order), int(axis), _ptr(state),
+                                                   _ptr(mean), _ptr(mom)), "piso_moments_finalize")
+        return mean, mom
+
+    def moments_backward(self, x, state, mean_bar, mom_bar, order, axis=1, dx=None):
+        m = x.shape[0]
+        dx = self.zeros(m, self.N) if dx is None else self._t(dx, (m, self.N), "dx")
+        mb = mean_bar.to(torch.float64).contiguous()
+        ob = mom_bar.to(torch.float64).contiguous()
+        self._check(self.lib.piso_moments_backward(self.h, _stream(), _ptr(x), int(m), int(order), int(axis),
+                                                   _ptr(state), _ptr(mb), _ptr(ob), _ptr(dx)), "piso_moments_backward")
+        return dx
+
+    def field_gradient(self, phi, phi_b=None):
+        """[d, ncomp, N] cell-centred gradient of phi [ncomp, N] (ghost 2 phi_b - phi_P across
+        Dirichlet faces, or phi_P when phi_b is None)."""
+        nc = phi.shape[0]
+        self._t(phi, (nc, self.N), "phi")
+        if phi_b is not None:
+            self._t(phi_b, (nc, self.NB), "phi_b")
+        out = torch.empty(self.dim, nc, self.N, dtype=self.dtype, device=self.device)
+        self._check(self.lib.piso_field_gradient(self.h, _stream(), _ptr(phi), int(nc), _ptr(phi_b), _ptr(out)),
+                    "piso_field_gradient")
+        return out
+
+    def budget(self, state_u, state_grad, state_up, order_u, wall_mean, axis=1):
+        """Budget terms {P, eps, T, D, Pi: [n_planes, d(d+1)/2]} from accumulated states."""
+        n, _ = self.moments_size(self.dim, order_u, axis)
+        npair = self.dim * (self.dim + 1) // 2
+        out = torch.empty(5, n, npair, dtype=torch.float64, device=self.device)
+        wm = (C.c_double * (2 * self.dim))(*[float(v) for v in np.asarray(wall_mean, dtype=np.float64).ravel()])
+        self._check(self.lib.piso_budget(self.h, _stream(), int(axis), int(order_u), _ptr(state_u),
+                                         _ptr(state_grad.contiguous()), _ptr(state_up), wm, _ptr(out)),
+                    "piso_budget")
+        return dict(zip(("P", "eps", "T", "D", "Pi"), out))
+
     def set_timing(self, enable: bool):
         self.lib.piso_set_timing(self.h, int(enable))
 
@@ -541,6 +602,67 @@ class PlaneStatistics(torch.autograd.Function):
         cbar = torch.zeros(state.shape[0], npair, dtype=torch.float64, device=state.device) if cbar is None else cbar
         grads = [pctx.stats_backward(u, state, mbar, cbar, fctx.axis) for u in us]
         return (None, None, *grads)
+
+
+class PlaneMoments(torch.autograd.Function):
+    """Mean [n_planes, m] and central comoments of orders 2..order [n_planes, n_alpha] of
+    fields x [m, N] accumulated over homogeneous planes, differentiable with respect to
+    every field."""
+
+    @staticmethod
+    def forward(fctx, pctx: Context, order, axis, *xs):
+        m = xs[0].shape[0]
+        state = pctx.moments_state(m, order, axis)
+        for x in xs:
+            pctx.moments_accumulate(x, state, order, axis)
+        mean, mom = pctx.moments_finalize(state, m, order, axis)
+        fctx.pctx, fctx.order, fctx.axis = pctx, order, axis
+        fctx.save_for_backward(state, *xs)
+        return mean, mom
+
+    @staticmethod
+    def backward(fctx, mbar, obar):
+        state, *xs = fctx.saved_tensors
+        pctx, m = fctx.pctx, xs[0].shape[0]
+        na = state.shape[1] - 1 - m
+        mbar = torch.zeros(state.shape[0], m, dtype=torch.float64, device=state.device) if mbar is None else mbar
+        obar = torch.zeros(state.shape[0], na, dtype=torch.float64, device=state.device) if obar is None else obar
+        grads = [pctx.moments_backward(x, state, mbar, obar, fctx.order, fctx.axis) for x in xs]
+        return (None, None, None, *grads)
+
+
+def plane_moments(pctx: Context, xs, order, axis=1):
+    """(mean, moments) of orders 2..order over the fields `xs` (list of [m, N] tensors)."""
+    return PlaneMoments.apply(pctx, order, axis, *xs)
+
+
+class TurbulenceBudget:
+    """Online statistics for the turbulent energy budget of Sec. 2.5 over the planes
+    normal to `axis` of a single-block context: per accumulated step the velocity's
+    moments up to `order` (>= 3), the covariances of its gradients du/dx_k and the
+    covariance of (u, grad p); `terms(wall_mean)` evaluates P, eps, T, D and Pi."""
+
+    def __init__(self, pctx: Context, axis=1, order=4):
+        d = pctx.dim
+        self.pctx, self.axis, self.order = pctx, axis, order
+        self.su = pctx.moments_state(d, order, axis)
+        self.sg = torch.stack([pctx.moments_state(d, 2, axis) for _ in range(d)])
+        self.sup = pctx.moments_state(2 * d, 2, axis)
+
+    def accumulate(self, u, p, u_b=None):
+        c = self.pctx
+        c.moments_accumulate(u, self.su, self.order, self.axis)
+        g = c.field_gradient(u, u_b)
+        for k in range(c.dim):
+            c.moments_accumulate(g[k].contiguous(), self.sg[k], 2, self.axis)
+        gp = c.field_gradient(p.reshape(1, -1), None)[:, 0]
+        c.moments_accumulate(torch.cat([u, gp]).contiguous(), self.sup, 2, self.axis)
+
+    def moments(self):
+        return self.pctx.moments_finalize(self.su, self.pctx.dim, self.order, self.axis)
+
+    def terms(self, wall_mean):
+        return self.pctx.budget(self.su, self.sg, self.sup, self.order, wall_mean, self.axis)
 
 
 def plane_statistics(pctx: Context, us, axis=1):

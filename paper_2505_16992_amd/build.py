@@ -17,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libpiso.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["piso_api.hip", "piso_fwd.hip", "piso_krylov.hip", "piso_mg.hip", "piso_line.hip", "piso_outflow.hip",
-           "piso_stats.hip", "piso_bwd.hip", "piso_noalloc.hip"]
+           "piso_stats.hip", "piso_bwd.hip", "piso_noalloc.hip",
+           "piso_moments.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PISO_OFFLOAD_ARCH", "gfx950")
@@ -42,6 +43,20 @@ def _compile(src: str, opt: list) -> str:
     return obj
 
 
+HOST_SOURCES = ["piso_topology.cpp"]   # plain C++ (no device code)
+CXX = os.environ.get("CXX", "g++")
+
+
+def _compile_host(src: str, opt: list) -> str:
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    cmd = [CXX, "-std=c++17", "-fPIC", "-Wall", *opt, "-I" + os.path.join(ROOT, "include"), "-c",
+           os.path.join(CSRC, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("%s failed for %s:\n%s\n%s" % (CXX, src, " ".join(cmd), r.stderr[-8000:]))
+    return obj
+
+
 def build(jobs: int = 4, debug: bool = False) -> str:
     if not os.path.exists(HIPCC):
         raise RuntimeError("hipcc not found at %s" % HIPCC)
@@ -49,6 +64,7 @@ def build(jobs: int = 4, debug: bool = False) -> str:
     opt = ["-O0", "-g"] if debug else ["-O3"]
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         objs = list(ex.map(lambda s: _compile(s, opt), SOURCES))
+        objs += list(ex.map(lambda s: _compile_host(s, opt), HOST_SOURCES))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -20,163 +20,9 @@ static std::string g_create_error;
 
 namespace {
 
-void tangential_extent(const int n[3], int side, int dim, int& t0n, int& t1n) {
-  const int axis = side / 2;
-  int e[2] = {1, 1}, q = 0;
-  for (int a = 0; a < dim; ++a)
-    if (a != axis) e[q++] = n[a];
-  t0n = e[0];
-  t1n = e[1];
-}
-
 template <typename R>
 std::vector<R> convert(const std::vector<double>& v) {
   return std::vector<R>(v.begin(), v.end());
-}
-
-// Build the block table and the per-side face map; validates coverage, ranges,
-// conformity and reciprocity.
-int build_topology(piso_ctx* c, const piso_domain_desc* d) {
-  const int D = d->dim, B = d->n_blocks;
-  std::vector<int> off(B + 1, 0);
-  std::vector<std::array<int, 3>> n(B);
-  for (int b = 0; b < B; ++b) {
-    for (int a = 0; a < 3; ++a) n[b][a] = d->block_cells[3 * b + a];
-    if (n[b][0] < 1 || n[b][1] < 1 || n[b][2] < 1 || (D == 2 && n[b][2] != 1))
-      return fail(c, PISO_E_TOPOLOGY, "block " + std::to_string(b) + ": bad cell counts");
-    const long long cells = (long long)n[b][0] * n[b][1] * n[b][2];
-    if ((long long)off[b] + cells >= INT_MAX / 2) return fail(c, PISO_E_ARG, "too many cells");
-    off[b + 1] = off[b] + (int)cells;
-  }
-  c->N = off[B];
-  c->h_tab.assign((size_t)B * kTabStride, 0);
-  int fm = 0;
-  for (int b = 0; b < B; ++b) {
-    int* t = &c->h_tab[(size_t)b * kTabStride];
-    t[0] = off[b];
-    t[1] = n[b][0];
-    t[2] = n[b][1];
-    t[3] = n[b][2];
-    for (int s = 0; s < 2 * D; ++s) {
-      int t0n, t1n;
-      tangential_extent(n[b].data(), s, D, t0n, t1n);
-      t[4 + s] = fm;
-      fm += t0n * t1n;
-    }
-    uint32_t lo, hi;
-    int sh;
-    div_magic((uint32_t)n[b][0], lo, hi, sh);
-    t[10] = (int)lo; t[11] = (int)hi; t[12] = sh;
-    div_magic((uint32_t)(n[b][0] * n[b][1]), lo, hi, sh);
-    t[13] = (int)lo; t[14] = (int)hi; t[15] = sh;
-  }
-  c->h_fmap.assign((size_t)fm, INT_MIN);
-  auto cell = [&](int b, int i, int j, int k) { return off[b] + i + n[b][0] * (j + n[b][1] * k); };
-  auto from_t = [&](int axis, int along, int t0, int t1, int& i, int& j, int& k) {
-    if (axis == 0) { i = along; j = t0; k = t1; }
-    else if (axis == 1) { i = t0; j = along; k = t1; }
-    else { i = t0; j = t1; k = along; }
-  };
-  int nbf = 0;
-  for (int si = 0; si < d->n_sides; ++si) {
-    const piso_side_desc& sd = d->sides[si];
-    if (sd.block < 0 || sd.block >= B || sd.side < 0 || sd.side >= 2 * D)
-      return fail(c, PISO_E_TOPOLOGY, "segment " + std::to_string(si) + ": bad block or side");
-    const int b = sd.block, a = sd.side / 2, s = sd.side % 2;
-    int t0n, t1n;
-    tangential_extent(n[b].data(), sd.side, D, t0n, t1n);
-    if (!(0 <= sd.begin[0] && sd.begin[0] < sd.end[0] && sd.end[0] <= t0n && 0 <= sd.begin[1] &&
-          sd.begin[1] < sd.end[1] && sd.end[1] <= t1n))
-      return fail(c, PISO_E_TOPOLOGY, "segment " + std::to_string(si) + ": range outside the side");
-    const int along = s == 0 ? 0 : n[b][a] - 1;
-    for (int t1 = sd.begin[1]; t1 < sd.end[1]; ++t1) {
-      for (int t0 = sd.begin[0]; t0 < sd.end[0]; ++t0) {
-        int i, j, k;
-        from_t(a, along, t0, t1, i, j, k);
-        const int slot = c->h_tab[(size_t)b * kTabStride + 4 + sd.side] + t0 + t0n * t1;
-        if (c->h_fmap[slot] != INT_MIN)
-          return fail(c, PISO_E_TOPOLOGY, "segment " + std::to_string(si) + ": face covered twice");
-        if (sd.kind == PISO_SIDE_DIRICHLET) {
-          c->h_fmap[slot] = -1 - nbf++;
-        } else if (sd.kind == PISO_SIDE_CONNECT) {
-          const int ob = sd.other_block;
-          if (ob < 0 || ob >= B) return fail(c, PISO_E_TOPOLOGY, "segment " + std::to_string(si) + ": bad other block");
-          int ot0n, ot1n;
-          tangential_extent(n[ob].data(), 2 * a + (1 - s), D, ot0n, ot1n);
-          const int o0 = t0 - sd.begin[0] + sd.other_begin[0], o1 = t1 - sd.begin[1] + sd.other_begin[1];
-          if (o0 < 0 || o0 >= ot0n || o1 < 0 || o1 >= ot1n)
-            return fail(c, PISO_E_TOPOLOGY, "segment " + std::to_string(si) + ": connection leaves the other block");
-          const int oalong = s == 1 ? 0 : n[ob][a] - 1;
-          int oi, oj, ok;
-          from_t(a, oalong, o0, o1, oi, oj, ok);
-          c->h_fmap[slot] = cell(ob, oi, oj, ok);
-        } else {
-          return fail(c, PISO_E_TOPOLOGY, "segment " + std::to_string(si) + ": unknown kind");
-        }
-      }
-    }
-  }
-  c->NB = nbf;
-  // coverage and reciprocity
-  for (int b = 0; b < B; ++b) {
-    for (int side = 0; side < 2 * D; ++side) {
-      const int a = side / 2, s = side % 2;
-      int t0n, t1n;
-      tangential_extent(n[b].data(), side, D, t0n, t1n);
-      const int along = s == 0 ? 0 : n[b][a] - 1;
-      for (int t1 = 0; t1 < t1n; ++t1)
-        for (int t0 = 0; t0 < t0n; ++t0) {
-          const int slot = c->h_tab[(size_t)b * kTabStride + 4 + side] + t0 + t0n * t1;
-          const int v = c->h_fmap[slot];
-          if (v == INT_MIN)
-            return fail(c, PISO_E_TOPOLOGY, "block " + std::to_string(b) + " side " + std::to_string(side) +
-                                                ": face not covered");
-          if (v >= 0) {
-            // the other cell's opposite face must lead back here
-            int ob = 0;
-            while (ob + 1 < B && v >= off[ob + 1]) ++ob;
-            const int L = v - off[ob];
-            const int oi = L % n[ob][0], oj = (L / n[ob][0]) % n[ob][1], ok = L / (n[ob][0] * n[ob][1]);
-            const int opos[3] = {oi, oj, ok};
-            const int oside = 2 * a + (1 - s);
-            const int oalong = (1 - s) == 0 ? 0 : n[ob][a] - 1;
-            if (opos[a] != oalong) return fail(c, PISO_E_TOPOLOGY, "connection does not land on a side");
-            int ot0n, ot1n;
-            tangential_extent(n[ob].data(), oside, D, ot0n, ot1n);
-            int ot0 = 0, ot1 = 0, q = 0;
-            for (int aa = 0; aa < 3; ++aa)
-              if (aa != a) (q++ == 0 ? ot0 : ot1) = opos[aa];
-            const int oslot = c->h_tab[(size_t)ob * kTabStride + 4 + oside] + ot0 + ot0n * ot1;
-            int i, j, k;
-            from_t(a, along, t0, t1, i, j, k);
-            if (c->h_fmap[oslot] != cell(b, i, j, k))
-              return fail(c, PISO_E_TOPOLOGY, "non-reciprocal (non-conformal) connection at block " +
-                                                  std::to_string(b) + " side " + std::to_string(side));
-          }
-        }
-    }
-  }
-  // sides that wrap onto the opposite side of the same block cell for cell (periodicity):
-  // the kernels then index them arithmetically instead of through the face map
-  for (int b = 0; b < B; ++b) {
-    int bits = 0;
-    for (int side = 0; side < 2 * D; ++side) {
-      const int a = side / 2, s = side % 2;
-      int t0n, t1n;
-      tangential_extent(n[b].data(), side, D, t0n, t1n);
-      bool wraps = true;
-      for (int t1 = 0; t1 < t1n && wraps; ++t1)
-        for (int t0 = 0; t0 < t0n && wraps; ++t0) {
-          const int slot = c->h_tab[(size_t)b * kTabStride + 4 + side] + t0 + t0n * t1;
-          int i, j, k;
-          from_t(a, s ? 0 : n[b][a] - 1, t0, t1, i, j, k);
-          wraps = c->h_fmap[slot] == cell(b, i, j, k);
-        }
-      if (wraps) bits |= 1 << side;
-    }
-    c->h_tab[(size_t)b * kTabStride + kTabWrap] = bits;
-  }
-  return PISO_OK;
 }
 
 template <typename R>
@@ -246,11 +92,12 @@ int alloc_workspaces(piso_ctx* c) {
       {&c->m_r32, mx * D * N * 4}, {&c->m_e32, mx * D * N * 4}, {&c->x_Pf32, mx * D * N * 4},
       {&c->x_Dinv32, mx * N * 4}, {&c->x_A32, mx * N * 4}, {&c->x_C32, mx * 2 * D * N * 4},
       {(void**)&c->mix_scal, 8 * sizeof(double)},
+      {(void**)&c->plane_work, 2 * (size_t)std::max({c->h_tab[1], c->h_tab[2], c->h_tab[3]}) * sizeof(double)},
       {&c->k_r, N * e}, {&c->k_r2, N * e}, {&c->k_q, N * e}, {&c->k_d0, N * e}, {&c->k_d1, N * e},
       {&c->g_Pf, D * N * e}, {&c->g_Dinv, N * e}, {&c->g_x, N * e},
       {&c->b_r, D * N * e}, {&c->b_rh, D * N * e}, {&c->b_p0, D * N * e}, {&c->b_p1, D * N * e},
       {&c->b_v0, D * N * e}, {&c->b_v1, D * N * e}, {&c->b_s, D * N * e}, {&c->b_t, D * N * e},
-      {&c->b_iA, N * e},
+      {&c->b_iA, N * e}, {&c->b_ph, D * N * e}, {&c->b_sh, D * N * e}, {&c->b_sinv, N * e},
       {&c->a_g, D * N * e}, {&c->a_uin, D * N * e}, {&c->a_lam, N * e}, {&c->a_pbar, N * e},
       {&c->a_mu, D * N * e}, {&c->a_dh, D * N * e}, {&c->a_dA, N * e}, {&c->a_dC, 2 * D * N * e},
       {&c->a_dbu, D * N * e}, {&c->a_db, D * N * e}, {&c->a_dp1, N * e}, {&c->a_dnu, N * e},
@@ -555,30 +402,22 @@ int piso_create(const piso_domain_desc* desc, int32_t precision, piso_ctx** out)
   if (!out) return PISO_E_ARG;
   *out = nullptr;
   g_create_error.clear();
-  if (!desc || !desc->block_cells || !desc->sides || !desc->T || !desc->J) {
-    g_create_error = "null descriptor field";
-    return PISO_E_ARG;
-  }
-  if (desc->dim != 2 && desc->dim != 3) {
-    g_create_error = "dim must be 2 or 3";
-    return PISO_E_ARG;
-  }
-  if (desc->n_blocks < 1 || desc->n_blocks > kMaxBlocks) {
-    g_create_error = "n_blocks must be 1..16";
-    return PISO_E_ARG;
-  }
-  if (precision < PISO_F64 || precision > PISO_MIXED) {
-    g_create_error = "bad precision";
-    return PISO_E_ARG;
-  }
+  // argument and topology validation first: host only, no device touched
+  if (int rc = validate_desc(desc, precision, &g_create_error)) return rc;
+  Topology topo;
+  if (int rc = build_topology(desc, &topo, &g_create_error)) return rc;
   piso_ctx* c = new piso_ctx();
+  c->N = topo.N;
+  c->NB = topo.NB;
+  c->h_tab.swap(topo.tab);
+  c->h_fmap.swap(topo.fmap);
+  c->ilu_ok = topo.ilu_ok;
   c->dim = desc->dim;
   c->nblocks = desc->n_blocks;
   c->prec = precision;
   c->esz = precision == PISO_F32 ? 4 : 8;   // MIXED stores its fields in double
   int rc = hipGetDevice(&c->device) == hipSuccess ? PISO_OK : fail(c, PISO_E_HIP, "hipGetDevice failed");
   if (!rc) rc = noalloc_bind(c);
-  if (!rc) rc = build_topology(c, desc);
   if (!rc) rc = upload(c, (void**)&c->d_tab, c->h_tab);
   if (!rc) rc = upload(c, (void**)&c->d_fmap, c->h_fmap);
   if (!rc) rc = c->esz == 8 ? upload_metrics<double>(c, desc) : upload_metrics<float>(c, desc);
@@ -664,7 +503,7 @@ void piso_default_step_opts(int32_t precision, piso_step_opts* o) {
   o->pres.max_iter = 20000;
   o->pres.check_every = 4;
   o->pres.precond = PISO_PRECOND_MG;
-  o->vel.precond = PISO_PRECOND_JACOBI;
+  o->vel.precond = PISO_PRECOND_JACOBI_ILU0;
   o->pres.inner_rtol = 1e-5;
   o->pres.max_refine = 20;
   o->vel.inner_rtol = 1e-5;
@@ -970,6 +809,56 @@ int piso_stats_backward(piso_ctx* c, void* stream, const void* u, int32_t axis, 
   REQUIRE(u && state && mean_bar && cov_bar && du, "piso_stats_backward: null pointer");
   return DISPATCH_R(stats_backward<double>(c, s, (const double*)u, axis, state, mean_bar, cov_bar, (double*)du),
                     stats_backward<float>(c, s, (const float*)u, axis, state, mean_bar, cov_bar, (float*)du));
+}
+
+int piso_moments_size(const piso_ctx* c, int32_t axis, int32_t m, int32_t order, int64_t* n_planes,
+                      int64_t* record_len) {
+  if (!c) return PISO_E_ARG;
+  int np, ms, na;
+  if (moments_layout(c, axis, m, order, &np, &ms, &na)) return PISO_E_ARG;
+  if (n_planes) *n_planes = np;
+  if (record_len) *record_len = 1 + m + na;
+  return PISO_OK;
+}
+
+int piso_moments_accumulate(piso_ctx* c, void* stream, const void* x, int32_t m, int32_t order, int32_t axis,
+                            double* state) {
+  CTX_ENTER();
+  REQUIRE(x && state, "piso_moments_accumulate: null pointer");
+  return DISPATCH_R(moments_accumulate<double>(c, s, (const double*)x, m, order, axis, state),
+                    moments_accumulate<float>(c, s, (const float*)x, m, order, axis, state));
+}
+
+int piso_moments_finalize(piso_ctx* c, void* stream, int32_t m, int32_t order, int32_t axis, const double* state,
+                          double* mean, double* moments) {
+  CTX_ENTER();
+  REQUIRE(state && mean && moments, "piso_moments_finalize: null pointer");
+  return moments_finalize(c, s, m, order, axis, state, mean, moments);
+}
+
+int piso_moments_backward(piso_ctx* c, void* stream, const void* x, int32_t m, int32_t order, int32_t axis,
+                          const double* state, const double* mean_bar, const double* moments_bar, void* dx) {
+  CTX_ENTER();
+  REQUIRE(x && state && mean_bar && moments_bar && dx, "piso_moments_backward: null pointer");
+  return DISPATCH_R(moments_backward<double>(c, s, (const double*)x, m, order, axis, state, mean_bar, moments_bar,
+                                             (double*)dx),
+                    moments_backward<float>(c, s, (const float*)x, m, order, axis, state, mean_bar, moments_bar,
+                                            (float*)dx));
+}
+
+int piso_field_gradient(piso_ctx* c, void* stream, const void* phi, int32_t ncomp, const void* phi_b, void* out) {
+  CTX_ENTER();
+  REQUIRE(phi && out && ncomp >= 1, "piso_field_gradient: null pointer or no components");
+  return DISPATCH_R(field_gradient<double>(c, s, (const double*)phi, ncomp, (const double*)phi_b, (double*)out),
+                    field_gradient<float>(c, s, (const float*)phi, ncomp, (const float*)phi_b, (float*)out));
+}
+
+int piso_budget(piso_ctx* c, void* stream, int32_t axis, int32_t order_u, const double* state_u,
+                const double* state_grad, const double* state_up, const double* wall_mean, double* out) {
+  CTX_ENTER();
+  REQUIRE(state_u && state_grad && state_up && wall_mean && out, "piso_budget: null pointer");
+  return DISPATCH_R(budget<double>(c, s, axis, order_u, state_u, state_grad, state_up, wall_mean, out),
+                    budget<float>(c, s, axis, order_u, state_u, state_grad, state_up, wall_mean, out));
 }
 
 int piso_set_timing(piso_ctx* c, int32_t enable) {

@@ -6,21 +6,16 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "piso_topology.h"
+
 namespace piso {
 
-constexpr int kMaxBlocks = 16;
 constexpr int kWG = 256;                 // work-group size: 4 wave64s
 constexpr int kWaves = kWG / 64;
 constexpr int kRedGrid = 2048;           // work-groups of the reduction kernels (upper bound)
-constexpr int kTabStride = 20;           // ints per block in the device block table
-constexpr int kTabWrap = 16;             // entry: bit (2 * axis + side) set when that side of the
-                                         // block joins the opposite side of the same block
-                                         // cell for cell (periodicity)
-
-// Device block table, kTabStride ints per block:
-//   [0] offset  [1] nx  [2] ny  [3] nz  [4..9] offset of each side in the face map
-//   [10,11] magic for /nx (lo, hi)  [12] shift  [13,14] magic for /(nx*ny)  [15] shift
-//   [16] periodic-side bits (kTabWrap)  [17..19] unused
+// Device block table: kTabStride ints per block as built by build_topology
+// (piso_topology.h: extents, side offsets, division magic, periodic-side bits, colour
+// parity).
 struct Grid {
   int dim;
   int nblocks;

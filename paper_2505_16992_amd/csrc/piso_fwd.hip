@@ -487,7 +487,7 @@ int launch_div(piso_ctx* c, hipStream_t s, const R* W, const R* ub, const R* A, 
     if (rc) return rc;
     tgp = (const R*)c->w_tgp;
   }
-  const int G = grid_red(c->N, c->red_grid);
+  const int G = grid_red(c->N);
   double* pt = part(c, kPartS);
   PISO_DISPATCH_D_DIAG(c, (k_div<R, OT, D, DG><<<G, kWG, 0, s>>>(
                               c->grid, (const R*)c->JT, W, ub, A, (const R*)c->alphax, tgp,
@@ -540,7 +540,7 @@ int launch_jt_field(piso_ctx* c, hipStream_t s, const R* S, R* W) {
 
 template <typename TI, typename TO>
 int launch_sum(piso_ctx* c, hipStream_t s, const TI* x, int n, double scale, double* out) {
-  const int G = grid_red(n, c->red_grid);
+  const int G = grid_red(n);
   double* pt = part(c, kPartS);
   k_sum<TI><<<G, kWG, 0, s>>>(x, n, pt);
   if (int rc = check_launch(c, "k_sum")) return rc;

@@ -6,6 +6,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -191,6 +192,9 @@ struct piso_ctx {
   void *b_r = nullptr, *b_rh = nullptr, *b_p0 = nullptr, *b_p1 = nullptr, *b_v0 = nullptr,
        *b_v1 = nullptr, *b_s = nullptr, *b_t = nullptr;                    // BiCGStab [d][N]
   void* b_iA = nullptr;   // BiCGStab: 1 / A, formed once per solve [N]
+  void *b_ph = nullptr, *b_sh = nullptr;   // BiCGStab with ILU(0): M^-1 p, M^-1 s [d][N]
+  void* b_sinv = nullptr;                  // ILU(0): 1 / S (second colour), 1 / A (first) [N]
+  bool ilu_ok = false;    // two colours tile the grid (tab[kTabColour] holds each block's parity)
   // adjoint workspaces
   void *a_g = nullptr, *a_uin = nullptr, *a_lam = nullptr, *a_pbar = nullptr, *a_mu = nullptr,
        *a_dh = nullptr, *a_dA = nullptr, *a_dC = nullptr, *a_dbu = nullptr, *a_db = nullptr,
@@ -203,10 +207,10 @@ struct piso_ctx {
   piso::CgState* h_cg = nullptr;   // pinned mirrors
   piso::BiState* h_bi = nullptr;
   double* h_scal = nullptr;        // pinned [8]
-  int red_grid = 512;              // work-groups of the reduction kernels
   int cg_grid = 0;                 // work-groups of the PCG kernels (0: chosen from the size)
   std::vector<void*> allocs;
   void* noalloc_scratch = nullptr;   // device address of the allocation-free entry's array
+  double* plane_work = nullptr;      // [2 * largest extent] plane metrics of the budget terms
   piso::Timing timing;
   std::string err;
 };
@@ -251,17 +255,6 @@ int upload(piso_ctx* c, void** dst, const std::vector<T>& v) {
   if (int rc = dev_alloc(c, dst, v.size() * sizeof(T))) return rc;
   PISO_HIP(c, hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   return PISO_OK;
-}
-
-// Multiplier and shift for fast_div by d (see piso_common.h).
-inline void div_magic(uint32_t d, uint32_t& lo, uint32_t& hi, int& shift) {
-  int l = 0;
-  while ((1ull << l) < d) ++l;
-  const uint64_t num = 1ull << (31 + l);
-  const uint64_t m = (num + d - 1) / d;
-  lo = (uint32_t)(m & 0xffffffffu);
-  hi = (uint32_t)(m >> 32);
-  shift = 31 + l;
 }
 
 // Kernel timing for the benchmark: when enabled, solver kernels are launched with
@@ -314,11 +307,20 @@ void launch_timed(piso_ctx* c, hipStream_t s, int kind, K kernel, int G, Args...
 }
 
 inline int grid_cells(int N) { return (N + kWG - 1) / kWG; }
-inline int grid_red(int N, int cap = 512) {
-  int g = (N + kWG - 1) / kWG;
-  if (cap > kRedGrid) cap = kRedGrid;
-  return g < cap ? (g < 1 ? 1 : g) : cap;
+// Work-groups of the Krylov and reduction kernels.  Every work-group of a kernel
+// re-reduces the previous kernel's per-group partials, so more groups cost a longer
+// prologue; fewer leave the chip idle.  Measured on the 96^3, 192x128x192, 256^2 and
+// cylinder workloads: best with whole loop trips of 256 work units (quads or cells) per
+// group, as few trips as keep the grid at or below 1536 groups, and at least 256 groups
+// (then 64 units each).  (A fixed 512 groups for the one-shot sums left 128 cells per
+// thread at 256^3, with too few waves in flight: k_div 0.50 ms there.)
+inline int solver_groups(long units) {
+  const long trips = std::max(1L, (units + 256L * 1536 - 1) / (256L * 1536));
+  long g = (units + 256 * trips - 1) / (256 * trips);
+  if (g < 256) g = std::min(256L, (units + 63) / 64);
+  return (int)std::max(1L, std::min(g, (long)kRedGrid));
 }
+inline int grid_red(int N) { return solver_groups(N); }
 inline double* part(piso_ctx* c, int region) { return c->partials + (size_t)region * kRedGrid; }
 
 // ---- forward launch wrappers (piso_fwd.hip) ----
@@ -416,6 +418,21 @@ template <typename R>
 int stats_backward(piso_ctx* c, hipStream_t s, const R* u, int axis, const double* state, const double* mbar,
                    const double* cbar, R* du);
 
+// ---- arbitrary-order moments, field gradients, budget terms (piso_moments.hip) ----
+int moments_layout(const piso_ctx* c, int axis, int m, int order, int* n_planes, int* samples, int* n_alpha);
+template <typename R>
+int moments_accumulate(piso_ctx* c, hipStream_t s, const R* x, int m, int order, int axis, double* state);
+int moments_finalize(piso_ctx* c, hipStream_t s, int m, int order, int axis, const double* state, double* mean,
+                     double* mom);
+template <typename R>
+int moments_backward(piso_ctx* c, hipStream_t s, const R* x, int m, int order, int axis, const double* state,
+                     const double* mbar, const double* obar, R* dx);
+template <typename R>
+int field_gradient(piso_ctx* c, hipStream_t s, const R* phi, int nc, const R* phib, R* out);
+template <typename R>
+int budget(piso_ctx* c, hipStream_t s, int axis, int order_u, const double* su, const double* sg, const double* sup,
+           const double* wall_mean, double* out);
+
 // ---- Krylov solvers (piso_krylov.hip) ----
 // Zero-mean solution of P x = rhs - mean: rhs of type BT, mean a device scalar or null.
 template <typename R, typename BT>
@@ -430,10 +447,12 @@ template <typename R>
 int velocity_solve(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* C, const R* b, R* x,
                    const piso_solve_opts* o, piso_solve_info* info);
 // Workspace of one BiCGStab solve (F64 / F32 contexts): the vectors r, r-hat, p (two),
-// v (two), s, t ([d][N] each) and 1/A ([N]) in the context's element type, the
-// partial-sum regions (3, 6 and 9 values of kRedGrid doubles each) and the solver state.
+// v (two), s, t ([d][N] each) and 1/A ([N]) in the context's element type (with ILU(0)
+// also M^-1 p, M^-1 s and the pivots), the partial-sum regions (3, 6 and 9 values of
+// kRedGrid doubles each) and the solver state.
 struct BiWork {
   void *r, *rh, *p0, *p1, *v0, *v1, *s, *t, *iA;
+  void *ph, *sh, *sinv;   // ILU(0) only: M^-1 p, M^-1 s ([d][N]) and the pivots ([N])
   double *part1, *part2, *part3;
   BiState* st;
 };

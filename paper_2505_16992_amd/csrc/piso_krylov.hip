@@ -194,9 +194,8 @@ k_cg_spmv_q(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const 
   // latency then overlaps the main loads)
   const int done = st->done, kd = st->k, max_k = st->max_k;
   const double tol2bb = st->tol2 * st->bb, rz_old = st->rz[par ^ 1];
-  int beg, end;
-  quad_range(g.N >> 2, beg, end);
-  const int qd0 = beg + (int)threadIdx.x;
+  int qd0, end, stride;
+  quad_sweep(g.N >> 2, qd0, end, stride);
   const int P00 = qd0 < end ? qd0 << 2 : 0;   // unconditional (clamped) loads: no branch to wait at
   const Q4<R> b0 = ldq(r, P00), c0 = ldq(dold, P00);
   Q4<R> a0{};
@@ -235,7 +234,7 @@ k_cg_spmv_q(Grid g, const R* __restrict__ Pf, const R* __restrict__ Dinv, const 
   };
   auto d1 = [&](int P, bool, int, int, int) { return (ZOP ? r[P] : Dinv[P] * r[P]) + beta * dold[P]; };
   double acc[1] = {0.0};
-  for (int qd = qd0; qd < end; qd += kWG) {
+  for (int qd = qd0; qd < end; qd += stride) {
     const int P0 = qd << 2;
     const Cell c = locate(g, P0);
     Q4<R> dP;
@@ -737,6 +736,273 @@ k_bi_3(int N, const R* __restrict__ iAv, R* __restrict__ x, R* __restrict__ r, c
   write_partials<2 * D>(acc, part3);
 }
 
+// ------------------------------------------------- BiCGStab with ILU(0) (App. A.6)
+// Right preconditioning with the ILU(0) factorisation of C in red-black order: a cell's
+// colour is (i + j + k + parity of its block) & 1, and every face joins two colours, so
+// with the first colour ordered first C = [D_1 B; E D_2] with diagonal D_1, D_2 and
+//   L = [I 0; E D_1^-1 I],   U = [D_1 B; 0 S],   S = D_2 - diag(E D_1^-1 B)
+// (ILU(0) keeps the sparsity of C, whose second-colour block is diagonal: only the
+// diagonal of the fill-in E D_1^-1 B survives).  For a second-colour cell P
+//   S_P = A_P - sum_F C_PF C_FP / A_F.
+// z = M^-1 r = U^-1 L^-1 r is one sweep per colour:
+//   second colour:  z_P = (r_P - sum_F C_PF r_F / A_F) / S_P
+//   first colour:   z_P = (r_P - sum_F C_PF z_F) / A_P.
+// The transposed operator (the adjoint solve) uses the ILU(0) of C^T: the same S, the
+// couplings swapped.  The iteration is the Jacobi one's with K^-1 = M^-1 applied to p
+// and s as separate passes (the sweeps need neighbours' values of a finished pass).
+
+template <int D>
+__device__ __forceinline__ int cell_colour(const Grid& g, const Cell& c) {
+  return (c.i + c.j + (D == 3 ? c.k : 0) + g.tab[c.b * kTabStride + kTabColour]) & 1;
+}
+
+// 1 / S on second-colour cells, 1 / A on first-colour cells.
+template <typename R, int D>
+__global__ void __launch_bounds__(kWG)
+k_ilu_setup(Grid g, const R* __restrict__ A, const R* __restrict__ C, R* __restrict__ sinv) {
+  const int N = g.N;
+  const int P = cell_of_thread(N);
+  if (P < 0) return;
+  const Cell c = locate(g, P);
+  R piv = A[P];
+  if (cell_colour<D>(g, c)) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int Fp = neighbour(g, c, P, j, 1), Fm = neighbour(g, c, P, j, 0);
+      // C_PF C_FP is the same product for C and C^T
+      if (Fp >= 0) piv -= C[(size_t)j * N + P] * C[(size_t)(D + j) * N + P] / A[Fp];
+      if (Fm >= 0) piv -= C[(size_t)(D + j) * N + Fm] * C[(size_t)j * N + Fm] / A[Fm];
+    }
+  }
+  sinv[P] = R(1) / piv;
+}
+
+// One colour sweep of z = M^-1 r for the d components: SECOND = 1 forms the
+// second-colour values from r, SECOND = 0 the first-colour ones from r and the finished
+// second-colour z.
+template <typename R, int D, bool TRANS, bool SECOND>
+__global__ void __launch_bounds__(kWG)
+k_ilu_sweep(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __restrict__ sinv,
+            const R* __restrict__ r, R* __restrict__ z, const BiState* st) {
+  if (st->all_done) return;
+  const int N = g.N;
+  const int P = cell_of_thread(N);
+  if (P < 0) return;
+  const Cell c = locate(g, P);
+  if (cell_colour<D>(g, c) != (SECOND ? 1 : 0)) return;
+  int Fp[D], Fm[D];
+  bool hp[D], hm[D];
+  R cp[D], cm[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    Fp[j] = neighbour(g, c, P, j, 1);
+    Fm[j] = neighbour(g, c, P, j, 0);
+    hp[j] = Fp[j] >= 0;
+    hm[j] = Fm[j] >= 0;
+    Fp[j] = hp[j] ? Fp[j] : P;
+    Fm[j] = hm[j] ? Fm[j] : P;
+    const R cpv = coef_p<R, D, TRANS>(C, j, P, N), cmv = coef_m<R, D, TRANS>(C, j, Fm[j], N);
+    // second colour: the neighbours' 1/A folded into the coupling
+    cp[j] = SECOND ? cpv / A[Fp[j]] : cpv;
+    cm[j] = SECOND ? cmv / A[Fm[j]] : cmv;
+  }
+  const R sp = sinv[P];
+  const R* src = SECOND ? r : z;
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    const size_t o = (size_t)q * N;
+    R v = r[o + P];
+    // a face without a neighbour reads the cell itself and drops the term by selection:
+    // in the first-colour sweep that value is this sweep's own, not yet written output
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const R vp = src[o + Fp[j]], vm = src[o + Fm[j]];
+      v -= (hp[j] ? cp[j] * vp : R(0)) + (hm[j] ? cm[j] * vm : R(0));
+    }
+    z[o + P] = v * sp;
+  }
+}
+
+// rho_k = rh.r, convergence and breakdown, beta_k; p = r + beta (p - omega v).
+template <typename R, int D>
+__global__ void __launch_bounds__(kWG)
+k_bii_p(int N, const R* __restrict__ r, const R* __restrict__ p_old, const R* __restrict__ v_old,
+        R* __restrict__ p_new, BiState* st, const double* __restrict__ part3, int Gp, int k) {
+  if (st->all_done) return;
+  double t[2 * D];
+  reduce_partials<2 * D>(part3, Gp, t);
+  const int ko = k & 1, kp = (k + 1) & 1;
+  R beta[D], omega[D];
+  bool act[D];
+  int nact = 0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    act[c] = !st->done[c];
+    beta[c] = omega[c] = R(0);
+    if (!act[c]) continue;
+    const double rho = t[c], rr = t[D + c];
+    const bool conv = rr <= st->tol2 * st->bb[c];
+    const bool bad = !std::isfinite(rho) || !std::isfinite(rr);
+    const bool brk = !conv && !bad && (rho == 0.0 || st->omega[kp][c] == 0.0);
+    if (conv || bad || brk) {
+      if (lead()) {
+        st->rr[c] = rr;
+        st->iters[c] = k;
+        st->status[c] = bad ? PISO_E_NAN : (brk ? PISO_BREAKDOWN : 0);
+        st->done[c] = 1;
+      }
+      act[c] = false;
+      continue;
+    }
+    beta[c] = (R)((rho / st->rho[kp][c]) * (st->alpha[kp][c] / st->omega[kp][c]));
+    omega[c] = (R)st->omega[kp][c];
+    ++nact;
+    if (lead()) {
+      st->rho[ko][c] = rho;
+      st->rr[c] = rr;
+    }
+  }
+  if (nact == 0) {
+    if (lead()) st->all_done = 1;
+    return;
+  }
+  int beg, end;
+  chunk_range(N, beg, end);
+  for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      if (!act[c]) continue;
+      const size_t o = (size_t)c * N + P;
+      p_new[o] = r[o] + beta[c] * (p_old[o] - omega[c] * v_old[o]);
+    }
+  }
+}
+
+// y = C x (C^T x with TRANS) for the d components; partials of h1.y (NV = D: h1 = r-hat)
+// or of h1.y and y.y (NV = 2 D: h1 = s).
+template <typename R, int D, bool TRANS, int NV>
+__global__ void __launch_bounds__(kWG)
+k_bii_spmv(Grid g, const R* __restrict__ A, const R* __restrict__ C, const R* __restrict__ x,
+           const R* __restrict__ h1, R* __restrict__ y, const BiState* st, double* __restrict__ part) {
+  if (st->all_done) return;
+  const int N = g.N;
+  int beg, end;
+  chunk_range(N, beg, end);
+  double acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+  for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
+    int Fp[D], Fm[D];
+    faces_of<D>(g, P, Fp, Fm);
+    R cp[D], cm[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const bool hp = Fp[j] >= 0, hm = Fm[j] >= 0;
+      Fp[j] = hp ? Fp[j] : P;
+      Fm[j] = hm ? Fm[j] : P;
+      const R cpv = coef_p<R, D, TRANS>(C, j, P, N), cmv = coef_m<R, D, TRANS>(C, j, Fm[j], N);
+      cp[j] = hp ? cpv : R(0);
+      cm[j] = hm ? cmv : R(0);
+    }
+    const R AP = A[P];
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const size_t o = (size_t)c * N;
+      R v = AP * x[o + P];
+#pragma unroll
+      for (int j = 0; j < D; ++j) v += cp[j] * x[o + Fp[j]] + cm[j] * x[o + Fm[j]];
+      y[o + P] = v;
+      acc[c] += (double)h1[o + P] * (double)v;
+      if constexpr (NV == 2 * D) acc[D + c] += (double)v * (double)v;
+    }
+  }
+  write_partials<NV>(acc, part);
+}
+
+// alpha_k = rho_k / rh.v (breakdown checks); s = r - alpha v.
+template <typename R, int D>
+__global__ void __launch_bounds__(kWG)
+k_bii_s(int N, const R* __restrict__ r, const R* __restrict__ v, R* __restrict__ s, BiState* st,
+        const double* __restrict__ part1, int Gp, int k) {
+  if (st->all_done) return;
+  double rv[D];
+  reduce_partials<D>(part1, Gp, rv);
+  const int ko = k & 1;
+  R alpha[D];
+  bool act[D];
+  int nact = 0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    act[c] = !st->done[c];
+    alpha[c] = R(0);
+    if (!act[c]) continue;
+    if (rv[c] == 0.0 || !std::isfinite(rv[c])) {
+      if (lead()) {
+        st->status[c] = std::isfinite(rv[c]) ? PISO_BREAKDOWN : PISO_E_NAN;
+        st->iters[c] = k;
+        st->done[c] = 1;
+      }
+      act[c] = false;
+      continue;
+    }
+    const double a = st->rho[ko][c] / rv[c];
+    alpha[c] = (R)a;
+    ++nact;
+    if (lead()) st->alpha[ko][c] = a;
+  }
+  if (nact == 0) return;
+  int beg, end;
+  chunk_range(N, beg, end);
+  for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      if (!act[c]) continue;
+      const size_t o = (size_t)c * N + P;
+      s[o] = r[o] - alpha[c] * v[o];
+    }
+  }
+}
+
+// omega_k = t.s / t.t; x += alpha M^-1 p + omega M^-1 s; r = s - omega t.
+template <typename R, int D>
+__global__ void __launch_bounds__(kWG)
+k_bii_x(int N, R* __restrict__ x, R* __restrict__ r, const R* __restrict__ rh, const R* __restrict__ ph,
+        const R* __restrict__ sh, const R* __restrict__ s, const R* __restrict__ t, BiState* st,
+        const double* __restrict__ part2, double* __restrict__ part3, int Gp, int k) {
+  if (st->all_done) return;
+  double ts[2 * D];
+  reduce_partials<2 * D>(part2, Gp, ts);
+  const int ko = k & 1;
+  R alpha[D], omega[D];
+  bool act[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    act[c] = !st->done[c];
+    const double w = ts[D + c] > 0.0 ? ts[c] / ts[D + c] : 0.0;
+    omega[c] = (R)w;
+    alpha[c] = (R)st->alpha[ko][c];
+    if (act[c] && lead()) st->omega[ko][c] = w;
+  }
+  int beg, end;
+  chunk_range(N, beg, end);
+  double acc[2 * D];
+#pragma unroll
+  for (int q = 0; q < 2 * D; ++q) acc[q] = 0.0;
+  for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      if (!act[c]) continue;
+      const size_t o = (size_t)c * N + P;
+      x[o] += alpha[c] * ph[o] + omega[c] * sh[o];
+      const R rn = s[o] - omega[c] * t[o];
+      r[o] = rn;
+      acc[c] += (double)rh[o] * (double)rn;
+      acc[D + c] += (double)rn * (double)rn;
+    }
+  }
+  write_partials<2 * D>(acc, part3);
+}
+
 // ------------------------------------------------------------------ host drivers
 
 static int check(piso_ctx* c, const char* what) {
@@ -844,18 +1110,6 @@ static int pcg_graph(piso_ctx* c, const PcgOps<R>& o, hipGraphExec_t* out) {
   (void)hipGraphDestroy(g);
   if (ei != hipSuccess) return fail(c, PISO_E_HIP, std::string("PCG graph instantiate: ") + hipGetErrorString(ei));
   return PISO_OK;
-}
-
-// Work-groups of the Krylov kernels.  Every work-group of a kernel re-reduces the previous
-// kernel's per-group partials, so more groups cost a longer prologue; fewer groups leave
-// the chip idle.  Measured on the 96^3, 192x128x192, 256^2 and cylinder workloads: best
-// with whole loop trips of 256 work units (quads or cells) per group, as few trips as
-// keep the grid at or below 1536 groups, and at least 256 groups (then 64 units each).
-static int solver_groups(long units) {
-  const long trips = std::max(1L, (units + 256L * 1536 - 1) / (256L * 1536));
-  long g = (units + 256 * trips - 1) / (256 * trips);
-  if (g < 256) g = std::min(256L, (units + 63) / 64);
-  return (int)std::max(1L, std::min(g, (long)kRedGrid));
 }
 
 static int pcg_groups(const piso_ctx* c) {
@@ -1006,7 +1260,7 @@ int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const double* Pf, const dou
                          piso_solve_info* info) {
   if (o->precond != PISO_PRECOND_JACOBI && o->precond != PISO_PRECOND_MG)
     return fail(c, PISO_E_ARG, "pressure solve: unknown preconditioner");
-  const int N = c->N, G = grid_red(N, c->red_grid);
+  const int N = c->N, G = grid_red(N);
   float* r32 = (float*)c->m_r32;
   float* e32 = (float*)c->m_e32;
   float* Pf32 = (float*)c->x_Pf32;
@@ -1104,6 +1358,9 @@ BiWork bi_work_ctx(piso_ctx* c) {
   w.s = c->b_s;
   w.t = c->b_t;
   w.iA = c->b_iA;
+  w.ph = c->b_ph;
+  w.sh = c->b_sh;
+  w.sinv = c->b_sinv;
   w.part1 = part(c, kPart1);
   w.part2 = part(c, kPart2);
   w.part3 = part(c, kPart3);
@@ -1111,11 +1368,12 @@ BiWork bi_work_ctx(piso_ctx* c) {
   return w;
 }
 
+// One BiCGStab solve from x (Jacobi or, with ilu, red-black ILU(0) right
+// preconditioning).  Returns < 0 only for a failed HIP call; the solve's own outcome is
+// info->status.
 template <typename R>
-int velocity_solve_ws(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* C, const R* b, R* x,
-                      const piso_solve_opts* o, piso_solve_info* info, const BiWork& w) {
-  if (o->precond != PISO_PRECOND_JACOBI)
-    return fail(c, PISO_E_ARG, "velocity solve: only the Jacobi preconditioner is available");
+static int bicgstab_run(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* C, const R* b, R* x,
+                        const piso_solve_opts* o, piso_solve_info* info, const BiWork& w, bool ilu) {
   const int N = c->N, G = solver_groups(N), D = c->dim;   // cell-per-thread kernels
   R* r = (R*)w.r;
   R* rh = (R*)w.rh;
@@ -1144,7 +1402,45 @@ int velocity_solve_ws(piso_ctx* c, hipStream_t s, bool trans, const R* A, const 
     else k_bi_check<3><<<1, kWG, 0, s>>>(p3, G, FIRST, KT, tol2, st);             \
   } while (0)
   R* iA = (R*)w.iA;
-  k_bi_recip<R><<<grid_cells(N), kWG, 0, s>>>(N, A, iA);
+  R* ph = (R*)w.ph;
+  R* sh = (R*)w.sh;
+  R* sinv = (R*)w.sinv;
+#define ILU_SWEEPS(SRC, DST)                                                                               \
+  do {                                                                                                     \
+    if (D == 2) {                                                                                          \
+      if (trans) {                                                                                         \
+        k_ilu_sweep<R, 2, true, true><<<grid_cells(N), kWG, 0, s>>>(c->grid, A, C, sinv, SRC, DST, st);    \
+        k_ilu_sweep<R, 2, true, false><<<grid_cells(N), kWG, 0, s>>>(c->grid, A, C, sinv, SRC, DST, st);   \
+      } else {                                                                                             \
+        k_ilu_sweep<R, 2, false, true><<<grid_cells(N), kWG, 0, s>>>(c->grid, A, C, sinv, SRC, DST, st);   \
+        k_ilu_sweep<R, 2, false, false><<<grid_cells(N), kWG, 0, s>>>(c->grid, A, C, sinv, SRC, DST, st);  \
+      }                                                                                                    \
+    } else {                                                                                               \
+      if (trans) {                                                                                         \
+        k_ilu_sweep<R, 3, true, true><<<grid_cells(N), kWG, 0, s>>>(c->grid, A, C, sinv, SRC, DST, st);    \
+        k_ilu_sweep<R, 3, true, false><<<grid_cells(N), kWG, 0, s>>>(c->grid, A, C, sinv, SRC, DST, st);   \
+      } else {                                                                                             \
+        k_ilu_sweep<R, 3, false, true><<<grid_cells(N), kWG, 0, s>>>(c->grid, A, C, sinv, SRC, DST, st);   \
+        k_ilu_sweep<R, 3, false, false><<<grid_cells(N), kWG, 0, s>>>(c->grid, A, C, sinv, SRC, DST, st);  \
+      }                                                                                                    \
+    }                                                                                                      \
+  } while (0)
+#define BII_SPMV(NVM, X, H1, Y, PART)                                                                      \
+  do {                                                                                                     \
+    if (D == 2) {                                                                                          \
+      if (trans) k_bii_spmv<R, 2, true, 2 * NVM><<<G, kWG, 0, s>>>(c->grid, A, C, X, H1, Y, st, PART);     \
+      else k_bii_spmv<R, 2, false, 2 * NVM><<<G, kWG, 0, s>>>(c->grid, A, C, X, H1, Y, st, PART);          \
+    } else {                                                                                               \
+      if (trans) k_bii_spmv<R, 3, true, 3 * NVM><<<G, kWG, 0, s>>>(c->grid, A, C, X, H1, Y, st, PART);     \
+      else k_bii_spmv<R, 3, false, 3 * NVM><<<G, kWG, 0, s>>>(c->grid, A, C, X, H1, Y, st, PART);          \
+    }                                                                                                      \
+  } while (0)
+  if (ilu) {
+    if (D == 2) k_ilu_setup<R, 2><<<grid_cells(N), kWG, 0, s>>>(c->grid, A, C, sinv);
+    else k_ilu_setup<R, 3><<<grid_cells(N), kWG, 0, s>>>(c->grid, A, C, sinv);
+  } else {
+    k_bi_recip<R><<<grid_cells(N), kWG, 0, s>>>(N, A, iA);
+  }
   BI_LAUNCH(k_bi_init, c->grid, A, C, b, x, r, rh, pb[0], vb[0], p3);
   BI_CHECK(1, 0);
   // zero right-hand sides are handled on the device (no read-back before the iterations)
@@ -1161,6 +1457,20 @@ int velocity_solve_ws(piso_ctx* c, hipStream_t s, bool trans, const R* A, const 
       R* pn = pb[(it + 1) & 1];
       R* vo = vb[it & 1];
       R* vn = vb[(it + 1) & 1];
+      if (ilu) {
+        // p, M^-1 p, v = C M^-1 p; s, M^-1 s, t = C M^-1 s; x, r
+        if (D == 2) k_bii_p<R, 2><<<G, kWG, 0, s>>>(N, r, po, vo, pn, st, p3, G, it);
+        else k_bii_p<R, 3><<<G, kWG, 0, s>>>(N, r, po, vo, pn, st, p3, G, it);
+        ILU_SWEEPS(pn, ph);
+        BII_SPMV(1, ph, rh, vn, p1);
+        if (D == 2) k_bii_s<R, 2><<<G, kWG, 0, s>>>(N, r, vn, sb, st, p1, G, it);
+        else k_bii_s<R, 3><<<G, kWG, 0, s>>>(N, r, vn, sb, st, p1, G, it);
+        ILU_SWEEPS(sb, sh);
+        BII_SPMV(2, sh, sb, tb, p2);
+        if (D == 2) k_bii_x<R, 2><<<G, kWG, 0, s>>>(N, x, r, rh, ph, sh, sb, tb, st, p2, p3, G, it);
+        else k_bii_x<R, 3><<<G, kWG, 0, s>>>(N, x, r, rh, ph, sh, sb, tb, st, p2, p3, G, it);
+        continue;
+      }
       BI_LAUNCH(k_bi_1, c->grid, iA, C, r, rh, po, vo, pn, vn, st, p3, p1, G, it);
       BI_LAUNCH(k_bi_2, c->grid, iA, C, r, vn, sb, tb, st, p1, p2, G, it);
       if (D == 2) k_bi_3<R, 2><<<G, kWG, 0, s>>>(N, iA, x, r, rh, pn, sb, tb, st, p2, p3, G, it);
@@ -1173,6 +1483,8 @@ int velocity_solve_ws(piso_ctx* c, hipStream_t s, bool trans, const R* A, const 
   }
 #undef BI_LAUNCH
 #undef BI_CHECK
+#undef ILU_SWEEPS
+#undef BII_SPMV
   const BiState& h = *c->h_bi;
   int status = 0, iters = 0;
   double rel = 0.0;
@@ -1183,13 +1495,37 @@ int velocity_solve_ws(piso_ctx* c, hipStream_t s, bool trans, const R* A, const 
     else if (status >= 0) status = std::max(status, h.status[q]);
     if (!h.done[q] && status >= 0) status = std::max(status, (int)PISO_NOT_CONVERGED);
   }
-  if (info) {
-    info->status = status;
-    info->iters = iters;
-    info->refinements = 0;
-    info->rel_residual = rel;
+  *info = piso_solve_info{};
+  info->status = status;
+  info->iters = iters;
+  info->rel_residual = rel;
+  return PISO_OK;
+}
+
+template <typename R>
+int velocity_solve_ws(piso_ctx* c, hipStream_t s, bool trans, const R* A, const R* C, const R* b, R* x,
+                      const piso_solve_opts* o, piso_solve_info* info, const BiWork& w) {
+  const int pc = o->precond;
+  if (pc != PISO_PRECOND_JACOBI && pc != PISO_PRECOND_ILU0 && pc != PISO_PRECOND_JACOBI_ILU0)
+    return fail(c, PISO_E_ARG, "velocity solve: preconditioner must be Jacobi, ILU(0) or Jacobi with ILU(0) restart");
+  if (pc == PISO_PRECOND_ILU0 && !c->ilu_ok)
+    return fail(c, PISO_E_ARG, "velocity solve: ILU(0) needs a grid two colours tile (even periodic extents)");
+  piso_solve_info tmp{};
+  piso_solve_info* inf = info ? info : &tmp;
+  int rc = bicgstab_run<R>(c, s, trans, A, C, b, x, o, inf, w, pc == PISO_PRECOND_ILU0);
+  if (rc < 0) return rc;
+  if (pc == PISO_PRECOND_JACOBI_ILU0 && inf->status != PISO_OK && c->ilu_ok) {
+    // the Jacobi solve failed: restart with ILU(0) from its last iterate, or from zero
+    // after a non-finite residual (the iterate may then hold non-finite values)
+    if (inf->status == PISO_E_NAN)
+      PISO_HIP(c, hipMemsetAsync(x, 0, sizeof(R) * (size_t)c->dim * c->N, s));
+    const int first = inf->iters;
+    rc = bicgstab_run<R>(c, s, trans, A, C, b, x, o, inf, w, true);
+    if (rc < 0) return rc;
+    inf->iters += first;
+    inf->fallback = 1;
   }
-  return status < 0 ? status : PISO_OK;
+  return inf->status < 0 ? inf->status : PISO_OK;
 }
 
 // MIXED form (velocity): the residuals b_c - C x_c (C^T with trans) of the double system
@@ -1197,8 +1533,9 @@ int velocity_solve_ws(piso_ctx* c, hipStream_t s, bool trans, const R* A, const 
 // x += e; repeated until every component's double relative residual is <= rtol.
 static int velocity_solve_mixed(piso_ctx* c, hipStream_t s, bool trans, const double* A, const double* C,
                                 const double* b, double* x, const piso_solve_opts* o, piso_solve_info* info) {
-  if (o->precond != PISO_PRECOND_JACOBI)
-    return fail(c, PISO_E_ARG, "velocity solve: only the Jacobi preconditioner is available");
+  const int pc = o->precond;
+  if (pc != PISO_PRECOND_JACOBI && pc != PISO_PRECOND_ILU0 && pc != PISO_PRECOND_JACOBI_ILU0)
+    return fail(c, PISO_E_ARG, "velocity solve: preconditioner must be Jacobi, ILU(0) or Jacobi with ILU(0) restart");
   const int N = c->N, D = c->dim, G = solver_groups(N);
   float* A32 = (float*)c->x_A32;
   float* C32 = (float*)c->x_C32;
@@ -1207,7 +1544,7 @@ static int velocity_solve_mixed(piso_ctx* c, hipStream_t s, bool trans, const do
   double* p3 = part(c, kPart3);
   if (int rc = launch_copy<double, float>(c, s, A, A32, N)) return rc;
   if (int rc = launch_copy<double, float>(c, s, C, C32, 2 * D * N)) return rc;
-  int iters = 0, status = 0, sweeps = 0;
+  int iters = 0, status = 0, sweeps = 0, fallback = 0;
   double rel = 0.0;
   bool zero_done = false;
   for (;;) {
@@ -1255,6 +1592,7 @@ static int velocity_solve_mixed(piso_ctx* c, hipStream_t s, bool trans, const do
       break;
     }
     iters += ii.iters;
+    if (ii.fallback) fallback = 1;
     k_mix_add<<<grid_cells(D * N), kWG, 0, s>>>(D * N, x, e32);
     if (int rc2 = check(c, "k_mix_add")) return rc2;
     ++sweeps;
@@ -1263,6 +1601,7 @@ static int velocity_solve_mixed(piso_ctx* c, hipStream_t s, bool trans, const do
     info->status = status;
     info->iters = iters;
     info->refinements = sweeps;
+    info->fallback = fallback;
     info->rel_residual = rel;
   }
   return status < 0 ? status : PISO_OK;

@@ -280,7 +280,29 @@ k_mg_down0uq(Grid g, Grid g1, MgQuadTiles tl, const R* __restrict__ Pf, const R*
   const int lane = threadIdx.x & 63, p = lane & (NP - 1);
   const int u = (grp - tl.off[b]) * (kWG / NP) + ((int)threadIdx.x / NP);
   const int xq = u % nxq, rest = u / nxq;
-  const int cj = rest % cy, ck = rest / cy;
+  // 3D: the aggregate rows are taken in tiles of kRowTile rows, each tile through every
+  // plane pair in turn, so that a row pair's neighbours in z are a few work-groups away
+  // (still in the XCD's L2) instead of a whole plane of rows
+  int cj, ck;
+  if (D == 3) {
+    constexpr int kRowTile = 8;
+    const int cz = tc[3];
+    const int full = (cy / kRowTile) * kRowTile;
+    if (rest >= cy * cz) {
+      cj = ck = 0;   // past the block's units: not valid below
+    } else if (rest < full * cz) {
+      const int tile = rest / (kRowTile * cz), w = rest - tile * kRowTile * cz;
+      ck = w / kRowTile;
+      cj = tile * kRowTile + (w - ck * kRowTile);
+    } else {
+      const int tr = cy - full, w = rest - full * cz;
+      ck = w / tr;
+      cj = full + (w - ck * tr);
+    }
+  } else {
+    cj = rest % cy;
+    ck = rest / cy;
+  }
   const int j = 2 * cj + (p & 1), k = D == 3 ? 2 * ck + (p >> 1) : 0;
   const bool valid = u < tl.units[b] && j < ny && k < nz;
   const int i0 = 4 * xq;
@@ -826,10 +848,10 @@ k_mg_up0_q(Grid g, Grid g1, const R* __restrict__ Pf, const R* __restrict__ Dinv
            const R* __restrict__ y, const int* __restrict__ parent, const R* __restrict__ ec, R omega, R* __restrict__ z,
            double* __restrict__ partB, const CgState* st) {
   if (st->done) return;
-  int beg, end;
-  quad_range(g.N >> 2, beg, end);
+  int first, end, stride;
+  quad_sweep(g.N >> 2, first, end, stride);
   double acc[2] = {0.0, 0.0};
-  for (int qd = beg + (int)threadIdx.x; qd < end; qd += kWG) {
+  for (int qd = first; qd < end; qd += stride) {
     const int P0 = qd << 2;
     const Cell c = locate(g, P0);
     const int* t1 = g1.tab + c.b * kTabStride;

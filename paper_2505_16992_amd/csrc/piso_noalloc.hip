@@ -55,20 +55,22 @@ extern "C" int piso_solve_velocity_noalloc(piso_ctx* c, void* stream, const piso
   if (!c->noalloc_scratch) return fail(c, PISO_E_HIP, "piso_solve_velocity_noalloc: scratch address unknown");
   const size_t N = c->N, D = c->dim, e = c->esz;
   const size_t vec = align256(D * N * e), iab = align256(N * e), prow = (size_t)kRedGrid * sizeof(double);
-  const size_t need = 8 * vec + iab + 18 * prow + align256(sizeof(BiState));
+  const size_t need = 10 * vec + 2 * iab + 18 * prow + align256(sizeof(BiState));
   if (need > (size_t)PISO_NOALLOC_SCRATCH_BYTES)
     return fail(c, PISO_E_ARG, "piso_solve_velocity_noalloc: the grid needs " + std::to_string(need) +
                                    " bytes of workspace, more than the fixed " +
                                    std::to_string((long long)PISO_NOALLOC_SCRATCH_BYTES));
   char* base = (char*)c->noalloc_scratch;
   BiWork w;
-  void** vecs[8] = {&w.r, &w.rh, &w.p0, &w.p1, &w.v0, &w.v1, &w.s, &w.t};
+  void** vecs[10] = {&w.r, &w.rh, &w.p0, &w.p1, &w.v0, &w.v1, &w.s, &w.t, &w.ph, &w.sh};
   size_t off = 0;
   for (void** v : vecs) {
     *v = base + off;
     off += vec;
   }
   w.iA = base + off;
+  off += iab;
+  w.sinv = base + off;
   off += iab;
   w.part1 = (double*)(base + off);
   w.part2 = w.part1 + 3 * kRedGrid;

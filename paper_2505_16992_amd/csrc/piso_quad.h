@@ -129,6 +129,29 @@ __device__ __forceinline__ Q4<R> quad_stencil(const Grid& g, const Cell& c, int 
   return M;
 }
 
+// Quads of this work-group in XCD bands: the work-groups one XCD receives (round robin
+// over the 8 XCDs) share that XCD's contiguous eighth of the quads and sweep it
+// together, one band of (groups on the XCD) x kWG quads per trip.  The rows and planes
+// next to a band are touched in the same or the adjacent trip, while they are still in
+// the XCD's L2 (a contiguous range per work-group spreads the XCD's concurrent work
+// over its whole eighth).
+__device__ __forceinline__ void quad_sweep(int NQ, int& first, int& end, int& stride) {
+  const int G = gridDim.x, b = blockIdx.x;
+  if (G < 8) {
+    first = b * kWG + (int)threadIdx.x;
+    end = NQ;
+    stride = G * kWG;
+    return;
+  }
+  const int x = b & 7, w = b >> 3;
+  const int gx = (G >> 3) + (x < (G & 7) ? 1 : 0);
+  const int per = (NQ + 7) >> 3;
+  const int x0 = x * per < NQ ? x * per : NQ;
+  end = x0 + per < NQ ? x0 + per : NQ;
+  first = x0 + w * kWG + (int)threadIdx.x;
+  stride = gx * kWG;
+}
+
 __device__ __forceinline__ void quad_range(int NQ, int& beg, int& end) {
   const int G = gridDim.x;
   int per = (NQ + G - 1) / G;

@@ -5,8 +5,9 @@
 * 5-block cylinder (65,536 cells): 64-step rollout with a checkpoint every 8 steps,
   gradient of <w, u^64> with respect to the per-cell source; central differences of
   the FP64 path on 10 seeded cells; FP32 adjoint against the FP64 adjoint.
-* 192x128x192 channel (4.7 M cells): one step of each form against the oracle, and a
-  forward+adjoint rollout with step checkpointing (k = 1 and k = 4 agree).
+* 192x128x192 channel (4.7 M cells): one step of each form against the oracle, and the
+  32-step forward+adjoint MIXED rollout with step checkpointing (k = 1 and k = 4 give
+  the same gradient with respect to u^0 bit for bit, with respect to S to rounding).
 """
 import numpy as np
 import pytest
@@ -169,7 +170,8 @@ def test_channel192_forms_and_checkpointed_rollout():
         tol = 1e-9 if prec == "f64" else 1e-7
         assert eu < tol and ep < tol
         assert mu_ < 10 * tol and mp < 10 * tol
-    # 4-step forward+adjoint rollout with checkpointing (k = 1 and k = 4), MIXED
+    # the 32-step forward+adjoint rollout with step checkpointing (k = 1: every step's
+    # tape recomputed in the backward; k = 4), MIXED: the same gradients bit for bit
     ctx = api.Context(case.domain, "mixed")
     t = ctx.dtype
     u0, p0, nu, ub = dev(u, t), dev(case.p0, t), dev([case.nu], t), dev(case.u_b, t)
@@ -178,8 +180,13 @@ def test_channel192_forms_and_checkpointed_rollout():
     res = []
     for kk in (1, 4):
         u_ = u0.clone().requires_grad_(True)
-        uT, _ = api.rollout(ctx, u_, p0, S, nu, ub, case.dt, 4, checkpoint_every=kk)
-        (gu,) = torch.autograd.grad((uT * w).sum(), [u_])
-        res.append(gu)
-    assert torch.isfinite(res[0]).all()
-    assert torch.equal(res[0], res[1])
+        S_ = S.clone().requires_grad_(True)
+        uT, _ = api.rollout(ctx, u_, p0, S_, nu, ub, case.dt, 32, checkpoint_every=kk)
+        res.append(torch.autograd.grad((uT * w).sum(), [u_, S_]))
+        say("  32-step rollout k=%d done" % kk)
+    assert all(torch.isfinite(g).all() for g in res[0])
+    # du0 flows through the same chain of step adjoints: identical; dS sums the steps'
+    # contributions in an order that depends on the segmenting: equal to rounding
+    assert torch.equal(res[0][0], res[1][0])
+    assert rel(host(res[0][1]), host(res[1][1])) < 1e-12
+
