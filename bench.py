@@ -32,7 +32,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2505_16992_amd", "csrc")
-DIGEST_SOURCES = ["piso_common.h", "piso_quad.h", "piso_krylov.hip", "piso_mg.hip", "piso_line.hip"]
+DIGEST_SOURCES = ["piso_common.h", "piso_quad.h", "piso_krylov.hip", "piso_mg.hip", "piso_line.hip",
+                  "piso_zmarch.hip"]
 
 
 def kernel_digest():
@@ -167,6 +168,7 @@ def pcg_roofline(ctx, dom, opts, tm, workload, precision):
     quad = all(b[0] % 4 == 0 for b in dom.blocks)
     nch = 2 ** d
     line = mg and bool(ctx.mg_line_axis)
+    zm = mg and ctx.mg_marching_groups > 0   # plane-marching fine-grid kernels (same bytes)
     model = {
         # Pf (d), operand (z, or r and Dinv), d_old -> d_new, q
         "cg_stencil": ("k_cg_spmv_q" if quad else "k_cg_spmv", N * ((d + 4) if mg else (d + 5)) * es),
@@ -179,6 +181,9 @@ def pcg_roofline(ctx, dom, opts, tm, workload, precision):
         # y, r, Dinv, Pf (d), level-1 correction -> z
         "mg_up0": ("k_mg_up0_q" if quad else "k_mg_up0", N * (d + 4) * es + (N // nch) * es),
     }
+    if zm:
+        for k, name in (("cg_stencil", "k_zm_spmv"), ("cg_update_restrict", "k_zm_down"), ("mg_up0", "k_zm_up")):
+            model[k] = (name, model[k][1])
     if line:
         # line smoothing: the update kernel smooths (x, r, d_new, q, Dinv, Pf along the
         # line -> x, r', y) and the restriction runs every iteration; the first

@@ -231,6 +231,17 @@ int piso_mg_info(const piso_ctx* ctx, int32_t* n_levels, int64_t* cells, int32_t
  * grid allows them. */
 int piso_mg_smoother(const piso_ctx* ctx, int32_t* line_axis);
 
+/* Work-groups of the plane-marching fine-grid kernels of the multigrid PCG: *groups > 0
+ * when they run for this context's pressure solves, else 0.  They run on 3D grids whose
+ * blocks all have nx % 4 == 0, with point smoothing on the fine level, when one field of
+ * the pressure Krylov vectors (float in the F32 and MIXED forms, double in F64) takes at
+ * least 64 MiB.  They compute the same iteration as the one-quad-per-thread kernels (the
+ * PCG of App. A.6 with the multigrid preconditioner) in another summation order; a tile of
+ * rows marches through a run of planes, its neighbours in x and y shared in LDS and those
+ * in z carried from plane to plane.  PISO_ZMARCH=0 in the environment at creation keeps
+ * the one-quad-per-thread kernels, PISO_ZMARCH=1 takes the marching ones at every size. */
+int piso_mg_marching(const piso_ctx* ctx, int32_t* groups);
+
 /* Default options for a precision: vel rtol 1e-7 (F32) / 1e-10 (F64, MIXED), Jacobi with
  * the ILU(0) restart on failure (PISO_PRECOND_JACOBI_ILU0);
  * pres rtol 1e-10 (F64), 1e-6 (F32), 1e-8 (MIXED), multigrid-preconditioned; MIXED inner

@@ -80,6 +80,7 @@ _SIGS = {
     "piso_create_error": (C.c_char_p, []),
     "piso_sizes": (I32, [VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                          C.POINTER(C.c_int64), C.POINTER(I32)]),
+    "piso_mg_marching": (I32, [VP, C.POINTER(I32)]),
     "piso_mg_info": (I32, [VP, C.POINTER(I32), C.POINTER(C.c_int64), C.POINTER(I32)]),
     "piso_default_step_opts": (None, [I32, C.POINTER(StepOpts)]),
     "piso_assemble": (I32, [VP, VP, VP, VP, VP, I32, VP, VP, F64, I32, C.POINTER(System)]),

@@ -90,6 +90,9 @@ class Context:
         la = C.c_int32(0)
         self._check(self.lib.piso_mg_smoother(self.h, C.byref(la)), "piso_mg_smoother")
         self.mg_line_axis = int(la.value)   # 0: point Jacobi on the fine level, 1/2: lines along y/z
+        zg = C.c_int32(0)
+        self._check(self.lib.piso_mg_marching(self.h, C.byref(zg)), "piso_mg_marching")
+        self.mg_marching_groups = int(zg.value)   # > 0: the plane-marching fine-grid kernels run
 
     def __del__(self):
         h = getattr(self, "h", None)

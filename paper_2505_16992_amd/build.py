@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libpiso.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["piso_api.hip", "piso_fwd.hip", "piso_krylov.hip", "piso_mg.hip", "piso_line.hip", "piso_outflow.hip",
            "piso_stats.hip", "piso_bwd.hip", "piso_noalloc.hip",
-           "piso_moments.hip"]
+           "piso_moments.hip", "piso_zmarch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PISO_OFFLOAD_ARCH", "gfx950")

@@ -440,6 +440,7 @@ int piso_create(const piso_domain_desc* desc, int32_t precision, piso_ctx** out)
   for (int b = 0; b < c->nblocks; ++b)
     if (desc->block_cells[3 * b] % 4 != 0) c->quad = false;
   if (const char* e = std::getenv("PISO_NO_QUAD")) c->quad = c->quad && e[0] == '0';   // can only turn it off
+  zm_setup(c);   // host only: tiles of the plane-marching kernels (needs quad and the hierarchy)
   if (const char* e = std::getenv("PISO_NO_GRAPH")) c->use_graphs = (e[0] == '0');
   if (const char* e = std::getenv("PISO_CG_GROUPS")) {
     const int v = std::atoi(e);
@@ -484,6 +485,13 @@ int piso_mg_info(const piso_ctx* c, int32_t* n_levels, int64_t* cells, int32_t* 
     if (cells) cells[l] = c->mg[l].n;
     if (slots) slots[l] = c->mg[l].K;
   }
+  return PISO_OK;
+}
+
+int piso_mg_marching(const piso_ctx* c, int32_t* groups) {
+  if (!c || !groups) return PISO_E_ARG;
+  // the pressure Krylov vectors are float in the F32 and MIXED forms
+  *groups = zm_use(c, c->prec == PISO_F64 ? 8 : 4) ? zm_groups(c) : 0;
   return PISO_OK;
 }
 

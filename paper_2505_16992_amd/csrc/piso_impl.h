@@ -107,6 +107,23 @@ struct MgQuadTiles {
   int units[kMaxBlocks];
 };
 
+// Work-groups of the plane-marching fine-grid kernels (piso_zmarch.hip): per block, the
+// first group, quads per tile row, rows per tile, planes per run, tiles in x and in y.
+struct ZmTiles {
+  int nb;
+  int off[kMaxBlocks + 1];
+  int xq[kMaxBlocks], rt[kMaxBlocks], ks[kMaxBlocks];
+  int ntx[kMaxBlocks], nty[kMaxBlocks];
+};
+constexpr int kZmWG = 512;         // threads of a plane-marching work-group
+constexpr int kZmTarget = 512;     // work-groups the run length aims at (2 per CU)
+constexpr int kZmMinPlanes = 8;    // shortest run of planes (each run re-reads two planes)
+// They pay where the one-quad-per-thread kernels' re-reads go to HBM: measured per PCG
+// iteration, 256^3 (64 MiB per float field) 505 -> 441 us in FP32 and 1019 -> 827 us in
+// FP64; at 192x128x192 they lose (FP32 142 against 148 us, FP64 300 against 311 us: the
+// re-reads still hit the 256 MB Infinity Cache, and 312 work-groups fill the chip badly).
+constexpr size_t kZmMinStreamBytes = size_t(64) << 20;
+
 constexpr int kMgCoarse = 2048;     // stop coarsening at this many cells (one work-group solves it)
 constexpr int kMgCoarseThreads = 1024;   // that work-group: kMgCoarse / kMgCoarseThreads cells per thread
 constexpr int kMgMaxLevels = 16;
@@ -180,6 +197,9 @@ struct piso_ctx {
   piso::Grid mg_g1{};             // level 1 as a block table (offsets, dims, division magic)
   piso::MgTiles mg_tiles{};       // work-group tiles of the fine-grid restriction
   piso::MgQuadTiles mg_qtiles{};  // the same for the quad-vectorised fused update (nx % 4 == 0)
+  piso::ZmTiles zm_tiles{};       // tiles of the plane-marching fine-grid kernels
+  bool zm_on = false;             // 3D quad grid with a hierarchy: those kernels may run
+  bool zm_force = false;          // PISO_ZMARCH=1: at every size
   bool mg_struct = false;         // single block: coarse levels indexed by position
   int mg_line_axis = 0;           // fine-level line smoothing along this axis (0: point Jacobi)
   int mg_line_L = 0;              // cells per line segment (8 segments per line)
@@ -375,6 +395,28 @@ template <typename R>
 int mg_update_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, R* x, const R* rin, R* rout,
                     const R* dnew, const R* q, R* y, R* z, CgState* st, const double* partA, int Gp, int par,
                     double* partB, int G);
+
+// ---- plane-marching fine-grid kernels (piso_zmarch.hip) ----
+// Tiles for 3D grids of quads with a multigrid hierarchy (sets zm_on).  PISO_ZMARCH=0 keeps
+// the one-quad-per-thread kernels, PISO_ZMARCH=1 takes the marching ones at every size.
+int zm_setup(piso_ctx* c);
+int zm_groups(const piso_ctx* c);
+// For Krylov vectors of es bytes per element: tiles built, point smoothing, and a large grid.
+inline bool zm_use(const piso_ctx* c, size_t es) {
+  return c->zm_on && c->mg_line_axis == 0 && (c->zm_force || (size_t)c->N * es >= kZmMinStreamBytes);
+}
+// The PCG update fused with the fine-level pre-smoothing and restriction (as k_mg_down0uq).
+template <typename R>
+int zm_launch_down(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, R* x, const R* rin, R* rout,
+                   const R* dnew, const R* q, R* y, R* rc, CgState* st, const double* partA, int Gp, int par);
+// The direction update and M d with the d.q partials (as k_cg_spmv_q with z as operand).
+template <typename R>
+int zm_launch_spmv(piso_ctx* c, hipStream_t s, const R* Pf, const R* z, const R* dold, R* dnew, R* q, CgState* st,
+                   const double* partB, double* partA, int Gp, int par);
+// The prolongation with the fine-level post-smoothing and the r.z, r.r partials (as k_mg_up0_q).
+template <typename R>
+int zm_launch_up(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, const R* y, const int* parent,
+                 const R* e1, R* z, double* partB, const CgState* st);
 
 // ---- fine-level line smoothing (piso_line.hip) ----
 // Chooses the line axis for a single-block grid whose metric is strongly anisotropic

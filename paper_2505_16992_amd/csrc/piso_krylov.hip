@@ -1035,7 +1035,12 @@ static int pcg_iteration(piso_ctx* c, hipStream_t s, const PcgOps<R>& o, int par
   R* dnew = par ? o.d0 : o.d1;
   const R* opnd = o.mg ? (const R*)o.z : (const R*)o.r;
   const double* pBc = o.pB;
-  if (o.quad) {
+  // 3D multigrid with point smoothing: the plane-marching kernels (their own grid)
+  const bool zm = o.quad && o.mg && !o.line && zm_use(c, sizeof(R));
+  const int Gs = zm ? zm_groups(c) : G;   // groups of the stencil kernel's d.q partials
+  if (zm) {
+    zm_launch_spmv<R>(c, s, o.Pf, (const R*)o.z, (const R*)dold, dnew, o.q, st, pBc, o.pA, o.Gz, par);
+  } else if (o.quad) {
     if (c->dim == 2) {
       if (o.mg)
         launch_timed(c, s, kTimeCgStencil, k_cg_spmv_q<R, 2, true>, G, c->grid, o.Pf, o.Dinv, opnd,
@@ -1087,7 +1092,7 @@ static int pcg_iteration(piso_ctx* c, hipStream_t s, const PcgOps<R>& o, int par
   }
   if (o.mg)
     return mg_update_apply<R>(c, s, o.Pf, o.Dinv, o.x, par ? (const R*)o.r2 : (const R*)o.r, par ? o.r : o.r2,
-                              (const R*)dnew, (const R*)o.q, o.y, o.z, st, (const double*)o.pA, G, par, o.pB, G);
+                              (const R*)dnew, (const R*)o.q, o.y, o.z, st, (const double*)o.pA, Gs, par, o.pB, G);
   return check(c, "PCG iteration");
 }
 
@@ -1142,7 +1147,7 @@ static int pcg_run(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
   o.mg = precond == PISO_PRECOND_MG && !c->mg.empty();
   o.quad = c->quad;   // the context's buffers are 256-byte aligned
   o.line = o.mg && c->mg_line_axis != 0;
-  o.Gz = o.line ? line_groups(c) : G;
+  o.Gz = o.line ? line_groups(c) : (o.mg && o.quad && zm_use(c, sizeof(R)) ? zm_groups(c) : G);
   const size_t es = sizeof(R);
   const bool reuse = c->pcg_same_op && c->pcg_op_src == (const void*)Pf && c->pcg_op_es == (int)es &&
                      (c->pcg_op_mg || !o.mg);

@@ -1204,7 +1204,9 @@ static int mg_tail(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const
     const bool quad = c->quad && ((((uintptr_t)Pf) | ((uintptr_t)Dinv) | ((uintptr_t)r) | ((uintptr_t)y) |
                                    ((uintptr_t)z)) & 15u) == 0;
     const R* e1 = (const R*)L1.e;
-    if (quad) {
+    if (quad && zm_use(c, sizeof(R))) {
+      zm_launch_up<R>(c, s, Pf, Dinv, r, y, (const int*)L1.parent, e1, z, partB, (const CgState*)st);
+    } else if (quad) {
       if (c->dim == 2)
         launch_timed(c, s, kTimeMgUp0, k_mg_up0_q<R, 2>, G, c->grid, g1, Pf, Dinv, r, y, (const int*)L1.parent, e1,
                      om, z, partB, (const CgState*)st);
@@ -1246,7 +1248,9 @@ int mg_update_apply(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, R* x
   const R om = (R)kMgOmega;
   const bool quad = c->quad && ((((uintptr_t)Pf) | ((uintptr_t)Dinv) | ((uintptr_t)x) | ((uintptr_t)rin) |
                                  ((uintptr_t)rout) | ((uintptr_t)dnew) | ((uintptr_t)q) | ((uintptr_t)y)) & 15u) == 0;
-  if (quad) {
+  if (quad && zm_use(c, sizeof(R))) {
+    zm_launch_down<R>(c, s, Pf, Dinv, x, rin, rout, dnew, q, y, (R*)c->mg[0].r, st, partA, Gp, par);
+  } else if (quad) {
     const int groups = c->mg_qtiles.off[c->nblocks];
     if (c->dim == 2)
       launch_timed(c, s, kTimeCgUpdateMg, k_mg_down0uq<R, 2>, groups, c->grid, c->mg_g1, c->mg_qtiles, Pf, Dinv, x,
