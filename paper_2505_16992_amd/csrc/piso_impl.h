@@ -114,6 +114,7 @@ struct ZmTiles {
   int off[kMaxBlocks + 1];
   int xq[kMaxBlocks], rt[kMaxBlocks], ks[kMaxBlocks];
   int ntx[kMaxBlocks], nty[kMaxBlocks];
+  bool plain;   // the kernels' form without sides connected to other blocks (see zm_setup)
 };
 constexpr int kZmWG = 512;         // threads of a plane-marching work-group
 constexpr int kZmTarget = 512;     // work-groups the run length aims at (2 per CU)

@@ -145,6 +145,15 @@ __device__ __forceinline__ Q4<R> zq4() {
 }  // namespace
 
 // ---------------------------------------------------------------------------------
+// Loop structure shared by the three kernels.  Step k: (a) issue the loads of plane k's
+// neighbours that come from memory (the rows beside the tile, the plane after the run),
+// (b) issue the next plane's own loads, unconditionally (the last step reads its own
+// plane again), (c) compute plane k, exchange through LDS, complete plane k - 1.  Every
+// load plane k needs is issued before (b): the hardware counts outstanding loads in
+// order, so a load issued after (b) and used in (c) would make (c) wait for the next
+// plane too.  Rarer paths (sides connected to other blocks, rows split over several
+// tiles in x) load in (c) and pay that wait.
+
 // PCG update fused with the fine-level pre-smoothing and restriction (the marching form
 // of k_mg_down0uq): alpha = rz / (d.q) from the stencil kernel's partials, x += alpha d,
 // r' = r - alpha q, y = omega D^-1 r', and the level-1 residual of each 2x2x2 aggregate,
@@ -152,8 +161,8 @@ __device__ __forceinline__ Q4<R> zq4() {
 // P_f (y_P - y_F).  Aggregates are pairs of quad cells (0,1) and (2,3), rows (j, j+1) with
 // j even (the two rows are two threads of the tile: the odd row hands its sums to the
 // even one through LDS) and planes (k, k+1) with k even (summed in the thread).
-template <typename R, int WGS>
-__global__ void __launch_bounds__(WGS) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 1)))
+template <typename R, int WGS, bool GEN>
+__global__ void __launch_bounds__(WGS)
 k_zm_down(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __restrict__ Dinv, R* __restrict__ x,
           const R* __restrict__ rin, R* __restrict__ rout, const R* __restrict__ dnew, const R* __restrict__ q,
           R* __restrict__ y, R omega, R* __restrict__ rc, CgState* st, const double* __restrict__ partA, int Gp,
@@ -174,25 +183,37 @@ k_zm_down(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __rest
   const bool in_tile = p.jr < p.RT;
   const int hu = (p.jr >> 1) * p.XQ + p.xl;   // slot of the row pair (p.jr < p.RT)
   const int* tc = g1.tab + p.b * kTabStride;
-  const int cx = tc[1], cy = tc[2];
+  const int tc0 = tc[0], cx = tc[1], cy = tc[2];
   const int i0 = 4 * p.xq;
+  const bool wym = (p.wrap >> 2) & 1, wyp = (p.wrap >> 3) & 1, wzp = (p.wrap >> 5) & 1;
+  // y faces crossed through memory: -y by the even row starting the tile (or row 0 of a
+  // block wrapping in y), +y by the odd row ending it (or the last row of a wrapping block,
+  // also when that row is even: a one-row aggregate)
+  const bool ym = p.act && !odd && (p.j > 0 ? p.jr == 0 : wym);
+  const bool yp = p.act && (odd ? (p.j + 1 < p.ny ? p.jr + 1 == p.RT : wyp) : (p.j + 1 == p.ny && wyp));
+  const int oym = p.j > 0 ? -p.nx : (p.ny - 1) * p.nx;
+  const int oyp = p.j + 1 < p.ny ? p.nx : -(p.ny - 1) * p.nx;
+  // P_y is needed by odd rows (and a one-row aggregate), P_z by odd planes (and a one-plane
+  // aggregate): the other rows and planes read P_x's line again instead, without a branch
+  const size_t oy = (odd || p.j + 1 == p.ny) ? (size_t)N : 0;   // offsets (a select of values, not of lvalues)
   struct Ld {
     Q4<R> x, d, r, q, D, px, py, pz;
   };
-  auto load = [&](int k) {
+  auto load = [=](int k) __attribute__((always_inline)) {
     Ld L;
     const int P = p.act ? p.base + S * k : 0;
+    const size_t oz = ((k & 1) || k + 1 == p.nz) ? 2 * (size_t)N : 0;
     L.x = ldq(x, P);
     L.d = ldq(dnew, P);
     L.r = ldq(rin, P);
     L.q = ldq(q, P);
     L.D = ldq(Dinv, P);
     L.px = ldq(Pf, P);
-    L.py = (odd || p.j + 1 == p.ny) ? ldq(Py, P) : zq4<R>();
-    L.pz = ((k & 1) || k + 1 == p.nz) ? ldq(Pz, P) : zq4<R>();
+    L.py = ldq(Pf + oy, P);
+    L.pz = ldq(Pf + oz, P);
     return L;
   };
-  Ld cur = load(p.k0);
+  Ld bufA = load(p.k0), bufB;
   // the plane before the run (its y and P_z cross into plane k0), when it lies in the block
   Q4<R> hr = zq4<R>(), hq = zq4<R>(), hD = zq4<R>(), hpz = zq4<R>();
   const bool hz_in = p.k0 > 0 || ((p.wrap >> 4) & 1);
@@ -217,32 +238,55 @@ k_zm_down(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __rest
   }
   const R alpha = (R)(rzp / dq);
   if (blockIdx.x == 0 && threadIdx.x == 0) st->k = st->k + 1;   // no other group reads it here
-  auto y1 = [&](int F) { return omega * Dinv[F] * (rin[F] - alpha * q[F]); };
-  auto y4 = [&](int P) {
-    const Q4<R> a = ldq(rin, P), b = ldq(q, P), c = ldq(Dinv, P);
+  auto yv = [&](const Q4<R>& a, const Q4<R>& b, const Q4<R>& c) __attribute__((always_inline)) {
     Q4<R> o;
 #pragma unroll
     for (int e = 0; e < 4; ++e) o.v[e] = omega * c.v[e] * (a.v[e] - alpha * b.v[e]);
     return o;
   };
+  const Q4<R> yh = yv(hr, hq, hD);   // y of the plane before the run
+  auto y1 = [&](int F) __attribute__((always_inline)) { return omega * Dinv[F] * (rin[F] - alpha * q[F]); };
   // completed aggregate sums (cells 0,1 and 2,3 of the quad) of the plane pair ck
-  auto emit = [&](R a, R bb, int ck, int buf) {
+  auto emit = [&](R a, R bb, int ck, int buf) __attribute__((always_inline)) {
     if (p.j + 1 < p.ny) {
       a += lag[buf][hu][0];
       bb += lag[buf][hu][1];
     }
-    const int I = tc[0] + 2 * p.xq + cx * ((p.j >> 1) + cy * ck);
+    const int I = tc0 + 2 * p.xq + cx * ((p.j >> 1) + cy * ck);
     rc[I] = a;
     rc[I + 1] = bb;
   };
   Q4<R> yprev = zq4<R>(), pzprev = zq4<R>();
   R agA = R(0), agB = R(0), pendA = R(0), pendB = R(0);
   int pend = -1;   // plane pair of a completed aggregate waiting for the odd row's sums
-  for (int k = p.k0; k < p.k1; ++k) {
-    Ld nxt;
-    if (k + 1 < p.k1) nxt = load(k + 1);
+  // one plane: cur holds its loads, the next plane's go to nxt (two buffers used in
+  // turn, so that no register copy waits for the loads in flight)
+  auto step = [&](const int k, const Ld& cur, Ld& nxt) __attribute__((always_inline)) {
     const int bs = k & 1;
     const int Pk = p.act ? p.base + S * k : 0;
+    // (a) neighbours in memory
+    Q4<R> a0, a1, a2, a3, b0, b1, b2, c0, c1, c2;
+    if (ym) {
+      a0 = ldq(rin, Pk + oym);
+      a1 = ldq(q, Pk + oym);
+      a2 = ldq(Dinv, Pk + oym);
+      a3 = ldq(Py, Pk + oym);
+    }
+    if (yp) {
+      b0 = ldq(rin, Pk + oyp);
+      b1 = ldq(q, Pk + oyp);
+      b2 = ldq(Dinv, Pk + oyp);
+    }
+    const bool zp = p.act && (k & 1) && k + 1 == p.k1 && (k + 1 < p.nz || wzp);
+    if (zp) {
+      const int Pn = k + 1 < p.nz ? Pk + S : Pk - (p.nz - 1) * S;
+      c0 = ldq(rin, Pn);
+      c1 = ldq(q, Pn);
+      c2 = ldq(Dinv, Pn);
+    }
+    // (b) the next plane
+    nxt = load(k + 1 < p.k1 ? k + 1 : k);
+    // (c) this plane
     Q4<R> yk, res, xv;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -269,7 +313,7 @@ k_zm_down(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __rest
         bool have = true;
         R yl = R(0), pl = R(0);
         if (i0 > 0) {
-          if (p.xl > 0) {
+          if (!GEN || p.xl > 0) {
             yl = ly[bs][u - 1].v[3];
             pl = lpx[bs][u - 1];
           } else {
@@ -277,13 +321,15 @@ k_zm_down(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __rest
             pl = Pf[Pk - 1];
           }
         } else if (p.wrap & 1) {
-          if (p.XQ == p.nxq) {
+          if (!GEN || p.XQ == p.nxq) {
             yl = ly[bs][u + p.nxq - 1].v[3];
             pl = lpx[bs][u + p.nxq - 1];
           } else {
             yl = y1(Pk + p.nx - 1);
             pl = Pf[Pk + p.nx - 1];
           }
+        } else if constexpr (!GEN) {
+          have = false;
         } else {
           const int F = g.fmap[p.tf[4] + p.j + p.ny * k];
           have = F >= 0;
@@ -300,9 +346,11 @@ k_zm_down(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __rest
         bool have = true;
         R yr = R(0);
         if (i0 + 4 < p.nx) {
-          yr = p.xl + 1 < p.XQ ? ly[bs][u + 1].v[0] : y1(Pk + 4);
+          yr = (!GEN || p.xl + 1 < p.XQ) ? ly[bs][u + 1].v[0] : y1(Pk + 4);
         } else if (p.wrap & 2) {
-          yr = p.XQ == p.nxq ? ly[bs][u - (p.nxq - 1)].v[0] : y1(Pk + 4 - p.nx);
+          yr = (!GEN || p.XQ == p.nxq) ? ly[bs][u - (p.nxq - 1)].v[0] : y1(Pk + 4 - p.nx);
+        } else if constexpr (!GEN) {
+          have = false;
         } else {
           const int F = g.fmap[p.tf[5] + p.j + p.ny * k];
           have = F >= 0;
@@ -313,19 +361,18 @@ k_zm_down(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __rest
       // y faces: the even row crosses to row j - 1 (coefficient stored there), the odd
       // row to row j + 1 (its own coefficient)
       if (!odd) {
-        if (p.j > 0 || ((p.wrap >> 2) & 1)) {
+        if (p.j > 0 || wym) {
           Q4<R> yn, wn;
-          if (p.j > 0 && p.jr > 0) {
+          if (p.jr > 0) {
             yn = ly[bs][u - p.XQ];
             wn = lpy[bs][((p.jr - 1) >> 1) * p.XQ + p.xl];
           } else {
-            const int Pn = p.j > 0 ? Pk - p.nx : Pk + (p.ny - 1) * p.nx;
-            yn = y4(Pn);
-            wn = ldq(Py, Pn);
+            yn = yv(a0, a1, a2);
+            wn = a3;
           }
 #pragma unroll
           for (int e = 0; e < 4; ++e) res.v[e] -= wn.v[e] * (yk.v[e] - yn.v[e]);
-        } else {
+        } else if constexpr (GEN) {
           const int bse = p.tf[6] + i0 + p.nx * k;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
@@ -333,12 +380,12 @@ k_zm_down(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __rest
             if (F >= 0) res.v[e] -= Py[F] * (yk.v[e] - y1(F));
           }
         }
-        if (p.j + 1 == p.ny) {   // a one-row aggregate at the block's end: its +y face leaves too
-          if ((p.wrap >> 3) & 1) {
-            const Q4<R> yn = y4(Pk - (p.ny - 1) * p.nx);
+        if (GEN && p.j + 1 == p.ny) {   // a one-row aggregate at the block's end: its +y face leaves too
+          if (wyp) {
+            const Q4<R> yn = yv(b0, b1, b2);
 #pragma unroll
             for (int e = 0; e < 4; ++e) res.v[e] -= cur.py.v[e] * (yk.v[e] - yn.v[e]);
-          } else {
+          } else if constexpr (GEN) {
             const int bse = p.tf[7] + i0 + p.nx * k;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -348,13 +395,11 @@ k_zm_down(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __rest
           }
         }
       } else {
-        if (p.j + 1 < p.ny || ((p.wrap >> 3) & 1)) {
-          Q4<R> yn;
-          if (p.j + 1 < p.ny && p.jr + 1 < p.RT) yn = ly[bs][u + p.XQ];
-          else yn = y4(p.j + 1 < p.ny ? Pk + p.nx : Pk - (p.ny - 1) * p.nx);
+        if (p.j + 1 < p.ny || wyp) {
+          const Q4<R> yn = (p.j + 1 < p.ny && p.jr + 1 < p.RT) ? ly[bs][u + p.XQ] : yv(b0, b1, b2);
 #pragma unroll
           for (int e = 0; e < 4; ++e) res.v[e] -= cur.py.v[e] * (yk.v[e] - yn.v[e]);
-        } else {
+        } else if constexpr (GEN) {
           const int bse = p.tf[7] + i0 + p.nx * k;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
@@ -374,8 +419,8 @@ k_zm_down(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __rest
       } else if (p.act) {
         if (hz_in) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) f.v[e] = hpz.v[e] * (omega * hD.v[e] * (hr.v[e] - alpha * hq.v[e]) - yk.v[e]);
-        } else {
+          for (int e = 0; e < 4; ++e) f.v[e] = hpz.v[e] * (yh.v[e] - yk.v[e]);
+        } else if constexpr (GEN) {
           const int bse = p.tf[8] + i0 + p.nx * p.j;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
@@ -399,12 +444,13 @@ k_zm_down(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __rest
       }
       agA = res.v[0] + res.v[1];
       agB = res.v[2] + res.v[3];
-      if (k + 1 == p.nz && p.act) {   // a one-plane aggregate at the block's end
-        if ((p.wrap >> 5) & 1) {
-          const Q4<R> yn = y4(Pk - (p.nz - 1) * S);
+      if (GEN && k + 1 == p.nz && p.act) {   // a one-plane aggregate at the block's end
+        if (wzp) {
+          const Q4<R> yn = yv(ldq(rin, Pk - (p.nz - 1) * S), ldq(q, Pk - (p.nz - 1) * S),
+                              ldq(Dinv, Pk - (p.nz - 1) * S));
           agA -= cur.pz.v[0] * (yk.v[0] - yn.v[0]) + cur.pz.v[1] * (yk.v[1] - yn.v[1]);
           agB -= cur.pz.v[2] * (yk.v[2] - yn.v[2]) + cur.pz.v[3] * (yk.v[3] - yn.v[3]);
-        } else {
+        } else if constexpr (GEN) {
           const int bse = p.tf[9] + i0 + p.nx * p.j;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
@@ -421,11 +467,11 @@ k_zm_down(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __rest
       yprev = yk;
       pzprev = cur.pz;
       if (k + 1 == p.k1 && p.act) {   // the run ends: face (k | k+1) to the next run or across the side
-        if (k + 1 < p.nz || ((p.wrap >> 5) & 1)) {
-          const Q4<R> yn = y4(k + 1 < p.nz ? Pk + S : Pk - (p.nz - 1) * S);
+        if (zp) {
+          const Q4<R> yn = yv(c0, c1, c2);
           agA -= cur.pz.v[0] * (yk.v[0] - yn.v[0]) + cur.pz.v[1] * (yk.v[1] - yn.v[1]);
           agB -= cur.pz.v[2] * (yk.v[2] - yn.v[2]) + cur.pz.v[3] * (yk.v[3] - yn.v[3]);
-        } else {
+        } else if constexpr (GEN) {
           const int bse = p.tf[9] + i0 + p.nx * p.j;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
@@ -437,7 +483,12 @@ k_zm_down(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __rest
         }
       }
     }
-    if (k + 1 < p.k1) cur = nxt;
+  };
+  for (int k = p.k0;;) {
+    step(k, bufA, bufB);
+    if (++k >= p.k1) break;
+    step(k, bufB, bufA);
+    if (++k >= p.k1) break;
   }
   // the run's last plane pair (and a pair completed at the last step)
   __syncthreads();
@@ -455,7 +506,7 @@ k_zm_down(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __rest
 // k_cg_spmv_q<R, 3, true>): the PCG's convergence test on the r.z, r.r partials of the
 // V-cycle, beta = rz / rz_old, d = z + beta d_old, q = M d.  q of plane k - 1 is completed
 // at step k (its face to plane k) and stored then.
-template <typename R, int WGS>
+template <typename R, int WGS, bool GEN>
 __global__ void __launch_bounds__(WGS)
 k_zm_spmv(Grid g, ZmTiles tl, const R* __restrict__ Pf, const R* __restrict__ zin, const R* __restrict__ dold,
           R* __restrict__ dnew, R* __restrict__ q, CgState* st, const double* __restrict__ partB,
@@ -471,10 +522,16 @@ k_zm_spmv(Grid g, ZmTiles tl, const R* __restrict__ Pf, const R* __restrict__ zi
   const R* __restrict__ Pz = Pf + 2 * (size_t)N;
   const int u = threadIdx.x;
   const int i0 = 4 * p.xq;
+  const bool wym = (p.wrap >> 2) & 1, wyp = (p.wrap >> 3) & 1, wzp = (p.wrap >> 5) & 1;
+  // y faces crossed through memory: -y by the tile's first row, +y by its last
+  const bool ym = p.act && (p.j > 0 ? p.jr == 0 : wym);
+  const bool yp = p.act && (p.j + 1 < p.ny ? p.jr + 1 == p.RT : wyp);
+  const int oym = p.j > 0 ? -p.nx : (p.ny - 1) * p.nx;
+  const int oyp = p.j + 1 < p.ny ? p.nx : -(p.ny - 1) * p.nx;
   struct Ld {
     Q4<R> z, o, px, py, pz;
   };
-  auto load = [&](int k) {
+  auto load = [&](int k) __attribute__((always_inline)) {
     Ld L;
     const int P = p.act ? p.base + S * k : 0;
     L.z = ldq(zin, P);
@@ -484,7 +541,7 @@ k_zm_spmv(Grid g, ZmTiles tl, const R* __restrict__ Pf, const R* __restrict__ zi
     L.pz = ldq(Pz, P);
     return L;
   };
-  Ld cur = load(p.k0);
+  Ld bufA = load(p.k0), bufB;
   Q4<R> hz = zq4<R>(), ho = zq4<R>(), hpz = zq4<R>();
   const bool hz_in = p.k0 > 0 || ((p.wrap >> 4) & 1);
   if (p.act && hz_in) {
@@ -513,21 +570,39 @@ k_zm_spmv(Grid g, ZmTiles tl, const R* __restrict__ Pf, const R* __restrict__ zi
     st->rz[par] = rz;
     st->rr = rr;
   }
-  auto d1 = [&](int F) { return zin[F] + beta * dold[F]; };
-  auto d4 = [&](int P) {
-    const Q4<R> a = ldq(zin, P), b = ldq(dold, P);
+  auto d1 = [&](int F) __attribute__((always_inline)) { return zin[F] + beta * dold[F]; };
+  auto dv = [&](const Q4<R>& a, const Q4<R>& b) __attribute__((always_inline)) {
     Q4<R> o;
 #pragma unroll
     for (int e = 0; e < 4; ++e) o.v[e] = a.v[e] + beta * b.v[e];
     return o;
   };
-  Q4<R> dprev = zq4<R>(), pzprev = zq4<R>(), Mprev = zq4<R>();
+  Q4<R> dprev = zq4<R>(), pzprev = zq4<R>(), Mprev = zq4<R>(), dzl = zq4<R>();
   double acc[1] = {0.0};
-  for (int k = p.k0; k < p.k1; ++k) {
-    Ld nxt;
-    if (k + 1 < p.k1) nxt = load(k + 1);
+  // one plane: cur holds its loads, the next plane's go to nxt (two buffers used in
+  // turn, so that no register copy waits for the loads in flight)
+  auto step = [&](const int k, const Ld& cur, Ld& nxt) __attribute__((always_inline)) {
     const int bs = k & 1;
     const int Pk = p.act ? p.base + S * k : 0;
+    // (a) neighbours in memory
+    Q4<R> a0, a1, a3, b0, b1;
+    if (ym) {
+      a0 = ldq(zin, Pk + oym);
+      a1 = ldq(dold, Pk + oym);
+      a3 = ldq(Py, Pk + oym);
+    }
+    if (yp) {
+      b0 = ldq(zin, Pk + oyp);
+      b1 = ldq(dold, Pk + oyp);
+    }
+    const bool zp = p.act && k + 1 == p.k1 && (k + 1 < p.nz || wzp);
+    if (zp) {
+      const int Pn = k + 1 < p.nz ? Pk + S : Pk - (p.nz - 1) * S;
+      dzl = dv(ldq(zin, Pn), ldq(dold, Pn));
+    }
+    // (b) the next plane
+    nxt = load(k + 1 < p.k1 ? k + 1 : k);
+    // (c) this plane
     Q4<R> dk, M;
 #pragma unroll
     for (int e = 0; e < 4; ++e) dk.v[e] = cur.z.v[e] + beta * cur.o.v[e];
@@ -544,7 +619,7 @@ k_zm_spmv(Grid g, ZmTiles tl, const R* __restrict__ Pf, const R* __restrict__ zi
         bool have = true;
         R dl = R(0), pl = R(0);
         if (i0 > 0) {
-          if (p.xl > 0) {
+          if (!GEN || p.xl > 0) {
             dl = ld[bs][u - 1].v[3];
             pl = lpx[bs][u - 1];
           } else {
@@ -552,13 +627,15 @@ k_zm_spmv(Grid g, ZmTiles tl, const R* __restrict__ Pf, const R* __restrict__ zi
             pl = Pf[Pk - 1];
           }
         } else if (p.wrap & 1) {
-          if (p.XQ == p.nxq) {
+          if (!GEN || p.XQ == p.nxq) {
             dl = ld[bs][u + p.nxq - 1].v[3];
             pl = lpx[bs][u + p.nxq - 1];
           } else {
             dl = d1(Pk + p.nx - 1);
             pl = Pf[Pk + p.nx - 1];
           }
+        } else if constexpr (!GEN) {
+          have = false;
         } else {
           const int F = g.fmap[p.tf[4] + p.j + p.ny * k];
           have = F >= 0;
@@ -575,9 +652,11 @@ k_zm_spmv(Grid g, ZmTiles tl, const R* __restrict__ Pf, const R* __restrict__ zi
         bool have = true;
         R dr = R(0);
         if (i0 + 4 < p.nx) {
-          dr = p.xl + 1 < p.XQ ? ld[bs][u + 1].v[0] : d1(Pk + 4);
+          dr = (!GEN || p.xl + 1 < p.XQ) ? ld[bs][u + 1].v[0] : d1(Pk + 4);
         } else if (p.wrap & 2) {
-          dr = p.XQ == p.nxq ? ld[bs][u - (p.nxq - 1)].v[0] : d1(Pk + 4 - p.nx);
+          dr = (!GEN || p.XQ == p.nxq) ? ld[bs][u - (p.nxq - 1)].v[0] : d1(Pk + 4 - p.nx);
+        } else if constexpr (!GEN) {
+          have = false;
         } else {
           const int F = g.fmap[p.tf[5] + p.j + p.ny * k];
           have = F >= 0;
@@ -586,13 +665,11 @@ k_zm_spmv(Grid g, ZmTiles tl, const R* __restrict__ Pf, const R* __restrict__ zi
         M.v[3] = (have ? px.v[3] * (dk.v[3] - dr) : R(0)) + px.v[2] * (dk.v[3] - dk.v[2]);
       }
       // +y face: own coefficient
-      if (p.j + 1 < p.ny || ((p.wrap >> 3) & 1)) {
-        Q4<R> dn;
-        if (p.j + 1 < p.ny && p.jr + 1 < p.RT) dn = ld[bs][u + p.XQ];
-        else dn = d4(p.j + 1 < p.ny ? Pk + p.nx : Pk - (p.ny - 1) * p.nx);
+      if (p.j + 1 < p.ny || wyp) {
+        const Q4<R> dn = (p.j + 1 < p.ny && p.jr + 1 < p.RT) ? ld[bs][u + p.XQ] : dv(b0, b1);
 #pragma unroll
         for (int e = 0; e < 4; ++e) M.v[e] += cur.py.v[e] * (dk.v[e] - dn.v[e]);
-      } else {
+      } else if constexpr (GEN) {
         const int bse = p.tf[7] + i0 + p.nx * k;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -601,19 +678,18 @@ k_zm_spmv(Grid g, ZmTiles tl, const R* __restrict__ Pf, const R* __restrict__ zi
         }
       }
       // -y face: coefficient stored at row j - 1
-      if (p.j > 0 || ((p.wrap >> 2) & 1)) {
+      if (p.j > 0 || wym) {
         Q4<R> dn, wn;
-        if (p.j > 0 && p.jr > 0) {
+        if (p.jr > 0) {
           dn = ld[bs][u - p.XQ];
           wn = lpy[bs][u - p.XQ];
         } else {
-          const int Pn = p.j > 0 ? Pk - p.nx : Pk + (p.ny - 1) * p.nx;
-          dn = d4(Pn);
-          wn = ldq(Py, Pn);
+          dn = dv(a0, a1);
+          wn = a3;
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) M.v[e] += wn.v[e] * (dk.v[e] - dn.v[e]);
-      } else {
+      } else if constexpr (GEN) {
         const int bse = p.tf[6] + i0 + p.nx * k;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -632,7 +708,7 @@ k_zm_spmv(Grid g, ZmTiles tl, const R* __restrict__ Pf, const R* __restrict__ zi
       } else if (hz_in) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) M.v[e] += hpz.v[e] * (dk.v[e] - (hz.v[e] + beta * ho.v[e]));
-      } else {
+      } else if constexpr (GEN) {
         const int bse = p.tf[8] + i0 + p.nx * p.j;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -650,16 +726,20 @@ k_zm_spmv(Grid g, ZmTiles tl, const R* __restrict__ Pf, const R* __restrict__ zi
     dprev = dk;
     pzprev = cur.pz;
     Mprev = M;
-    if (k + 1 < p.k1) cur = nxt;
+  };
+  for (int k = p.k0;;) {
+    step(k, bufA, bufB);
+    if (++k >= p.k1) break;
+    step(k, bufB, bufA);
+    if (++k >= p.k1) break;
   }
   // +z face of the run's last plane
   if (p.act) {
     const int kl = p.k1 - 1;
     const int Pk = p.base + S * kl;
-    if (kl + 1 < p.nz || ((p.wrap >> 5) & 1)) {
-      const Q4<R> dn = d4(kl + 1 < p.nz ? Pk + S : Pk - (p.nz - 1) * S);
+    if (kl + 1 < p.nz || wzp) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) Mprev.v[e] += pzprev.v[e] * (dprev.v[e] - dn.v[e]);
+      for (int e = 0; e < 4; ++e) Mprev.v[e] += pzprev.v[e] * (dprev.v[e] - dzl.v[e]);
     } else {
       const int bse = p.tf[9] + i0 + p.nx * p.j;
 #pragma unroll
@@ -678,7 +758,7 @@ k_zm_spmv(Grid g, ZmTiles tl, const R* __restrict__ Pf, const R* __restrict__ zi
 // ---------------------------------------------------------------------------------
 // Prolongation and fine-level post-smoothing with the r.z, r.r partials (the marching
 // form of k_mg_up0_q<R, 3>): with v = y + e_1[parent], z = v + omega D^-1 (r - M v).
-template <typename R, int WGS>
+template <typename R, int WGS, bool GEN>
 __global__ void __launch_bounds__(WGS)
 k_zm_up(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __restrict__ Dinv, const R* __restrict__ r,
         const R* __restrict__ y, const int* __restrict__ parent, const R* __restrict__ ec, R omega,
@@ -694,14 +774,17 @@ k_zm_up(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __restri
   const int u = threadIdx.x;
   const int i0 = 4 * p.xq;
   const int* tc = g1.tab + p.b * kTabStride;
-  const int cx = tc[1], cy = tc[2];
+  const int tc0 = tc[0], cx = tc[1], cy = tc[2];
+  const bool wym = (p.wrap >> 2) & 1, wyp = (p.wrap >> 3) & 1, wzp = (p.wrap >> 5) & 1;
+  const bool ym = p.act && (p.j > 0 ? p.jr == 0 : wym);
+  const bool yp = p.act && (p.j + 1 < p.ny ? p.jr + 1 == p.RT : wyp);
+  const int oym = p.j > 0 ? -p.nx : (p.ny - 1) * p.nx;
+  const int oyp = p.j + 1 < p.ny ? p.nx : -(p.ny - 1) * p.nx;
+  const int jm = p.j > 0 ? p.j - 1 : p.ny - 1, jp = p.j + 1 < p.ny ? p.j + 1 : 0;
   // coarse cell of aggregate row jj, plane kk (the quad's first aggregate; the second is +1)
-  auto cbase = [&](int jj, int kk) { return tc[0] + 2 * p.xq + cx * ((jj >> 1) + cy * (kk >> 1)); };
-  // operand over the quad at P in row jj, plane kk of this block
-  auto v4 = [&](int P, int jj, int kk) {
-    const int cb = cbase(jj, kk);
-    const R e0 = ec[cb], e1 = ec[cb + 1];
-    const Q4<R> a = ldq(y, P);
+  auto cbase = [&](int jj, int kk) __attribute__((always_inline)) { return tc0 + 2 * p.xq + cx * ((jj >> 1) + cy * (kk >> 1)); };
+  // operand over a quad of this block from y and the two coarse values
+  auto vq = [&](const Q4<R>& a, R e0, R e1) __attribute__((always_inline)) {
     Q4<R> o;
     o.v[0] = a.v[0] + e0;
     o.v[1] = a.v[1] + e0;
@@ -710,14 +793,14 @@ k_zm_up(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __restri
     return o;
   };
   // one cell of this block at (i, jj, kk), or (known = false) across a block side
-  auto v1 = [&](int F, bool known, int i, int jj, int kk) {
-    return y[F] + ec[known ? tc[0] + (i >> 1) + cx * ((jj >> 1) + cy * (kk >> 1)) : parent[F]];
+  auto v1 = [&](int F, bool known, int i, int jj, int kk) __attribute__((always_inline)) {
+    return y[F] + ec[known ? tc0 + (i >> 1) + cx * ((jj >> 1) + cy * (kk >> 1)) : parent[F]];
   };
   struct Ld {
     Q4<R> y, r, D, px, py, pz;
     R e0, e1;
   };
-  auto load = [&](int k) {
+  auto load = [&](int k) __attribute__((always_inline)) {
     Ld L;
     const int P = p.act ? p.base + S * k : 0;
     const int cb = p.act ? cbase(p.j, k) : 0;
@@ -731,11 +814,23 @@ k_zm_up(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __restri
     L.e1 = ec[cb + 1];
     return L;
   };
-  Ld cur = load(p.k0);
+  Ld bufA = load(p.k0), bufB;
   const bool hz_in = p.k0 > 0 || ((p.wrap >> 4) & 1);
-  Q4<R> vprev = zq4<R>(), pzprev = zq4<R>(), Mprev = zq4<R>(), rprev = zq4<R>(), Dprev = zq4<R>();
+  const int km = p.k0 > 0 ? p.k0 - 1 : p.nz - 1;
+  Q4<R> hy = zq4<R>(), hpz = zq4<R>();
+  R he0 = R(0), he1 = R(0);
+  if (p.act && hz_in) {
+    const int Pm = p.base + S * km;
+    const int cb = cbase(p.j, km);
+    hy = ldq(y, Pm);
+    hpz = ldq(Pz, Pm);
+    he0 = ec[cb];
+    he1 = ec[cb + 1];
+  }
+  Q4<R> vprev = zq4<R>(), pzprev = zq4<R>(), Mprev = zq4<R>(), rprev = zq4<R>(), Dprev = zq4<R>(),
+        vzl = zq4<R>();
   double acc[2] = {0.0, 0.0};
-  auto finish = [&](int P, const Q4<R>& v, const Q4<R>& M, const Q4<R>& rq, const Q4<R>& Dq) {
+  auto finish = [&](int P, const Q4<R>& v, const Q4<R>& M, const Q4<R>& rq, const Q4<R>& Dq) __attribute__((always_inline)) {
     Q4<R> o;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -745,16 +840,38 @@ k_zm_up(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __restri
     }
     stq(z, P, o);
   };
-  for (int k = p.k0; k < p.k1; ++k) {
-    Ld nxt;
-    if (k + 1 < p.k1) nxt = load(k + 1);
+  // one plane: cur holds its loads, the next plane's go to nxt (two buffers used in
+  // turn, so that no register copy waits for the loads in flight)
+  auto step = [&](const int k, const Ld& cur, Ld& nxt) __attribute__((always_inline)) {
     const int bs = k & 1;
     const int Pk = p.act ? p.base + S * k : 0;
-    Q4<R> vk, M;
-    vk.v[0] = cur.y.v[0] + cur.e0;
-    vk.v[1] = cur.y.v[1] + cur.e0;
-    vk.v[2] = cur.y.v[2] + cur.e1;
-    vk.v[3] = cur.y.v[3] + cur.e1;
+    // (a) neighbours in memory
+    Q4<R> a0, a3, b0;
+    R ae0, ae1, be0, be1;
+    if (ym) {
+      const int cb = cbase(jm, k);
+      a0 = ldq(y, Pk + oym);
+      a3 = ldq(Py, Pk + oym);
+      ae0 = ec[cb];
+      ae1 = ec[cb + 1];
+    }
+    if (yp) {
+      const int cb = cbase(jp, k);
+      b0 = ldq(y, Pk + oyp);
+      be0 = ec[cb];
+      be1 = ec[cb + 1];
+    }
+    const bool zp = p.act && k + 1 == p.k1 && (k + 1 < p.nz || wzp);
+    if (zp) {
+      const int kn = k + 1 < p.nz ? k + 1 : 0;
+      const int cb = cbase(p.j, kn);
+      vzl = vq(ldq(y, p.base + S * kn), ec[cb], ec[cb + 1]);
+    }
+    // (b) the next plane
+    nxt = load(k + 1 < p.k1 ? k + 1 : k);
+    // (c) this plane
+    const Q4<R> vk = vq(cur.y, cur.e0, cur.e1);
+    Q4<R> M;
     lv[bs][u] = vk;
     lpx[bs][u] = cur.px.v[3];
     lpy[bs][u] = cur.py;
@@ -766,7 +883,7 @@ k_zm_up(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __restri
         bool have = true;
         R dl = R(0), pl = R(0);
         if (i0 > 0) {
-          if (p.xl > 0) {
+          if (!GEN || p.xl > 0) {
             dl = lv[bs][u - 1].v[3];
             pl = lpx[bs][u - 1];
           } else {
@@ -774,13 +891,15 @@ k_zm_up(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __restri
             pl = Pf[Pk - 1];
           }
         } else if (p.wrap & 1) {
-          if (p.XQ == p.nxq) {
+          if (!GEN || p.XQ == p.nxq) {
             dl = lv[bs][u + p.nxq - 1].v[3];
             pl = lpx[bs][u + p.nxq - 1];
           } else {
             dl = v1(Pk + p.nx - 1, true, p.nx - 1, p.j, k);
             pl = Pf[Pk + p.nx - 1];
           }
+        } else if constexpr (!GEN) {
+          have = false;
         } else {
           const int F = g.fmap[p.tf[4] + p.j + p.ny * k];
           have = F >= 0;
@@ -797,9 +916,11 @@ k_zm_up(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __restri
         bool have = true;
         R dr = R(0);
         if (i0 + 4 < p.nx) {
-          dr = p.xl + 1 < p.XQ ? lv[bs][u + 1].v[0] : v1(Pk + 4, true, i0 + 4, p.j, k);
+          dr = (!GEN || p.xl + 1 < p.XQ) ? lv[bs][u + 1].v[0] : v1(Pk + 4, true, i0 + 4, p.j, k);
         } else if (p.wrap & 2) {
-          dr = p.XQ == p.nxq ? lv[bs][u - (p.nxq - 1)].v[0] : v1(Pk + 4 - p.nx, true, 0, p.j, k);
+          dr = (!GEN || p.XQ == p.nxq) ? lv[bs][u - (p.nxq - 1)].v[0] : v1(Pk + 4 - p.nx, true, 0, p.j, k);
+        } else if constexpr (!GEN) {
+          have = false;
         } else {
           const int F = g.fmap[p.tf[5] + p.j + p.ny * k];
           have = F >= 0;
@@ -807,14 +928,11 @@ k_zm_up(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __restri
         }
         M.v[3] = (have ? px.v[3] * (vk.v[3] - dr) : R(0)) + px.v[2] * (vk.v[3] - vk.v[2]);
       }
-      if (p.j + 1 < p.ny || ((p.wrap >> 3) & 1)) {
-        Q4<R> vn;
-        if (p.j + 1 < p.ny && p.jr + 1 < p.RT) vn = lv[bs][u + p.XQ];
-        else if (p.j + 1 < p.ny) vn = v4(Pk + p.nx, p.j + 1, k);
-        else vn = v4(Pk - (p.ny - 1) * p.nx, 0, k);
+      if (p.j + 1 < p.ny || wyp) {
+        const Q4<R> vn = (p.j + 1 < p.ny && p.jr + 1 < p.RT) ? lv[bs][u + p.XQ] : vq(b0, be0, be1);
 #pragma unroll
         for (int e = 0; e < 4; ++e) M.v[e] += cur.py.v[e] * (vk.v[e] - vn.v[e]);
-      } else {
+      } else if constexpr (GEN) {
         const int bse = p.tf[7] + i0 + p.nx * k;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -822,20 +940,18 @@ k_zm_up(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __restri
           if (F >= 0) M.v[e] += cur.py.v[e] * (vk.v[e] - v1(F, false, 0, 0, 0));
         }
       }
-      if (p.j > 0 || ((p.wrap >> 2) & 1)) {
+      if (p.j > 0 || wym) {
         Q4<R> vn, wn;
-        if (p.j > 0 && p.jr > 0) {
+        if (p.jr > 0) {
           vn = lv[bs][u - p.XQ];
           wn = lpy[bs][u - p.XQ];
         } else {
-          const int jn = p.j > 0 ? p.j - 1 : p.ny - 1;
-          const int Pn = p.j > 0 ? Pk - p.nx : Pk + (p.ny - 1) * p.nx;
-          vn = v4(Pn, jn, k);
-          wn = ldq(Py, Pn);
+          vn = vq(a0, ae0, ae1);
+          wn = a3;
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) M.v[e] += wn.v[e] * (vk.v[e] - vn.v[e]);
-      } else {
+      } else if constexpr (GEN) {
         const int bse = p.tf[6] + i0 + p.nx * k;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -851,12 +967,10 @@ k_zm_up(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __restri
           Mprev.v[e] -= f;
         }
       } else if (hz_in) {
-        const int km = p.k0 > 0 ? p.k0 - 1 : p.nz - 1;
-        const int Pm = p.base + S * km;
-        const Q4<R> vn = v4(Pm, p.j, km), wn = ldq(Pz, Pm);
+        const Q4<R> vn = vq(hy, he0, he1);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) M.v[e] += wn.v[e] * (vk.v[e] - vn.v[e]);
-      } else {
+        for (int e = 0; e < 4; ++e) M.v[e] += hpz.v[e] * (vk.v[e] - vn.v[e]);
+      } else if constexpr (GEN) {
         const int bse = p.tf[8] + i0 + p.nx * p.j;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -871,16 +985,19 @@ k_zm_up(Grid g, Grid g1, ZmTiles tl, const R* __restrict__ Pf, const R* __restri
     Mprev = M;
     rprev = cur.r;
     Dprev = cur.D;
-    if (k + 1 < p.k1) cur = nxt;
+  };
+  for (int k = p.k0;;) {
+    step(k, bufA, bufB);
+    if (++k >= p.k1) break;
+    step(k, bufB, bufA);
+    if (++k >= p.k1) break;
   }
   if (p.act) {
     const int kl = p.k1 - 1;
     const int Pk = p.base + S * kl;
-    if (kl + 1 < p.nz || ((p.wrap >> 5) & 1)) {
-      const int kn = kl + 1 < p.nz ? kl + 1 : 0;
-      const Q4<R> vn = v4(kl + 1 < p.nz ? Pk + S : Pk - (p.nz - 1) * S, p.j, kn);
+    if (kl + 1 < p.nz || wzp) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) Mprev.v[e] += pzprev.v[e] * (vprev.v[e] - vn.v[e]);
+      for (int e = 0; e < 4; ++e) Mprev.v[e] += pzprev.v[e] * (vprev.v[e] - vzl.v[e]);
     } else {
       const int bse = p.tf[9] + i0 + p.nx * p.j;
 #pragma unroll
@@ -941,6 +1058,20 @@ int zm_setup(piso_ctx* c) {
     t.nty[b] = nty;
     t.off[b + 1] = t.off[b] + ntx * nty * ntz;
   }
+  // the plain form (no code for sides connected to other blocks, rows split over tiles in
+  // x, or one-row and one-plane aggregates): one block, every side a wall or wrapping onto
+  // the block, whole rows per tile, even ny and nz
+  t.plain = c->nblocks == 1 && t.xq[0] == c->h_tab[1] / 4 && c->h_tab[2] % 2 == 0 && c->h_tab[3] % 2 == 0;
+  for (int side = 0; side < 6 && t.plain; ++side) {
+    if ((c->h_tab[kTabWrap] >> side) & 1) continue;
+    const int a = side / 2;
+    const int faces = a == 0 ? c->h_tab[2] * c->h_tab[3] : (a == 1 ? c->h_tab[1] * c->h_tab[3] : c->h_tab[1] * c->h_tab[2]);
+    for (int f = 0; f < faces; ++f)
+      if (c->h_fmap[(size_t)c->h_tab[4 + side] + f] >= 0) {
+        t.plain = false;
+        break;
+      }
+  }
   // the groups' partial sums share the reduction buffers
   c->zm_on = t.off[c->nblocks] <= kRedGrid;
   return PISO_OK;
@@ -951,24 +1082,27 @@ int zm_groups(const piso_ctx* c) { return c->zm_tiles.off[c->nblocks]; }
 template <typename R>
 int zm_launch_down(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, R* x, const R* rin, R* rout,
                    const R* dnew, const R* q, R* y, R* rc, CgState* st, const double* partA, int Gp, int par) {
-  launch_timed_wg(c, s, kTimeCgUpdateMg, k_zm_down<R, kZmWG>, zm_groups(c), kZmWG, c->grid, c->mg_g1,
-                  c->zm_tiles, Pf, Dinv, x, rin, rout, dnew, q, y, (R)kMgOmega, rc, st, partA, Gp, par);
+  auto k = c->zm_tiles.plain ? k_zm_down<R, kZmWG, false> : k_zm_down<R, kZmWG, true>;
+  launch_timed_wg(c, s, kTimeCgUpdateMg, k, zm_groups(c), kZmWG, c->grid, c->mg_g1, c->zm_tiles, Pf, Dinv, x, rin,
+                  rout, dnew, q, y, (R)kMgOmega, rc, st, partA, Gp, par);
   return PISO_OK;
 }
 
 template <typename R>
 int zm_launch_spmv(piso_ctx* c, hipStream_t s, const R* Pf, const R* z, const R* dold, R* dnew, R* q, CgState* st,
                    const double* partB, double* partA, int Gp, int par) {
-  launch_timed_wg(c, s, kTimeCgStencil, k_zm_spmv<R, kZmWG>, zm_groups(c), kZmWG, c->grid, c->zm_tiles, Pf, z,
-                  dold, dnew, q, st, partB, partA, Gp, par);
+  auto k = c->zm_tiles.plain ? k_zm_spmv<R, kZmWG, false> : k_zm_spmv<R, kZmWG, true>;
+  launch_timed_wg(c, s, kTimeCgStencil, k, zm_groups(c), kZmWG, c->grid, c->zm_tiles, Pf, z, dold, dnew, q, st,
+                  partB, partA, Gp, par);
   return PISO_OK;
 }
 
 template <typename R>
 int zm_launch_up(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* r, const R* y, const int* parent,
                  const R* e1, R* z, double* partB, const CgState* st) {
-  launch_timed_wg(c, s, kTimeMgUp0, k_zm_up<R, kZmWG>, zm_groups(c), kZmWG, c->grid, c->mg_g1, c->zm_tiles, Pf,
-                  Dinv, r, y, parent, e1, (R)kMgOmega, z, partB, st);
+  auto k = c->zm_tiles.plain ? k_zm_up<R, kZmWG, false> : k_zm_up<R, kZmWG, true>;
+  launch_timed_wg(c, s, kTimeMgUp0, k, zm_groups(c), kZmWG, c->grid, c->mg_g1, c->zm_tiles, Pf, Dinv, r, y, parent,
+                  e1, (R)kMgOmega, z, partB, st);
   return PISO_OK;
 }
 
