@@ -235,7 +235,7 @@ int piso_mg_smoother(const piso_ctx* ctx, int32_t* line_axis);
  * when they run for this context's pressure solves, else 0.  They run on 3D grids whose
  * blocks all have nx % 4 == 0, with point smoothing on the fine level, when one field of
  * the pressure Krylov vectors (float in the F32 and MIXED forms, double in F64) takes at
- * least 64 MiB.  They compute the same iteration as the one-quad-per-thread kernels (the
+ * least 8 MiB.  They compute the same iteration as the one-quad-per-thread kernels (the
  * PCG of App. A.6 with the multigrid preconditioner) in another summation order; a tile of
  * rows marches through a run of planes, its neighbours in x and y shared in LDS and those
  * in z carried from plane to plane.  PISO_ZMARCH=0 in the environment at creation keeps

@@ -117,13 +117,15 @@ struct ZmTiles {
   bool plain;   // the kernels' form without sides connected to other blocks (see zm_setup)
 };
 constexpr int kZmWG = 512;         // threads of a plane-marching work-group
-constexpr int kZmTarget = 512;     // work-groups the run length aims at (2 per CU)
-constexpr int kZmMinPlanes = 8;    // shortest run of planes (each run re-reads two planes)
-// They pay where the one-quad-per-thread kernels' re-reads go to HBM: measured per PCG
-// iteration, 256^3 (64 MiB per float field) 505 -> 441 us in FP32 and 1019 -> 827 us in
-// FP64; at 192x128x192 they lose (FP32 142 against 148 us, FP64 300 against 311 us: the
-// re-reads still hit the 256 MB Infinity Cache, and 312 work-groups fill the chip badly).
-constexpr size_t kZmMinStreamBytes = size_t(64) << 20;
+constexpr int kZmTarget = 256;     // work-groups the run length aims at (one per CU; measured
+                                   // against 384-1024 at 256^3 and 192x128x192: best or equal)
+constexpr int kZmMinPlanes = 4;    // shortest run of planes (each run re-reads two planes)
+// Measured per PCG iteration against the one-quad-per-thread kernels: 256^3 505 -> 412 us
+// (FP32) and 1020 -> 785 us (FP64); 192x128x192 145 -> 130 us (FP32) and 298 -> 265 us
+// (FP64); 128^3 FP32 (8 MiB per field) 95 -> 81 us.  On smaller grids they lose (96^3: FP32
+// 61 -> 58 us, FP64 80 -> 85 us; 64^3 FP32 47 -> 55 us): fewer, longer work-groups cost
+// more than the re-reads, which the Infinity Cache then holds.
+constexpr size_t kZmMinStreamBytes = size_t(8) << 20;
 
 constexpr int kMgCoarse = 2048;     // stop coarsening at this many cells (one work-group solves it)
 constexpr int kMgCoarseThreads = 1024;   // that work-group: kMgCoarse / kMgCoarseThreads cells per thread
