@@ -59,6 +59,26 @@ def blocks4():
     return cases.Case("blocks4", dom, np.zeros((3, N)), np.zeros(N), np.zeros((3, N)), 0.02, 0.05, ub, 1)
 
 
+def blocks2_unequal():
+    """Two blocks of different x extents (8 and 12 cells) side by side along x, periodic in x
+    through the pair, walls in y, z wrapping onto each block: tiles of different widths."""
+    y = cases.tanh_vertices(6, 1.1, 0.0, 1.0)
+    z = np.linspace(0.0, 0.5, 5)
+    parts = [cases.tensor_metrics([np.linspace(0.0, 0.8, 9), y, z]),
+             cases.tensor_metrics([np.linspace(0.8, 2.0, 13), y, z])]
+    T, J, c = cases.concat_blocks(parts)
+    S_ = cases.Side
+    sides = [S_(0, 1, cases.CONNECT, other_block=1), S_(1, 0, cases.CONNECT, other_block=0),
+             S_(1, 1, cases.CONNECT, other_block=0), S_(0, 0, cases.CONNECT, other_block=1)]
+    for b in range(2):
+        sides += cases.periodic_sides(b, 3, (2,)) + [S_(b, 2, cases.DIRICHLET), S_(b, 3, cases.DIRICHLET)]
+    dom = cases.Domain(3, [(8, 6, 4), (12, 6, 4)], sides, T, J, c)
+    N = dom.n_cells
+    ub = cases.boundary_values(dom, lambda si: np.array([0.4, 0.0, -0.2]) if dom.sides[si].side == 3
+                               else np.zeros(3))
+    return cases.Case("blocks2", dom, np.zeros((3, N)), np.zeros(N), np.zeros((3, N)), 0.02, 0.05, ub, 1)
+
+
 def periodic_box():
     """One 8x6x6 block, every side wrapping onto the block, mildly stretched in y."""
     xv = np.linspace(0.0, 1.0, 9)
@@ -76,6 +96,7 @@ def zm_cases():
         "channel_q": small_cases()["channel_q"],        # 12 x 10 x 8, walls in y
         "channel_odd": cases.channel(8, 7, 9),          # odd ny and nz: one-row and one-plane aggregates
         "blocks4": blocks4(),
+        "blocks2": blocks2_unequal(),
         "box": periodic_box(),
     }
 
