@@ -162,11 +162,19 @@ typedef struct {
                                       of a backward rollout have similar adjoint pressures);
                                       0 = from zero.  The result then depends on that history
                                       within the solver tolerance; piso_adjoint_reset clears it. */
+  int32_t report_flux_div;         /* forward only: 1 = fill piso_step_info.flux_div_linf (one
+                                      extra flux and divergence sweep per corrector, and a
+                                      synchronisation of the stream); 0 = leave it 0 */
 } piso_step_opts;
 
 typedef struct {
   piso_solve_info vel;
   piso_solve_info pres[2];
+  /* max over cells of |sum_f N_f F_f| for the corrected face flux F of corrector 1 and of
+   * the last corrector (eq. divtheorem, with the Dirichlet boundary fluxes): the
+   * face-flux divergence that the correction drives to the pressure solve's residual
+   * (App. A.3.5).  Filled when report_flux_div is set. */
+  double flux_div_linf[2];
 } piso_step_info;
 
 /* Intermediates of the fine-grained calls; every pointer is a caller-owned device

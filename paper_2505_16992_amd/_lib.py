@@ -51,14 +51,15 @@ class SolveInfo(C.Structure):
 class StepOpts(C.Structure):
     _fields_ = [("vel", SolveOpts), ("pres", SolveOpts), ("n_correctors", C.c_int32),
                 ("grad_p_in_predictor", C.c_int32), ("grad_path_flags", C.c_int32),
-                ("adjoint_warm_start", C.c_int32)]
+                ("adjoint_warm_start", C.c_int32), ("report_flux_div", C.c_int32)]
 
 
 class StepInfo(C.Structure):
-    _fields_ = [("vel", SolveInfo), ("pres", SolveInfo * 2)]
+    _fields_ = [("vel", SolveInfo), ("pres", SolveInfo * 2), ("flux_div_linf", C.c_double * 2)]
 
     def as_dict(self):
-        return {"vel": self.vel.as_dict(), "pres": [self.pres[0].as_dict(), self.pres[1].as_dict()]}
+        return {"vel": self.vel.as_dict(), "pres": [self.pres[0].as_dict(), self.pres[1].as_dict()],
+                "flux_div_linf": [self.flux_div_linf[0], self.flux_div_linf[1]]}
 
 
 class System(C.Structure):

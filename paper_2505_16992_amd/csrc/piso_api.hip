@@ -241,6 +241,10 @@ int do_step(piso_ctx* c, hipStream_t s, const R* u_n, const R* p_n, const R* nu,
   const int ncorr = o->n_correctors;
   const R* u_in = us;
   const R* p_lag = p_n;
+  // the face flux of a corrector for its divergence goes to the predictor's right-hand side
+  // buffer, which nothing reads after the velocity solve
+  const bool fdiv = info && o->report_flux_div;
+  R* Fbuf = fdiv ? (R*)c->w_b : nullptr;
   for (int k = 0; k < ncorr; ++k) {
     // the last corrector writes the outputs; earlier ones use the u**, h*, p* slots
     const bool last = (k == ncorr - 1);
@@ -254,8 +258,12 @@ int do_step(piso_ctx* c, hipStream_t s, const R* u_n, const R* p_n, const R* nu,
     c->pcg_kind = kPcgOther;
     c->pcg_same_op = false;
     if (rc < 0) return rc;
-    rc = launch_correct<R>(c, s, A, h, pk, Pf, p_lag, uk, nullptr);
+    rc = launch_correct<R>(c, s, A, h, pk, Pf, p_lag, uk, Fbuf);
     if (rc) return rc;
+    if (fdiv && (k == 0 || last)) {
+      rc = launch_flux_div<R>(c, s, Fbuf, ub, c->mix_scal + 6 + (last ? 1 : 0));
+      if (rc) return rc;
+    }
     u_in = uk;
     p_lag = pk;
   }
@@ -264,6 +272,13 @@ int do_step(piso_ctx* c, hipStream_t s, const R* u_n, const R* p_n, const R* nu,
     info->vel = vi;
     info->pres[0] = pi[0];
     info->pres[1] = pi[1];
+    info->flux_div_linf[0] = info->flux_div_linf[1] = 0.0;
+    if (fdiv) {
+      PISO_HIP(c, hipMemcpyAsync(c->h_scal + 6, c->mix_scal + 6, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      PISO_HIP(c, hipStreamSynchronize(s));
+      info->flux_div_linf[0] = c->h_scal[6];
+      info->flux_div_linf[1] = c->h_scal[7];
+    }
   }
   int st = vi.status;
   for (int k = 0; k < 2; ++k) st = (pi[k].status < 0 || st < 0) ? std::min(st, pi[k].status) : std::max(st, pi[k].status);

@@ -287,6 +287,68 @@ k_div(Grid g, const R* __restrict__ JT, const R* __restrict__ W, const R* __rest
   write_partials<1>(acc, partials);
 }
 
+// Face-flux divergence of a corrected flux F ([d][N], the +j face of every cell as
+// k_correct writes it) with the Dirichlet boundary fluxes J T_j(P) . u_b (eq. divtheorem,
+// N_f = +1 on high sides): the largest |sum_f N_f F_f| of the work-group's cells into
+// partials.  A face across the -j side is the +j face of the neighbour.
+template <typename R, int D, bool DIAG>
+__global__ void __launch_bounds__(kWG)
+k_flux_div(Grid g, const R* __restrict__ JT, const R* __restrict__ F, const R* __restrict__ ub,
+           double* __restrict__ partials) {
+  const int N = g.N, NB = g.NB;
+  int beg, end;
+  chunk_range(N, beg, end);
+  double m = 0.0;
+  for (int P = beg + (int)threadIdx.x; P < end; P += kWG) {
+    const Cell c = locate(g, P);
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        const double Nf = sd ? 1.0 : -1.0;
+        const int Fn = neighbour(g, c, P, j, sd);
+        if (Fn >= 0) {
+          s += Nf * (double)F[(size_t)j * N + (sd ? P : Fn)];
+        } else {
+          const int f = -1 - Fn;
+          double Ub = 0.0;
+#pragma unroll
+          for (int i = 0; i < D; ++i) Ub += (double)jt<R, D, DIAG>(JT, j, i, P, N) * (double)ub[(size_t)i * NB + f];
+          s += Nf * Ub;
+        }
+      }
+    }
+    m = fmax(m, fabs(s));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  __shared__ double wm[kWaves];
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kWaves; ++w) t = fmax(t, wm[w]);
+    partials[blockIdx.x] = t;
+  }
+}
+
+// One work-group: *out = the largest of G partials.
+__global__ void __launch_bounds__(kWG) k_max_partials(const double* __restrict__ partials, int G, double* out) {
+  double m = 0.0;
+  for (int w = (int)threadIdx.x; w < G; w += kWG) m = fmax(m, partials[w]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  __shared__ double wm[kWaves];
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kWaves; ++w) t = fmax(t, wm[w]);
+    *out = t;
+  }
+}
+
 // One work-group: out[q] = scale * sum of the G partials of value q (q < nv <= 2).
 __global__ void __launch_bounds__(kWG)
 k_finalize(const double* __restrict__ partials, int G, int nv, double scale, double* __restrict__ out) {
@@ -514,6 +576,16 @@ int launch_correct(piso_ctx* c, hipStream_t s, const R* A, const R* h, const R* 
 }
 
 template <typename R>
+int launch_flux_div(piso_ctx* c, hipStream_t s, const R* F, const R* ub, double* out) {
+  const int G = grid_red(c->N);
+  double* pt = part(c, kPartS);
+  PISO_DISPATCH_D_DIAG(c, (k_flux_div<R, D, DG><<<G, kWG, 0, s>>>(c->grid, (const R*)c->JT, F, ub, pt)));
+  if (int rc = check_launch(c, "k_flux_div")) return rc;
+  k_max_partials<<<1, kWG, 0, s>>>(pt, G, out);
+  return check_launch(c, "k_max_partials");
+}
+
+template <typename R>
 int launch_scale_invJ(piso_ctx* c, hipStream_t s, const R* x, int ncomp, R* y) {
   k_scale_invJ<R><<<grid_cells(c->N), kWG, 0, s>>>(c->N, ncomp, (const R*)c->invJ, x, y);
   return check_launch(c, "k_scale_invJ");
@@ -569,6 +641,7 @@ int launch_copy(piso_ctx* c, hipStream_t s, const TI* x, TO* y, int n) {
   template int launch_correct<R>(piso_ctx*, hipStream_t, const R*, const R*, const R*, const R*,     \
                                  const R*, R*, R*);                                                  \
   template int launch_scale_invJ<R>(piso_ctx*, hipStream_t, const R*, int, R*);                      \
+  template int launch_flux_div<R>(piso_ctx*, hipStream_t, const R*, const R*, double*);                      \
   template int launch_add_scalar<R>(piso_ctx*, hipStream_t, const double*, R*);                       \
   template int launch_fill<R>(piso_ctx*, hipStream_t, int, R, R*);                                    \
   template int launch_jt_field<R>(piso_ctx*, hipStream_t, const R*, R*);

@@ -364,6 +364,10 @@ int launch_correct(piso_ctx* c, hipStream_t s, const R* A, const R* h, const R* 
                    const R* p_lag, R* u_out, R* F_out);
 template <typename R>
 int launch_scale_invJ(piso_ctx* c, hipStream_t s, const R* x, int ncomp, R* y);
+// max over cells of |face-flux divergence| of a corrected flux F [d][N] (+ Dirichlet fluxes
+// of u_b) into *out (device)
+template <typename R>
+int launch_flux_div(piso_ctx* c, hipStream_t s, const R* F, const R* ub, double* out);
 template <typename R>
 int launch_add_scalar(piso_ctx* c, hipStream_t s, const double* v, R* y);
 template <typename R>

@@ -34,6 +34,20 @@ def test_default_opts_without_device():
     assert o.pres.rtol == pytest.approx(1e-8)
     lib.piso_default_step_opts(L.PISO_F64, ctypes.byref(o))
     assert o.pres.rtol == pytest.approx(1e-10) and o.vel.rtol == pytest.approx(1e-10)
+    assert o.report_flux_div == 0
+
+
+def test_step_opts_layout_matches_library():
+    """piso_default_step_opts clears sizeof(piso_step_opts) bytes: in a buffer with a canary
+    after the binding's structure, the canary survives (the binding is not shorter than the
+    library's struct) and the last field is cleared (not longer)."""
+    lib = L.load()
+    n = ctypes.sizeof(L.StepOpts)
+    buf = (ctypes.c_uint8 * (n + 64))(*([0xAB] * (n + 64)))
+    lib.piso_default_step_opts(L.PISO_F32, ctypes.cast(buf, ctypes.POINTER(L.StepOpts)))
+    assert all(b == 0xAB for b in buf[n:])
+    o = L.StepOpts.from_buffer(buf)
+    assert o.report_flux_div == 0 and o.adjoint_warm_start == 1 and o.n_correctors == 2
 
 
 def _magic(d):

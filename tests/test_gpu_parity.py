@@ -262,3 +262,52 @@ def test_no_quad_switch(api, name, value, monkeypatch):
     assert info["vel"]["status"] == 0 and info["pres"][1]["status"] == 0, info
     assert rel(host(u1), ref.u2) < 1e-9
     assert rel_p(host(p1), ref.p2) < 1e-9
+
+
+def _tape_fields(tape, N, d):
+    """The step tape as piso_step lays it out: A, C, P_f, D^-1, u*, h*, p*, u**, h**, p**."""
+    sizes = [("A", N), ("C", 2 * d * N), ("Pf", d * N), ("Dinv", N), ("us", d * N), ("h1", d * N),
+             ("p1", N), ("u1", d * N), ("h2", d * N), ("p2", N)]
+    out, o = {}, 0
+    t = host(tape)
+    for k, n in sizes:
+        out[k] = t[o:o + n].reshape((d, N) if n == d * N else (-1,) if n == N else (2, d, N))
+        o += n
+    return out
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_flux_divergence_report(api, name):
+    """piso_step_info.flux_div_linf (report_flux_div = 1): the largest face-flux divergence
+    after corrector 1 and corrector 2, against the oracle's face-by-face sum on the step's
+    own h, A and pressures (from the tape).  With random boundary velocities the net
+    boundary flux of a closed domain is not zero and the divergence keeps that mean (the
+    solve removes it, A4/A5); with the case's own boundary data and a tight pressure
+    tolerance the divergence meets the pin (<= 1e-10 of the largest face flux, A17)."""
+    say("test_flux_divergence_report", name)
+    case, ctx, (u, p, S, ub, nu), (ud, pd, Sd, ubd, nud) = _setup(api, name, seed=9)
+    geo = Geometry(case.domain)
+    d, N = u.shape
+    for rtol, own_ub in ((1e-6, False), (1e-12, False), (1e-12, True)):
+        if own_ub:
+            ub, ubd = case.u_b, dev(case.u_b, ctx.dtype)
+        o = tight_opts(ctx, rtol_p=rtol)
+        o.report_flux_div = 1
+        tape = ctx.new_tape()
+        _, _, info = ctx.step(ud, pd, nud, Sd, ubd, case.dt, o, tape=tape, info=True)
+        T = _tape_fields(tape, N, d)
+        ref1 = face_flux_divergence(geo, T["h1"], T["A"], T["p1"], p, ub)
+        ref2 = face_flux_divergence(geo, T["h2"], T["A"], T["p2"], T["p1"], ub)
+        W = np.einsum("jin,in->jn", geo.JT, T["h1"])
+        scale = max(1.0, np.abs(W).max())
+        got = info["flux_div_linf"]
+        want = [np.abs(ref1).max(), np.abs(ref2).max()]
+        say("  rtol %.0e: GPU %.3e %.3e, host %.3e %.3e (flux scale %.2e)" % (rtol, got[0], got[1], want[0],
+                                                                          want[1], scale))
+        for g_, w_ in zip(got, want):
+            assert abs(g_ - w_) <= 1e-6 * w_ + 1e-13 * scale
+        if own_ub:
+            assert max(got) <= 1e-10 * scale
+    o = tight_opts(ctx)
+    _, _, info = ctx.step(ud, pd, nud, Sd, ubd, case.dt, o, info=True)
+    assert info["flux_div_linf"] == [0.0, 0.0]   # not requested
