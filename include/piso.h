@@ -165,6 +165,12 @@ typedef struct {
   int32_t report_flux_div;         /* forward only: 1 = fill piso_step_info.flux_div_linf (one
                                       extra flux and divergence sweep per corrector, and a
                                       synchronisation of the stream); 0 = leave it 0 */
+  const void* p_prev;              /* forward only, per call: NULL, or the previous step's p_n
+                                      (device [N], the context's element type) of the same
+                                      rollout: the first corrector's pressure solve then starts
+                                      from 2 p_n - p_prev instead of p_n (p_n stays the lagged
+                                      pressure of eqs. implEuler1 and velCorrDiscrete).  The
+                                      result changes only within the solver tolerance. */
 } piso_step_opts;
 
 typedef struct {

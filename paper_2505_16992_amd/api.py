@@ -163,16 +163,23 @@ class Context:
         return L.SystemGrad(*[g[k].data_ptr() for k in ("dA", "dC", "db_u", "db")])
 
     # ---------------------------------------------------------------- whole step
-    def step(self, u, p, nu, S, u_b, dt, opts=None, tape=None, info=False):
+    def step(self, u, p, nu, S, u_b, dt, opts=None, tape=None, info=False, p_prev=None):
+        """One PISO step.  p_prev: the previous step's p of the same rollout (optional): the
+        first pressure solve then starts from 2 p - p_prev."""
         d, N = self.dim, self.N
         self._t(u, (d, N), "u")
         self._t(p, (N,), "p")
+        if p_prev is not None:
+            self._t(p_prev, (N,), "p_prev")
         self._t(S, (d, N), "S")
         nu_t, nf = self._nu(nu)
         ub = self._ub(u_b)
         if tape is not None:
             self._t(tape, (self.tape_bytes // self.elem_bytes,), "tape")
         o = opts if opts is not None else self.default_opts()
+        if p_prev is not None:
+            o = L.StepOpts.from_buffer_copy(o)
+            o.p_prev = _ptr(p_prev)
         u1 = torch.empty_like(u)
         p1 = torch.empty_like(p)
         inf = L.StepInfo()
@@ -457,9 +464,9 @@ class PisoStep(torch.autograd.Function):
     of one rollout for the adjoint warm start (None: a stand-alone step)."""
 
     @staticmethod
-    def forward(fctx, pctx: Context, opts, dt, owner, u, p, S, nu, u_b):
+    def forward(fctx, pctx: Context, opts, dt, owner, u, p, S, nu, u_b, p_prev=None):
         tape = pctx.new_tape()
-        u1, p1 = pctx.step(u, p, nu, S, u_b, dt, opts, tape=tape)
+        u1, p1 = pctx.step(u, p, nu, S, u_b, dt, opts, tape=tape, p_prev=p_prev)
         fctx.pctx, fctx.opts, fctx.dt = pctx, opts, dt
         fctx.owner = owner if owner is not None else object()
         fctx.save_for_backward(tape, u, p, nu, u_b if u_b is not None else torch.empty(0))
@@ -473,7 +480,7 @@ class PisoStep(torch.autograd.Function):
         _adjoint_owner(pctx, fctx.owner)
         g = pctx.step_backward(tape, u, p, nu, u_b if fctx.has_ub else None, fctx.dt, du1, dp1, fctx.opts)
         return (None, None, None, None, g["u"], g["p"], g["S"], g["nu"].reshape(nu.shape),
-                g["u_b"] if fctx.has_ub else None)
+                g["u_b"] if fctx.has_ub else None, None)
 
 
 class _Segment(torch.autograd.Function):
@@ -481,25 +488,33 @@ class _Segment(torch.autograd.Function):
     (step checkpointing): memory O(1 state + k tapes) per segment."""
 
     @staticmethod
-    def forward(fctx, pctx: Context, opts, dt, k, owner, u, p, S, nu, u_b):
-        uu, pp = u, p
+    def forward(fctx, pctx: Context, opts, dt, k, owner, chain, u, p, S, nu, u_b, p_prev):
+        uu, pp, pv = u, p, p_prev
         for _ in range(k):
-            uu, pp = pctx.step(uu, pp, nu, S, u_b, dt, opts)
+            last = pp
+            uu, pp = pctx.step(uu, pp, nu, S, u_b, dt, opts, p_prev=pv)
+            pv = last if chain else None
         fctx.pctx, fctx.opts, fctx.dt, fctx.k, fctx.owner = pctx, opts, dt, k, owner
+        fctx.chain = chain
+        fctx.p_prev = None if p_prev is None else p_prev.detach()   # the recomputation repeats the chain
         fctx.has_ub = u_b is not None
         fctx.save_for_backward(u, p, S, nu, u_b if u_b is not None else torch.empty(0))
-        return uu, pp
+        prev = last.detach().clone()   # the last step's starting p: the next step's p_prev
+        fctx.mark_non_differentiable(prev)
+        return uu, pp, prev
 
     @staticmethod
-    def backward(fctx, du, dp):
+    def backward(fctx, du, dp, _dpv):
         u, p, S, nu, u_b = fctx.saved_tensors
         pctx, opts, dt, k = fctx.pctx, fctx.opts, fctx.dt, fctx.k
         ub = u_b if fctx.has_ub else None
         states, tapes = [(u, p)], []
-        uu, pp = u, p
+        uu, pp, pv = u, p, fctx.p_prev
         for _ in range(k):
             t = pctx.new_tape()
-            uu, pp = pctx.step(uu, pp, nu, S, ub, dt, opts, tape=t)
+            last = pp
+            uu, pp = pctx.step(uu, pp, nu, S, ub, dt, opts, tape=t, p_prev=pv)
+            pv = last if fctx.chain else None
             states.append((uu, pp))
             tapes.append(t)
         dS = torch.zeros_like(S)
@@ -516,7 +531,7 @@ class _Segment(torch.autograd.Function):
             if dub is not None:
                 dub += g["u_b"]
             tapes[q] = None
-        return None, None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), dub
+        return None, None, None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), dub, None
 
 
 class OutflowUpdate(torch.autograd.Function):
@@ -540,26 +555,33 @@ class _OutflowSegment(torch.autograd.Function):
     values: (u, p, S, nu, u_b) -> (u^{n+k}, p^{n+k}, u_b^{n+k})."""
 
     @staticmethod
-    def forward(fctx, pctx: Context, opts, dt, k, owner, mask, u_m, u, p, S, nu, u_b):
-        uu, pp, bb = u, p, u_b
+    def forward(fctx, pctx: Context, opts, dt, k, owner, chain, mask, u_m, u, p, S, nu, u_b, p_prev):
+        uu, pp, bb, pv = u, p, u_b, p_prev
         for _ in range(k):
             bb = pctx.outflow_update(uu, bb, mask, u_m, dt)
-            uu, pp = pctx.step(uu, pp, nu, S, bb, dt, opts)
+            last = pp
+            uu, pp = pctx.step(uu, pp, nu, S, bb, dt, opts, p_prev=pv)
+            pv = last if chain else None
         fctx.pctx, fctx.opts, fctx.dt, fctx.k, fctx.mask, fctx.u_m = pctx, opts, dt, k, mask, u_m
-        fctx.owner = owner
+        fctx.owner, fctx.chain = owner, chain
+        fctx.p_prev = None if p_prev is None else p_prev.detach()
         fctx.save_for_backward(u, p, S, nu, u_b)
-        return uu, pp, bb
+        prev = last.detach().clone()
+        fctx.mark_non_differentiable(prev)
+        return uu, pp, bb, prev
 
     @staticmethod
-    def backward(fctx, du, dp, dbb):
+    def backward(fctx, du, dp, dbb, _dpv):
         u, p, S, nu, u_b = fctx.saved_tensors
         pctx, opts, dt, k, mask, u_m = fctx.pctx, fctx.opts, fctx.dt, fctx.k, fctx.mask, fctx.u_m
         states, tapes, used = [(u, p, u_b)], [], []
-        uu, pp, bb = u, p, u_b
+        uu, pp, bb, pv = u, p, u_b, fctx.p_prev
         for _ in range(k):
             nb = pctx.outflow_update(uu, bb, mask, u_m, dt)
             t = pctx.new_tape()
-            uu, pp = pctx.step(uu, pp, nu, S, nb, dt, opts, tape=t)
+            last = pp
+            uu, pp = pctx.step(uu, pp, nu, S, nb, dt, opts, tape=t, p_prev=pv)
+            pv = last if fctx.chain else None
             used.append(nb)
             states.append((uu, pp, nb))
             tapes.append(t)
@@ -578,7 +600,7 @@ class _OutflowSegment(torch.autograd.Function):
             gb, gu = pctx.outflow_update_backward(un, bprev, mask, u_m, dt, gb_used, du=g["u"])
             gp = g["p"]
             tapes[q] = None
-        return None, None, None, None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), gb
+        return None, None, None, None, None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), gb, None
 
 
 class PlaneStatistics(torch.autograd.Function):
@@ -701,7 +723,7 @@ def step(pctx: Context, u, p, S, nu, u_b, dt, opts=None):
 
 
 def rollout(pctx: Context, u0, p0, S, nu, u_b, dt, n_steps: int, checkpoint_every: int = 0, opts=None,
-            warmup: int = 0, return_all: bool = False, outflow=None):
+            warmup: int = 0, return_all: bool = False, outflow=None, extrapolate: bool = True):
     """n_steps differentiable steps.  checkpoint_every = 0 keeps every tape; k > 0
     stores only the state at the start of each k-step segment and recomputes the
     segment's tapes in the backward.  warmup steps run first without a tape.
@@ -713,10 +735,15 @@ def rollout(pctx: Context, u0, p0, S, nu, u_b, dt, n_steps: int, checkpoint_ever
 
     outflow = (mask, u_m): before every step the Dirichlet values of the masked faces
     are advanced by the advective outflow update (the boundary values then become part
-    of the state; the result gains a third entry, the final u_b)."""
+    of the state; the result gains a third entry, the final u_b).
+
+    extrapolate: every step after the first starts its first pressure solve from
+    2 p^n - p^{n-1} (piso_step_opts.p_prev); the chain runs through warm-up steps and
+    checkpointed segments alike, so that results do not depend on checkpoint_every."""
     o = opts if opts is not None else pctx.default_opts()
     owner = object()   # the backward steps of this rollout share the adjoint warm start
     u, p, ub = u0, p0, u_b
+    pv = None   # the previous step's pressure (extrapolation of the first solve's start)
     if outflow is not None:
         mask, u_m = outflow
         mask = pctx._mask(mask)
@@ -726,26 +753,30 @@ def rollout(pctx: Context, u0, p0, S, nu, u_b, dt, n_steps: int, checkpoint_ever
             for _ in range(warmup):
                 if outflow is not None:
                     ub = pctx.outflow_update(u.detach(), ub, mask, u_m, dt)
-                u, p = pctx.step(u.detach(), p.detach(), nu.detach(), S.detach(), ub, dt, o)
+                last = p.detach()
+                u, p = pctx.step(u.detach(), p.detach(), nu.detach(), S.detach(), ub, dt, o, p_prev=pv)
+                pv = last if extrapolate else None
     traj = []
     done = 0
     while done < n_steps:
+        last = p.detach()
         if outflow is not None:
             if checkpoint_every > 0:
                 k = min(checkpoint_every, n_steps - done)
-                u, p, ub = _OutflowSegment.apply(pctx, o, dt, k, owner, mask, u_m, u, p, S, nu, ub)
+                u, p, ub, last = _OutflowSegment.apply(pctx, o, dt, k, owner, extrapolate, mask, u_m, u, p, S, nu, ub, pv)
                 done += k
             else:
                 ub = OutflowUpdate.apply(pctx, mask, u_m, dt, u, ub)
-                u, p = PisoStep.apply(pctx, o, dt, owner, u, p, S, nu, ub)
+                u, p = PisoStep.apply(pctx, o, dt, owner, u, p, S, nu, ub, pv)
                 done += 1
         elif checkpoint_every > 0:
             k = min(checkpoint_every, n_steps - done)
-            u, p = _Segment.apply(pctx, o, dt, k, owner, u, p, S, nu, ub)
+            u, p, last = _Segment.apply(pctx, o, dt, k, owner, extrapolate, u, p, S, nu, ub, pv)
             done += k
         else:
-            u, p = PisoStep.apply(pctx, o, dt, owner, u, p, S, nu, ub)
+            u, p = PisoStep.apply(pctx, o, dt, owner, u, p, S, nu, ub, pv)
             done += 1
+        pv = last if extrapolate else None
         if return_all:
             traj.append((u, p) if outflow is None else (u, p, ub))
     if return_all:

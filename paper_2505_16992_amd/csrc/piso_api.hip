@@ -251,7 +251,12 @@ int do_step(piso_ctx* c, hipStream_t s, const R* u_n, const R* p_n, const R* nu,
     R* h = last ? h2 : h1;
     R* pk = last ? p2 : p1;
     R* uk = last ? u_np1 : u1;
-    if (pk != p_lag) PISO_HIP(c, hipMemcpyAsync(pk, p_lag, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
+    if (k == 0 && o->p_prev && pk != p_lag) {
+      // the first corrector starts from the pressure extrapolated in time
+      if (int e = launch_extrapolate<R>(c, s, p_lag, (const R*)o->p_prev, pk)) return e;
+    } else if (pk != p_lag) {
+      PISO_HIP(c, hipMemcpyAsync(pk, p_lag, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
+    }
     c->pcg_kind = kPcgFwd1 + std::min(k, 1);
     c->pcg_same_op = k > 0;   // the correctors of a step share P_f and D^-1
     rc = do_pressure<R>(c, s, A, C, bu, Pf, Dinv, u_in, ub, p_lag, h, nullptr, pk, &o->pres, &pi[std::min(k, 1)]);

@@ -431,6 +431,14 @@ __global__ void k_add_scalar(const double* __restrict__ v, R* __restrict__ y) {
   if (threadIdx.x == 0 && blockIdx.x == 0) y[0] += (R)v[0];
 }
 
+// y = 2 p - q (a linear extrapolation in time of the pressure initial guess)
+template <typename R>
+__global__ void __launch_bounds__(kWG) k_extrapolate(int n, const R* __restrict__ p, const R* __restrict__ q,
+                                                    R* __restrict__ y) {
+  const int i = blockIdx.x * kWG + threadIdx.x;
+  if (i < n) y[i] = R(2) * p[i] - q[i];
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kWG) k_fill(int n, R v, R* __restrict__ y) {
   const int i = blockIdx.x * kWG + threadIdx.x;
@@ -586,6 +594,12 @@ int launch_flux_div(piso_ctx* c, hipStream_t s, const R* F, const R* ub, double*
 }
 
 template <typename R>
+int launch_extrapolate(piso_ctx* c, hipStream_t s, const R* p, const R* q, R* y) {
+  k_extrapolate<R><<<grid_cells(c->N), kWG, 0, s>>>(c->N, p, q, y);
+  return check_launch(c, "k_extrapolate");
+}
+
+template <typename R>
 int launch_scale_invJ(piso_ctx* c, hipStream_t s, const R* x, int ncomp, R* y) {
   k_scale_invJ<R><<<grid_cells(c->N), kWG, 0, s>>>(c->N, ncomp, (const R*)c->invJ, x, y);
   return check_launch(c, "k_scale_invJ");
@@ -642,6 +656,7 @@ int launch_copy(piso_ctx* c, hipStream_t s, const TI* x, TO* y, int n) {
                                  const R*, R*, R*);                                                  \
   template int launch_scale_invJ<R>(piso_ctx*, hipStream_t, const R*, int, R*);                      \
   template int launch_flux_div<R>(piso_ctx*, hipStream_t, const R*, const R*, double*);                      \
+  template int launch_extrapolate<R>(piso_ctx*, hipStream_t, const R*, const R*, R*);                      \
   template int launch_add_scalar<R>(piso_ctx*, hipStream_t, const double*, R*);                       \
   template int launch_fill<R>(piso_ctx*, hipStream_t, int, R, R*);                                    \
   template int launch_jt_field<R>(piso_ctx*, hipStream_t, const R*, R*);

@@ -368,6 +368,9 @@ int launch_scale_invJ(piso_ctx* c, hipStream_t s, const R* x, int ncomp, R* y);
 // of u_b) into *out (device)
 template <typename R>
 int launch_flux_div(piso_ctx* c, hipStream_t s, const R* F, const R* ub, double* out);
+// y = 2 p - q
+template <typename R>
+int launch_extrapolate(piso_ctx* c, hipStream_t s, const R* p, const R* q, R* y);
 template <typename R>
 int launch_add_scalar(piso_ctx* c, hipStream_t s, const double* v, R* y);
 template <typename R>

@@ -248,7 +248,10 @@ def test_adjoint_history_isolated_between_rollouts(api):
 
 def test_rollout_warmup(api):
     """warmup steps run without a tape before the differentiated ones: the same final
-    state as running them by hand, and the gradient of the rollout that starts there."""
+    state as running them by hand, and the gradient of the rollout that starts there.
+    Without the pressure extrapolation a rollout after warm-up equals a rollout started
+    from the warmed-up state; with it, the chain of previous pressures runs on through
+    the warm-up, so the states equal those of stand-alone steps chained by hand."""
     say("test_rollout_warmup")
     case = small_cases()["cylinder_q"]
     ctx = api.Context(case.domain, "f64")
@@ -256,13 +259,76 @@ def test_rollout_warmup(api):
     o = tight_opts(ctx)
     w = torch.randn_like(u)
     S1 = S.clone().requires_grad_(True)
-    uT, pT = api.rollout(ctx, u, p, S1, nu, ub, case.dt, 2, warmup=3, opts=o)
+    uT, pT = api.rollout(ctx, u, p, S1, nu, ub, case.dt, 2, warmup=3, opts=o, extrapolate=False)
     (g1,) = torch.autograd.grad((uT * w).sum(), [S1])
     uu, pp = u, p
     for _ in range(3):
         uu, pp = ctx.step(uu, pp, nu, S, ub, case.dt, o)
     S2 = S.clone().requires_grad_(True)
-    uT2, pT2 = api.rollout(ctx, uu, pp, S2, nu, ub, case.dt, 2, opts=o)
+    uT2, pT2 = api.rollout(ctx, uu, pp, S2, nu, ub, case.dt, 2, opts=o, extrapolate=False)
     (g2,) = torch.autograd.grad((uT2 * w).sum(), [S2])
     assert torch.equal(uT.detach(), uT2.detach()) and torch.equal(pT.detach(), pT2.detach())
     assert torch.equal(g1, g2)
+    uE, pE = api.rollout(ctx, u, p, S, nu, ub, case.dt, 2, warmup=3, opts=o)
+    uu, pp, pv = u, p, None
+    for _ in range(5):
+        uu, p1 = ctx.step(uu, pp, nu, S, ub, case.dt, o, p_prev=pv)
+        pv, pp = pp, p1
+    assert torch.equal(uE.detach(), uu) and torch.equal(pE.detach(), pp)
+
+
+@pytest.mark.parametrize("name", ["tgv16", "cavity12", "channel_q", "cylinder_q"])
+def test_extrapolated_start_matches_oracle(api, name):
+    """A step given p_prev (its first pressure solve starts from 2 p - p_prev) reaches
+    the oracle's step to the solver tolerance, whatever p_prev is: the start of a
+    converged Krylov solve does not enter the result."""
+    say("test_extrapolated_start_matches_oracle", name)
+    case = small_cases()[name]
+    ctx = api.Context(case.domain, "f64")
+    (u0, p0, S0, ub0, _), (u, p, S, ub, nu) = _inputs(ctx, case, 21)
+    o = tight_opts(ctx)
+    ref = oracle_step(Geometry(case.domain), u0, p0, case.nu, S0, case.dt, ub0)
+    rng = np.random.default_rng(22)
+    for pv in (p0 + 0.05 * rng.standard_normal(p0.shape), rng.standard_normal(p0.shape)):
+        u1, p1, info = ctx.step(u, p, nu, S, ub, case.dt, o, info=True, p_prev=dev(pv, ctx.dtype))
+        assert info["pres"][0]["status"] == 0 and info["pres"][1]["status"] == 0, info
+        assert rel(host(u1), ref.u2) < 1e-9
+        assert rel_p(host(p1), ref.p2) < 1e-9
+    with pytest.raises(ValueError):
+        ctx.step(u, p, nu, S, ub, case.dt, o, p_prev=p[:-1])
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_extrapolated_start_saves_iterations(api, prec):
+    """On a developed flow, the pressure of the previous step extrapolated in time is a
+    better start for the first corrector's solve than the lagged pressure alone; the
+    rollout's result agrees with the unextrapolated one to the solver tolerance, and a
+    rollout of stand-alone steps with p_prev equals api.rollout's chain bit for bit."""
+    say("test_extrapolated_start_saves_iterations", prec)
+    case = cases.channel(32, 24, 16)
+    ctx = api.Context(case.domain, prec)
+    t = ctx.dtype
+    u, p, S, ub = (dev(x, t) for x in (case.u0, case.p0, case.S, case.u_b))
+    nu = dev(np.array([case.nu]), t)
+    o = ctx.default_opts()
+    with torch.no_grad():
+        for _ in range(10):                 # let the pressure develop from p0 = 0
+            u, p = ctx.step(u, p, nu, S, ub, case.dt, o)
+        runs = {}
+        for extra in (False, True):
+            uu, pp, pv, its = u, p, None, []
+            for _ in range(8):
+                uu, p1, inf = ctx.step(uu, pp, nu, S, ub, case.dt, o, info=True,
+                                       p_prev=pv if extra else None)
+                pv, pp = pp, p1
+                its.append(inf["pres"][0]["iters"])
+            runs[extra] = (uu, pp, its)
+        say("corrector-1 CG iterations plain %s extrapolated %s" % (runs[False][2], runs[True][2]))
+        assert sum(runs[True][2][1:]) < sum(runs[False][2][1:])
+        assert rel(host(runs[True][0]), host(runs[False][0])) < 1e-5
+        uT, pT = api.rollout(ctx, u, p, S, nu, ub, case.dt, 8, opts=o)
+        assert torch.equal(uT, runs[True][0]) and torch.equal(pT, runs[True][1])
+        uC, pC = api.rollout(ctx, u, p, S, nu, ub, case.dt, 8, checkpoint_every=3, opts=o)
+        assert torch.equal(uC, uT) and torch.equal(pC, pT)
+        uN, _ = api.rollout(ctx, u, p, S, nu, ub, case.dt, 8, opts=o, extrapolate=False)
+        assert torch.equal(uN, runs[False][0])
