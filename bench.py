@@ -435,10 +435,13 @@ def main():
             """n-step rollout with tapes, then its adjoint; returns (dS, info)."""
             us, ps, tapes = [u0], [p0], []
             infos = []
+            pst = None
             for _ in range(n_steps):
                 t = cx.new_tape()
-                pv = ps[-2] if len(ps) > 1 else None   # extrapolated start of the first pressure solve
-                u1, p1, inf = cx.step(us[-1], ps[-1], nu, S, ub, case.dt, opts, tape=t, info=True, p_prev=pv)
+                # pressure solves start from the previous step's pressures (piso_step_opts)
+                pv, pvs, pst = (ps[-2] if len(ps) > 1 else None), pst, torch.empty_like(p0)
+                u1, p1, inf = cx.step(us[-1], ps[-1], nu, S, ub, case.dt, opts, tape=t, info=True, p_prev=pv,
+                                      p_prev_star=pvs, p_star_out=pst)
                 us.append(u1)
                 ps.append(p1)
                 tapes.append(t)
@@ -460,11 +463,13 @@ def main():
             return dS, infos
 
         def fwd(n_steps):
-            u, p, pv = u0, p0, None
+            u, p, pv, pvs = u0, p0, None, None
             infos = []
             for _ in range(n_steps):
-                u, p1, inf = cx.step(u, p, nu, S, ub, case.dt, opts, info=True, p_prev=pv)
-                pv, p = p, p1
+                pst = torch.empty_like(p0)
+                u, p1, inf = cx.step(u, p, nu, S, ub, case.dt, opts, info=True, p_prev=pv, p_prev_star=pvs,
+                                     p_star_out=pst)
+                pv, pvs, p = p, pst, p1
                 infos.append(inf)
             return infos
 

@@ -163,23 +163,29 @@ class Context:
         return L.SystemGrad(*[g[k].data_ptr() for k in ("dA", "dC", "db_u", "db")])
 
     # ---------------------------------------------------------------- whole step
-    def step(self, u, p, nu, S, u_b, dt, opts=None, tape=None, info=False, p_prev=None):
-        """One PISO step.  p_prev: the previous step's p of the same rollout (optional): the
-        first pressure solve then starts from 2 p - p_prev."""
+    def step(self, u, p, nu, S, u_b, dt, opts=None, tape=None, info=False, p_prev=None, p_prev_star=None,
+             p_star_out=None):
+        """One PISO step.  Optional starts of its pressure solves from the previous step of
+        the same rollout: p_prev, that step's input pressure, and p_prev_star, its
+        first-corrector pressure p* (which p_star_out, if given, receives for this step);
+        see piso_step_opts."""
         d, N = self.dim, self.N
         self._t(u, (d, N), "u")
         self._t(p, (N,), "p")
-        if p_prev is not None:
-            self._t(p_prev, (N,), "p_prev")
+        for x, nm in ((p_prev, "p_prev"), (p_prev_star, "p_prev_star"), (p_star_out, "p_star_out")):
+            if x is not None:
+                self._t(x, (N,), nm)
         self._t(S, (d, N), "S")
         nu_t, nf = self._nu(nu)
         ub = self._ub(u_b)
         if tape is not None:
             self._t(tape, (self.tape_bytes // self.elem_bytes,), "tape")
         o = opts if opts is not None else self.default_opts()
-        if p_prev is not None:
+        if p_prev is not None or p_prev_star is not None or p_star_out is not None:
             o = L.StepOpts.from_buffer_copy(o)
             o.p_prev = _ptr(p_prev)
+            o.p_prev_star = _ptr(p_prev_star)
+            o.p_star_out = _ptr(p_star_out)
         u1 = torch.empty_like(u)
         p1 = torch.empty_like(p)
         inf = L.StepInfo()
@@ -456,65 +462,88 @@ def _adjoint_owner(pctx: Context, owner):
         pctx._adj_owner = owner
 
 
+def _chained_step(pctx: Context, u, p, nu, S, u_b, dt, opts, start, tape=None):
+    """One step whose pressure solves start from the previous step of the rollout
+    (start = (p_prev, p_prev_star) or None; see piso_step_opts).  Returns
+    (u^{n+1}, p^{n+1}, p*): p* is this step's first-corrector pressure, the next step's
+    p_prev_star, so the next step's start is (p, p*)."""
+    pv, pvs = start if start is not None else (None, None)
+    pst = torch.empty_like(p)
+    u1, p1 = pctx.step(u, p, nu, S, u_b, dt, opts, tape=tape, p_prev=pv, p_prev_star=pvs, p_star_out=pst)
+    return u1, p1, pst
+
+
 class PisoStep(torch.autograd.Function):
-    """One differentiable PISO step: (u, p, S, nu, u_b) -> (u^{n+1}, p^{n+1}).
+    """One differentiable PISO step: (u, p, S, nu, u_b) -> (u^{n+1}, p^{n+1}), plus the
+    step's first-corrector pressure p* (not differentiable) for the next step's start.
 
     The forward keeps a tape of the intermediates; the backward runs the hand-written
     adjoint (transposed solves and per-operation adjoints).  `owner` groups the steps
-    of one rollout for the adjoint warm start (None: a stand-alone step)."""
+    of one rollout for the adjoint warm start (None: a stand-alone step).  p_prev and
+    p_prev_star only choose where the pressure solves start (piso_step_opts)."""
 
     @staticmethod
-    def forward(fctx, pctx: Context, opts, dt, owner, u, p, S, nu, u_b, p_prev=None):
+    def forward(fctx, pctx: Context, opts, dt, owner, u, p, S, nu, u_b, p_prev=None, p_prev_star=None):
         tape = pctx.new_tape()
-        u1, p1 = pctx.step(u, p, nu, S, u_b, dt, opts, tape=tape, p_prev=p_prev)
+        start = None if p_prev is None and p_prev_star is None else (p_prev, p_prev_star)
+        u1, p1, pst = _chained_step(pctx, u, p, nu, S, u_b, dt, opts, start, tape=tape)
         fctx.pctx, fctx.opts, fctx.dt = pctx, opts, dt
         fctx.owner = owner if owner is not None else object()
         fctx.save_for_backward(tape, u, p, nu, u_b if u_b is not None else torch.empty(0))
         fctx.has_ub = u_b is not None
-        return u1, p1
+        fctx.mark_non_differentiable(pst)
+        return u1, p1, pst
 
     @staticmethod
-    def backward(fctx, du1, dp1):
+    def backward(fctx, du1, dp1, _dpst):
         tape, u, p, nu, u_b = fctx.saved_tensors
         pctx = fctx.pctx
         _adjoint_owner(pctx, fctx.owner)
         g = pctx.step_backward(tape, u, p, nu, u_b if fctx.has_ub else None, fctx.dt, du1, dp1, fctx.opts)
         return (None, None, None, None, g["u"], g["p"], g["S"], g["nu"].reshape(nu.shape),
-                g["u_b"] if fctx.has_ub else None, None)
+                g["u_b"] if fctx.has_ub else None, None, None)
+
+
+def _segment_start(p_prev, p_prev_star):
+    return None if p_prev is None and p_prev_star is None else (p_prev.detach(), p_prev_star.detach())
 
 
 class _Segment(torch.autograd.Function):
     """k steps whose tapes are dropped in the forward and recomputed in the backward
-    (step checkpointing): memory O(1 state + k tapes) per segment."""
+    (step checkpointing): memory O(1 state + k tapes) per segment.  The pressure starts
+    chain through the segment (chain = True) from (p_prev, p_prev_star), in the forward
+    and in its recomputation alike; the last step's start pair for the next step is
+    returned beside the state (not differentiable)."""
 
     @staticmethod
-    def forward(fctx, pctx: Context, opts, dt, k, owner, chain, u, p, S, nu, u_b, p_prev):
-        uu, pp, pv = u, p, p_prev
+    def forward(fctx, pctx: Context, opts, dt, k, owner, chain, u, p, S, nu, u_b, p_prev, p_prev_star):
+        start = _segment_start(p_prev, p_prev_star)
+        fctx.start = start
+        uu, pp = u, p
         for _ in range(k):
             last = pp
-            uu, pp = pctx.step(uu, pp, nu, S, u_b, dt, opts, p_prev=pv)
-            pv = last if chain else None
+            uu, pp, pst = _chained_step(pctx, uu, pp, nu, S, u_b, dt, opts, start)
+            start = (last, pst) if chain else None
         fctx.pctx, fctx.opts, fctx.dt, fctx.k, fctx.owner = pctx, opts, dt, k, owner
         fctx.chain = chain
-        fctx.p_prev = None if p_prev is None else p_prev.detach()   # the recomputation repeats the chain
         fctx.has_ub = u_b is not None
         fctx.save_for_backward(u, p, S, nu, u_b if u_b is not None else torch.empty(0))
-        prev = last.detach().clone()   # the last step's starting p: the next step's p_prev
-        fctx.mark_non_differentiable(prev)
-        return uu, pp, prev
+        nxt = (last.detach().clone(), pst)
+        fctx.mark_non_differentiable(*nxt)
+        return uu, pp, nxt[0], nxt[1]
 
     @staticmethod
-    def backward(fctx, du, dp, _dpv):
+    def backward(fctx, du, dp, _d1, _d2):
         u, p, S, nu, u_b = fctx.saved_tensors
         pctx, opts, dt, k = fctx.pctx, fctx.opts, fctx.dt, fctx.k
         ub = u_b if fctx.has_ub else None
         states, tapes = [(u, p)], []
-        uu, pp, pv = u, p, fctx.p_prev
+        uu, pp, start = u, p, fctx.start
         for _ in range(k):
             t = pctx.new_tape()
             last = pp
-            uu, pp = pctx.step(uu, pp, nu, S, ub, dt, opts, tape=t, p_prev=pv)
-            pv = last if fctx.chain else None
+            uu, pp, pst = _chained_step(pctx, uu, pp, nu, S, ub, dt, opts, start, tape=t)
+            start = (last, pst) if fctx.chain else None
             states.append((uu, pp))
             tapes.append(t)
         dS = torch.zeros_like(S)
@@ -531,7 +560,7 @@ class _Segment(torch.autograd.Function):
             if dub is not None:
                 dub += g["u_b"]
             tapes[q] = None
-        return None, None, None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), dub, None
+        return None, None, None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), dub, None, None
 
 
 class OutflowUpdate(torch.autograd.Function):
@@ -552,36 +581,38 @@ class OutflowUpdate(torch.autograd.Function):
 
 class _OutflowSegment(torch.autograd.Function):
     """k checkpointed steps, each preceded by the outflow update of the boundary
-    values: (u, p, S, nu, u_b) -> (u^{n+k}, p^{n+k}, u_b^{n+k})."""
+    values: (u, p, S, nu, u_b) -> (u^{n+k}, p^{n+k}, u_b^{n+k}), with the pressure
+    starts chained as in _Segment."""
 
     @staticmethod
-    def forward(fctx, pctx: Context, opts, dt, k, owner, chain, mask, u_m, u, p, S, nu, u_b, p_prev):
-        uu, pp, bb, pv = u, p, u_b, p_prev
+    def forward(fctx, pctx: Context, opts, dt, k, owner, chain, mask, u_m, u, p, S, nu, u_b, p_prev, p_prev_star):
+        start = _segment_start(p_prev, p_prev_star)
+        fctx.start = start
+        uu, pp, bb = u, p, u_b
         for _ in range(k):
             bb = pctx.outflow_update(uu, bb, mask, u_m, dt)
             last = pp
-            uu, pp = pctx.step(uu, pp, nu, S, bb, dt, opts, p_prev=pv)
-            pv = last if chain else None
+            uu, pp, pst = _chained_step(pctx, uu, pp, nu, S, bb, dt, opts, start)
+            start = (last, pst) if chain else None
         fctx.pctx, fctx.opts, fctx.dt, fctx.k, fctx.mask, fctx.u_m = pctx, opts, dt, k, mask, u_m
         fctx.owner, fctx.chain = owner, chain
-        fctx.p_prev = None if p_prev is None else p_prev.detach()
         fctx.save_for_backward(u, p, S, nu, u_b)
-        prev = last.detach().clone()
-        fctx.mark_non_differentiable(prev)
-        return uu, pp, bb, prev
+        nxt = (last.detach().clone(), pst)
+        fctx.mark_non_differentiable(*nxt)
+        return uu, pp, bb, nxt[0], nxt[1]
 
     @staticmethod
-    def backward(fctx, du, dp, dbb, _dpv):
+    def backward(fctx, du, dp, dbb, _d1, _d2):
         u, p, S, nu, u_b = fctx.saved_tensors
         pctx, opts, dt, k, mask, u_m = fctx.pctx, fctx.opts, fctx.dt, fctx.k, fctx.mask, fctx.u_m
         states, tapes, used = [(u, p, u_b)], [], []
-        uu, pp, bb, pv = u, p, u_b, fctx.p_prev
+        uu, pp, bb, start = u, p, u_b, fctx.start
         for _ in range(k):
             nb = pctx.outflow_update(uu, bb, mask, u_m, dt)
             t = pctx.new_tape()
             last = pp
-            uu, pp = pctx.step(uu, pp, nu, S, nb, dt, opts, tape=t, p_prev=pv)
-            pv = last if fctx.chain else None
+            uu, pp, pst = _chained_step(pctx, uu, pp, nu, S, nb, dt, opts, start, tape=t)
+            start = (last, pst) if fctx.chain else None
             used.append(nb)
             states.append((uu, pp, nb))
             tapes.append(t)
@@ -600,7 +631,7 @@ class _OutflowSegment(torch.autograd.Function):
             gb, gu = pctx.outflow_update_backward(un, bprev, mask, u_m, dt, gb_used, du=g["u"])
             gp = g["p"]
             tapes[q] = None
-        return None, None, None, None, None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), gb, None
+        return None, None, None, None, None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), gb, None, None
 
 
 class PlaneStatistics(torch.autograd.Function):
@@ -719,7 +750,8 @@ def divfree_gradient_hook(pctx: Context, S, lam, opts=None):
 
 def step(pctx: Context, u, p, S, nu, u_b, dt, opts=None):
     """Differentiable single step (keeps its tape until backward)."""
-    return PisoStep.apply(pctx, opts if opts is not None else pctx.default_opts(), dt, None, u, p, S, nu, u_b)
+    u1, p1, _ = PisoStep.apply(pctx, opts if opts is not None else pctx.default_opts(), dt, None, u, p, S, nu, u_b)
+    return u1, p1
 
 
 def rollout(pctx: Context, u0, p0, S, nu, u_b, dt, n_steps: int, checkpoint_every: int = 0, opts=None,
@@ -737,13 +769,15 @@ def rollout(pctx: Context, u0, p0, S, nu, u_b, dt, n_steps: int, checkpoint_ever
     are advanced by the advective outflow update (the boundary values then become part
     of the state; the result gains a third entry, the final u_b).
 
-    extrapolate: every step after the first starts its first pressure solve from
-    2 p^n - p^{n-1} (piso_step_opts.p_prev); the chain runs through warm-up steps and
-    checkpointed segments alike, so that results do not depend on checkpoint_every."""
+    extrapolate: every step after the first starts its pressure solves from the previous
+    step's pressures (piso_step_opts.p_prev and p_prev_star: corrector 1 from
+    p*_{n-1} + (p_n - p_{n-1}), corrector 2 from p* + (p_n - p*_{n-1})); the chain runs
+    through warm-up steps and checkpointed segments alike, so that results do not depend
+    on checkpoint_every."""
     o = opts if opts is not None else pctx.default_opts()
     owner = object()   # the backward steps of this rollout share the adjoint warm start
     u, p, ub = u0, p0, u_b
-    pv = None   # the previous step's pressure (extrapolation of the first solve's start)
+    start = None   # (p_{n-1}, p*_{n-1}) of the previous step, once there is one
     if outflow is not None:
         mask, u_m = outflow
         mask = pctx._mask(mask)
@@ -754,29 +788,31 @@ def rollout(pctx: Context, u0, p0, S, nu, u_b, dt, n_steps: int, checkpoint_ever
                 if outflow is not None:
                     ub = pctx.outflow_update(u.detach(), ub, mask, u_m, dt)
                 last = p.detach()
-                u, p = pctx.step(u.detach(), p.detach(), nu.detach(), S.detach(), ub, dt, o, p_prev=pv)
-                pv = last if extrapolate else None
+                u, p, pst = _chained_step(pctx, u.detach(), last, nu.detach(), S.detach(), ub, dt, o, start)
+                start = (last, pst) if extrapolate else None
     traj = []
     done = 0
+    pv, pvs = start if start is not None else (None, None)
     while done < n_steps:
         last = p.detach()
         if outflow is not None:
             if checkpoint_every > 0:
                 k = min(checkpoint_every, n_steps - done)
-                u, p, ub, last = _OutflowSegment.apply(pctx, o, dt, k, owner, extrapolate, mask, u_m, u, p, S, nu, ub, pv)
+                u, p, ub, last, pst = _OutflowSegment.apply(pctx, o, dt, k, owner, extrapolate, mask, u_m, u, p, S,
+                                                            nu, ub, pv, pvs)
                 done += k
             else:
                 ub = OutflowUpdate.apply(pctx, mask, u_m, dt, u, ub)
-                u, p = PisoStep.apply(pctx, o, dt, owner, u, p, S, nu, ub, pv)
+                u, p, pst = PisoStep.apply(pctx, o, dt, owner, u, p, S, nu, ub, pv, pvs)
                 done += 1
         elif checkpoint_every > 0:
             k = min(checkpoint_every, n_steps - done)
-            u, p, last = _Segment.apply(pctx, o, dt, k, owner, extrapolate, u, p, S, nu, ub, pv)
+            u, p, last, pst = _Segment.apply(pctx, o, dt, k, owner, extrapolate, u, p, S, nu, ub, pv, pvs)
             done += k
         else:
-            u, p = PisoStep.apply(pctx, o, dt, owner, u, p, S, nu, ub, pv)
+            u, p, pst = PisoStep.apply(pctx, o, dt, owner, u, p, S, nu, ub, pv, pvs)
             done += 1
-        pv = last if extrapolate else None
+        pv, pvs = (last, pst) if extrapolate else (None, None)
         if return_all:
             traj.append((u, p) if outflow is None else (u, p, ub))
     if return_all:

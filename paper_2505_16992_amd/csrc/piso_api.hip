@@ -228,7 +228,8 @@ int do_step(piso_ctx* c, hipStream_t s, const R* u_n, const R* p_n, const R* nu,
     A = t.A; C = t.C; Pf = t.Pf; Dinv = t.Dinv; us = t.us; h1 = t.h1; p1 = t.p1; u1 = t.u1; h2 = t.h2; p2 = t.p2;
   } else {
     A = (R*)c->w_A; C = (R*)c->w_C; Pf = (R*)c->w_Pf; Dinv = (R*)c->w_Dinv; us = (R*)c->w_us;
-    h1 = (R*)c->w_h1; p1 = (R*)c->w_p1; u1 = (R*)c->w_u1; h2 = (R*)c->w_h; p2 = p_np1;
+    h1 = (R*)c->w_h1; p1 = o->p_star_out ? (R*)o->p_star_out : (R*)c->w_p1; u1 = (R*)c->w_u1; h2 = (R*)c->w_h;
+    p2 = p_np1;
   }
   R* bu = (R*)c->w_bu;
   R* b = (R*)c->w_b;
@@ -251,9 +252,17 @@ int do_step(piso_ctx* c, hipStream_t s, const R* u_n, const R* p_n, const R* nu,
     R* h = last ? h2 : h1;
     R* pk = last ? p2 : p1;
     R* uk = last ? u_np1 : u1;
-    if (k == 0 && o->p_prev && pk != p_lag) {
-      // the first corrector starts from the pressure extrapolated in time
-      if (int e = launch_extrapolate<R>(c, s, p_lag, (const R*)o->p_prev, pk)) return e;
+    // starts of the solves from the earlier steps of the rollout: corrector 1 from the
+    // previous p* advanced by the last change of p, or from p extrapolated in time;
+    // corrector 2 from p* advanced by the previous step's corrector-2 increment
+    const R* pv = (const R*)o->p_prev;
+    const R* pvs = (const R*)o->p_prev_star;
+    if (k == 0 && pv && pvs) {
+      if (int e = launch_add_diff<R>(c, s, pvs, p_n, pv, pk)) return e;
+    } else if (k == 0 && pv) {
+      if (int e = launch_extrapolate<R>(c, s, p_n, pv, pk)) return e;
+    } else if (k == 1 && pvs) {
+      if (int e = launch_add_diff<R>(c, s, p_lag, p_n, pvs, pk)) return e;
     } else if (pk != p_lag) {
       PISO_HIP(c, hipMemcpyAsync(pk, p_lag, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
     }
@@ -273,6 +282,11 @@ int do_step(piso_ctx* c, hipStream_t s, const R* u_n, const R* p_n, const R* nu,
     p_lag = pk;
   }
   if (p2 != p_np1) PISO_HIP(c, hipMemcpyAsync(p_np1, p2, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
+  if (o->p_star_out) {
+    const R* pst = ncorr == 1 ? p_np1 : p1;
+    if (pst != o->p_star_out)
+      PISO_HIP(c, hipMemcpyAsync(o->p_star_out, pst, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
+  }
   if (info) {
     info->vel = vi;
     info->pres[0] = pi[0];
@@ -618,6 +632,9 @@ int piso_step(piso_ctx* c, void* stream, const void* u_n, const void* p_n, const
   REQUIRE(o->n_correctors >= 1 && o->n_correctors <= 8, "piso_step: n_correctors must be 1..8");
   REQUIRE(!tape || o->n_correctors == 2, "piso_step: a tape requires n_correctors = 2");
   REQUIRE(u_np1 != u_n && p_np1 != p_n, "piso_step: outputs must not alias inputs");
+  REQUIRE(!o->p_star_out || (o->p_star_out != p_n && o->p_star_out != p_np1 && o->p_star_out != o->p_prev &&
+                             o->p_star_out != o->p_prev_star),
+          "piso_step: p_star_out must not alias p_n, p_np1, p_prev or p_prev_star");
 #define ARGS(R)                                                                                              \
   c, s, (const R*)u_n, (const R*)p_n, (const R*)nu, nu_is_field, (const R*)S, (const R*)u_b, dt, (R*)u_np1, \
       (R*)p_np1, tape, o, info

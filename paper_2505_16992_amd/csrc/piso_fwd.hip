@@ -439,6 +439,14 @@ __global__ void __launch_bounds__(kWG) k_extrapolate(int n, const R* __restrict_
   if (i < n) y[i] = R(2) * p[i] - q[i];
 }
 
+// y = a + b - c
+template <typename R>
+__global__ void __launch_bounds__(kWG) k_add_diff(int n, const R* __restrict__ a, const R* __restrict__ b,
+                                                 const R* __restrict__ q, R* __restrict__ y) {
+  const int i = blockIdx.x * kWG + threadIdx.x;
+  if (i < n) y[i] = a[i] + (b[i] - q[i]);
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kWG) k_fill(int n, R v, R* __restrict__ y) {
   const int i = blockIdx.x * kWG + threadIdx.x;
@@ -600,6 +608,12 @@ int launch_extrapolate(piso_ctx* c, hipStream_t s, const R* p, const R* q, R* y)
 }
 
 template <typename R>
+int launch_add_diff(piso_ctx* c, hipStream_t s, const R* a, const R* b, const R* q, R* y) {
+  k_add_diff<R><<<grid_cells(c->N), kWG, 0, s>>>(c->N, a, b, q, y);
+  return check_launch(c, "k_add_diff");
+}
+
+template <typename R>
 int launch_scale_invJ(piso_ctx* c, hipStream_t s, const R* x, int ncomp, R* y) {
   k_scale_invJ<R><<<grid_cells(c->N), kWG, 0, s>>>(c->N, ncomp, (const R*)c->invJ, x, y);
   return check_launch(c, "k_scale_invJ");
@@ -657,6 +671,7 @@ int launch_copy(piso_ctx* c, hipStream_t s, const TI* x, TO* y, int n) {
   template int launch_scale_invJ<R>(piso_ctx*, hipStream_t, const R*, int, R*);                      \
   template int launch_flux_div<R>(piso_ctx*, hipStream_t, const R*, const R*, double*);                      \
   template int launch_extrapolate<R>(piso_ctx*, hipStream_t, const R*, const R*, R*);                      \
+  template int launch_add_diff<R>(piso_ctx*, hipStream_t, const R*, const R*, const R*, R*);               \
   template int launch_add_scalar<R>(piso_ctx*, hipStream_t, const double*, R*);                       \
   template int launch_fill<R>(piso_ctx*, hipStream_t, int, R, R*);                                    \
   template int launch_jt_field<R>(piso_ctx*, hipStream_t, const R*, R*);

@@ -371,6 +371,9 @@ int launch_flux_div(piso_ctx* c, hipStream_t s, const R* F, const R* ub, double*
 // y = 2 p - q
 template <typename R>
 int launch_extrapolate(piso_ctx* c, hipStream_t s, const R* p, const R* q, R* y);
+// y = a + b - q
+template <typename R>
+int launch_add_diff(piso_ctx* c, hipStream_t s, const R* a, const R* b, const R* q, R* y);
 template <typename R>
 int launch_add_scalar(piso_ctx* c, hipStream_t s, const double* v, R* y);
 template <typename R>

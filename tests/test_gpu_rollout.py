@@ -270,18 +270,20 @@ def test_rollout_warmup(api):
     assert torch.equal(uT.detach(), uT2.detach()) and torch.equal(pT.detach(), pT2.detach())
     assert torch.equal(g1, g2)
     uE, pE = api.rollout(ctx, u, p, S, nu, ub, case.dt, 2, warmup=3, opts=o)
-    uu, pp, pv = u, p, None
+    uu, pp, pv, pvs = u, p, None, None
     for _ in range(5):
-        uu, p1 = ctx.step(uu, pp, nu, S, ub, case.dt, o, p_prev=pv)
-        pv, pp = pp, p1
+        pst = torch.empty_like(pp)
+        uu, p1 = ctx.step(uu, pp, nu, S, ub, case.dt, o, p_prev=pv, p_prev_star=pvs, p_star_out=pst)
+        pv, pvs, pp = pp, pst, p1
     assert torch.equal(uE.detach(), uu) and torch.equal(pE.detach(), pp)
 
 
 @pytest.mark.parametrize("name", ["tgv16", "cavity12", "channel_q", "cylinder_q"])
 def test_extrapolated_start_matches_oracle(api, name):
-    """A step given p_prev (its first pressure solve starts from 2 p - p_prev) reaches
-    the oracle's step to the solver tolerance, whatever p_prev is: the start of a
-    converged Krylov solve does not enter the result."""
+    """A step given earlier pressures (p_prev, p_prev_star: its pressure solves start from
+    them) reaches the oracle's step to the solver tolerance, whatever they are: the start
+    of a converged Krylov solve does not enter the result.  p_star_out receives the first
+    corrector's pressure, which the tape holds too."""
     say("test_extrapolated_start_matches_oracle", name)
     case = small_cases()[name]
     ctx = api.Context(case.domain, "f64")
@@ -289,21 +291,34 @@ def test_extrapolated_start_matches_oracle(api, name):
     o = tight_opts(ctx)
     ref = oracle_step(Geometry(case.domain), u0, p0, case.nu, S0, case.dt, ub0)
     rng = np.random.default_rng(22)
-    for pv in (p0 + 0.05 * rng.standard_normal(p0.shape), rng.standard_normal(p0.shape)):
-        u1, p1, info = ctx.step(u, p, nu, S, ub, case.dt, o, info=True, p_prev=dev(pv, ctx.dtype))
+    t = ctx.dtype
+    near = (p0 + 0.05 * rng.standard_normal(p0.shape), p0 + 0.05 * rng.standard_normal(p0.shape))
+    far = (rng.standard_normal(p0.shape), rng.standard_normal(p0.shape))
+    for pv, pvs in (near, far, (near[0], None), (None, far[1])):
+        pst = torch.empty_like(p)
+        tape = ctx.new_tape()
+        u1, p1, info = ctx.step(u, p, nu, S, ub, case.dt, o, info=True, tape=tape,
+                                p_prev=None if pv is None else dev(pv, t),
+                                p_prev_star=None if pvs is None else dev(pvs, t), p_star_out=pst)
         assert info["pres"][0]["status"] == 0 and info["pres"][1]["status"] == 0, info
         assert rel(host(u1), ref.u2) < 1e-9
         assert rel_p(host(p1), ref.p2) < 1e-9
+        assert rel_p(host(pst), ref.p1) < 1e-9
+        N, d = ctx.N, ctx.dim
+        off = 2 * N + 5 * d * N   # A, C, P_f, D^-1, u*, h* precede p* on the tape
+        assert torch.equal(pst, tape[off:off + N])
     with pytest.raises(ValueError):
         ctx.step(u, p, nu, S, ub, case.dt, o, p_prev=p[:-1])
+    with pytest.raises(RuntimeError, match="p_star_out"):
+        ctx.step(u, p, nu, S, ub, case.dt, o, p_prev=p.clone(), p_star_out=p)
 
 
 @pytest.mark.parametrize("prec", ["f64", "mixed"])
 def test_extrapolated_start_saves_iterations(api, prec):
-    """On a developed flow, the pressure of the previous step extrapolated in time is a
-    better start for the first corrector's solve than the lagged pressure alone; the
-    rollout's result agrees with the unextrapolated one to the solver tolerance, and a
-    rollout of stand-alone steps with p_prev equals api.rollout's chain bit for bit."""
+    """On a developed flow, starts from the previous step's pressures save pressure
+    iterations in both correctors; the rollout's result agrees with the unextrapolated
+    one to the solver tolerance, and a rollout of stand-alone steps with the chained
+    starts equals api.rollout's chain bit for bit, checkpointed or not."""
     say("test_extrapolated_start_saves_iterations", prec)
     case = cases.channel(32, 24, 16)
     ctx = api.Context(case.domain, prec)
@@ -316,15 +331,17 @@ def test_extrapolated_start_saves_iterations(api, prec):
             u, p = ctx.step(u, p, nu, S, ub, case.dt, o)
         runs = {}
         for extra in (False, True):
-            uu, pp, pv, its = u, p, None, []
+            uu, pp, pv, pvs, its = u, p, None, None, []
             for _ in range(8):
-                uu, p1, inf = ctx.step(uu, pp, nu, S, ub, case.dt, o, info=True,
-                                       p_prev=pv if extra else None)
-                pv, pp = pp, p1
-                its.append(inf["pres"][0]["iters"])
-            runs[extra] = (uu, pp, its)
-        say("corrector-1 CG iterations plain %s extrapolated %s" % (runs[False][2], runs[True][2]))
-        assert sum(runs[True][2][1:]) < sum(runs[False][2][1:])
+                pst = torch.empty_like(pp)
+                uu, p1, inf = ctx.step(uu, pp, nu, S, ub, case.dt, o, info=True, p_star_out=pst,
+                                       p_prev=pv if extra else None, p_prev_star=pvs if extra else None)
+                pv, pvs, pp = pp, pst, p1
+                its.append([q["iters"] for q in inf["pres"]])
+            runs[extra] = (uu, pp, np.array(its))
+        say("CG iterations per corrector, plain %s extrapolated %s" % (runs[False][2].tolist(), runs[True][2].tolist()))
+        plain, extra = runs[False][2][2:].sum(axis=0), runs[True][2][2:].sum(axis=0)
+        assert extra[0] < plain[0] and extra[1] < plain[1]
         assert rel(host(runs[True][0]), host(runs[False][0])) < 1e-5
         uT, pT = api.rollout(ctx, u, p, S, nu, ub, case.dt, 8, opts=o)
         assert torch.equal(uT, runs[True][0]) and torch.equal(pT, runs[True][1])
