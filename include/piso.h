@@ -158,10 +158,12 @@ typedef struct {
                                       2 = skip the adjoint pressure solves (Sec. 2.4) */
   int32_t adjoint_warm_start;      /* backward only: 1 = each adjoint pressure solve of
                                       piso_step_backward starts from the solution of the same
-                                      corrector's solve in the previous call (consecutive steps
-                                      of a backward rollout have similar adjoint pressures);
-                                      0 = from zero.  The result then depends on that history
-                                      within the solver tolerance; piso_adjoint_reset clears it. */
+                                      corrector's solve in the previous call, or from the linear
+                                      extrapolation 2 l_1 - l_2 of the solutions of the two
+                                      previous calls once there are two (consecutive steps of a
+                                      backward rollout have similar adjoint pressures); 0 = from
+                                      zero.  The result then depends on that history within the
+                                      solver tolerance; piso_adjoint_reset clears it. */
   int32_t report_flux_div;         /* forward only: 1 = fill piso_step_info.flux_div_linf (one
                                       extra flux and divergence sweep per corrector, and a
                                       synchronisation of the stream); 0 = leave it 0 */

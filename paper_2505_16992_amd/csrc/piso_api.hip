@@ -101,7 +101,8 @@ int alloc_workspaces(piso_ctx* c) {
       {&c->a_g, D * N * e}, {&c->a_uin, D * N * e}, {&c->a_lam, N * e}, {&c->a_pbar, N * e},
       {&c->a_mu, D * N * e}, {&c->a_dh, D * N * e}, {&c->a_dA, N * e}, {&c->a_dC, 2 * D * N * e},
       {&c->a_dbu, D * N * e}, {&c->a_db, D * N * e}, {&c->a_dp1, N * e}, {&c->a_dnu, N * e},
-      {&c->a_ybar, D * N * e}, {&c->a_cbar, D * D * N * e}, {&c->a_lam_hist[0], N * 8}, {&c->a_lam_hist[1], N * 8}, {&c->w_zb, D * (size_t)std::max(c->NB, 1) * e},
+      {&c->a_ybar, D * N * e}, {&c->a_cbar, D * D * N * e}, {&c->a_lam_hist[0], N * 8}, {&c->a_lam_hist[1], N * 8},
+      {&c->a_lam_hist2[0], N * 8}, {&c->a_lam_hist2[1], N * 8}, {&c->w_zb, D * (size_t)std::max(c->NB, 1) * e},
       {(void**)&c->partials, (size_t)kPartRegions * kRedGrid * sizeof(double)},
       {(void**)&c->mean, 8 * sizeof(double)}, {(void**)&c->cg, sizeof(CgState)}, {(void**)&c->bi, sizeof(BiState)},
   };
@@ -169,7 +170,8 @@ int do_pressure(piso_ctx* c, hipStream_t s, const R* A, const R* C, const R* bu,
 
 // Zero-mean lambda of P lambda = g - mean(g) (pressure adjoint).  x0 = 0, or with
 // hist = 0 / 1 the kept solution of that corrector's previous adjoint solve when there is
-// one; a solve that ends with status >= 0 is kept for the next call.
+// one, or 2 lambda_prev - lambda_prev2 when the two previous ones are kept; a solve that
+// ends with status >= 0 is kept for the next calls.
 template <typename R>
 int do_pressure_adjoint(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, const R* g, R* lam,
                         const piso_solve_opts* o, piso_solve_info* info, int hist = -1) {
@@ -178,13 +180,23 @@ int do_pressure_adjoint(piso_ctx* c, hipStream_t s, const R* Pf, const R* Dinv, 
   piso_solve_info tmp{};
   piso_solve_info* inf = info ? info : &tmp;
   if (int rc = launch_sum<R, double>(c, s, g, N, 1.0 / N, c->mean)) return rc;
-  if (warm)
+  if (warm && c->lam_hist_valid2[hist]) {
+    // two earlier solutions of this corrector's adjoint: start from their linear
+    // extrapolation (consecutive backward steps walk back through time)
+    if (int e = launch_extrapolate<R>(c, s, (const R*)c->a_lam_hist[hist], (const R*)c->a_lam_hist2[hist], lam))
+      return e;
+  } else if (warm) {
     PISO_HIP(c, hipMemcpyAsync(lam, c->a_lam_hist[hist], sizeof(R) * N, hipMemcpyDeviceToDevice, s));
-  else
+  } else {
     PISO_HIP(c, hipMemsetAsync(lam, 0, sizeof(R) * N, s));
+  }
   const int rc = pressure_solve<R, R>(c, s, Pf, Dinv, g, c->mean, lam, o, inf);
   if (rc < 0) return rc;
   if (hist >= 0 && inf->status >= 0) {
+    if (c->lam_hist_valid[hist]) {
+      PISO_HIP(c, hipMemcpyAsync(c->a_lam_hist2[hist], c->a_lam_hist[hist], sizeof(R) * N, hipMemcpyDeviceToDevice, s));
+      c->lam_hist_valid2[hist] = true;
+    }
     PISO_HIP(c, hipMemcpyAsync(c->a_lam_hist[hist], lam, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
     c->lam_hist_valid[hist] = true;
   }
@@ -771,6 +783,7 @@ int piso_step_backward(piso_ctx* c, void* stream, const void* tape, const void* 
 int piso_adjoint_reset(piso_ctx* c) {
   if (!c) return PISO_E_ARG;
   c->lam_hist_valid[0] = c->lam_hist_valid[1] = false;
+  c->lam_hist_valid2[0] = c->lam_hist_valid2[1] = false;
   return PISO_OK;
 }
 

@@ -174,6 +174,8 @@ struct piso_ctx {
   // cell), the warm start of the next call
   void* a_lam_hist[2] = {nullptr, nullptr};
   bool lam_hist_valid[2] = {false, false};
+  void* a_lam_hist2[2] = {nullptr, nullptr};
+  bool lam_hist_valid2[2] = {false, false};
   void* k_z = nullptr;            // PCG preconditioned residual [N] (multigrid)
   void* k_y = nullptr;            // omega D^-1 r, the multigrid pre-smoothing [N]
   // PCG operands copied into context-owned buffers (graph-stable pointers)
