@@ -438,10 +438,10 @@ def main():
             pst = None
             for _ in range(n_steps):
                 t = cx.new_tape()
-                # pressure solves start from the previous step's pressures (piso_step_opts)
-                pv, pvs, pst = (ps[-2] if len(ps) > 1 else None), pst, torch.empty_like(p0)
+                # the linear solves start from the previous step's fields (piso_step_opts)
+                uv, pv, pvs, pst = ((us[-2], ps[-2]) if len(ps) > 1 else (None, None)) + (pst, torch.empty_like(p0))
                 u1, p1, inf = cx.step(us[-1], ps[-1], nu, S, ub, case.dt, opts, tape=t, info=True, p_prev=pv,
-                                      p_prev_star=pvs, p_star_out=pst)
+                                      p_prev_star=pvs, p_star_out=pst, u_prev=uv)
                 us.append(u1)
                 ps.append(p1)
                 tapes.append(t)
@@ -463,13 +463,13 @@ def main():
             return dS, infos
 
         def fwd(n_steps):
-            u, p, pv, pvs = u0, p0, None, None
+            u, p, uv, pv, pvs = u0, p0, None, None, None
             infos = []
             for _ in range(n_steps):
                 pst = torch.empty_like(p0)
-                u, p1, inf = cx.step(u, p, nu, S, ub, case.dt, opts, info=True, p_prev=pv, p_prev_star=pvs,
-                                     p_star_out=pst)
-                pv, pvs, p = p, pst, p1
+                u1, p1, inf = cx.step(u, p, nu, S, ub, case.dt, opts, info=True, p_prev=pv, p_prev_star=pvs,
+                                      p_star_out=pst, u_prev=uv)
+                uv, pv, pvs, u, p = u, p, pst, u1, p1
                 infos.append(inf)
             return infos
 

@@ -167,8 +167,8 @@ typedef struct {
   int32_t report_flux_div;         /* forward only: 1 = fill piso_step_info.flux_div_linf (one
                                       extra flux and divergence sweep per corrector, and a
                                       synchronisation of the stream); 0 = leave it 0 */
-  /* Starts of the pressure solves from earlier steps of the same rollout (forward only, per
-     call; device [N] arrays of the context's element type, NULL = not given).  They change
+  /* Starts of the linear solves from earlier steps of the same rollout (forward only, per
+     call; device arrays of the context's element type, NULL = not given).  They change
      only where the Krylov solves start, so the result changes only within the solver
      tolerance; p_n stays the lagged pressure of eqs. implEuler1 and velCorrDiscrete.
        corrector 1 starts from  p*_{n-1} + (p_n - p_prev)   with p_prev and p_prev_star,
@@ -178,10 +178,12 @@ typedef struct {
                                 p* (corrector 1's pressure)  otherwise.
      p_star_out receives this step's p* (with one corrector: its only pressure) for the next
      step's p_prev_star.  p_star_out must not alias p_n, p_np1, p_prev or p_prev_star
-     (PISO_E_ARG). */
+     (PISO_E_ARG).  With u_prev (device [d][N]) the velocity solve starts from
+     2 u_n - u_prev instead of u_n. */
   const void* p_prev;              /* the previous step's pressure p_{n-1} */
   const void* p_prev_star;         /* the previous step's first-corrector pressure p*_{n-1} */
   void* p_star_out;                /* NULL, or device [N] for this step's p* */
+  const void* u_prev;              /* the previous step's velocity u_{n-1} */
 } piso_step_opts;
 
 typedef struct {

@@ -52,7 +52,8 @@ class StepOpts(C.Structure):
     _fields_ = [("vel", SolveOpts), ("pres", SolveOpts), ("n_correctors", C.c_int32),
                 ("grad_p_in_predictor", C.c_int32), ("grad_path_flags", C.c_int32),
                 ("adjoint_warm_start", C.c_int32), ("report_flux_div", C.c_int32),
-                ("p_prev", C.c_void_p), ("p_prev_star", C.c_void_p), ("p_star_out", C.c_void_p)]
+                ("p_prev", C.c_void_p), ("p_prev_star", C.c_void_p), ("p_star_out", C.c_void_p),
+                ("u_prev", C.c_void_p)]
 
 
 class StepInfo(C.Structure):

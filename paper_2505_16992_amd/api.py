@@ -164,28 +164,31 @@ class Context:
 
     # ---------------------------------------------------------------- whole step
     def step(self, u, p, nu, S, u_b, dt, opts=None, tape=None, info=False, p_prev=None, p_prev_star=None,
-             p_star_out=None):
-        """One PISO step.  Optional starts of its pressure solves from the previous step of
-        the same rollout: p_prev, that step's input pressure, and p_prev_star, its
-        first-corrector pressure p* (which p_star_out, if given, receives for this step);
-        see piso_step_opts."""
+             p_star_out=None, u_prev=None):
+        """One PISO step.  Optional starts of its linear solves from the previous step of
+        the same rollout: u_prev and p_prev, that step's input velocity and pressure, and
+        p_prev_star, its first-corrector pressure p* (which p_star_out, if given, receives
+        for this step); see piso_step_opts."""
         d, N = self.dim, self.N
         self._t(u, (d, N), "u")
         self._t(p, (N,), "p")
         for x, nm in ((p_prev, "p_prev"), (p_prev_star, "p_prev_star"), (p_star_out, "p_star_out")):
             if x is not None:
                 self._t(x, (N,), nm)
+        if u_prev is not None:
+            self._t(u_prev, (d, N), "u_prev")
         self._t(S, (d, N), "S")
         nu_t, nf = self._nu(nu)
         ub = self._ub(u_b)
         if tape is not None:
             self._t(tape, (self.tape_bytes // self.elem_bytes,), "tape")
         o = opts if opts is not None else self.default_opts()
-        if p_prev is not None or p_prev_star is not None or p_star_out is not None:
+        if any(x is not None for x in (p_prev, p_prev_star, p_star_out, u_prev)):
             o = L.StepOpts.from_buffer_copy(o)
             o.p_prev = _ptr(p_prev)
             o.p_prev_star = _ptr(p_prev_star)
             o.p_star_out = _ptr(p_star_out)
+            o.u_prev = _ptr(u_prev)
         u1 = torch.empty_like(u)
         p1 = torch.empty_like(p)
         inf = L.StepInfo()
@@ -463,13 +466,14 @@ def _adjoint_owner(pctx: Context, owner):
 
 
 def _chained_step(pctx: Context, u, p, nu, S, u_b, dt, opts, start, tape=None):
-    """One step whose pressure solves start from the previous step of the rollout
-    (start = (p_prev, p_prev_star) or None; see piso_step_opts).  Returns
+    """One step whose linear solves start from the previous step of the rollout
+    (start = (u_prev, p_prev, p_prev_star) or None; see piso_step_opts).  Returns
     (u^{n+1}, p^{n+1}, p*): p* is this step's first-corrector pressure, the next step's
-    p_prev_star, so the next step's start is (p, p*)."""
-    pv, pvs = start if start is not None else (None, None)
+    p_prev_star, so the next step's start is (u, p, p*)."""
+    uv, pv, pvs = start if start is not None else (None, None, None)
     pst = torch.empty_like(p)
-    u1, p1 = pctx.step(u, p, nu, S, u_b, dt, opts, tape=tape, p_prev=pv, p_prev_star=pvs, p_star_out=pst)
+    u1, p1 = pctx.step(u, p, nu, S, u_b, dt, opts, tape=tape, p_prev=pv, p_prev_star=pvs, p_star_out=pst,
+                       u_prev=uv)
     return u1, p1, pst
 
 
@@ -479,13 +483,13 @@ class PisoStep(torch.autograd.Function):
 
     The forward keeps a tape of the intermediates; the backward runs the hand-written
     adjoint (transposed solves and per-operation adjoints).  `owner` groups the steps
-    of one rollout for the adjoint warm start (None: a stand-alone step).  p_prev and
-    p_prev_star only choose where the pressure solves start (piso_step_opts)."""
+    of one rollout for the adjoint warm start (None: a stand-alone step).  u_prev,
+    p_prev and p_prev_star only choose where the linear solves start (piso_step_opts)."""
 
     @staticmethod
-    def forward(fctx, pctx: Context, opts, dt, owner, u, p, S, nu, u_b, p_prev=None, p_prev_star=None):
+    def forward(fctx, pctx: Context, opts, dt, owner, u, p, S, nu, u_b, u_prev=None, p_prev=None, p_prev_star=None):
         tape = pctx.new_tape()
-        start = None if p_prev is None and p_prev_star is None else (p_prev, p_prev_star)
+        start = _segment_start(u_prev, p_prev, p_prev_star)
         u1, p1, pst = _chained_step(pctx, u, p, nu, S, u_b, dt, opts, start, tape=tape)
         fctx.pctx, fctx.opts, fctx.dt = pctx, opts, dt
         fctx.owner = owner if owner is not None else object()
@@ -501,11 +505,13 @@ class PisoStep(torch.autograd.Function):
         _adjoint_owner(pctx, fctx.owner)
         g = pctx.step_backward(tape, u, p, nu, u_b if fctx.has_ub else None, fctx.dt, du1, dp1, fctx.opts)
         return (None, None, None, None, g["u"], g["p"], g["S"], g["nu"].reshape(nu.shape),
-                g["u_b"] if fctx.has_ub else None, None, None)
+                g["u_b"] if fctx.has_ub else None, None, None, None)
 
 
-def _segment_start(p_prev, p_prev_star):
-    return None if p_prev is None and p_prev_star is None else (p_prev.detach(), p_prev_star.detach())
+def _segment_start(u_prev, p_prev, p_prev_star):
+    if u_prev is None and p_prev is None and p_prev_star is None:
+        return None
+    return tuple(None if x is None else x.detach() for x in (u_prev, p_prev, p_prev_star))
 
 
 class _Segment(torch.autograd.Function):
@@ -516,24 +522,24 @@ class _Segment(torch.autograd.Function):
     returned beside the state (not differentiable)."""
 
     @staticmethod
-    def forward(fctx, pctx: Context, opts, dt, k, owner, chain, u, p, S, nu, u_b, p_prev, p_prev_star):
-        start = _segment_start(p_prev, p_prev_star)
+    def forward(fctx, pctx: Context, opts, dt, k, owner, chain, u, p, S, nu, u_b, u_prev, p_prev, p_prev_star):
+        start = _segment_start(u_prev, p_prev, p_prev_star)
         fctx.start = start
         uu, pp = u, p
         for _ in range(k):
-            last = pp
+            lu, lp = uu, pp
             uu, pp, pst = _chained_step(pctx, uu, pp, nu, S, u_b, dt, opts, start)
-            start = (last, pst) if chain else None
+            start = (lu, lp, pst) if chain else None
         fctx.pctx, fctx.opts, fctx.dt, fctx.k, fctx.owner = pctx, opts, dt, k, owner
         fctx.chain = chain
         fctx.has_ub = u_b is not None
         fctx.save_for_backward(u, p, S, nu, u_b if u_b is not None else torch.empty(0))
-        nxt = (last.detach().clone(), pst)
+        nxt = (lu.detach().clone(), lp.detach().clone(), pst)
         fctx.mark_non_differentiable(*nxt)
-        return uu, pp, nxt[0], nxt[1]
+        return (uu, pp) + nxt
 
     @staticmethod
-    def backward(fctx, du, dp, _d1, _d2):
+    def backward(fctx, du, dp, _d1, _d2, _d3):
         u, p, S, nu, u_b = fctx.saved_tensors
         pctx, opts, dt, k = fctx.pctx, fctx.opts, fctx.dt, fctx.k
         ub = u_b if fctx.has_ub else None
@@ -541,9 +547,9 @@ class _Segment(torch.autograd.Function):
         uu, pp, start = u, p, fctx.start
         for _ in range(k):
             t = pctx.new_tape()
-            last = pp
+            lu, lp = uu, pp
             uu, pp, pst = _chained_step(pctx, uu, pp, nu, S, ub, dt, opts, start, tape=t)
-            start = (last, pst) if fctx.chain else None
+            start = (lu, lp, pst) if fctx.chain else None
             states.append((uu, pp))
             tapes.append(t)
         dS = torch.zeros_like(S)
@@ -560,7 +566,7 @@ class _Segment(torch.autograd.Function):
             if dub is not None:
                 dub += g["u_b"]
             tapes[q] = None
-        return None, None, None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), dub, None, None
+        return None, None, None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), dub, None, None, None
 
 
 class OutflowUpdate(torch.autograd.Function):
@@ -585,24 +591,25 @@ class _OutflowSegment(torch.autograd.Function):
     starts chained as in _Segment."""
 
     @staticmethod
-    def forward(fctx, pctx: Context, opts, dt, k, owner, chain, mask, u_m, u, p, S, nu, u_b, p_prev, p_prev_star):
-        start = _segment_start(p_prev, p_prev_star)
+    def forward(fctx, pctx: Context, opts, dt, k, owner, chain, mask, u_m, u, p, S, nu, u_b, u_prev, p_prev,
+                p_prev_star):
+        start = _segment_start(u_prev, p_prev, p_prev_star)
         fctx.start = start
         uu, pp, bb = u, p, u_b
         for _ in range(k):
             bb = pctx.outflow_update(uu, bb, mask, u_m, dt)
-            last = pp
+            lu, lp = uu, pp
             uu, pp, pst = _chained_step(pctx, uu, pp, nu, S, bb, dt, opts, start)
-            start = (last, pst) if chain else None
+            start = (lu, lp, pst) if chain else None
         fctx.pctx, fctx.opts, fctx.dt, fctx.k, fctx.mask, fctx.u_m = pctx, opts, dt, k, mask, u_m
         fctx.owner, fctx.chain = owner, chain
         fctx.save_for_backward(u, p, S, nu, u_b)
-        nxt = (last.detach().clone(), pst)
+        nxt = (lu.detach().clone(), lp.detach().clone(), pst)
         fctx.mark_non_differentiable(*nxt)
-        return uu, pp, bb, nxt[0], nxt[1]
+        return (uu, pp, bb) + nxt
 
     @staticmethod
-    def backward(fctx, du, dp, dbb, _d1, _d2):
+    def backward(fctx, du, dp, dbb, _d1, _d2, _d3):
         u, p, S, nu, u_b = fctx.saved_tensors
         pctx, opts, dt, k, mask, u_m = fctx.pctx, fctx.opts, fctx.dt, fctx.k, fctx.mask, fctx.u_m
         states, tapes, used = [(u, p, u_b)], [], []
@@ -610,9 +617,9 @@ class _OutflowSegment(torch.autograd.Function):
         for _ in range(k):
             nb = pctx.outflow_update(uu, bb, mask, u_m, dt)
             t = pctx.new_tape()
-            last = pp
+            lu, lp = uu, pp
             uu, pp, pst = _chained_step(pctx, uu, pp, nu, S, nb, dt, opts, start, tape=t)
-            start = (last, pst) if fctx.chain else None
+            start = (lu, lp, pst) if fctx.chain else None
             used.append(nb)
             states.append((uu, pp, nb))
             tapes.append(t)
@@ -631,7 +638,7 @@ class _OutflowSegment(torch.autograd.Function):
             gb, gu = pctx.outflow_update_backward(un, bprev, mask, u_m, dt, gb_used, du=g["u"])
             gp = g["p"]
             tapes[q] = None
-        return None, None, None, None, None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), gb, None, None
+        return None, None, None, None, None, None, None, None, gu, gp, dS, dnu.reshape(nu.shape), gb, None, None, None
 
 
 class PlaneStatistics(torch.autograd.Function):
@@ -769,15 +776,15 @@ def rollout(pctx: Context, u0, p0, S, nu, u_b, dt, n_steps: int, checkpoint_ever
     are advanced by the advective outflow update (the boundary values then become part
     of the state; the result gains a third entry, the final u_b).
 
-    extrapolate: every step after the first starts its pressure solves from the previous
-    step's pressures (piso_step_opts.p_prev and p_prev_star: corrector 1 from
-    p*_{n-1} + (p_n - p_{n-1}), corrector 2 from p* + (p_n - p*_{n-1})); the chain runs
-    through warm-up steps and checkpointed segments alike, so that results do not depend
-    on checkpoint_every."""
+    extrapolate: every step after the first starts its linear solves from the previous
+    step's fields (piso_step_opts.u_prev, p_prev and p_prev_star: the velocity solve from
+    2 u_n - u_{n-1}, corrector 1 from p*_{n-1} + (p_n - p_{n-1}), corrector 2 from
+    p* + (p_n - p*_{n-1})); the chain runs through warm-up steps and checkpointed
+    segments alike, so that results do not depend on checkpoint_every."""
     o = opts if opts is not None else pctx.default_opts()
     owner = object()   # the backward steps of this rollout share the adjoint warm start
     u, p, ub = u0, p0, u_b
-    start = None   # (p_{n-1}, p*_{n-1}) of the previous step, once there is one
+    start = None   # (u_{n-1}, p_{n-1}, p*_{n-1}) of the previous step, once there is one
     if outflow is not None:
         mask, u_m = outflow
         mask = pctx._mask(mask)
@@ -787,32 +794,32 @@ def rollout(pctx: Context, u0, p0, S, nu, u_b, dt, n_steps: int, checkpoint_ever
             for _ in range(warmup):
                 if outflow is not None:
                     ub = pctx.outflow_update(u.detach(), ub, mask, u_m, dt)
-                last = p.detach()
-                u, p, pst = _chained_step(pctx, u.detach(), last, nu.detach(), S.detach(), ub, dt, o, start)
-                start = (last, pst) if extrapolate else None
+                lu, lp = u.detach(), p.detach()
+                u, p, pst = _chained_step(pctx, lu, lp, nu.detach(), S.detach(), ub, dt, o, start)
+                start = (lu, lp, pst) if extrapolate else None
     traj = []
     done = 0
-    pv, pvs = start if start is not None else (None, None)
+    uv, pv, pvs = start if start is not None else (None, None, None)
     while done < n_steps:
-        last = p.detach()
+        lu, lp = u.detach(), p.detach()
         if outflow is not None:
             if checkpoint_every > 0:
                 k = min(checkpoint_every, n_steps - done)
-                u, p, ub, last, pst = _OutflowSegment.apply(pctx, o, dt, k, owner, extrapolate, mask, u_m, u, p, S,
-                                                            nu, ub, pv, pvs)
+                u, p, ub, lu, lp, pst = _OutflowSegment.apply(pctx, o, dt, k, owner, extrapolate, mask, u_m, u, p,
+                                                              S, nu, ub, uv, pv, pvs)
                 done += k
             else:
                 ub = OutflowUpdate.apply(pctx, mask, u_m, dt, u, ub)
-                u, p, pst = PisoStep.apply(pctx, o, dt, owner, u, p, S, nu, ub, pv, pvs)
+                u, p, pst = PisoStep.apply(pctx, o, dt, owner, u, p, S, nu, ub, uv, pv, pvs)
                 done += 1
         elif checkpoint_every > 0:
             k = min(checkpoint_every, n_steps - done)
-            u, p, last, pst = _Segment.apply(pctx, o, dt, k, owner, extrapolate, u, p, S, nu, ub, pv, pvs)
+            u, p, lu, lp, pst = _Segment.apply(pctx, o, dt, k, owner, extrapolate, u, p, S, nu, ub, uv, pv, pvs)
             done += k
         else:
-            u, p, pst = PisoStep.apply(pctx, o, dt, owner, u, p, S, nu, ub, pv, pvs)
+            u, p, pst = PisoStep.apply(pctx, o, dt, owner, u, p, S, nu, ub, uv, pv, pvs)
             done += 1
-        pv, pvs = (last, pst) if extrapolate else (None, None)
+        uv, pv, pvs = (lu, lp, pst) if extrapolate else (None, None, None)
         if return_all:
             traj.append((u, p) if outflow is None else (u, p, ub))
     if return_all:

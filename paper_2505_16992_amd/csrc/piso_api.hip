@@ -247,7 +247,12 @@ int do_step(piso_ctx* c, hipStream_t s, const R* u_n, const R* p_n, const R* nu,
   R* b = (R*)c->w_b;
   if (int rc = do_assemble<R>(c, s, u_n, p_n, nu, nu_field, S, ub, dt, o->grad_p_in_predictor, A, C, bu, b, Pf, Dinv))
     return rc;
-  PISO_HIP(c, hipMemcpyAsync(us, u_n, sizeof(R) * D * N, hipMemcpyDeviceToDevice, s));
+  if (o->u_prev) {
+    // the velocity solve starts from u extrapolated in time, 2 u_n - u_{n-1}
+    if (int e = launch_extrapolate<R>(c, s, u_n, (const R*)o->u_prev, us, D)) return e;
+  } else {
+    PISO_HIP(c, hipMemcpyAsync(us, u_n, sizeof(R) * D * N, hipMemcpyDeviceToDevice, s));
+  }
   piso_solve_info vi{}, pi[2]{};
   int rc = velocity_solve<R>(c, s, false, A, C, b, us, &o->vel, &vi);
   if (rc < 0) return rc;

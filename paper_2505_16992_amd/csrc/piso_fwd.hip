@@ -602,8 +602,9 @@ int launch_flux_div(piso_ctx* c, hipStream_t s, const R* F, const R* ub, double*
 }
 
 template <typename R>
-int launch_extrapolate(piso_ctx* c, hipStream_t s, const R* p, const R* q, R* y) {
-  k_extrapolate<R><<<grid_cells(c->N), kWG, 0, s>>>(c->N, p, q, y);
+int launch_extrapolate(piso_ctx* c, hipStream_t s, const R* p, const R* q, R* y, int ncomp) {
+  const int n = ncomp * c->N;
+  k_extrapolate<R><<<grid_cells(n), kWG, 0, s>>>(n, p, q, y);
   return check_launch(c, "k_extrapolate");
 }
 
@@ -670,7 +671,7 @@ int launch_copy(piso_ctx* c, hipStream_t s, const TI* x, TO* y, int n) {
                                  const R*, R*, R*);                                                  \
   template int launch_scale_invJ<R>(piso_ctx*, hipStream_t, const R*, int, R*);                      \
   template int launch_flux_div<R>(piso_ctx*, hipStream_t, const R*, const R*, double*);                      \
-  template int launch_extrapolate<R>(piso_ctx*, hipStream_t, const R*, const R*, R*);                      \
+  template int launch_extrapolate<R>(piso_ctx*, hipStream_t, const R*, const R*, R*, int);                 \
   template int launch_add_diff<R>(piso_ctx*, hipStream_t, const R*, const R*, const R*, R*);               \
   template int launch_add_scalar<R>(piso_ctx*, hipStream_t, const double*, R*);                       \
   template int launch_fill<R>(piso_ctx*, hipStream_t, int, R, R*);                                    \

@@ -370,9 +370,9 @@ int launch_scale_invJ(piso_ctx* c, hipStream_t s, const R* x, int ncomp, R* y);
 // of u_b) into *out (device)
 template <typename R>
 int launch_flux_div(piso_ctx* c, hipStream_t s, const R* F, const R* ub, double* out);
-// y = 2 p - q
+// y = 2 p - q over ncomp fields of N cells
 template <typename R>
-int launch_extrapolate(piso_ctx* c, hipStream_t s, const R* p, const R* q, R* y);
+int launch_extrapolate(piso_ctx* c, hipStream_t s, const R* p, const R* q, R* y, int ncomp = 1);
 // y = a + b - q
 template <typename R>
 int launch_add_diff(piso_ctx* c, hipStream_t s, const R* a, const R* b, const R* q, R* y);

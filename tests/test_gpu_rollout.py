@@ -270,20 +270,20 @@ def test_rollout_warmup(api):
     assert torch.equal(uT.detach(), uT2.detach()) and torch.equal(pT.detach(), pT2.detach())
     assert torch.equal(g1, g2)
     uE, pE = api.rollout(ctx, u, p, S, nu, ub, case.dt, 2, warmup=3, opts=o)
-    uu, pp, pv, pvs = u, p, None, None
+    uu, pp, uv, pv, pvs = u, p, None, None, None
     for _ in range(5):
         pst = torch.empty_like(pp)
-        uu, p1 = ctx.step(uu, pp, nu, S, ub, case.dt, o, p_prev=pv, p_prev_star=pvs, p_star_out=pst)
-        pv, pvs, pp = pp, pst, p1
+        u1, p1 = ctx.step(uu, pp, nu, S, ub, case.dt, o, p_prev=pv, p_prev_star=pvs, p_star_out=pst, u_prev=uv)
+        uv, pv, pvs, uu, pp = uu, pp, pst, u1, p1
     assert torch.equal(uE.detach(), uu) and torch.equal(pE.detach(), pp)
 
 
 @pytest.mark.parametrize("name", ["tgv16", "cavity12", "channel_q", "cylinder_q"])
 def test_extrapolated_start_matches_oracle(api, name):
-    """A step given earlier pressures (p_prev, p_prev_star: its pressure solves start from
-    them) reaches the oracle's step to the solver tolerance, whatever they are: the start
-    of a converged Krylov solve does not enter the result.  p_star_out receives the first
-    corrector's pressure, which the tape holds too."""
+    """A step given earlier fields (u_prev, p_prev, p_prev_star: its linear solves start
+    from them) reaches the oracle's step to the solver tolerance, whatever they are: the
+    start of a converged Krylov solve does not enter the result.  p_star_out receives the
+    first corrector's pressure, which the tape holds too."""
     say("test_extrapolated_start_matches_oracle", name)
     case = small_cases()[name]
     ctx = api.Context(case.domain, "f64")
@@ -292,14 +292,17 @@ def test_extrapolated_start_matches_oracle(api, name):
     ref = oracle_step(Geometry(case.domain), u0, p0, case.nu, S0, case.dt, ub0)
     rng = np.random.default_rng(22)
     t = ctx.dtype
-    near = (p0 + 0.05 * rng.standard_normal(p0.shape), p0 + 0.05 * rng.standard_normal(p0.shape))
-    far = (rng.standard_normal(p0.shape), rng.standard_normal(p0.shape))
-    for pv, pvs in (near, far, (near[0], None), (None, far[1])):
+    near = (u0 + 0.05 * rng.standard_normal(u0.shape), p0 + 0.05 * rng.standard_normal(p0.shape),
+            p0 + 0.05 * rng.standard_normal(p0.shape))
+    far = (rng.standard_normal(u0.shape), rng.standard_normal(p0.shape), rng.standard_normal(p0.shape))
+    for uv, pv, pvs in (near, far, (None, near[1], None), (far[0], None, far[2])):
         pst = torch.empty_like(p)
         tape = ctx.new_tape()
         u1, p1, info = ctx.step(u, p, nu, S, ub, case.dt, o, info=True, tape=tape,
+                                u_prev=None if uv is None else dev(uv, t),
                                 p_prev=None if pv is None else dev(pv, t),
                                 p_prev_star=None if pvs is None else dev(pvs, t), p_star_out=pst)
+        assert info["vel"]["status"] == 0, info
         assert info["pres"][0]["status"] == 0 and info["pres"][1]["status"] == 0, info
         assert rel(host(u1), ref.u2) < 1e-9
         assert rel_p(host(p1), ref.p2) < 1e-9
@@ -315,10 +318,11 @@ def test_extrapolated_start_matches_oracle(api, name):
 
 @pytest.mark.parametrize("prec", ["f64", "mixed"])
 def test_extrapolated_start_saves_iterations(api, prec):
-    """On a developed flow, starts from the previous step's pressures save pressure
-    iterations in both correctors; the rollout's result agrees with the unextrapolated
-    one to the solver tolerance, and a rollout of stand-alone steps with the chained
-    starts equals api.rollout's chain bit for bit, checkpointed or not."""
+    """On a developed flow, starts from the previous step's fields save pressure
+    iterations in both correctors and velocity iterations; the rollout's result agrees
+    with the unextrapolated one to the solver tolerance, and a rollout of stand-alone
+    steps with the chained starts equals api.rollout's chain bit for bit, checkpointed
+    or not."""
     say("test_extrapolated_start_saves_iterations", prec)
     case = cases.channel(32, 24, 16)
     ctx = api.Context(case.domain, prec)
@@ -331,17 +335,18 @@ def test_extrapolated_start_saves_iterations(api, prec):
             u, p = ctx.step(u, p, nu, S, ub, case.dt, o)
         runs = {}
         for extra in (False, True):
-            uu, pp, pv, pvs, its = u, p, None, None, []
+            uu, pp, uv, pv, pvs, its = u, p, None, None, None, []
             for _ in range(8):
                 pst = torch.empty_like(pp)
-                uu, p1, inf = ctx.step(uu, pp, nu, S, ub, case.dt, o, info=True, p_star_out=pst,
-                                       p_prev=pv if extra else None, p_prev_star=pvs if extra else None)
-                pv, pvs, pp = pp, pst, p1
-                its.append([q["iters"] for q in inf["pres"]])
+                u1, p1, inf = ctx.step(uu, pp, nu, S, ub, case.dt, o, info=True, p_star_out=pst,
+                                       p_prev=pv if extra else None, p_prev_star=pvs if extra else None,
+                                       u_prev=uv if extra else None)
+                uv, pv, pvs, uu, pp = uu, pp, pst, u1, p1
+                its.append([q["iters"] for q in inf["pres"]] + [inf["vel"]["iters"]])
             runs[extra] = (uu, pp, np.array(its))
         say("CG iterations per corrector, plain %s extrapolated %s" % (runs[False][2].tolist(), runs[True][2].tolist()))
         plain, extra = runs[False][2][2:].sum(axis=0), runs[True][2][2:].sum(axis=0)
-        assert extra[0] < plain[0] and extra[1] < plain[1]
+        assert extra[0] < plain[0] and extra[1] < plain[1] and extra[2] <= plain[2]
         assert rel(host(runs[True][0]), host(runs[False][0])) < 1e-5
         uT, pT = api.rollout(ctx, u, p, S, nu, ub, case.dt, 8, opts=o)
         assert torch.equal(uT, runs[True][0]) and torch.equal(pT, runs[True][1])
