@@ -49,6 +49,10 @@ class Domain:
     T: np.ndarray                               # [d, d, N], T[j, i, P] = d xi^j / d x_i
     J: np.ndarray                               # [N], det(d x / d xi) > 0
     centres: Optional[np.ndarray] = None        # [d, N] physical cell centres (diagnostics only)
+    # optional metrics on the Dirichlet faces, in u_b's face order (None: those of the
+    # boundary cell): Tb[j, i, f] = d xi^j / d x_i and Jb[f] at the face
+    Tb: Optional[np.ndarray] = None             # [d, d, NB]
+    Jb: Optional[np.ndarray] = None             # [NB]
 
     @property
     def n_cells(self) -> int:

@@ -168,13 +168,13 @@ def step_vjp(geo: Geometry, rec: StepRecord, ubar, pbar, mode="direct", rtol=1e-
     G.S += G.b_u
     if geo.nb:
         P, j = geo.bP, geo.bj
-        JTb = geo.JT[j, :, P].T                       # [d, NB]
+        JTb = geo.bJT                                 # [d, NB]
         Ub = np.einsum("in,in->n", JTb, u_b)
-        coef = 2.0 * geo.alpha[j, j, P] * nu[P] - geo.bN * Ub
+        coef = 2.0 * geo.balpha_jj * nu[P] - geo.bN * Ub
         bub = G.b_u[:, P]                              # [d, NB]
         G.u_b += bub * coef / geo.J[P]
         G.u_b += (-geo.bN / geo.J[P]) * JTb * np.sum(bub * u_b, axis=0)
-        np.add.at(G.nu, P, np.sum(bub * u_b, axis=0) * 2.0 * geo.alpha[j, j, P] / geo.J[P])
+        np.add.at(G.nu, P, np.sum(bub * u_b, axis=0) * 2.0 * geo.balpha_jj / geo.J[P])
     if geo.non_orthogonal:
         K = geo.cross_operator(nu)
         for i in range(d):
@@ -184,7 +184,7 @@ def step_vjp(geo: Geometry, rec: StepRecord, ubar, pbar, mode="direct", rtol=1e-
             if geo.nb:
                 yb = y[geo.bP]
                 for k in range(d):
-                    w = geo.bN * geo.alpha[geo.bj, k, geo.bP] * np.where(geo.bj == k, 0.0, 1.0)
+                    w = geo.bN * geo.balpha[k] * np.where(geo.bj == k, 0.0, 1.0)
                     G.u_b[i] += geo.Bt[k].T @ (w * nu[geo.bP] * yb)
                     np.add.at(G.nu, geo.bP, w * (geo.Bt[k] @ u_b[i]) * yb)
     # C and A from the face fluxes and nu (eqs. advMatDiscrete, difMatDiscrete)
@@ -199,7 +199,7 @@ def step_vjp(geo: Geometry, rec: StepRecord, ubar, pbar, mode="direct", rtol=1e-
         np.add.at(Ubar[j], P, 0.5 * phibar)
         np.add.at(Ubar[j], F, 0.5 * phibar)
     if geo.nb:
-        np.add.at(G.nu, geo.bP, 2.0 * geo.alpha[geo.bj, geo.bj, geo.bP] * G.A[geo.bP] / geo.J[geo.bP])
+        np.add.at(G.nu, geo.bP, 2.0 * geo.balpha_jj * G.A[geo.bP] / geo.J[geo.bP])
     G.u_n += np.einsum("jin,jn->in", geo.JT, Ubar)
     return {"u_n": G.u_n, "p_n": G.p_n, "S": G.S, "nu": G.nu, "u_b": G.u_b,
             "A": G.A, "mu": mu}

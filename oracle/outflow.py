@@ -34,12 +34,13 @@ from .piso import Geometry
 
 
 def face_coefficients(geo: Geometry, u_m, dt):
-    """c_b = 2 dt |T_j(P) . u_m| of every Dirichlet face and the flux weights
-    w_b = N_b J_P T_j(P) (shape [d, NB])."""
+    """c_b = 2 dt |T_j(P) . u_m| of every Dirichlet face (the half cell from the boundary
+    cell P) and the flux weights w_b = N_b (J T_j)_b of the face (shape [d, NB]), the
+    weights of the Dirichlet flux the step adds to the pressure right-hand side."""
     u_m = np.asarray(u_m, dtype=np.float64)
     Tj = geo.T[geo.bj, :, geo.bP].T           # [d, NB]: T[j_b, i, P_b]
     c = 2.0 * dt * np.abs(np.einsum("in,i->n", Tj, u_m))
-    w = geo.bN[None, :] * geo.J[geo.bP][None, :] * Tj
+    w = geo.bN[None, :] * geo.bJT
     return c, w
 
 

@@ -75,9 +75,28 @@ class Geometry:
         self.nb = topo.n_bfaces
         self.bP, self.bj, self.bs = topo.bface_cell, topo.bface_axis, topo.bface_side
         self.bN = 2.0 * self.bs - 1.0          # outward face sign of each boundary face
+        # metrics of the Dirichlet faces (App. A.4: a prescribed boundary carries its values
+        # and metrics on the face itself); without them those of the boundary cell.
+        # bJT[i, f] = J T_{j_f, i} (the face's own axis j_f), balpha[k, f] = alpha_{j_f k}
+        fb = np.arange(self.nb)
+        if getattr(dom, "Tb", None) is None:
+            self.bJT = self.JT[self.bj, :, self.bP].T
+            self.balpha = self.alpha[self.bj, :, self.bP].T
+        else:
+            Tb = np.asarray(dom.Tb, dtype=np.float64)
+            Jb = np.asarray(dom.Jb, dtype=np.float64)
+            if Tb.shape != (d, d, self.nb) or Jb.shape != (self.nb,) or not np.all(Jb > 0):
+                raise ValueError("face metrics: Tb [d, d, NB] and Jb [NB] > 0 expected")
+            alpha_b = Jb[None, None] * np.einsum("jib,kib->jkb", Tb, Tb)
+            self.bJT = (Jb[None, None] * Tb)[self.bj, :, fb].T
+            self.balpha = alpha_b[self.bj, :, fb].T
+        self.balpha_jj = self.balpha[self.bj, fb]
         off = np.abs(self.alpha[~np.eye(d, dtype=bool)]) if d > 1 else np.zeros(1)
         diag = np.abs(self.alpha[np.eye(d, dtype=bool)]).min(axis=0)
         self.non_orthogonal = bool(np.max(off / diag) > 1e-12)
+        if self.nb and d > 1:   # cross terms of the face metrics count too
+            cross = np.abs(np.where(np.arange(d)[:, None] == self.bj[None, :], 0.0, self.balpha)).max(axis=0)
+            self.non_orthogonal |= bool(np.max(cross / np.abs(self.balpha_jj)) > 1e-12)
 
         # pressure gradient: (grad p)_i = sum_j T_ji (p_{+j} - p_{-j}) / 2, p_b = p_P
         self.dcomp = []
@@ -117,10 +136,10 @@ class Geometry:
             h = 0.5 * np.ones(len(P))
             self.Dv.append(_csr(np.r_[P, P, F, F], np.r_[P, F, P, F], np.r_[h, h, -h, -h], N))
 
-        # prescribed Dirichlet face flux N_b U_b(u_b), U_b = J_P T_j,P . u_b
+        # prescribed Dirichlet face flux N_b U_b(u_b), U_b = (J T_j)_b . u_b
         self.Bflux = []
         for i in range(d):
-            v = self.bN * self.J[self.bP] * self.T[self.bj, i, self.bP]
+            v = self.bN * self.bJT[i]
             self.Bflux.append(_csr(self.bP, np.arange(self.nb), v, N, self.nb))
 
         # tangential derivative of boundary values along a Dirichlet side
@@ -187,7 +206,7 @@ class Geometry:
             return out
         for k in range(self.d):
             gk = self.Bt[k] @ ub_i
-            v = self.bN * self.alpha[self.bj, k, self.bP] * nu[self.bP] * gk
+            v = self.bN * self.balpha[k] * nu[self.bP] * gk
             v = np.where(self.bj == k, 0.0, v)
             np.add.at(out, self.bP, v)
         return out
@@ -219,7 +238,7 @@ def assemble_C(geo: Geometry, u_n, nu, dt):
         np.add.at(A, P, (0.5 * phi + knu) / geo.J[P])
         np.add.at(A, F, (-0.5 * phi + knu) / geo.J[F])
     if geo.nb:
-        np.add.at(A, geo.bP, 2.0 * geo.alpha[geo.bj, geo.bj, geo.bP] * nu[geo.bP] / geo.J[geo.bP])
+        np.add.at(A, geo.bP, 2.0 * geo.balpha_jj * nu[geo.bP] / geo.J[geo.bP])
     H = _csr(np.concatenate(rows), np.concatenate(cols), np.concatenate(vals).astype(dtype), N)
     return H, A
 
@@ -231,8 +250,8 @@ def predictor_rhs(geo: Geometry, u_n, nu, S, dt, u_b):
     b_u = u_n / dt + S
     b_u = b_u.astype(np.result_type(b_u, nu, u_b, np.float64))
     if geo.nb:
-        Ub = np.einsum("in,in->n", geo.JT[geo.bj, :, geo.bP].T, u_b)
-        coef = 2.0 * geo.alpha[geo.bj, geo.bj, geo.bP] * nu[geo.bP] - geo.bN * Ub
+        Ub = np.einsum("in,in->n", geo.bJT, u_b)
+        coef = 2.0 * geo.balpha_jj * nu[geo.bP] - geo.bN * Ub
         for i in range(geo.d):
             np.add.at(b_u[i], geo.bP, u_b[i] * coef / geo.J[geo.bP])
     if geo.non_orthogonal:
