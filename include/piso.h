@@ -101,6 +101,17 @@ typedef struct {
   const piso_side_desc* sides;     /* host [n_sides]; must tile every block side exactly once */
   const double* T;                 /* host [d][d][N]: T[(j*d + i)*N + P] = d xi^j / d x_i at centres */
   const double* J;                 /* host [N]: det(d x / d xi) > 0 (cell volume) */
+  /* Metrics on the Dirichlet faces (App. A.4: a prescribed boundary carries its values
+     and metrics on the face itself; eq. velRHSdiscrete takes alpha and U there without
+     interpolation).  Both NULL: every Dirichlet face takes the metrics of its boundary
+     cell.  Otherwise both given, in the face order of u_b: Tb[(j*d + i)*NB + f] =
+     d xi^j / d x_i and Jb[f] > 0 on face f.  They enter the 2 alpha_jj nu diagonal and
+     the boundary terms of the predictor (eqs. difMatDiscrete, velRHSdiscrete), the
+     deferred cross terms through the face (eq. velRHSnonOrtho), the Dirichlet flux
+     N (J T_j) . u_b of the pressure right-hand side and of the outflow balance, and
+     their adjoints.  Non-finite values or Jb <= 0: PISO_E_ARG. */
+  const double* Tb;                /* host [d][d][NB] or NULL */
+  const double* Jb;                /* host [NB] or NULL */
 } piso_domain_desc;
 
 /* Preconditioner of a Krylov solve (piso_solve_opts.precond). */

@@ -31,7 +31,8 @@ class SideDesc(C.Structure):
 class DomainDesc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_blocks", C.c_int32), ("n_sides", C.c_int32),
                 ("block_cells", C.POINTER(C.c_int32)), ("sides", C.POINTER(SideDesc)),
-                ("T", C.POINTER(C.c_double)), ("J", C.POINTER(C.c_double))]
+                ("T", C.POINTER(C.c_double)), ("J", C.POINTER(C.c_double)),
+                ("Tb", C.POINTER(C.c_double)), ("Jb", C.POINTER(C.c_double))]
 
 
 class SolveOpts(C.Structure):

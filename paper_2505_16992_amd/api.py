@@ -67,10 +67,22 @@ class Context:
             sides[q].other_begin[0], sides[q].other_begin[1] = s.other_begin
         T = np.ascontiguousarray(domain.T, dtype=np.float64)
         J = np.ascontiguousarray(domain.J, dtype=np.float64)
-        self._keep = (cells, sides, T, J)
+        # metrics on the Dirichlet faces (u_b's face order), or None: the boundary cells'
+        Tb, Jb = getattr(domain, "Tb", None), getattr(domain, "Jb", None)
+        dptr = C.POINTER(C.c_double)
+        if Tb is not None:
+            Tb = np.ascontiguousarray(Tb, dtype=np.float64)
+            Jb = np.ascontiguousarray(Jb, dtype=np.float64)
+            nb = sum((sd.end[0] - sd.begin[0]) * (sd.end[1] - sd.begin[1])
+                     for sd in sides if sd.kind == L.PISO_SIDE_DIRICHLET)
+            if Tb.shape != (self.dim, self.dim, nb) or Jb.shape != (nb,):
+                raise ValueError("face metrics: Tb [d, d, %d] and Jb [%d] expected" % (nb, nb))
+        self._keep = (cells, sides, T, J, Tb, Jb)
         desc = L.DomainDesc(self.dim, len(domain.blocks), len(domain.sides),
                             cells.ctypes.data_as(C.POINTER(C.c_int32)), sides,
-                            T.ctypes.data_as(C.POINTER(C.c_double)), J.ctypes.data_as(C.POINTER(C.c_double)))
+                            T.ctypes.data_as(dptr), J.ctypes.data_as(dptr),
+                            None if Tb is None else Tb.ctypes.data_as(dptr),
+                            None if Jb is None else Jb.ctypes.data_as(dptr))
         h = C.c_void_p()
         rc = self.lib.piso_create(C.byref(desc), self.prec, C.byref(h))
         if rc != 0:

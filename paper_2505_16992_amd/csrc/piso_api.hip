@@ -69,7 +69,37 @@ int upload_metrics(piso_ctx* c, const piso_domain_desc* d) {
         nonorth = std::max(nonorth, std::fabs(a[j][k]) / mind);
       }
   }
+  // metrics of the Dirichlet faces: given on the faces, or the boundary cell's (then the
+  // same numbers as the cell arrays above, so results do not change)
+  const int NB = c->NB;
+  std::vector<double> bjt((size_t)D * std::max(NB, 1), 0.0), bal((size_t)D * std::max(NB, 1), 0.0);
+  if (NB > 0) {
+    std::vector<int> bcell, bside;
+    if (int rc = bface_cells(c, bcell, bside)) return rc;
+    for (int f = 0; f < NB; ++f) {
+      const int P = bcell[f], j = bside[f] / 2;
+      const double* Tf = d->Tb ? d->Tb + f : T + P;
+      const size_t st = d->Tb ? (size_t)NB : (size_t)N;
+      const double Jf = d->Tb ? d->Jb[f] : J[P];
+      for (int i = 0; i < D; ++i) bjt[(size_t)i * NB + f] = Jf * Tf[(size_t)(j * D + i) * st];
+      double mind = 0.0, mx = 0.0;
+      for (int k = 0; k < D; ++k) {
+        double sm = 0.0;
+        for (int i = 0; i < D; ++i) sm += Tf[(size_t)(j * D + i) * st] * Tf[(size_t)(k * D + i) * st];
+        bal[(size_t)k * NB + f] = Jf * sm;
+        if (k == j) mind = std::fabs(Jf * sm);
+        else mx = std::max(mx, std::fabs(Jf * sm));
+      }
+      if (d->Tb && !(Jf > 0.0 && std::isfinite(Jf)))
+        return fail(c, PISO_E_ARG, "face metrics: Jb of Dirichlet face " + std::to_string(f) + " not positive");
+      if (!(mind > 0.0) || !std::isfinite(mind) || !std::isfinite(mx))
+        return fail(c, PISO_E_ARG, "face metrics: alpha_jj of Dirichlet face " + std::to_string(f) + " not positive");
+      nonorth = std::max(nonorth, mx / mind);   // cross terms of the face metrics count too
+    }
+  }
   c->nonorth = nonorth > 1e-12;
+  if (int rc = upload(c, &c->bjt, convert<R>(bjt))) return rc;
+  if (int rc = upload(c, &c->balpha, convert<R>(bal))) return rc;
   if (int rc = upload(c, &c->JT, convert<R>(jt))) return rc;
   if (int rc = upload(c, &c->invJ, convert<R>(invJ))) return rc;
   if (int rc = upload(c, &c->alpha, convert<R>(al))) return rc;

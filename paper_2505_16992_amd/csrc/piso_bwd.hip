@@ -100,9 +100,9 @@ k_pface_bwd(Grid g, const R* __restrict__ alpha, const R* __restrict__ A, const 
 // dA += -hbar . h / A; du_b += N J T_j . lam at Dirichlet faces.
 template <typename R, int D, bool DIAG>
 __global__ void __launch_bounds__(kWG)
-k_h_bwd(Grid g, const R* __restrict__ JT, const R* __restrict__ A, const R* __restrict__ h,
-        const R* __restrict__ dh, const R* __restrict__ lam, R* __restrict__ gout, R* __restrict__ dbu,
-        R* __restrict__ dA, R* __restrict__ dub) {
+k_h_bwd(Grid g, const R* __restrict__ JT, const R* __restrict__ bjt, const R* __restrict__ A,
+        const R* __restrict__ h, const R* __restrict__ dh, const R* __restrict__ lam, R* __restrict__ gout,
+        R* __restrict__ dbu, R* __restrict__ dA, R* __restrict__ dub) {
   const int X = cell_of_thread(g.N);
   if (X < 0) return;
   const int N = g.N, NB = g.NB;
@@ -123,7 +123,7 @@ k_h_bwd(Grid g, const R* __restrict__ JT, const R* __restrict__ A, const R* __re
           const int f = -1 - F;
           const R Nf = s ? R(1) : R(-1);
 #pragma unroll
-          for (int i = 0; i < D; ++i) dub[(size_t)i * NB + f] += Nf * jtb<R, D, DIAG>(JT, j, i, X, N) * lX;
+          for (int i = 0; i < D; ++i) dub[(size_t)i * NB + f] += Nf * bjt[(size_t)i * NB + f] * lX;
         }
       }
     }
@@ -310,7 +310,7 @@ __device__ __forceinline__ R bcoef(const Grid& g, int P, int j, int s, int k, in
 
 template <typename R, int D>
 __global__ void __launch_bounds__(kWG)
-k_bcross_bwd(Grid g, const R* __restrict__ alphax, const R* __restrict__ invJ, const R* __restrict__ nu,
+k_bcross_bwd(Grid g, const R* __restrict__ balpha, const R* __restrict__ invJ, const R* __restrict__ nu,
              int nu_field, const R* __restrict__ ub, const R* __restrict__ dbu, R* __restrict__ dnu_cell,
              R* __restrict__ dub) {
   const int P = cell_of_thread(g.N);
@@ -329,8 +329,7 @@ k_bcross_bwd(Grid g, const R* __restrict__ alphax, const R* __restrict__ invJ, c
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         if (k == j) continue;
-        const int ai = ax_idx(j, k);
-        // nu gradient: sum_i N alpha bdiff_k(u_b,i) dbu_i(P) / J_P
+        // nu gradient: sum_i N alpha bdiff_k(u_b,i) dbu_i(P) / J_P (alpha of the face)
         if (dnu_cell) {
           R acc = R(0);
 #pragma unroll
@@ -347,7 +346,7 @@ k_bcross_bwd(Grid g, const R* __restrict__ alphax, const R* __restrict__ invJ, c
             else if (fm >= 0) bd = uc[f] - uc[fm];
             acc += bd * dbu[(size_t)i * N + P];
           }
-          dnu_cell[P] += Nf * alphax[(size_t)ai * N + P] * acc * invJ[P];
+          dnu_cell[P] += Nf * balpha[(size_t)k * NB + f] * acc * invJ[P];
         }
         // u_b gradient of the faces entering this face's difference: gather for face f
         if (dub) {
@@ -365,7 +364,7 @@ k_bcross_bwd(Grid g, const R* __restrict__ alphax, const R* __restrict__ invJ, c
             const R cf = bcoef<R, D>(g, Y, j, s, k, f);
             if (cf == R(0)) continue;
             const R nuY = nu_field ? nu[Y] : nu[0];
-            const R w = Nf * alphax[(size_t)ai * N + Y] * nuY * invJ[Y] * cf;
+            const R w = Nf * balpha[(size_t)k * NB + (-1 - ey)] * nuY * invJ[Y] * cf;
 #pragma unroll
             for (int i = 0; i < D; ++i) dub[(size_t)i * NB + f] += w * dbu[(size_t)i * N + Y];
           }
@@ -382,7 +381,8 @@ k_bcross_bwd(Grid g, const R* __restrict__ alphax, const R* __restrict__ invJ, c
 template <typename R, int D, bool DIAG>
 __global__ void __launch_bounds__(kWG)
 k_assemble_bwd(Grid g, const R* __restrict__ JT, const R* __restrict__ invJ, const R* __restrict__ alpha,
-               const R* __restrict__ nu, int nu_field, const R* __restrict__ ub, R dt_inv,
+               const R* __restrict__ bjt, const R* __restrict__ balpha, const R* __restrict__ nu, int nu_field,
+               const R* __restrict__ ub, R dt_inv,
                const R* __restrict__ dA, const R* __restrict__ dC, const R* __restrict__ dbu,
                R* __restrict__ du, R* __restrict__ dS, R* __restrict__ dnu_cell, R* __restrict__ dub) {
   const int X = cell_of_thread(g.N);
@@ -412,20 +412,21 @@ k_assemble_bwd(Grid g, const R* __restrict__ JT, const R* __restrict__ invJ, con
       } else {
         const int f = -1 - F;
         const R Nf = s ? R(1) : R(-1);
-        dnu += R(2) * aX * dA[X] * iJX;
+        const R ab = balpha[(size_t)j * NB + f];   // the face's own metrics
+        dnu += R(2) * ab * dA[X] * iJX;
         R ubv[D], Ubd = R(0), dot = R(0);
 #pragma unroll
         for (int i = 0; i < D; ++i) {
           ubv[i] = ub[(size_t)i * NB + f];
-          Ubd += jtb<R, D, DIAG>(JT, j, i, X, N) * ubv[i];
+          Ubd += bjt[(size_t)i * NB + f] * ubv[i];
           dot += dbu[(size_t)i * N + X] * ubv[i];
         }
-        dnu += dot * R(2) * aX * iJX;
+        dnu += dot * R(2) * ab * iJX;
         if (dub) {
-          const R coef = (R(2) * aX * nuX - Nf * Ubd) * iJX;
+          const R coef = (R(2) * ab * nuX - Nf * Ubd) * iJX;
 #pragma unroll
           for (int i = 0; i < D; ++i)
-            dub[(size_t)i * NB + f] += dbu[(size_t)i * N + X] * coef - Nf * jtb<R, D, DIAG>(JT, j, i, X, N) * iJX * dot;
+            dub[(size_t)i * NB + f] += dbu[(size_t)i * N + X] * coef - Nf * bjt[(size_t)i * NB + f] * iJX * dot;
         }
       }
     }
@@ -508,8 +509,8 @@ template <typename R>
 int launch_h_bwd(piso_ctx* c, hipStream_t s, const R* A, const R* h, const R* du_h, const R* lam,
                  R* gout, R* dbu, R* dA, R* dub) {
   const int G = grid_cells(c->N);
-  PISO_DISPATCH_D_DIAG(c, (k_h_bwd<R, D, DG><<<G, kWG, 0, s>>>(c->grid, (const R*)c->JT, A, h, du_h, lam,
-                                                                  gout, dbu, dA, dub)));
+  PISO_DISPATCH_D_DIAG(c, (k_h_bwd<R, D, DG><<<G, kWG, 0, s>>>(c->grid, (const R*)c->JT, (const R*)c->bjt, A, h,
+                                                                  du_h, lam, gout, dbu, dA, dub)));
   return check_b(c, "k_h_bwd");
 }
 
@@ -549,10 +550,10 @@ int launch_bcross_bwd(piso_ctx* c, hipStream_t s, const R* nu, int nu_field, con
                       R* dnu_cell, R* dub) {
   const int G = grid_cells(c->N);
   if (c->dim == 2)
-    k_bcross_bwd<R, 2><<<G, kWG, 0, s>>>(c->grid, (const R*)c->alphax, (const R*)c->invJ, nu, nu_field, ub, dbu,
+    k_bcross_bwd<R, 2><<<G, kWG, 0, s>>>(c->grid, (const R*)c->balpha, (const R*)c->invJ, nu, nu_field, ub, dbu,
                                          dnu_cell, dub);
   else
-    k_bcross_bwd<R, 3><<<G, kWG, 0, s>>>(c->grid, (const R*)c->alphax, (const R*)c->invJ, nu, nu_field, ub, dbu,
+    k_bcross_bwd<R, 3><<<G, kWG, 0, s>>>(c->grid, (const R*)c->balpha, (const R*)c->invJ, nu, nu_field, ub, dbu,
                                          dnu_cell, dub);
   return check_b(c, "k_bcross_bwd");
 }
@@ -562,8 +563,9 @@ int launch_assemble_bwd(piso_ctx* c, hipStream_t s, const R* u, const R* nu, int
                         double dt, const R* dA, const R* dC, const R* dbu, R* du, R* dS, R* dnu_cell, R* dub) {
   const int G = grid_cells(c->N);
   PISO_DISPATCH_D_DIAG(c, (k_assemble_bwd<R, D, DG><<<G, kWG, 0, s>>>(
-                              c->grid, (const R*)c->JT, (const R*)c->invJ, (const R*)c->alpha, nu, nu_field, ub,
-                              R(1.0 / dt), dA, dC, dbu, du, dS, dnu_cell, dub)));
+                              c->grid, (const R*)c->JT, (const R*)c->invJ, (const R*)c->alpha, (const R*)c->bjt,
+                              (const R*)c->balpha, nu, nu_field, ub, R(1.0 / dt), dA, dC, dbu, du, dS, dnu_cell,
+                              dub)));
   (void)u;
   return check_b(c, "k_assemble_bwd");
 }

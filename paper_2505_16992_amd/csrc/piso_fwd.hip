@@ -79,7 +79,8 @@ __device__ __forceinline__ R bdiff(const Grid& g, const Cell& c, int P, int j, i
 template <typename R, int D, bool DIAG>
 __global__ void __launch_bounds__(kWG)
 k_assemble(Grid g, const R* __restrict__ JT, const R* __restrict__ invJ, const R* __restrict__ alpha,
-           const R* __restrict__ alphax, const R* __restrict__ u, const R* __restrict__ p,
+           const R* __restrict__ alphax, const R* __restrict__ bjt, const R* __restrict__ balpha,
+           const R* __restrict__ u, const R* __restrict__ p,
            const R* __restrict__ nu, int nu_field, const R* __restrict__ S, const R* __restrict__ ub,
            R dt_inv, int gradp, const R* __restrict__ tgu, int nonorth, R* __restrict__ A,
            R* __restrict__ C, R* __restrict__ bu, R* __restrict__ b) {
@@ -134,18 +135,20 @@ k_assemble(Grid g, const R* __restrict__ JT, const R* __restrict__ invJ, const R
           C[(size_t)j * N + P] = R(0);
           C[(size_t)(D + j) * N + P] = R(0);
         }
-        Ad += R(2) * aP * nuP * iJ;
+        // the face's own metrics (App. A.4; the boundary cell's unless given)
+        const R ab = balpha[(size_t)j * NB + f];
+        Ad += R(2) * ab * nuP * iJ;
         R Ub = R(0);
 #pragma unroll
-        for (int i = 0; i < D; ++i) Ub += jt<R, D, DIAG>(JT, j, i, P, N) * ub[(size_t)i * NB + f];
-        const R coef = (R(2) * aP * nuP - Nf * Ub) * iJ;
+        for (int i = 0; i < D; ++i) Ub += bjt[(size_t)i * NB + f] * ub[(size_t)i * NB + f];
+        const R coef = (R(2) * ab * nuP - Nf * Ub) * iJ;
 #pragma unroll
         for (int i = 0; i < D; ++i) r[i] += ub[(size_t)i * NB + f] * coef;
         if (nonorth) {
 #pragma unroll
           for (int k = 0; k < D; ++k) {
             if (k == j) continue;
-            const R w = alphax[(size_t)ax_index(j, k) * N + P] * nuP;
+            const R w = balpha[(size_t)k * NB + f] * nuP;
 #pragma unroll
             for (int i = 0; i < D; ++i) r[i] += Nf * w * bdiff<R>(g, c, P, j, s, k, f, ub + (size_t)i * NB) * iJ;
           }
@@ -242,7 +245,7 @@ k_h(Grid g, const R* __restrict__ JT, const R* __restrict__ A, const R* __restri
 // mean_out[0] receives mean(rhs).  OT is the output type (double in the MIXED form).
 template <typename R, typename OT, int D, bool DIAG>
 __global__ void __launch_bounds__(kWG)
-k_div(Grid g, const R* __restrict__ JT, const R* __restrict__ W, const R* __restrict__ ub,
+k_div(Grid g, const R* __restrict__ bjt, const R* __restrict__ W, const R* __restrict__ ub,
       const R* __restrict__ A, const R* __restrict__ alphax, const R* __restrict__ tgp, int nonorth,
       OT* __restrict__ rhs, double* __restrict__ partials) {
   const int N = g.N, NB = g.NB;
@@ -276,7 +279,7 @@ k_div(Grid g, const R* __restrict__ JT, const R* __restrict__ W, const R* __rest
           const int f = -1 - F;
           OT Ub = OT(0);
 #pragma unroll
-          for (int i = 0; i < D; ++i) Ub += (OT)jt<R, D, DIAG>(JT, j, i, P, N) * (OT)ub[(size_t)i * NB + f];
+          for (int i = 0; i < D; ++i) Ub += (OT)bjt[(size_t)i * NB + f] * (OT)ub[(size_t)i * NB + f];
           r += Nf * Ub;
         }
       }
@@ -288,12 +291,12 @@ k_div(Grid g, const R* __restrict__ JT, const R* __restrict__ W, const R* __rest
 }
 
 // Face-flux divergence of a corrected flux F ([d][N], the +j face of every cell as
-// k_correct writes it) with the Dirichlet boundary fluxes J T_j(P) . u_b (eq. divtheorem,
+// k_correct writes it) with the Dirichlet boundary fluxes (J T_j)_f . u_b (eq. divtheorem,
 // N_f = +1 on high sides): the largest |sum_f N_f F_f| of the work-group's cells into
 // partials.  A face across the -j side is the +j face of the neighbour.
 template <typename R, int D, bool DIAG>
 __global__ void __launch_bounds__(kWG)
-k_flux_div(Grid g, const R* __restrict__ JT, const R* __restrict__ F, const R* __restrict__ ub,
+k_flux_div(Grid g, const R* __restrict__ bjt, const R* __restrict__ F, const R* __restrict__ ub,
            double* __restrict__ partials) {
   const int N = g.N, NB = g.NB;
   int beg, end;
@@ -314,7 +317,7 @@ k_flux_div(Grid g, const R* __restrict__ JT, const R* __restrict__ F, const R* _
           const int f = -1 - Fn;
           double Ub = 0.0;
 #pragma unroll
-          for (int i = 0; i < D; ++i) Ub += (double)jt<R, D, DIAG>(JT, j, i, P, N) * (double)ub[(size_t)i * NB + f];
+          for (int i = 0; i < D; ++i) Ub += (double)bjt[(size_t)i * NB + f] * (double)ub[(size_t)i * NB + f];
           s += Nf * Ub;
         }
       }
@@ -536,7 +539,8 @@ int launch_assemble(piso_ctx* c, hipStream_t s, const R* u, const R* p, const R*
   }
   PISO_DISPATCH_D_DIAG(c, (k_assemble<R, D, DG><<<G, kWG, 0, s>>>(
                               c->grid, (const R*)c->JT, (const R*)c->invJ, (const R*)c->alpha,
-                              (const R*)c->alphax, u, p, nu, nu_field, S, ub, R(1.0 / dt), gradp, tgu,
+                              (const R*)c->alphax, (const R*)c->bjt, (const R*)c->balpha, u, p, nu, nu_field, S,
+                              ub, R(1.0 / dt), gradp, tgu,
                               c->nonorth ? 1 : 0, A, C, bu, b)));
   return check_launch(c, "k_assemble");
 }
@@ -568,7 +572,7 @@ int launch_div(piso_ctx* c, hipStream_t s, const R* W, const R* ub, const R* A, 
   const int G = grid_red(c->N);
   double* pt = part(c, kPartS);
   PISO_DISPATCH_D_DIAG(c, (k_div<R, OT, D, DG><<<G, kWG, 0, s>>>(
-                              c->grid, (const R*)c->JT, W, ub, A, (const R*)c->alphax, tgp,
+                              c->grid, (const R*)c->bjt, W, ub, A, (const R*)c->alphax, tgp,
                               c->nonorth ? 1 : 0, rhs, pt)));
   if (int rc = check_launch(c, "k_div")) return rc;
   k_finalize<<<1, kWG, 0, s>>>(pt, G, 1, 1.0 / c->N, mean_out);
@@ -595,7 +599,7 @@ template <typename R>
 int launch_flux_div(piso_ctx* c, hipStream_t s, const R* F, const R* ub, double* out) {
   const int G = grid_red(c->N);
   double* pt = part(c, kPartS);
-  PISO_DISPATCH_D_DIAG(c, (k_flux_div<R, D, DG><<<G, kWG, 0, s>>>(c->grid, (const R*)c->JT, F, ub, pt)));
+  PISO_DISPATCH_D_DIAG(c, (k_flux_div<R, D, DG><<<G, kWG, 0, s>>>(c->grid, (const R*)c->bjt, F, ub, pt)));
   if (int rc = check_launch(c, "k_flux_div")) return rc;
   k_max_partials<<<1, kWG, 0, s>>>(pt, G, out);
   return check_launch(c, "k_max_partials");

@@ -155,6 +155,10 @@ struct piso_ctx {
   void* invJ = nullptr;   // [N]
   void* alpha = nullptr;  // [d][N] alpha_jj
   void* alphax = nullptr; // [d(d-1)/2][N] alpha_jk (j < k), non-orthogonal grids only
+  // metrics of the Dirichlet faces (the boundary cell's unless given at piso_create), with
+  // j_f the axis of face f: bjt[i][f] = (J T)_{j_f i}, balpha[k][f] = alpha_{j_f k}
+  void* bjt = nullptr;    // [d][NB]
+  void* balpha = nullptr; // [d][NB]
   // workspaces, working precision unless noted
   void *w_A = nullptr, *w_C = nullptr, *w_bu = nullptr, *w_b = nullptr, *w_Pf = nullptr,
        *w_Dinv = nullptr, *w_h = nullptr, *w_W = nullptr, *w_rhs = nullptr, *w_us = nullptr,
@@ -370,6 +374,8 @@ int launch_scale_invJ(piso_ctx* c, hipStream_t s, const R* x, int ncomp, R* y);
 // of u_b) into *out (device)
 template <typename R>
 int launch_flux_div(piso_ctx* c, hipStream_t s, const R* F, const R* ub, double* out);
+// Cell and side (2 axis + high) of every Dirichlet face, from the face map.
+int bface_cells(piso_ctx* c, std::vector<int>& bcell, std::vector<int>& bside);
 // y = 2 p - q over ncomp fields of N cells
 template <typename R>
 int launch_extrapolate(piso_ctx* c, hipStream_t s, const R* p, const R* q, R* y, int ncomp = 1);

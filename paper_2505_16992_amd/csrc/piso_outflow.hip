@@ -32,12 +32,22 @@ __device__ __forceinline__ R jt_dot(const R* __restrict__ JT, int N, int P, int 
   return s;
 }
 
+// (J T_j)_f . v with the metrics of Dirichlet face f (bjt [d][NB]): the face's flux of v,
+// the Dirichlet flux the step adds to the pressure right-hand side.
+template <typename R, int D>
+__device__ __forceinline__ R bjt_dot(const R* __restrict__ bjt, int NB, int f, const R (&v)[D]) {
+  R s = R(0);
+#pragma unroll
+  for (int i = 0; i < D; ++i) s += bjt[(size_t)i * NB + f] * v[i];
+  return s;
+}
+
 // Per face: the advanced value u_b* (outflow faces) or u_b (others), written to
 // star, and the partial sums of Q_out and Q_rest.
 template <typename R, int D, bool DIAG>
 __global__ void __launch_bounds__(kWG)
 k_out_star(int N, int NB, const int* __restrict__ bcell, const int* __restrict__ bside,
-           const R* __restrict__ JT, const R* __restrict__ invJ, const R* __restrict__ u,
+           const R* __restrict__ JT, const R* __restrict__ bjt, const R* __restrict__ invJ, const R* __restrict__ u,
            const R* __restrict__ ub, const int* __restrict__ outflow, OutflowUm um, R dt2,
            R* __restrict__ star, double* __restrict__ partials) {
   double acc[2] = {0.0, 0.0};
@@ -58,7 +68,7 @@ k_out_star(int N, int NB, const int* __restrict__ bcell, const int* __restrict__
     }
 #pragma unroll
     for (int i = 0; i < D; ++i) star[(size_t)i * NB + f] = v[i];
-    const double q = (double)(sgn * jt_dot<R, D, DIAG>(JT, N, P, j, v));
+    const double q = (double)(sgn * bjt_dot<R, D>(bjt, NB, f, v));
     if (out) acc[0] += q;
     else acc[1] += q;
   }
@@ -88,7 +98,7 @@ k_out_scale(int NB, const int* __restrict__ outflow, const R* __restrict__ star,
 template <typename R, int D, bool DIAG>
 __global__ void __launch_bounds__(kWG)
 k_outb_1(int N, int NB, const int* __restrict__ bcell, const int* __restrict__ bside,
-         const R* __restrict__ JT, const R* __restrict__ invJ, const R* __restrict__ u,
+         const R* __restrict__ JT, const R* __restrict__ bjt, const R* __restrict__ invJ, const R* __restrict__ u,
          const R* __restrict__ ub, const int* __restrict__ outflow, OutflowUm um, R dt2,
          const R* __restrict__ gbar, R* __restrict__ star, double* __restrict__ partials) {
   double acc[3] = {0.0, 0.0, 0.0};
@@ -113,7 +123,7 @@ k_outb_1(int N, int NB, const int* __restrict__ bcell, const int* __restrict__ b
     }
 #pragma unroll
     for (int i = 0; i < D; ++i) star[(size_t)i * NB + f] = v[i];
-    const double q = (double)(sgn * jt_dot<R, D, DIAG>(JT, N, P, j, v));
+    const double q = (double)(sgn * bjt_dot<R, D>(bjt, NB, f, v));
     if (out) acc[0] += q;
     else acc[1] += q;
   }
@@ -126,7 +136,8 @@ k_outb_1(int N, int NB, const int* __restrict__ bcell, const int* __restrict__ b
 template <typename R, int D, bool DIAG>
 __global__ void __launch_bounds__(kWG)
 k_outb_2(int N, int NB, const int* __restrict__ bcell, const int* __restrict__ bside,
-         const R* __restrict__ JT, const R* __restrict__ invJ, const int* __restrict__ outflow, OutflowUm um,
+         const R* __restrict__ JT, const R* __restrict__ bjt, const R* __restrict__ invJ,
+         const int* __restrict__ outflow, OutflowUm um,
          R dt2, const R* __restrict__ gbar, const double* __restrict__ partials, int Gp, R* __restrict__ dub,
          R* __restrict__ contrib) {
   double t[3];
@@ -149,10 +160,8 @@ k_outb_2(int N, int NB, const int* __restrict__ bcell, const int* __restrict__ b
     }
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      // flux weight w_i = N_b J T_ji(P)
-      R w;
-      if (DIAG) w = i == j ? sgn * JT[(size_t)j * N + P] : R(0);
-      else w = sgn * JT[(size_t)(j * D + i) * N + P];
+      // flux weight w_i = N_b (J T_ji)_f of the face
+      const R w = sgn * bjt[(size_t)i * NB + f];
       const R g = gbar[(size_t)i * NB + f];
       const R sb = out ? s * g - k_out * w : g - k_rest * w;
       dub[(size_t)i * NB + f] = out ? sb / (R(1) + cf) : sb;
@@ -179,10 +188,10 @@ k_outb_3(int N, int NB, int nbc, const int* __restrict__ bc_cell, const int* __r
 
 // ------------------------------------------------------------------ host
 
-int outflow_build(piso_ctx* c) {
+int bface_cells(piso_ctx* c, std::vector<int>& bcell, std::vector<int>& bside) {
   const int NB = c->NB, B = c->nblocks, D = c->dim;
-  if (NB == 0) return PISO_OK;
-  std::vector<int> bcell(NB, -1), bside(NB, -1);
+  bcell.assign(NB, -1);
+  bside.assign(NB, -1);
   for (int b = 0; b < B; ++b) {
     const int* t = &c->h_tab[(size_t)b * kTabStride];
     const int n[3] = {t[1], t[2], t[3]};
@@ -207,6 +216,16 @@ int outflow_build(piso_ctx* c) {
         }
     }
   }
+  for (int f = 0; f < NB; ++f)
+    if (bcell[f] < 0) return fail(c, PISO_E_TOPOLOGY, "Dirichlet face without a cell");
+  return PISO_OK;
+}
+
+int outflow_build(piso_ctx* c) {
+  const int NB = c->NB, D = c->dim;
+  if (NB == 0) return PISO_OK;
+  std::vector<int> bcell, bside;
+  if (int rc = bface_cells(c, bcell, bside)) return rc;
   // boundary cells and their faces, cells ascending, faces ascending
   std::vector<std::pair<int, int>> cf(NB);
   for (int f = 0; f < NB; ++f) cf[f] = {bcell[f], f};
@@ -258,7 +277,8 @@ int outflow_update(piso_ctx* c, hipStream_t s, const R* u, const R* ub, const in
   R* star = (R*)c->out_star;
   const R dt2 = (R)(2.0 * dt);
   PISO_OUT_DISPATCH(c, (k_out_star<R, D, DG><<<G, kWG, 0, s>>>(N, NB, c->out_bcell, c->out_bside,
-                                                                (const R*)c->JT, (const R*)c->invJ, u, ub,
+                                                                (const R*)c->JT, (const R*)c->bjt,
+                                                                (const R*)c->invJ, u, ub,
                                                                 outflow, um, dt2, star, pS)));
   if (c->dim == 2) k_out_scale<R, 2><<<G, kWG, 0, s>>>(NB, outflow, star, pS, G, ub_out);
   else k_out_scale<R, 3><<<G, kWG, 0, s>>>(NB, outflow, star, pS, G, ub_out);
@@ -276,10 +296,12 @@ int outflow_update_bwd(piso_ctx* c, hipStream_t s, const R* u, const R* ub, cons
   R* contrib = (R*)c->out_contrib;
   const R dt2 = (R)(2.0 * dt);
   PISO_OUT_DISPATCH(c, (k_outb_1<R, D, DG><<<G, kWG, 0, s>>>(N, NB, c->out_bcell, c->out_bside, (const R*)c->JT,
-                                                              (const R*)c->invJ, u, ub, outflow, um, dt2, gbar,
+                                                              (const R*)c->bjt, (const R*)c->invJ, u, ub, outflow,
+                                                              um, dt2, gbar,
                                                               star, pS)));
   PISO_OUT_DISPATCH(c, (k_outb_2<R, D, DG><<<G, kWG, 0, s>>>(N, NB, c->out_bcell, c->out_bside, (const R*)c->JT,
-                                                              (const R*)c->invJ, outflow, um, dt2, gbar, pS, G,
+                                                              (const R*)c->bjt, (const R*)c->invJ, outflow, um,
+                                                              dt2, gbar, pS, G,
                                                               dub, contrib)));
   if (du) {
     const int Gc = grid_cells(c->out_nbc);

@@ -33,6 +33,8 @@ int validate_desc(const piso_domain_desc* desc, int precision, std::string* err)
   if (desc->n_blocks < 1 || desc->n_blocks > kMaxBlocks) return topo_fail(err, PISO_E_ARG, "n_blocks must be 1..16");
   if (desc->n_sides < 0) return topo_fail(err, PISO_E_ARG, "n_sides must be >= 0");
   if (precision < PISO_F64 || precision > PISO_MIXED) return topo_fail(err, PISO_E_ARG, "bad precision");
+  if ((desc->Tb == nullptr) != (desc->Jb == nullptr))
+    return topo_fail(err, PISO_E_ARG, "face metrics: Tb and Jb are given together or not at all");
   return PISO_OK;
 }
 
