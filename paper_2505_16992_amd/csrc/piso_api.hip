@@ -270,8 +270,7 @@ int do_step(piso_ctx* c, hipStream_t s, const R* u_n, const R* p_n, const R* nu,
     A = t.A; C = t.C; Pf = t.Pf; Dinv = t.Dinv; us = t.us; h1 = t.h1; p1 = t.p1; u1 = t.u1; h2 = t.h2; p2 = t.p2;
   } else {
     A = (R*)c->w_A; C = (R*)c->w_C; Pf = (R*)c->w_Pf; Dinv = (R*)c->w_Dinv; us = (R*)c->w_us;
-    h1 = (R*)c->w_h1; p1 = o->p_star_out ? (R*)o->p_star_out : (R*)c->w_p1; u1 = (R*)c->w_u1; h2 = (R*)c->w_h;
-    p2 = p_np1;
+    h1 = (R*)c->w_h1; p1 = (R*)c->w_p1; u1 = (R*)c->w_u1; h2 = (R*)c->w_h; p2 = p_np1;
   }
   R* bu = (R*)c->w_bu;
   R* b = (R*)c->w_b;
@@ -294,10 +293,13 @@ int do_step(piso_ctx* c, hipStream_t s, const R* u_n, const R* p_n, const R* nu,
   const bool fdiv = info && o->report_flux_div;
   R* Fbuf = fdiv ? (R*)c->w_b : nullptr;
   for (int k = 0; k < ncorr; ++k) {
-    // the last corrector writes the outputs; earlier ones use the u**, h*, p* slots
+    // the last corrector writes the outputs; earlier ones use the u**, h*, p* slots, and
+    // correctors between the first and the last alternate their pressure between a spare
+    // buffer (the adjoint's, unused here) and p1, so that p_lag is never overwritten
+    // before the right-hand side has read it
     const bool last = (k == ncorr - 1);
     R* h = last ? h2 : h1;
-    R* pk = last ? p2 : p1;
+    R* pk = last ? p2 : (k == 0 ? p1 : ((k & 1) ? (R*)c->a_pbar : p1));
     R* uk = last ? u_np1 : u1;
     // starts of the solves from the earlier steps of the rollout: corrector 1 from the
     // previous p* advanced by the last change of p, or from p extrapolated in time;
@@ -325,15 +327,12 @@ int do_step(piso_ctx* c, hipStream_t s, const R* u_n, const R* p_n, const R* nu,
       rc = launch_flux_div<R>(c, s, Fbuf, ub, c->mix_scal + 6 + (last ? 1 : 0));
       if (rc) return rc;
     }
+    if (k == 0 && o->p_star_out && o->p_star_out != (void*)pk)   // p* for the next step's start
+      PISO_HIP(c, hipMemcpyAsync(o->p_star_out, pk, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
     u_in = uk;
     p_lag = pk;
   }
   if (p2 != p_np1) PISO_HIP(c, hipMemcpyAsync(p_np1, p2, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
-  if (o->p_star_out) {
-    const R* pst = ncorr == 1 ? p_np1 : p1;
-    if (pst != o->p_star_out)
-      PISO_HIP(c, hipMemcpyAsync(o->p_star_out, pst, sizeof(R) * N, hipMemcpyDeviceToDevice, s));
-  }
   if (info) {
     info->vel = vi;
     info->pres[0] = pi[0];

@@ -354,3 +354,32 @@ def test_extrapolated_start_saves_iterations(api, prec):
         assert torch.equal(uC, uT) and torch.equal(pC, pT)
         uN, _ = api.rollout(ctx, u, p, S, nu, ub, case.dt, 8, opts=o, extrapolate=False)
         assert torch.equal(uN, runs[False][0])
+
+
+@pytest.mark.parametrize("ncorr", [1, 3])
+def test_solve_starts_with_other_corrector_counts(api, ncorr):
+    """With one or three correctors the starts still only move where the solves begin:
+    the result equals the step without them to the solver tolerance, and p_star_out holds
+    the first corrector's pressure (with one corrector, the step's output pressure)."""
+    say("test_solve_starts_with_other_corrector_counts", ncorr)
+    case = small_cases()["cylinder_q"]
+    ctx = api.Context(case.domain, "f64")
+    _, (u, p, S, ub, nu) = _inputs(ctx, case, 31)
+    o = tight_opts(ctx)
+    o.n_correctors = ncorr
+    g = torch.Generator(device=u.device).manual_seed(32)
+    u_prev = u + 0.01 * torch.randn(u.shape, generator=g, device=u.device, dtype=u.dtype)
+    p_prev = p + 0.01 * torch.randn(p.shape, generator=g, device=p.device, dtype=p.dtype)
+    p_prev_star = p + 0.01 * torch.randn(p.shape, generator=g, device=p.device, dtype=p.dtype)
+    u0, p0 = ctx.step(u, p, nu, S, ub, case.dt, o)
+    pst = torch.empty_like(p)
+    u1, p1 = ctx.step(u, p, nu, S, ub, case.dt, o, u_prev=u_prev, p_prev=p_prev, p_prev_star=p_prev_star,
+                      p_star_out=pst)
+    assert rel(host(u1), host(u0)) < 1e-10 and rel_p(host(p1), host(p0)) < 1e-9
+    if ncorr == 1:
+        assert torch.equal(pst, p1)
+    else:
+        o1 = tight_opts(ctx)
+        o1.n_correctors = 1
+        _, pstar_ref = ctx.step(u, p, nu, S, ub, case.dt, o1)   # corrector 1 alone
+        assert rel_p(host(pst), host(pstar_ref)) < 1e-9
