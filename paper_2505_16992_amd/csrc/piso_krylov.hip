@@ -1309,9 +1309,10 @@ int pressure_solve_mixed(piso_ctx* c, hipStream_t s, const double* Pf, const dou
     PISO_HIP(c, hipMemsetAsync(e32, 0, sizeof(float) * (size_t)N, s));
     int st_in = 0;
     double rel_in = 0.0;
-    // ask the inner solve only for the reduction still missing (with a margin of 2), but
-    // never for more than inner_rtol, the floor the float iteration reliably reaches
-    const double tol_in = std::min(0.5, std::max(o->inner_rtol, 0.5 * o->rtol / rel));
+    // ask the inner solve only for the reduction still missing, rtol / rel (the check of
+    // the double residual above decides whether another sweep follows), but never for more
+    // than inner_rtol, the floor the float iteration reliably reaches
+    const double tol_in = std::min(0.5, std::max(o->inner_rtol, o->rtol / rel));
     const bool same_in = c->pcg_same_op;
     c->pcg_same_op = same || sweeps > 0;   // later sweeps and correctors: same operator
     int rc = pcg_run<float, float>(c, s, Pf32, Dinv32, r32, nullptr, 1.0, e32, tol_in, o->max_iter,
