@@ -51,7 +51,8 @@ void add(Layout& L, int b, int s, int kind, int other = 0) {
   L.sides.push_back(side(b, s, kind, other, t0n, t1n));
 }
 
-int run(const Layout& L, Topology* t, std::string* err, int precision = PISO_F64) {
+int run(const Layout& L, Topology* t, std::string* err, int precision = PISO_F64, const double* Tb = nullptr,
+        const double* Jb = nullptr) {
   piso_domain_desc d{};
   d.dim = L.dim;
   d.n_blocks = (int)L.cells.size() / 3;
@@ -60,6 +61,8 @@ int run(const Layout& L, Topology* t, std::string* err, int precision = PISO_F64
   d.sides = L.sides.data();
   d.T = kDummy;
   d.J = kDummy;
+  d.Tb = Tb;
+  d.Jb = Jb;
   if (int rc = validate_desc(&d, precision, err)) return rc;
   return build_topology(&d, t, err);
 }
@@ -103,6 +106,13 @@ Layout box(int nx, int ny, int nz, bool px, bool py, bool pz, int dim = 3) {
 void handwritten() {
   Topology t;
   std::string err;
+  {
+    // face metrics come as a pair
+    Layout L = box(4, 4, 4, true, false, true);
+    expect("face metrics: Tb without Jb", run(L, &t, &err, PISO_F64, kDummy, nullptr), PISO_E_ARG);
+    expect("face metrics: Jb without Tb", run(L, &t, &err, PISO_F64, nullptr, kDummy), PISO_E_ARG);
+    expect("face metrics: both", run(L, &t, &err, PISO_F64, kDummy, kDummy), PISO_OK);
+  }
   {
     Layout L = box(6, 4, 4, true, true, true);
     expect("periodic box", run(L, &t, &err), PISO_OK);
