@@ -186,7 +186,8 @@ typedef struct {
                                 2 p_n - p_prev               with p_prev alone,
                                 p_n                          otherwise;
        corrector 2 starts from  p* + (p_n - p*_{n-1})        with p_prev_star,
-                                p* (corrector 1's pressure)  otherwise.
+                                p* (corrector 1's pressure)  otherwise;
+       later correctors start from the pressure of the corrector before them.
      p_star_out receives this step's p* (with one corrector: its only pressure) for the next
      step's p_prev_star.  p_star_out must not alias p_n, p_np1, p_prev or p_prev_star
      (PISO_E_ARG).  With u_prev (device [d][N]) the velocity solve starts from
