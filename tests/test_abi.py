@@ -48,6 +48,7 @@ def test_step_opts_layout_matches_library():
     assert all(b == 0xAB for b in buf[n:])
     o = L.StepOpts.from_buffer(buf)
     assert o.report_flux_div == 0 and o.adjoint_warm_start == 1 and o.n_correctors == 2
+    assert o.p_prev is None and o.p_prev_star is None and o.p_star_out is None and o.u_prev is None
 
 
 def _magic(d):
@@ -65,3 +66,34 @@ def test_division_magic_exact(d):
     for n in samples:
         assert (n * m) >> s == n // d
     assert m * ((1 << 31) - 1) < (1 << 64)
+
+
+def _header_structs():
+    """Field names of every 'typedef struct { ... } name;' in include/piso.h, in order
+    (comments removed; several declarators per line split; array sizes dropped)."""
+    import os
+    import re
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "piso.h")
+    text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct \{(.*?)\}\s*(\w+);", text, flags=re.S):
+        fields = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            first, *rest = decl.split(",")
+            names = [first.split()[-1]] + [r.strip() for r in rest]
+            fields += [re.sub(r"\[.*\]", "", n).lstrip("*") for n in names]
+        out[name] = fields
+    return out
+
+
+@pytest.mark.parametrize("c_name, py", [("piso_side_desc", "SideDesc"), ("piso_domain_desc", "DomainDesc"),
+                                        ("piso_solve_opts", "SolveOpts"), ("piso_solve_info", "SolveInfo"),
+                                        ("piso_step_opts", "StepOpts"), ("piso_step_info", "StepInfo"),
+                                        ("piso_system", "System"), ("piso_system_grad", "SystemGrad")])
+def test_binding_structs_follow_the_header(c_name, py):
+    """The ctypes structures list the header's fields in the header's order."""
+    fields = _header_structs()[c_name]
+    assert [f[0] for f in getattr(L, py)._fields_] == fields
